@@ -1,0 +1,676 @@
+/*
+ * ibb_oracle.c -- plain, slow, CPU reference ("oracle") for the interval
+ * branch-and-bound sweep of Zhang, Shan & Cagan, "Global optimization tailored
+ * for GPUs: complete and rigorous search for large-scale nonlinear
+ * minimization" (arXiv 2507.01770).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product links, imports or calls
+ * this file; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no source with the GPU library.
+ *
+ * Every endpoint operation switches the x86 rounding mode with fesetround()
+ * right before it and reads its operands through volatile copies, so the
+ * compiler can neither fold nor move the arithmetic across the mode switch.
+ * This is deliberately the most literal way to get IEEE directed rounding.
+ *
+ * What each part follows (paper section / equation):
+ *   - interval +, -, x, / : Sec. 2.1, Eqs. (3)-(6); division is multiplication
+ *     by the reciprocal interval, exactly as Eq. (6) writes it.
+ *   - outward rounding (lower endpoint rounded down, upper rounded up): Sec. 2.1.
+ *   - natural interval extension of f and of its first derivatives: Sec. 2.1
+ *     and Sec. 3.1 ("Partition the selected region ..." and the first-order test).
+ *   - the iteration (select smallest lower bound, sample, cut off regions whose
+ *     lower bound exceeds GUB, partition with variable cycling, first-order
+ *     test, insert, stop, output [GLB, GUB]): Sec. 3.1 and Sec. 3.2.
+ * Readings of points the paper leaves open are listed in the design notes of
+ * the repository; the ones that change numbers are restated where they apply.
+ */
+#include <fenv.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#pragma STDC FENV_ACCESS ON
+
+/* ------------------------------------------------------------------------- */
+/* directed scalar operations                                                */
+/* ------------------------------------------------------------------------- */
+
+static double dn_add(double a, double b) { volatile double x = a, y = b; fesetround(FE_DOWNWARD); volatile double r = x + y; fesetround(FE_TONEAREST); return r; }
+static double up_add(double a, double b) { volatile double x = a, y = b; fesetround(FE_UPWARD);   volatile double r = x + y; fesetround(FE_TONEAREST); return r; }
+static double dn_sub(double a, double b) { volatile double x = a, y = b; fesetround(FE_DOWNWARD); volatile double r = x - y; fesetround(FE_TONEAREST); return r; }
+static double up_sub(double a, double b) { volatile double x = a, y = b; fesetround(FE_UPWARD);   volatile double r = x - y; fesetround(FE_TONEAREST); return r; }
+static double dn_mul(double a, double b) { volatile double x = a, y = b; fesetround(FE_DOWNWARD); volatile double r = x * y; fesetround(FE_TONEAREST); return r; }
+static double up_mul(double a, double b) { volatile double x = a, y = b; fesetround(FE_UPWARD);   volatile double r = x * y; fesetround(FE_TONEAREST); return r; }
+static double dn_div(double a, double b) { volatile double x = a, y = b; fesetround(FE_DOWNWARD); volatile double r = x / y; fesetround(FE_TONEAREST); return r; }
+static double up_div(double a, double b) { volatile double x = a, y = b; fesetround(FE_UPWARD);   volatile double r = x / y; fesetround(FE_TONEAREST); return r; }
+static double dn_sqrt(double a) { volatile double x = a; fesetround(FE_DOWNWARD); volatile double r = sqrt(x); fesetround(FE_TONEAREST); return r; }
+static double up_sqrt(double a) { volatile double x = a; fesetround(FE_UPWARD);   volatile double r = sqrt(x); fesetround(FE_TONEAREST); return r; }
+
+static double dmin(double a, double b) { return b < a ? b : a; }
+static double dmax(double a, double b) { return b > a ? b : a; }
+
+/* ------------------------------------------------------------------------- */
+/* intervals                                                                 */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { double lo, hi; } iv;
+
+static iv mk(double lo, double hi) { iv r; r.lo = lo; r.hi = hi; return r; }
+static iv entire(void) { return mk(-INFINITY, INFINITY); }
+static int bad(iv a) { return isnan(a.lo) || isnan(a.hi); }
+static iv fix(iv r) { return bad(r) ? entire() : r; }
+
+/* Eq. (3) */
+static iv iv_add(iv a, iv b) { return fix(mk(dn_add(a.lo, b.lo), up_add(a.hi, b.hi))); }
+/* Eq. (4) */
+static iv iv_sub(iv a, iv b) { return fix(mk(dn_sub(a.lo, b.hi), up_sub(a.hi, b.lo))); }
+/* Eq. (5): min / max over the four endpoint products, each rounded outward */
+static iv iv_mul(iv a, iv b) {
+  double p[4] = { a.lo, a.lo, a.hi, a.hi }, q[4] = { b.lo, b.hi, b.lo, b.hi };
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = 0; i < 4; ++i) {
+    double l = dn_mul(p[i], q[i]), h = up_mul(p[i], q[i]);
+    if (isnan(l) || isnan(h)) return entire();
+    lo = dmin(lo, l);
+    hi = dmax(hi, h);
+  }
+  return mk(lo, hi);
+}
+/* reciprocal of an interval not containing zero; otherwise the whole line */
+static iv iv_recip(iv b) {
+  if (!(b.lo > 0.0 || b.hi < 0.0)) return entire();
+  return fix(mk(dn_div(1.0, b.hi), up_div(1.0, b.lo)));
+}
+/* Eq. (6): a / b = a * (1 / b) */
+static iv iv_div(iv a, iv b) { return iv_mul(a, iv_recip(b)); }
+/* square root on the non-negative part */
+static iv iv_sqrt(iv a) {
+  if (bad(a) || a.hi < 0.0) return entire();
+  return mk(a.lo > 0.0 ? dn_sqrt(a.lo) : 0.0, up_sqrt(a.hi));
+}
+/* x^2 as a single operation (tighter than a*a when 0 lies inside) */
+static iv iv_sqr(iv a) {
+  if (a.lo >= 0.0) return fix(mk(dn_mul(a.lo, a.lo), up_mul(a.hi, a.hi)));
+  if (a.hi <= 0.0) return fix(mk(dn_mul(a.hi, a.hi), up_mul(a.lo, a.lo)));
+  double m = dmax(-a.lo, a.hi);
+  return fix(mk(0.0, up_mul(m, m)));
+}
+static iv iv_abs(iv a) {
+  if (a.lo >= 0.0) return a;
+  if (a.hi <= 0.0) return mk(-a.hi, -a.lo);
+  return mk(0.0, dmax(-a.lo, a.hi));
+}
+/* enclosure of the generalized derivative of |x| over a */
+static iv iv_dabs(iv a) {
+  if (a.lo > 0.0) return mk(1.0, 1.0);
+  if (a.hi < 0.0) return mk(-1.0, -1.0);
+  return mk(-1.0, 1.0);
+}
+static iv iv_scale(double s, iv a) { return iv_mul(mk(s, s), a); }
+static iv iv_sub_s(iv a, double s) { return iv_sub(a, mk(s, s)); }
+
+/* ------------------------------------------------------------------------- */
+/* cos(2 pi y) and sin(2 pi y)                                              */
+/*                                                                           */
+/* The families use the elementary functions cos(2*pi*y) and sin(2*pi*y) of  */
+/* an argument y that carries no pi.  The point enclosure at a double y:     */
+/*   f = y - nearest_integer(y)      (exact, |f| <= 1/2)                      */
+/*   then exact octant identities bring the argument to g with |g| <= 1/8:   */
+/*     cos(2 pi a) = sin(2 pi (1/4 - a)),   cos(2 pi a) = -cos(2 pi (1/2 - a)) */
+/*     sin(2 pi a) = cos(2 pi (a - 1/4)),   sin(2 pi a) =  sin(2 pi (1/2 - a)) */
+/*   v = cosl/sinl(2 pi * g) in x87 extended precision, round to nearest,    */
+/*   and the enclosure is [v - |v| 2^-58, v + |v| 2^-58] rounded outward to   */
+/*   double, then clamped to [-1, 1].                                         */
+/* The extended-precision error (argument rounding plus the library) is a    */
+/* few units of 2^-63 relative, far inside the 2^-58 margin.                 */
+/* ------------------------------------------------------------------------- */
+
+static const long double TWO_PI_L = 6.283185307179586476925286766559005768L;
+
+static void ld_enclose(long double v, double* lo, double* hi) {
+  long double m = fabsl(v) * 0x1p-58L;
+  volatile long double vv = v, mm = m;
+  fesetround(FE_DOWNWARD);
+  volatile long double l = vv - mm;
+  volatile double ld = (double)l;
+  fesetround(FE_UPWARD);
+  volatile long double h = vv + mm;
+  volatile double hd = (double)h;
+  fesetround(FE_TONEAREST);
+  *lo = ld < -1.0 ? -1.0 : ld;
+  *hi = hd > 1.0 ? 1.0 : hd;
+}
+
+/* which = 0: cos(2 pi y); which = 1: sin(2 pi y) */
+static void pt_trig2pi(int which, double y, double* lo, double* hi) {
+  if (isnan(y) || isinf(y)) { *lo = -1.0; *hi = 1.0; return; }
+  double f = y - nearbyint(y);          /* exact */
+  double a = fabs(f);
+  double s = f < 0.0 ? -1.0 : 1.0;
+  long double v;
+  double g;                             /* reduced argument, |g| <= 1/8 */
+  if (which == 0) {                     /* cos is even in f */
+    if (a <= 0.125)       { g = a;         v = cosl(TWO_PI_L * (long double)g); }
+    else if (a <= 0.375)  { g = 0.25 - a;  v = sinl(TWO_PI_L * (long double)g); }   /* 0.25 - a exact */
+    else                  { g = 0.5 - a;   v = -cosl(TWO_PI_L * (long double)g); }  /* 0.5 - a exact  */
+  } else {                              /* sin is odd in f */
+    if (a <= 0.125)       { g = a;         v = sinl(TWO_PI_L * (long double)g); }
+    else if (a <= 0.375)  { g = a - 0.25;  v = cosl(TWO_PI_L * (long double)g); }
+    else                  { g = 0.5 - a;   v = sinl(TWO_PI_L * (long double)g); }
+    v = (long double)s * v;
+  }
+  if (g == 0.0) {                       /* sin 0 = 0 and cos 0 = 1 exactly */
+    *lo = *hi = (double)v;
+    return;
+  }
+  ld_enclose(v, lo, hi);
+}
+
+/* does [p, q] contain an integer? (exact) */
+static int has_int(double p, double q) { return ceil(p) <= floor(q); }
+
+/* interval cos(2 pi Y): hull of the endpoint enclosures, +1 added when Y holds
+ * an integer, -1 added when Y holds a half-integer, whole [-1,1] when the
+ * width (rounded up) reaches one period. */
+static iv iv_cos2pi(iv y) {
+  if (bad(y) || isinf(y.lo) || isinf(y.hi)) return mk(-1.0, 1.0);
+  if (up_sub(y.hi, y.lo) >= 1.0) return mk(-1.0, 1.0);
+  double al, ah, bl, bh;
+  pt_trig2pi(0, y.lo, &al, &ah);
+  pt_trig2pi(0, y.hi, &bl, &bh);
+  double lo = dmin(al, bl), hi = dmax(ah, bh);
+  if (has_int(y.lo, y.hi)) hi = 1.0;                                   /* max at y in Z        */
+  if (has_int(dn_sub(y.lo, 0.5), up_sub(y.hi, 0.5))) lo = -1.0;        /* min at y in Z + 1/2  */
+  return mk(lo, hi);
+}
+/* interval sin(2 pi Y): max at y in Z + 1/4, min at y in Z - 1/4 */
+static iv iv_sin2pi(iv y) {
+  if (bad(y) || isinf(y.lo) || isinf(y.hi)) return mk(-1.0, 1.0);
+  if (up_sub(y.hi, y.lo) >= 1.0) return mk(-1.0, 1.0);
+  double al, ah, bl, bh;
+  pt_trig2pi(1, y.lo, &al, &ah);
+  pt_trig2pi(1, y.hi, &bl, &bh);
+  double lo = dmin(al, bl), hi = dmax(ah, bh);
+  if (has_int(dn_sub(y.lo, 0.25), up_sub(y.hi, 0.25))) hi = 1.0;
+  if (has_int(dn_add(y.lo, 0.25), up_add(y.hi, 0.25))) lo = -1.0;
+  return mk(lo, hi);
+}
+
+/* ------------------------------------------------------------------------- */
+/* pi enclosures used by the derivative scale factors                        */
+/* ------------------------------------------------------------------------- */
+
+static double hexd(uint64_t u) { double d; memcpy(&d, &u, 8); return d; }
+#define PI_LO_BITS 0x400921FB54442D18ull   /* largest double below pi  */
+#define PI_HI_BITS 0x400921FB54442D19ull   /* smallest double above pi */
+
+/* [c * pi * k * b] for a scale c in {1, 2} (exact power of two), k > 0 */
+static iv pi_k_b(double c, double k, double b) {
+  double pl = hexd(PI_LO_BITS) * c, ph = hexd(PI_HI_BITS) * c;   /* exact scaling */
+  iv pk = mk(dn_mul(pl, k), up_mul(ph, k));
+  return iv_mul(pk, mk(b, b));
+}
+
+/* ------------------------------------------------------------------------- */
+/* families                                                                  */
+/* ------------------------------------------------------------------------- */
+
+enum { FAM_SEP_COS = 1, FAM_CHAIN = 2, FAM_SEP_ABS_SIN2 = 3 };
+
+typedef struct {
+  int32_t family, n;
+  const double* coef; int64_t coef_len;
+  const double* lower; const double* upper;
+  double tol_f, tol_x;
+} orc_problem;
+
+static int64_t n_terms(const orc_problem* P) { return P->family == FAM_CHAIN ? (P->n >= 1 ? P->n - 1 : 0) : P->n; }
+
+/*
+ * Term t_i of f on the box x (intervals).  Expression trees:
+ *   SEP_COS      f = sum a_i (x_i - c_i)^2 + b_i (1 - cos(2 pi k_i (x_i - c_i)))
+ *                D = X_i - c_i,  Y = k_i D,  t = a_i D^2 + b_i (1 - cos2pi(Y))
+ *   CHAIN        f = sum_{i<n-1} alpha_i (x_{i+1} - x_i^2)^2 + beta_i (x_i - 1)^2
+ *                R = X_{i+1} - X_i^2,  E = X_i - 1,  t = alpha_i R^2 + beta_i E^2
+ *   SEP_ABS_SIN2 f = sum s_i |x_i - c_i| + b_i sin^2(pi k_i (x_i - c_i))
+ *                D = X_i - c_i,  H = (k_i/2) D,  t = s_i |D| + b_i sin2pi(H)^2
+ * (cos2pi(y) = cos(2 pi y), sin2pi(y) = sin(2 pi y).)
+ */
+static iv term(const orc_problem* P, const iv* X, int64_t i) {
+  const int64_t n = P->n;
+  const double* cf = P->coef;
+  switch (P->family) {
+  case FAM_SEP_COS: {
+    double a = cf[i], b = cf[n + i], k = cf[2 * n + i], c = cf[3 * n + i];
+    iv D = iv_sub_s(X[i], c);
+    iv Y = iv_scale(k, D);
+    iv S = iv_sqr(D);
+    iv C = iv_cos2pi(Y);
+    return iv_add(iv_scale(a, S), iv_scale(b, iv_sub(mk(1.0, 1.0), C)));
+  }
+  case FAM_CHAIN: {
+    double al = cf[i], be = cf[(n - 1) + i];
+    iv R = iv_sub(X[i + 1], iv_sqr(X[i]));
+    iv E = iv_sub_s(X[i], 1.0);
+    return iv_add(iv_scale(al, iv_sqr(R)), iv_scale(be, iv_sqr(E)));
+  }
+  case FAM_SEP_ABS_SIN2: {
+    double s = cf[i], b = cf[n + i], k = cf[2 * n + i], c = cf[3 * n + i];
+    iv D = iv_sub_s(X[i], c);
+    iv H = iv_scale(0.5 * k, D);
+    iv Sn = iv_sin2pi(H);
+    return iv_add(iv_scale(s, iv_abs(D)), iv_scale(b, iv_sqr(Sn)));
+  }
+  }
+  return entire();
+}
+
+/*
+ * Interval partial derivative G_j on the box x.
+ *   SEP_COS      G_j = (2 a_j) D + [2 pi k_j b_j] sin2pi(k_j D)
+ *   CHAIN        G_j = [j <= n-2] ( ((-4 alpha_j) X_j) R_j + (2 beta_j) E_j )
+ *                      + [j >= 1] (2 alpha_{j-1}) R_{j-1}
+ *                (parts that do not exist are left out, not added as zero)
+ *   SEP_ABS_SIN2 G_j = s_j dabs(D) + [pi k_j b_j] sin2pi(k_j D)
+ *                (d/dx b sin^2(pi k u) = pi k b sin(2 pi k u); dabs encloses
+ *                 the generalized derivative of |.|)
+ */
+static iv grad(const orc_problem* P, const iv* X, int64_t j) {
+  const int64_t n = P->n;
+  const double* cf = P->coef;
+  switch (P->family) {
+  case FAM_SEP_COS: {
+    double a = cf[j], b = cf[n + j], k = cf[2 * n + j], c = cf[3 * n + j];
+    iv D = iv_sub_s(X[j], c);
+    iv Y = iv_scale(k, D);
+    return iv_add(iv_scale(2.0 * a, D), iv_mul(pi_k_b(2.0, k, b), iv_sin2pi(Y)));
+  }
+  case FAM_CHAIN: {
+    int have = 0;
+    iv g = mk(0.0, 0.0);
+    if (j <= n - 2) {
+      double al = cf[j], be = cf[(n - 1) + j];
+      iv R = iv_sub(X[j + 1], iv_sqr(X[j]));
+      iv E = iv_sub_s(X[j], 1.0);
+      g = iv_add(iv_mul(iv_scale(-4.0 * al, X[j]), R), iv_scale(2.0 * be, E));
+      have = 1;
+    }
+    if (j >= 1) {
+      double al = cf[j - 1];
+      iv R = iv_sub(X[j], iv_sqr(X[j - 1]));
+      iv B = iv_scale(2.0 * al, R);
+      g = have ? iv_add(g, B) : B;
+      have = 1;
+    }
+    return g;
+  }
+  case FAM_SEP_ABS_SIN2: {
+    double s = cf[j], b = cf[n + j], k = cf[2 * n + j], c = cf[3 * n + j];
+    iv D = iv_sub_s(X[j], c);
+    iv Y = iv_scale(k, D);
+    return iv_add(iv_scale(s, iv_dabs(D)), iv_mul(pi_k_b(1.0, k, b), iv_sin2pi(Y)));
+  }
+  }
+  return entire();
+}
+
+/*
+ * Canonical sum: term t_i goes to slot i mod 64, each slot sums its terms left
+ * to right, then the slots are folded pairwise with strides 32, 16, 8, 4, 2, 1
+ * (slot s absorbs slot s + h); absent slots are skipped.  This order is part
+ * of the definition of the enclosure F (the paper does not fix one).
+ */
+static iv canonical_sum(const orc_problem* P, const iv* X) {
+  iv slot[64];
+  int present[64];
+  int64_t T = n_terms(P);
+  for (int s = 0; s < 64; ++s) present[s] = 0;
+  for (int64_t i = 0; i < T; ++i) {
+    int s = (int)(i % 64);
+    iv t = term(P, X, i);
+    slot[s] = present[s] ? iv_add(slot[s], t) : t;
+    present[s] = 1;
+  }
+  for (int h = 32; h >= 1; h /= 2)
+    for (int s = 0; s < h; ++s)
+      if (present[s + h]) {
+        slot[s] = present[s] ? iv_add(slot[s], slot[s + h]) : slot[s + h];
+        present[s] = 1;
+      }
+  return present[0] ? slot[0] : mk(0.0, 0.0);
+}
+
+/* bisection point of [lo, hi]: 0.5 lo + 0.5 hi rounded up, kept inside */
+static double midpoint(double lo, double hi) {
+  double m = up_add(up_mul(0.5, lo), up_mul(0.5, hi));
+  if (m < lo) m = lo;
+  if (m > hi) m = hi;
+  return m;
+}
+
+typedef struct { iv F; double ub; int mono; } box_eval;
+
+/*
+ * Bound one box: F over the box, the first-order test (Sec. 3.1: discard when
+ * some DLB_j > 0 and x_j^lo != l_j, or some DUB_j < 0 and x_j^hi != u_j), and
+ * the upper bound of f at the box midpoint (the sampling step of Sec. 3.1 with
+ * a single sample point).  G receives the gradient enclosure when non-NULL.
+ */
+static box_eval eval_box(const orc_problem* P, const double* lo, const double* hi, iv* X, iv* G) {
+  const int64_t n = P->n;
+  box_eval r;
+  for (int64_t i = 0; i < n; ++i) X[i] = mk(lo[i], hi[i]);
+  r.F = canonical_sum(P, X);
+  r.mono = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    iv g = grad(P, X, j);
+    if (G) G[j] = g;
+    if ((g.lo > 0.0 && lo[j] != P->lower[j]) || (g.hi < 0.0 && hi[j] != P->upper[j])) r.mono = 1;
+  }
+  for (int64_t i = 0; i < n; ++i) { double m = midpoint(lo[i], hi[i]); X[i] = mk(m, m); }
+  r.ub = canonical_sum(P, X).hi;
+  return r;
+}
+
+/* ------------------------------------------------------------------------- */
+/* the iteration                                                             */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { int32_t split_dims, select_k; int64_t max_sweeps, max_live_boxes; } orc_options;
+typedef struct { double f_lo, f_hi; int64_t n_boxes, sweeps, boxes_evaluated; int32_t status; } orc_info;
+
+enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_INVALID = -1, ST_NOMEM = -2, ST_INTERNAL = -5 };
+
+typedef struct { double* lo; double* hi; double flo, wmax; int64_t seq; int32_t cyc; } box;
+
+typedef struct {
+  int32_t n;
+  box* live; int64_t n_live, cap_live;
+  double gub;
+  orc_info info;
+  double* tr_gub; int64_t* tr_nsurv; int64_t* tr_nlive; int64_t* tr_sel; int64_t n_trace, cap_trace;
+} solve_state;
+
+static int push_box(solve_state* S, box b) {
+  if (S->n_live == S->cap_live) {
+    int64_t nc = S->cap_live ? 2 * S->cap_live : 1024;
+    box* nb = (box*)realloc(S->live, (size_t)nc * sizeof(box));
+    if (!nb) return 0;
+    S->live = nb; S->cap_live = nc;
+  }
+  S->live[S->n_live++] = b;
+  return 1;
+}
+static void free_box(box* b) { free(b->lo); free(b->hi); }
+
+static double box_wmax(int n, const double* lo, const double* hi) {
+  double w = 0.0;
+  for (int i = 0; i < n; ++i) w = dmax(w, up_sub(hi[i], lo[i]));
+  return w;
+}
+
+/* (flo, seq) lexicographic order used by the selection */
+static int key_less(const box* a, const box* b) {
+  if (a->flo != b->flo) return a->flo < b->flo;
+  return a->seq < b->seq;
+}
+
+/* remove every live box whose lower bound exceeds GUB (Sec. 3.1, "Remove the
+ * suboptimal regions"); equality is kept */
+static void cutoff(solve_state* S) {
+  int64_t w = 0;
+  for (int64_t i = 0; i < S->n_live; ++i) {
+    if (S->live[i].flo > S->gub) free_box(&S->live[i]);
+    else S->live[w++] = S->live[i];
+  }
+  S->n_live = w;
+}
+
+static int cmp_seq(const void* a, const void* b) {
+  int64_t x = ((const box*)a)->seq, y = ((const box*)b)->seq;
+  return (x > y) - (x < y);
+}
+
+void* orc_solve(const orc_problem* P, const orc_options* O, int64_t trace_cap) {
+  solve_state* S = (solve_state*)calloc(1, sizeof(solve_state));
+  if (!S) return NULL;
+  const int n = P->n;
+  S->n = n;
+  S->cap_trace = trace_cap > 0 ? trace_cap : 0;
+  if (S->cap_trace) {
+    S->tr_gub = (double*)malloc((size_t)S->cap_trace * sizeof(double));
+    S->tr_nsurv = (int64_t*)malloc((size_t)S->cap_trace * sizeof(int64_t));
+    S->tr_nlive = (int64_t*)malloc((size_t)S->cap_trace * sizeof(int64_t));
+    S->tr_sel = (int64_t*)malloc((size_t)S->cap_trace * sizeof(int64_t));
+  }
+  const int m = n < O->split_dims ? n : O->split_dims;
+  const int K = O->select_k > 0 ? O->select_k : 1;
+  iv* X = (iv*)malloc((size_t)n * sizeof(iv));
+  box* par = (box*)malloc((size_t)K * sizeof(box));
+  double* clo = (double*)malloc((size_t)n * sizeof(double));
+  double* chi = (double*)malloc((size_t)n * sizeof(double));
+
+  /* Initialization (Sec. 3.1): L = { whole domain } */
+  box root;
+  root.lo = (double*)malloc((size_t)n * sizeof(double));
+  root.hi = (double*)malloc((size_t)n * sizeof(double));
+  memcpy(root.lo, P->lower, (size_t)n * sizeof(double));
+  memcpy(root.hi, P->upper, (size_t)n * sizeof(double));
+  box_eval e0 = eval_box(P, root.lo, root.hi, X, NULL);
+  root.flo = e0.F.lo; root.seq = 0; root.cyc = 0; root.wmax = box_wmax(n, root.lo, root.hi);
+  S->gub = e0.ub;
+  S->info.boxes_evaluated = 1;
+  int64_t next_seq = 1;
+  push_box(S, root);
+  cutoff(S);
+
+  int32_t status = ST_NOT_CONVERGED;
+  int64_t sweeps = 0;
+  for (;;) {
+    if (S->n_live == 0) { status = ST_INTERNAL; break; }
+    /* GLB = smallest lower bound in L; stopping criteria (Sec. 3.1) */
+    double glb = INFINITY, wmax = 0.0;
+    for (int64_t i = 0; i < S->n_live; ++i) { glb = dmin(glb, S->live[i].flo); wmax = dmax(wmax, S->live[i].wmax); }
+    S->info.f_lo = glb; S->info.f_hi = S->gub;
+    if (up_sub(S->gub, glb) <= P->tol_f && (P->tol_x <= 0.0 || wmax < P->tol_x)) { status = ST_OK; break; }
+    if (sweeps >= O->max_sweeps) break;
+    if (O->max_live_boxes > 0 && S->n_live > O->max_live_boxes) break;
+
+    /* Select: the K boxes with the smallest (lower bound, seq), removed from L */
+    int kk = 0;
+    for (; kk < K && S->n_live > 0; ++kk) {
+      int64_t best = 0;
+      for (int64_t i = 1; i < S->n_live; ++i) if (key_less(&S->live[i], &S->live[best])) best = i;
+      par[kk] = S->live[best];
+      S->live[best] = S->live[--S->n_live];
+    }
+
+    /* Partition each parent on m cycled coordinates d_j = (cyc + j) mod n,
+     * child r takes the upper half of d_j when bit j of r is set (Sec. 3.2).
+     * A coordinate whose midpoint equals an endpoint is not split; children
+     * that would take its upper half are not formed. */
+    int64_t nch = (int64_t)1 << m;
+    int64_t cap_ch = (int64_t)kk * nch;
+    double* ch_flo = (double*)malloc((size_t)cap_ch * sizeof(double));
+    double* ch_ub = (double*)malloc((size_t)cap_ch * sizeof(double));
+    unsigned char* ch_ok = (unsigned char*)malloc((size_t)cap_ch);
+    double gub_new = S->gub;
+    for (int p = 0; p < kk; ++p) {
+      int dim[64]; double mid[64]; int split[64];
+      for (int j = 0; j < m; ++j) {
+        dim[j] = (int)(((int64_t)par[p].cyc + j) % n);
+        mid[j] = midpoint(par[p].lo[dim[j]], par[p].hi[dim[j]]);
+        split[j] = par[p].lo[dim[j]] < mid[j] && mid[j] < par[p].hi[dim[j]];
+      }
+      for (int64_t r = 0; r < nch; ++r) {
+        int64_t c = (int64_t)p * nch + r;
+        ch_ok[c] = 0;
+        int isvoid = 0;
+        for (int j = 0; j < m; ++j) if (((r >> j) & 1) && !split[j]) isvoid = 1;
+        if (isvoid) continue;
+        memcpy(clo, par[p].lo, (size_t)n * sizeof(double));
+        memcpy(chi, par[p].hi, (size_t)n * sizeof(double));
+        for (int j = 0; j < m; ++j) {
+          if (!split[j]) continue;
+          if ((r >> j) & 1) clo[dim[j]] = mid[j]; else chi[dim[j]] = mid[j];
+        }
+        box_eval e = eval_box(P, clo, chi, X, NULL);
+        S->info.boxes_evaluated++;
+        ch_flo[c] = e.F.lo;
+        ch_ub[c] = e.ub;
+        ch_ok[c] = e.mono ? 1 : 2;      /* 1: evaluated but fails the first-order test */
+        /* Sample: GUB = smallest upper bound seen (Sec. 3.1) */
+        if (e.ub < gub_new) gub_new = e.ub;
+      }
+    }
+    S->gub = gub_new;
+
+    /* Insert survivors: lower bound <= GUB and passing the first-order test */
+    int64_t nsurv = 0;
+    for (int p = 0; p < kk; ++p) {
+      int dim[64]; double mid[64]; int split[64];
+      for (int j = 0; j < m; ++j) {
+        dim[j] = (int)(((int64_t)par[p].cyc + j) % n);
+        mid[j] = midpoint(par[p].lo[dim[j]], par[p].hi[dim[j]]);
+        split[j] = par[p].lo[dim[j]] < mid[j] && mid[j] < par[p].hi[dim[j]];
+      }
+      for (int64_t r = 0; r < nch; ++r) {
+        int64_t c = (int64_t)p * nch + r;
+        if (ch_ok[c] != 2 || ch_flo[c] > S->gub) continue;
+        box b;
+        b.lo = (double*)malloc((size_t)n * sizeof(double));
+        b.hi = (double*)malloc((size_t)n * sizeof(double));
+        memcpy(b.lo, par[p].lo, (size_t)n * sizeof(double));
+        memcpy(b.hi, par[p].hi, (size_t)n * sizeof(double));
+        for (int j = 0; j < m; ++j) {
+          if (!split[j]) continue;
+          if ((r >> j) & 1) b.lo[dim[j]] = mid[j]; else b.hi[dim[j]] = mid[j];
+        }
+        b.flo = ch_flo[c];
+        b.seq = next_seq++;
+        b.cyc = (int32_t)(((int64_t)par[p].cyc + m) % n);
+        b.wmax = box_wmax(n, b.lo, b.hi);
+        if (!push_box(S, b)) { status = ST_NOMEM; goto done; }
+        nsurv++;
+      }
+    }
+    int64_t sel0 = par[0].seq;
+    for (int p = 0; p < kk; ++p) free_box(&par[p]);
+    free(ch_flo); free(ch_ub); free(ch_ok);
+    cutoff(S);
+    sweeps++;
+    if (S->n_trace < S->cap_trace) {
+      S->tr_gub[S->n_trace] = S->gub;
+      S->tr_nsurv[S->n_trace] = nsurv;
+      S->tr_nlive[S->n_trace] = S->n_live;
+      S->tr_sel[S->n_trace] = sel0;
+      S->n_trace++;
+    }
+  }
+done:
+  S->info.sweeps = sweeps;
+  S->info.status = status;
+  S->info.n_boxes = S->n_live;
+  S->info.f_hi = S->gub;
+  if (S->n_live) {
+    double glb = INFINITY;
+    for (int64_t i = 0; i < S->n_live; ++i) glb = dmin(glb, S->live[i].flo);
+    S->info.f_lo = glb;
+  }
+  qsort(S->live, (size_t)S->n_live, sizeof(box), cmp_seq);
+  free(X); free(par); free(clo); free(chi);
+  return S;
+}
+
+int orc_info_get(void* h, orc_info* out) { if (!h) return -1; *out = ((solve_state*)h)->info; return 0; }
+
+int64_t orc_boxes(void* h, double* lo, double* hi, double* flo, int64_t* seq, int64_t cap) {
+  solve_state* S = (solve_state*)h;
+  int64_t k = S->n_live < cap ? S->n_live : cap;
+  for (int64_t i = 0; i < k; ++i) {
+    if (lo) memcpy(lo + i * S->n, S->live[i].lo, (size_t)S->n * sizeof(double));
+    if (hi) memcpy(hi + i * S->n, S->live[i].hi, (size_t)S->n * sizeof(double));
+    if (flo) flo[i] = S->live[i].flo;
+    if (seq) seq[i] = S->live[i].seq;
+  }
+  return k;
+}
+
+int64_t orc_trace(void* h, double* gub, int64_t* nsurv, int64_t* nlive, int64_t* sel, int64_t cap) {
+  solve_state* S = (solve_state*)h;
+  int64_t k = S->n_trace < cap ? S->n_trace : cap;
+  for (int64_t i = 0; i < k; ++i) {
+    gub[i] = S->tr_gub[i]; nsurv[i] = S->tr_nsurv[i]; nlive[i] = S->tr_nlive[i]; sel[i] = S->tr_sel[i];
+  }
+  return k;
+}
+
+void orc_free(void* h) {
+  solve_state* S = (solve_state*)h;
+  if (!S) return;
+  for (int64_t i = 0; i < S->n_live; ++i) free_box(&S->live[i]);
+  free(S->live);
+  free(S->tr_gub); free(S->tr_nsurv); free(S->tr_nlive); free(S->tr_sel);
+  free(S);
+}
+
+/* ------------------------------------------------------------------------- */
+/* per-box and per-operation entry points used by the tests                  */
+/* ------------------------------------------------------------------------- */
+
+/* F[nb][2], ub[nb], mono[nb], G[nb][n][2] (G may be NULL) */
+int orc_eval_boxes(const orc_problem* P, int64_t nb, const double* lo, const double* hi,
+                   double* F, double* ub, unsigned char* mono, double* G) {
+  const int64_t n = P->n;
+  iv* X = (iv*)malloc((size_t)n * sizeof(iv));
+  iv* GG = (iv*)malloc((size_t)n * sizeof(iv));
+  for (int64_t b = 0; b < nb; ++b) {
+    box_eval e = eval_box(P, lo + b * n, hi + b * n, X, GG);
+    F[2 * b] = e.F.lo; F[2 * b + 1] = e.F.hi;
+    ub[b] = e.ub;
+    mono[b] = (unsigned char)e.mono;
+    if (G) for (int64_t j = 0; j < n; ++j) { G[(b * n + j) * 2] = GG[j].lo; G[(b * n + j) * 2 + 1] = GG[j].hi; }
+  }
+  free(X); free(GG);
+  return 0;
+}
+
+/* op codes shared with the test suite (values chosen here) */
+enum { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_DIV = 3, OP_SQRT = 4, OP_SQR = 5, OP_ABS = 6,
+       OP_RECIP = 7, OP_COS2PI = 8, OP_SIN2PI = 9, OP_DABS = 10 };
+
+/* a, b, out are [cnt][2] (lo, hi) arrays; b is ignored by the unary ops */
+int orc_iv_op(int op, int64_t cnt, const double* a, const double* b, double* out) {
+  for (int64_t i = 0; i < cnt; ++i) {
+    iv x = mk(a[2 * i], a[2 * i + 1]);
+    iv y = b ? mk(b[2 * i], b[2 * i + 1]) : mk(0.0, 0.0);
+    iv r;
+    switch (op) {
+    case OP_ADD: r = iv_add(x, y); break;
+    case OP_SUB: r = iv_sub(x, y); break;
+    case OP_MUL: r = iv_mul(x, y); break;
+    case OP_DIV: r = iv_div(x, y); break;
+    case OP_SQRT: r = iv_sqrt(x); break;
+    case OP_SQR: r = iv_sqr(x); break;
+    case OP_ABS: r = iv_abs(x); break;
+    case OP_RECIP: r = iv_recip(x); break;
+    case OP_COS2PI: r = iv_cos2pi(x); break;
+    case OP_SIN2PI: r = iv_sin2pi(x); break;
+    case OP_DABS: r = iv_dabs(x); break;
+    default: return -1;
+    }
+    out[2 * i] = r.lo; out[2 * i + 1] = r.hi;
+  }
+  return 0;
+}
+
+/* point enclosures: fn 0 = cos(2 pi y), 1 = sin(2 pi y); out [cnt][2] */
+int orc_point_trig(int fn, int64_t cnt, const double* y, double* out) {
+  for (int64_t i = 0; i < cnt; ++i) pt_trig2pi(fn, y[i], &out[2 * i], &out[2 * i + 1]);
+  return 0;
+}
+
+/* midpoint rule, exposed for the tests */
+double orc_midpoint(double lo, double hi) { return midpoint(lo, hi); }

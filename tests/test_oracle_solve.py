@@ -1,0 +1,122 @@
+"""Pins for the oracle's branch-and-bound iteration (Sec. 3.1-3.3 of the paper).
+
+* completeness: the known minimiser lies in a surviving box after every sweep,
+  and the final [GLB, GUB] contains the known minimum 0 at the stated width;
+* brute force: for n <= 3 a dense grid (numpy float64) plus a Lipschitz bound
+  brackets the true minimum; GLB/GUB must be consistent with the bracket and
+  the known minimiser must lie in a surviving box;
+* determinism (Sec. 4: no random variation is involved) and budget exits.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2507_01770_amd import problems as PR
+
+
+def inside_some_box(x, lo, hi, slack=0.0):
+    return bool(np.any(np.all((lo - slack <= x) & (x <= hi + slack), axis=1)))
+
+
+def test_workload0_encloses_zero():
+    p = PR.config(0)
+    r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6)
+    assert r.status == O.ST_OK
+    assert r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6
+    assert inside_some_box(p.x_star, r.lo, r.hi)
+
+
+@pytest.mark.parametrize("p", [PR.sep_cos(3, 11), PR.chain(3, 12), PR.sep_abs_sin2(3, 13),
+                               PR.sep_cos(12, 14), PR.sep_abs_sin2(12, 15)], ids=lambda p: p.name)
+def test_minimiser_never_cut(p):
+    full = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=4000)
+    assert full.status == O.ST_OK, full.status
+    assert full.f_lo <= 0.0 <= full.f_hi and full.f_hi - full.f_lo <= 1e-6
+    # the iteration is deterministic, so stopping after s sweeps shows the list at sweep s
+    for s in sorted(set(np.linspace(1, full.sweeps, 12).astype(int))):
+        r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=int(s))
+        assert r.sweeps == s
+        assert inside_some_box(p.x_star, r.lo, r.hi), s
+        assert r.f_lo <= 0.0 <= r.f_hi
+        assert np.array_equal(r.trace_gub, full.trace_gub[:s])
+
+
+def lipschitz(p):
+    """per-coordinate bound on |df/dx_i| over the domain"""
+    n, cf = p.n, p.coef
+    W = np.maximum(np.abs(p.lower), np.abs(p.upper))
+    if p.family == PR.SEP_COS:
+        a, b, k, c = cf[:n], cf[n:2 * n], cf[2 * n:3 * n], cf[3 * n:]
+        return 2 * a * (W + np.abs(c)) + 2 * np.pi * k * b
+    if p.family == PR.SEP_ABS_SIN2:
+        s, b, k, c = cf[:n], cf[n:2 * n], cf[2 * n:3 * n], cf[3 * n:]
+        return s + np.pi * k * b
+    al, be = np.append(cf[:n - 1], 0.0), np.append(cf[n - 1:], 0.0)
+    alp = np.insert(cf[:n - 1], 0, 0.0)
+    R = W + W * W
+    return 4 * al * W * R + 2 * be * (W + 1) + 2 * alp * R
+
+
+def f_grid(p, X):
+    """f on points X [..., n] in float64 (closed form)"""
+    n, cf = p.n, p.coef
+    if p.family == PR.SEP_COS:
+        a, b, k, c = cf[:n], cf[n:2 * n], cf[2 * n:3 * n], cf[3 * n:]
+        d = X - c
+        return np.sum(a * d * d + b * (1 - np.cos(2 * np.pi * k * d)), axis=-1)
+    if p.family == PR.SEP_ABS_SIN2:
+        s, b, k, c = cf[:n], cf[n:2 * n], cf[2 * n:3 * n], cf[3 * n:]
+        d = X - c
+        return np.sum(s * np.abs(d) + b * np.sin(np.pi * k * d) ** 2, axis=-1)
+    al, be = cf[:n - 1], cf[n - 1:]
+    return np.sum(al * (X[..., 1:] - X[..., :-1] ** 2) ** 2 + be * (X[..., :-1] - 1) ** 2, axis=-1)
+
+
+@pytest.mark.parametrize("fam,n", list(itertools.product([PR.SEP_COS, PR.CHAIN, PR.SEP_ABS_SIN2], [2, 3])))
+def test_brute_force_grid(fam, n):
+    p = PR.make(fam, n, 200 + 10 * fam + n)
+    pts = 1001 if n == 2 else 121
+    axes = [np.linspace(p.lower[i], p.upper[i], pts) for i in range(n)]
+    h = (p.upper - p.lower) / (pts - 1)
+    G = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, n)
+    vals = f_grid(p, G)
+    gmin = float(vals.min())
+    slack = float(np.sum(lipschitz(p) * h / 2)) + 1e-9
+    # the known minimum 0 sits in the grid bracket: checks f and the generator
+    assert gmin - slack <= 0.0 <= gmin + 1e-12
+    r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=20000)
+    assert r.status == O.ST_OK
+    assert r.f_lo <= gmin + 1e-12          # GLB below the true minimum, hence below the grid minimum
+    assert r.f_hi >= gmin - slack          # GUB above the true minimum
+    assert r.f_hi - r.f_lo <= 1e-6
+    assert inside_some_box(p.x_star, r.lo, r.hi)
+
+
+def test_deterministic_and_select_k():
+    p = PR.sep_cos(8, 31)
+    a = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6)
+    b = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6)
+    assert a.f_lo == b.f_lo and a.f_hi == b.f_hi and a.sweeps == b.sweeps
+    assert np.array_equal(a.lo, b.lo) and np.array_equal(a.seq, b.seq)
+    for k in [2, 7]:
+        r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, select_k=k)
+        assert r.status == O.ST_OK and r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6
+        assert inside_some_box(p.x_star, r.lo, r.hi)
+
+
+def test_budget_exit_is_still_rigorous():
+    p = PR.sep_cos(20, 32)
+    r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=5)
+    assert r.status == O.ST_NOT_CONVERGED and r.sweeps == 5
+    assert r.f_lo <= 0.0 <= r.f_hi
+    assert inside_some_box(p.x_star, r.lo, r.hi)
+
+
+def test_box_width_criterion():
+    p = PR.sep_cos(4, 33)
+    r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, tol_x=1e-4, max_sweeps=20000)
+    assert r.status == O.ST_OK
+    assert np.all(r.hi - r.lo < 1e-4)
+    assert inside_some_box(p.x_star, r.lo, r.hi)
