@@ -1,0 +1,161 @@
+/*
+ * ibb.h -- C ABI of libibb: rigorous interval branch-and-bound minimisation of a
+ * closed-form f over a box, on AMD MI355X (gfx950).
+ *
+ * Method: Zhang, Shan & Cagan, "Global optimization tailored for GPUs: complete
+ * and rigorous search for large-scale nonlinear minimization" (arXiv 2507.01770).
+ * The problem is Eqs. (1)-(2) (minimise f subject to l <= x <= u); the iteration
+ * is Sec. 3.1 (select the region with the smallest lower bound, sample it to
+ * update GUB, remove regions whose lower bound exceeds GUB, partition the
+ * selected region and rule out subregions by the cutoff and first-order tests,
+ * insert the rest, stop, output [GLB, GUB] and the regions); partitioning uses
+ * the variable cycling of Sec. 3.2; bounds are natural interval extensions with
+ * outward rounding (Sec. 2.1, Eqs. (3)-(6)).
+ *
+ * Conventions (every entry point):
+ *   - nothing throws across the ABI; every call returns an ibb_status and, on an
+ *     error, leaves a message for ibb_last_error() (per calling thread);
+ *   - problem arrays are host memory and are copied; the caller keeps ownership;
+ *   - "d_" pointers are device memory owned by the caller;
+ *   - work is enqueued on the given HIP stream (NULL = the null stream);
+ *     ibb_solve synchronises that stream before it returns, the kernel-level
+ *     entry points do not;
+ *   - device memory the library needs is taken from the ibb_allocator when one is
+ *     given (for example PyTorch's caching allocator), else from hipMalloc.
+ */
+#ifndef IBB_H
+#define IBB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IBB_OK = 0,
+  IBB_NOT_CONVERGED = 1, /* a budget ended the run; [f_lo, f_hi] and the boxes are still rigorous */
+  IBB_PENDING = 2,
+  IBB_E_INVALID = -1,    /* bad argument (see ibb_last_error) */
+  IBB_E_NOMEM = -2,      /* device or host allocation failed */
+  IBB_E_DEVICE = -3,     /* a HIP call failed */
+  IBB_E_CAPACITY = -4,   /* a size exceeds what the library supports */
+  IBB_E_INTERNAL = -5
+} ibb_status;
+
+/* Objective families (closed forms with per-coordinate coefficients).
+ *   IBB_SEP_COS      f = sum_i a_i (x_i - c_i)^2 + b_i (1 - cos(2 pi k_i (x_i - c_i)))
+ *                    coef = a[n], b[n], k[n], c[n]        (k_i positive integers)
+ *   IBB_CHAIN        f = sum_{i<n-1} alpha_i (x_{i+1} - x_i^2)^2 + beta_i (x_i - 1)^2
+ *                    coef = alpha[n-1], beta[n-1]         (n >= 2)
+ *   IBB_SEP_ABS_SIN2 f = sum_i s_i |x_i - c_i| + b_i sin^2(pi k_i (x_i - c_i))
+ *                    coef = s[n], b[n], k[n], c[n]        (k_i positive integers)
+ * The interval extension of each family follows a fixed expression tree and a
+ * fixed summation order (term i in slot i mod 64, slots summed left to right,
+ * then folded with strides 32..1), which makes the bounds reproducible bit for
+ * bit.  cos and sin are evaluated as cos(2 pi y), sin(2 pi y) of y = k (x - c)
+ * (or k/2 (x - c)), so the argument reduction is exact. */
+typedef enum { IBB_SEP_COS = 1, IBB_CHAIN = 2, IBB_SEP_ABS_SIN2 = 3 } ibb_family;
+
+typedef enum { IBB_FP64 = 0, IBB_FP32_BULK = 1 } ibb_precision;
+
+typedef struct {
+  int32_t family;        /* ibb_family */
+  int32_t n;             /* dimension, 1 <= n <= 1<<24 (CHAIN: n >= 2) */
+  const double* coef;    /* host, coef_len values, layout above */
+  int64_t coef_len;      /* 4n (SEP_COS, SEP_ABS_SIN2) or 2(n-1) (CHAIN) */
+  const double* lower;   /* host [n]: l, finite */
+  const double* upper;   /* host [n]: u, finite, l_i < u_i */
+  double tol_f;          /* stop once GUB - GLB (rounded up) <= tol_f; > 0 */
+  double tol_x;          /* optional: also require every box width < tol_x (0 = off) */
+} ibb_problem;
+
+typedef struct {
+  int32_t precision;     /* ibb_precision; default IBB_FP64 */
+  int32_t split_dims;    /* M: coordinates bisected per selected box, 1..16; default 10 */
+  int32_t select_k;      /* K: boxes selected per sweep; default 1 (the paper's choice) */
+  int32_t deterministic; /* results independent of scheduling; default 1 (always honoured) */
+  int64_t max_sweeps;    /* budget; default 1,000,000 */
+  int64_t max_live_boxes;/* budget on the live list; default 1<<26 */
+  double time_limit_s;   /* budget; <= 0 means none; default 0 */
+} ibb_options;
+
+typedef struct {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes, void* hip_stream);
+  void (*free)(void* ctx, void* p, size_t bytes, void* hip_stream);
+} ibb_allocator;
+
+typedef struct {
+  double f_lo, f_hi;          /* rigorous enclosure [GLB, GUB] of min f */
+  int64_t n_boxes;            /* live boxes at the end (lower bound <= GUB) */
+  int64_t sweeps;             /* iterations run */
+  int64_t boxes_evaluated;    /* children bounded, plus the root */
+  int64_t fp32_pruned;        /* children discarded by the FP32 filter */
+  int64_t fp64_confirmed;     /* children bounded in FP64 */
+  double seconds;             /* wall time of ibb_solve */
+  int32_t status;             /* IBB_OK or IBB_NOT_CONVERGED */
+} ibb_info;
+
+typedef struct ibb_result ibb_result;
+
+/* Fill *opts with the defaults listed above. */
+ibb_status ibb_options_default(ibb_options* opts);
+
+/* Run the whole iteration (Sec. 3.1) on the device.  On IBB_OK or
+ * IBB_NOT_CONVERGED, *out owns the result until ibb_result_free.  alloc may be
+ * NULL.  Validation failures (IBB_E_INVALID): family unknown, n out of range,
+ * coef_len mismatch, non-finite or |value| > 1e15 coefficients or bounds,
+ * l_i >= u_i, tol_f <= 0, k_i not a positive integer, split_dims or select_k out
+ * of range. */
+ibb_status ibb_solve(const ibb_problem* prob, const ibb_options* opts, const ibb_allocator* alloc,
+                     void* hip_stream, ibb_result** out);
+
+ibb_status ibb_result_info(const ibb_result* res, ibb_info* info);
+
+/* Copy up to `capacity` live boxes (ordered by insertion number) to host
+ * arrays lo, hi ([box][n], row-major), their lower bounds of f and insertion
+ * numbers; any output pointer may be NULL.  *written receives the count. */
+ibb_status ibb_result_boxes(const ibb_result* res, double* lo, double* hi, double* f_lo_per_box,
+                            int64_t* seq, int64_t capacity, int64_t* written);
+
+/* Per-sweep record (for comparisons with a reference implementation): GUB after
+ * the sweep, children inserted, live boxes after the cutoff, insertion number
+ * of the first selected parent.  Host arrays; *written receives the count. */
+ibb_status ibb_result_trace(const ibb_result* res, double* gub, int64_t* n_inserted, int64_t* n_live,
+                            int64_t* selected_seq, int64_t capacity, int64_t* written);
+
+void ibb_result_free(ibb_result* res);
+
+/* Bound nb boxes given in device memory (d_lo, d_hi: [nb][n] row-major):
+ * d_F[nb][2] receives the enclosure of f over each box, d_ub_mid[nb] the upper
+ * bound of f at the box midpoint (0.5 lo + 0.5 hi rounded up), d_mono_prune[nb]
+ * 1 when the first-order test of Sec. 3.1 discards the box (some DLB_j > 0 with
+ * x_j^lo != l_j, or some DUB_j < 0 with x_j^hi != u_j), and d_G (may be NULL)
+ * [nb][n][2] the enclosures of the partial derivatives.  precision must be
+ * IBB_FP64 here. */
+ibb_status ibb_eval_boxes(const ibb_problem* prob, int32_t precision, int64_t nb, const double* d_lo,
+                          const double* d_hi, double* d_F, double* d_ub_mid, uint8_t* d_mono_prune,
+                          double* d_G, void* hip_stream);
+
+/* Elementwise interval operations with outward rounding (Sec. 2.1, Eqs. (3)-(6)),
+ * for testing the arithmetic.  d_a, d_b, d_out: device [count][2] (lo, hi).
+ * op: 0 add, 1 sub, 2 mul, 3 div (= a * (1/b), Eq. (6)), 4 sqrt, 5 sqr, 6 abs,
+ * 7 reciprocal, 8 cos(2 pi a), 9 sin(2 pi a), 10 derivative of |.|.
+ * Unary ops ignore d_b (may be NULL).  A divisor that contains 0 gives
+ * [-inf, +inf]. */
+ibb_status ibb_interval_op(int32_t op, int64_t count, const double* d_a, const double* d_b, double* d_out,
+                           void* hip_stream);
+
+/* Point enclosures: d_out[count][2] receives [lo, hi] around cos(2 pi y)
+ * (fn = 0) or sin(2 pi y) (fn = 1) for each double d_y[i]. */
+ibb_status ibb_point_trig(int32_t fn, int64_t count, const double* d_y, double* d_out, void* hip_stream);
+
+const char* ibb_status_string(ibb_status s);
+const char* ibb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBB_H */

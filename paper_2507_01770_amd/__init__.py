@@ -1,1 +1,258 @@
-"""Interval branch-and-bound global minimisation on AMD MI355X (gfx950)."""
+"""Rigorous interval branch-and-bound minimisation on AMD MI355X (gfx950).
+
+Thin binding over ``libibb.so`` (C ABI in ``include/ibb.h``): it marshals
+arguments only.  Every step of the method runs in the HIP kernels of the
+library; PyTorch provides device memory (its caching allocator) and streams.
+There is no CPU fallback: when the library is missing, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import problems  # noqa: F401  (seeded inputs)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libibb.so")
+
+SEP_COS, CHAIN, SEP_ABS_SIN2 = 1, 2, 3
+FP64, FP32_BULK = 0, 1
+OK, NOT_CONVERGED = 0, 1
+OPS = dict(add=0, sub=1, mul=2, div=3, sqrt=4, sqr=5, abs=6, recip=7, cos2pi=8, sin2pi=9, dabs=10)
+
+
+class IbbError(RuntimeError):
+    pass
+
+
+class _Problem(C.Structure):
+    _fields_ = [("family", C.c_int32), ("n", C.c_int32),
+                ("coef", C.POINTER(C.c_double)), ("coef_len", C.c_int64),
+                ("lower", C.POINTER(C.c_double)), ("upper", C.POINTER(C.c_double)),
+                ("tol_f", C.c_double), ("tol_x", C.c_double)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("split_dims", C.c_int32), ("select_k", C.c_int32),
+                ("deterministic", C.c_int32), ("max_sweeps", C.c_int64), ("max_live_boxes", C.c_int64),
+                ("time_limit_s", C.c_double)]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("f_lo", C.c_double), ("f_hi", C.c_double), ("n_boxes", C.c_int64), ("sweeps", C.c_int64),
+                ("boxes_evaluated", C.c_int64), ("fp32_pruned", C.c_int64), ("fp64_confirmed", C.c_int64),
+                ("seconds", C.c_double), ("status", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libibb.so (built by ``__graft_entry__.build()``); raise when it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise IbbError(f"{LIB_PATH} is missing: build it with `python paper_2507_01770_amd/build.py`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    L.ibb_options_default.argtypes = [C.POINTER(_Options)]
+    L.ibb_solve.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), C.POINTER(_Allocator), vp, C.POINTER(vp)]
+    L.ibb_result_info.argtypes = [vp, C.POINTER(_Info)]
+    L.ibb_result_boxes.argtypes = [vp, dp, dp, dp, C.POINTER(i64), i64, C.POINTER(i64)]
+    L.ibb_result_trace.argtypes = [vp, dp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), i64, C.POINTER(i64)]
+    L.ibb_result_free.argtypes = [vp]
+    L.ibb_result_free.restype = None
+    L.ibb_eval_boxes.argtypes = [C.POINTER(_Problem), i32, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.ibb_interval_op.argtypes = [i32, i64, vp, vp, vp, vp]
+    L.ibb_point_trig.argtypes = [i32, i64, vp, vp, vp]
+    L.ibb_status_string.restype = C.c_char_p
+    L.ibb_status_string.argtypes = [C.c_int]
+    L.ibb_last_error.restype = C.c_char_p
+    for f in ["ibb_options_default", "ibb_solve", "ibb_result_info", "ibb_result_boxes", "ibb_result_trace",
+              "ibb_eval_boxes", "ibb_interval_op", "ibb_point_trig"]:
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, ok=(OK,)):
+    if rc not in ok:
+        L = lib()
+        raise IbbError(f"{L.ibb_status_string(rc).decode()}: {L.ibb_last_error().decode()}")
+    return rc
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise IbbError("no GPU visible: libibb runs on the device only")
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class _TorchAllocator:
+    """ibb_allocator backed by PyTorch's caching allocator."""
+
+    def __init__(self):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.cuda.current_device()
+
+        def _alloc(ctx, nbytes, stream):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream)
+            except Exception:  # out of memory -> NULL -> IBB_E_NOMEM
+                return None
+
+        def _free(ctx, p, nbytes, stream):
+            torch.cuda.caching_allocator_delete(p)
+
+        self._a = _ALLOC_FN(_alloc)
+        self._f = _FREE_FN(_free)
+        self.struct = _Allocator(None, self._a, self._f)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class _ProblemKeep:
+    def __init__(self, family, coef, lower, upper, tol_f, tol_x):
+        self.coef, self.lower, self.upper = _f64(coef), _f64(lower), _f64(upper)
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        self.s = _Problem(int(family), int(self.lower.shape[0]), dp(self.coef), int(self.coef.shape[0]),
+                          dp(self.lower), dp(self.upper), float(tol_f), float(tol_x))
+
+
+def _prob_args(problem=None, family=None, coef=None, lower=None, upper=None, tol_f=None, tol_x=None):
+    if problem is not None:
+        family = problem.family if family is None else family
+        coef = problem.coef if coef is None else coef
+        lower = problem.lower if lower is None else lower
+        upper = problem.upper if upper is None else upper
+        tol_f = problem.tol_f if tol_f is None else tol_f
+        tol_x = problem.tol_x if tol_x is None else tol_x
+    return _ProblemKeep(family, coef, lower, upper, 1e-6 if tol_f is None else tol_f, 0.0 if tol_x is None else tol_x)
+
+
+# ---------------------------------------------------------------------------
+# kernel-level entry points
+# ---------------------------------------------------------------------------
+
+def interval_op(op: str, a, b=None, stream=None):
+    """Elementwise interval op on device tensors a, b of shape [count, 2] (lo, hi)."""
+    torch = _torch()
+    a = a.to(device="cuda", dtype=torch.float64).contiguous()
+    bb = None if b is None else b.to(device="cuda", dtype=torch.float64).contiguous()
+    out = torch.empty_like(a)
+    _check(lib().ibb_interval_op(OPS[op], a.shape[0], C.c_void_p(a.data_ptr()),
+                                 None if bb is None else C.c_void_p(bb.data_ptr()), C.c_void_p(out.data_ptr()),
+                                 _stream_ptr(stream)))
+    return out
+
+
+def point_trig(fn: str, y, stream=None):
+    """[lo, hi] around cos(2 pi y) (fn='cos2pi') or sin(2 pi y) (fn='sin2pi') for a device tensor y."""
+    torch = _torch()
+    y = y.to(device="cuda", dtype=torch.float64).contiguous().reshape(-1)
+    out = torch.empty((y.shape[0], 2), dtype=torch.float64, device="cuda")
+    _check(lib().ibb_point_trig(0 if fn == "cos2pi" else 1, y.shape[0], C.c_void_p(y.data_ptr()),
+                                C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def eval_boxes(problem, lo, hi, want_grad=False, stream=None):
+    """Bound boxes lo, hi ([nb, n] device tensors).  Returns F [nb,2], ub [nb], mono [nb] (bool)
+    and, when want_grad, G [nb, n, 2]."""
+    torch = _torch()
+    k = _prob_args(problem)
+    lo = lo.to(device="cuda", dtype=torch.float64).contiguous()
+    hi = hi.to(device="cuda", dtype=torch.float64).contiguous()
+    nb = lo.shape[0]
+    F = torch.empty((nb, 2), dtype=torch.float64, device="cuda")
+    ub = torch.empty(nb, dtype=torch.float64, device="cuda")
+    mono = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    G = torch.empty((nb, lo.shape[1], 2), dtype=torch.float64, device="cuda") if want_grad else None
+    vp = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
+    _check(lib().ibb_eval_boxes(C.byref(k.s), FP64, nb, vp(lo), vp(hi), vp(F), vp(ub), vp(mono),
+                                None if G is None else vp(G), _stream_ptr(stream)))
+    return (F, ub, mono.bool(), G) if want_grad else (F, ub, mono.bool())
+
+
+# ---------------------------------------------------------------------------
+# whole solve
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Result:
+    f_lo: float
+    f_hi: float
+    status: int
+    sweeps: int
+    boxes_evaluated: int
+    n_boxes: int
+    seconds: float
+    lo: np.ndarray | None      # [n_boxes, n] live boxes in insertion order (None if not fetched)
+    hi: np.ndarray | None
+    flo: np.ndarray            # lower bound of f per live box
+    seq: np.ndarray            # insertion number per live box
+    trace_gub: np.ndarray
+    trace_nsurv: np.ndarray
+    trace_nlive: np.ndarray
+    trace_sel: np.ndarray
+
+
+def minimize(problem=None, *, family=None, coef=None, lower=None, upper=None, tol_f=None, tol_x=None,
+             precision=FP64, split_dims=10, select_k=1, max_sweeps=1_000_000, max_live_boxes=1 << 26,
+             time_limit_s=0.0, fetch_boxes=True, max_boxes_fetched=100_000, use_torch_allocator=True,
+             stream=None) -> Result:
+    """Enclose min f over [lower, upper]; returns [f_lo, f_hi] and the surviving boxes."""
+    k = _prob_args(problem, family, coef, lower, upper, tol_f, tol_x)
+    L = lib()
+    opts = _Options(precision, split_dims, select_k, 1, max_sweeps, max_live_boxes, time_limit_s)
+    alloc = _TorchAllocator() if use_torch_allocator else None
+    h = C.c_void_p()
+    rc = L.ibb_solve(C.byref(k.s), C.byref(opts), C.byref(alloc.struct) if alloc else None, _stream_ptr(stream),
+                     C.byref(h))
+    _check(rc, ok=(OK, NOT_CONVERGED))
+    try:
+        info = _Info()
+        _check(L.ibb_result_info(h, C.byref(info)))
+        n = k.lower.shape[0]
+        nb = info.n_boxes
+        nf = min(nb, max_boxes_fetched) if fetch_boxes else 0
+        flo = np.empty(nb)
+        seq = np.empty(nb, dtype=np.int64)
+        lo = np.empty((nf, n)) if fetch_boxes else None
+        hi = np.empty((nf, n)) if fetch_boxes else None
+        w = C.c_int64()
+        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))  # noqa: E731
+        _check(L.ibb_result_boxes(h, None, None, dp(flo), ip(seq), nb, C.byref(w)))
+        if fetch_boxes and nf:
+            _check(L.ibb_result_boxes(h, dp(lo), dp(hi), None, None, nf, C.byref(w)))
+        ts = info.sweeps
+        tg, tn, tl, tsel = np.empty(ts), np.empty(ts, np.int64), np.empty(ts, np.int64), np.empty(ts, np.int64)
+        _check(L.ibb_result_trace(h, dp(tg), ip(tn), ip(tl), ip(tsel), ts, C.byref(w)))
+        got = w.value
+        return Result(info.f_lo, info.f_hi, info.status, info.sweeps, info.boxes_evaluated, nb, info.seconds,
+                      lo, hi, flo, seq, tg[:got], tn[:got], tl[:got], tsel[:got])
+    finally:
+        L.ibb_result_free(h)

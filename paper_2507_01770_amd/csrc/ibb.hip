@@ -1,0 +1,999 @@
+// ibb.hip -- libibb: kernels, host driver and the C ABI declared in include/ibb.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "ibb.h"
+#include "kern.hpp"
+
+using namespace ibb;
+
+// ===========================================================================
+// kernels
+// ===========================================================================
+
+// per-coordinate coefficient records; [c pi k b] = [RD(c PI_LO k), RU(c PI_HI k)] * b
+__global__ void k_setup_sep(int n, int family, const double* __restrict__ coef, CoefSep* __restrict__ out) {
+  round_up_mode();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  CoefSep r;
+  r.a = coef[i];
+  r.b = coef[n + i];
+  r.k = coef[2 * n + i];
+  r.c = coef[3 * n + i];
+  // PI_LO < pi < PI_HI, adjacent doubles; the factor 2 is exact
+  const double pl = hexd(0x400921fb54442d18ull), ph = hexd(0x400921fb54442d19ull);
+  const double sc = family == FAM_SEP_COS ? 2.0 : 1.0;
+  const I pk{mul_neg(sc * pl, r.k), (sc * ph) * r.k};
+  r.pkb = mul(pk, point(r.b));
+  out[i] = r;
+}
+
+__global__ void k_setup_chain(int n, const double* __restrict__ coef, CoefChain* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  CoefChain r;
+  r.al = i < n - 1 ? coef[i] : 0.0;
+  r.be = i < n - 1 ? coef[(n - 1) + i] : 0.0;
+  out[i] = r;
+}
+
+// bound nb boxes given by their real endpoints (one wavefront per box)
+template <int FAM>
+__global__ __launch_bounds__(kWave* kBoundWaves) void k_eval_boxes(const Params* __restrict__ PP, int64_t nb,
+                                                                  const double* __restrict__ lo,
+                                                                  const double* __restrict__ hi,
+                                                                  double* __restrict__ F, double* __restrict__ ub,
+                                                                  uint8_t* __restrict__ mono,
+                                                                  double* __restrict__ G) {
+  round_up_mode();
+  const Params P = *PP;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t b = (int64_t)blockIdx.x * kBoundWaves + (threadIdx.x >> 6);
+  if (b >= nb) return;
+  const PlainRow X{lo + b * P.n, hi + b * P.n};
+  I Fb;
+  bool mo;
+  double wm;
+  bound_box<FAM>(P, X, lane, Fb, mo, wm, G ? G + b * 2 * P.n : nullptr);
+  const double u = point_ub<FAM>(P, X, lane);
+  if (lane == 0) {
+    F[2 * b] = neg(Fb.n);
+    F[2 * b + 1] = Fb.h;
+    ub[b] = u;
+    mono[b] = mo ? 1 : 0;
+  }
+}
+
+// root box: key 0, GUB from its midpoint
+template <int FAM>
+__global__ __launch_bounds__(kWave) void k_root(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  const Params P = *PP;
+  const int lane = threadIdx.x;
+  const ChildRow X{P.hist_n, P.hist_h, P.hist_mid, P.n, P.m, 0, 0u, 0u};
+  I F;
+  bool mo;
+  double wm;
+  bound_box<FAM>(P, X, lane, F, mo, wm, nullptr);
+  const double u = point_ub<FAM>(P, X, lane);
+  if (lane == 0) {
+    S->gub_key = okey(u + 0.0);
+    P.key_flo[0] = neg(F.n);
+    P.key_seq[0] = 0;
+    P.key_ref[0] = 0;
+    P.key_r[0] = -1;
+    P.key_wmax[0] = wm;
+    P.hist_cyc[0] = 0;
+    P.hist_mask[0] = 0u;
+    S->n_keys = 1;
+    S->next_seq = 1;
+    S->sweeps = 0;
+    S->evaluated = 1;
+    S->n_live = 1;
+    S->stop = RUNNING;
+    S->sel_done = 0u;
+    S->bound_done = 0u;
+  }
+}
+
+// candidate order of the selection: smaller lower bound, then smaller insertion number
+struct Cand {
+  double f;
+  int64_t s, idx;
+};
+__device__ __forceinline__ bool better(const Cand& a, const Cand& b) {  // a before b
+  return a.f < b.f || (a.f == b.f && a.s < b.s);
+}
+
+// Stop test and selection of the next box to partition.
+__global__ __launch_bounds__(kSelThreads) void k_select(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params P = *PP;
+  const int64_t nk = S->n_keys;
+  const double gub = okey_inv(S->gub_key);
+  Cand best{__builtin_inf(), INT64_MAX, -1};
+  double wm = 0.0;
+  int64_t cnt = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; i < nk; i += (int64_t)gridDim.x * kSelThreads) {
+    const double f = P.key_flo[i];
+    if (!(f <= gub)) continue;   // removed (+inf) or above GUB
+    cnt++;
+    wm = dmax(wm, P.key_wmax[i]);
+    const Cand c{f, P.key_seq[i], i};
+    if (better(c, best)) best = c;
+  }
+  // wave reduce
+  for (int h = 32; h >= 1; h >>= 1) {
+    Cand o{__shfl_xor(best.f, h, kWave), (int64_t)__shfl_xor((long long)best.s, h, kWave),
+           (int64_t)__shfl_xor((long long)best.idx, h, kWave)};
+    if (better(o, best)) best = o;
+    wm = dmax(wm, __shfl_xor(wm, h, kWave));
+    cnt += (int64_t)__shfl_xor((long long)cnt, h, kWave);
+  }
+  __shared__ Cand sc[kSelThreads / kWave];
+  __shared__ double sw[kSelThreads / kWave];
+  __shared__ int64_t sn[kSelThreads / kWave];
+  __shared__ bool last;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) { sc[w] = best; sw[w] = wm; sn[w] = cnt; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kSelThreads / kWave; ++k) {
+      if (better(sc[k], best)) best = sc[k];
+      wm = dmax(wm, sw[k]);
+      cnt += sn[k];
+    }
+    P.part_flo[blockIdx.x] = best.f;
+    P.part_seq[blockIdx.x] = best.s;
+    P.part_idx[blockIdx.x] = best.idx;
+    P.part_wmax[blockIdx.x] = wm;
+    P.part_cnt[blockIdx.x] = cnt;
+    __threadfence();
+    const uint32_t prev = atomicAdd(&S->sel_done, 1u);
+    last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // ---- the last workgroup: merge partials ----
+  __shared__ Cand fbest;
+  __shared__ int32_t go;
+  if (threadIdx.x == 0) {
+    Cand b{__builtin_inf(), INT64_MAX, -1};
+    double wmx = 0.0;
+    int64_t total = 0;
+    for (uint32_t k = 0; k < gridDim.x; ++k) {
+      const Cand c{P.part_flo[k], P.part_seq[k], P.part_idx[k]};
+      if (better(c, b)) b = c;
+      wmx = dmax(wmx, P.part_wmax[k]);
+      total += P.part_cnt[k];
+    }
+    S->sel_done = 0u;
+    const int64_t t = S->sweeps;
+    if (t > 0 && t - 1 < P.trace_cap) P.tr_nlive[t - 1] = total;
+    S->n_live = total;
+    S->glb = b.f;
+    S->wmax = wmx;
+    int32_t stop = RUNNING;
+    if (total == 0) stop = STOP_EMPTY;
+    else if (gub - b.f <= P.tol_f && (P.tol_x <= 0.0 || wmx < P.tol_x)) stop = STOP_CONVERGED;
+    else if (t >= P.max_sweeps) stop = STOP_SWEEPS;
+    else if (P.max_live > 0 && total > P.max_live) stop = STOP_LIVE;
+    if (stop) S->stop = stop;
+    go = stop == RUNNING;
+    fbest = b;
+    if (go) {
+      P.key_flo[b.idx] = __builtin_inf();     // removed from the list
+      S->sel_seq = b.s;
+    }
+  }
+  __syncthreads();
+  if (!go) return;
+  // ---- build the selected box's row ----
+  const int64_t row = S->sweeps + 1;
+  const int32_t ref = P.key_ref[fbest.idx];
+  const int32_t r = P.key_r[fbest.idx];
+  const int n = P.n;
+  const int pcyc = P.hist_cyc[ref];
+  const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
+                     n, P.m, pcyc, r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
+  double* dn = P.hist_n + row * n;
+  double* dh = P.hist_h + row * n;
+  for (int i = threadIdx.x; i < n; i += kSelThreads) {
+    const I x = src.get(i);
+    dn[i] = x.n;
+    dh[i] = x.h;
+  }
+  const int cyc = r >= 0 ? (int)(((int64_t)pcyc + P.m) % n) : pcyc;
+  __syncthreads();
+  __threadfence_block();
+  if (threadIdx.x < (unsigned)P.m) {
+    const int j = threadIdx.x;
+    const int d = (int)(((int64_t)cyc + j) % n);
+    const I x{dn[d], dh[d]};
+    const double md = midpoint(x);
+    const bool ok = neg(x.n) < md && md < x.h;
+    P.hist_mid[row * kMaxSplit + j] = md;
+    S->sel_mid[j] = md;
+    const unsigned long long bal = __ballot(ok);
+    if (j == 0) {
+      const uint32_t mask = (uint32_t)bal & ((P.m >= 32) ? 0xffffffffu : ((1u << P.m) - 1u));
+      P.hist_mask[row] = mask;
+      P.hist_cyc[row] = cyc;
+      S->sel_mask = mask;
+      S->sel_cyc = cyc;
+      S->sel_row = (int32_t)row;
+    }
+  }
+}
+
+// Bound the children of the selected box; the last workgroup inserts survivors.
+template <int FAM>
+__global__ __launch_bounds__(kWave* kBoundWaves) void k_bound(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params P = *PP;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = blockIdx.x * kBoundWaves + (threadIdx.x >> 6);
+  const int row = S->sel_row;
+  const uint32_t mask = S->sel_mask;
+  if (c < P.nch) {
+    if (((uint32_t)c & ~mask) != 0u) {
+      if (lane == 0) P.ch_flag[c] = 0;   // splits a coordinate that cannot be split
+    } else {
+      const ChildRow X{P.hist_n + (int64_t)row * P.n, P.hist_h + (int64_t)row * P.n, P.hist_mid + (int64_t)row * kMaxSplit,
+                       P.n, P.m, S->sel_cyc, mask, (uint32_t)c};
+      I F;
+      bool mo;
+      double wm;
+      bound_box<FAM>(P, X, lane, F, mo, wm, nullptr);
+      const double flo = neg(F.n);
+      const double gcur = okey_inv(__hip_atomic_load(&S->gub_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (!(flo > gcur)) {
+        // a child whose lower bound exceeds the running GUB cannot lower GUB
+        const double u = point_ub<FAM>(P, X, lane);
+        if (lane == 0) atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(u + 0.0));
+      }
+      if (lane == 0) {
+        P.ch_flo[c] = flo;
+        P.ch_flag[c] = mo ? 1 : 2;
+        P.ch_wmax[c] = wm;
+      }
+    }
+  }
+  __shared__ bool last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t prev = atomicAdd(&S->bound_done, 1u);
+    last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // ---- the last workgroup: cutoff with the final GUB, insert survivors in child order ----
+  const int T = kWave * kBoundWaves;
+  const double gub = okey_inv(__hip_atomic_load(&S->gub_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  const int per = (P.nch + T - 1) / T;
+  const int c0 = threadIdx.x * per, c1 = min(P.nch, c0 + per);
+  int mine = 0, formed = 0;
+  for (int k = c0; k < c1; ++k) {
+    const uint8_t fl = P.ch_flag[k];
+    formed += fl != 0;
+    mine += (fl == 2 && !(P.ch_flo[k] > gub));
+  }
+  __shared__ int scan[kWave * kBoundWaves];
+  __shared__ int sformed[kWave * kBoundWaves];
+  scan[threadIdx.x] = mine;
+  sformed[threadIdx.x] = formed;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {   // inclusive scan
+    const int v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
+    const int f2 = threadIdx.x >= (unsigned)off ? sformed[threadIdx.x - off] : 0;
+    __syncthreads();
+    scan[threadIdx.x] += v;
+    sformed[threadIdx.x] += f2;
+    __syncthreads();
+  }
+  const int total = scan[T - 1];
+  const int64_t base = S->n_keys;
+  const int64_t seq0 = S->next_seq;
+  int64_t o = base + (scan[threadIdx.x] - mine);
+  for (int k = c0; k < c1; ++k) {
+    if (P.ch_flag[k] == 2 && !(P.ch_flo[k] > gub)) {
+      P.key_flo[o] = P.ch_flo[k];
+      P.key_seq[o] = seq0 + (o - base);
+      P.key_ref[o] = row;
+      P.key_r[o] = k;
+      P.key_wmax[o] = P.ch_wmax[k];
+      ++o;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t t = S->sweeps;
+    if (t < P.trace_cap) {
+      P.tr_gub[t] = gub;
+      P.tr_nsurv[t] = total;
+      P.tr_sel[t] = S->sel_seq;
+    }
+    S->n_keys = base + total;
+    S->next_seq = seq0 + total;
+    S->evaluated += sformed[T - 1];
+    S->sweeps = t + 1;
+    S->bound_done = 0u;
+  }
+}
+
+// count live keys (lower bound <= GUB) and the smallest lower bound
+__global__ __launch_bounds__(kSelThreads) void k_count_live(const Params* __restrict__ PP, State* __restrict__ S,
+                                                            int64_t* __restrict__ flags) {
+  const Params P = *PP;
+  const double gub = okey_inv(S->gub_key);
+  const int64_t nk = S->n_keys;
+  for (int64_t i = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; i < nk; i += (int64_t)gridDim.x * kSelThreads)
+    flags[i] = P.key_flo[i] <= gub ? 1 : 0;
+}
+
+// stable compaction, pass 1: per-block counts
+__global__ __launch_bounds__(256) void k_compact_count(const int64_t* __restrict__ flags, int64_t nk, int64_t per_block,
+                                                       int64_t* __restrict__ block_cnt) {
+  __shared__ int64_t s[256];
+  const int64_t b0 = (int64_t)blockIdx.x * per_block, b1 = (b0 + per_block < nk) ? b0 + per_block : nk;
+  int64_t c = 0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) c += flags[i];
+  s[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (threadIdx.x < (unsigned)h) s[threadIdx.x] += s[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) block_cnt[blockIdx.x] = s[0];
+}
+
+// pass 2: scatter kept keys in order (one block per segment, sequential within a segment)
+__global__ __launch_bounds__(256) void k_compact_scatter(const Params* __restrict__ PP, const int64_t* __restrict__ flags,
+                                                         int64_t nk, int64_t per_block,
+                                                         const int64_t* __restrict__ block_cnt, int nblocks,
+                                                         double* __restrict__ o_flo, int64_t* __restrict__ o_seq,
+                                                         int32_t* __restrict__ o_ref, int32_t* __restrict__ o_r,
+                                                         double* __restrict__ o_wmax) {
+  const Params P = *PP;
+  __shared__ int64_t base;
+  __shared__ int64_t s[256];
+  if (threadIdx.x == 0) {
+    int64_t b = 0;
+    for (int k = 0; k < (int)blockIdx.x; ++k) b += block_cnt[k];
+    base = b;
+  }
+  __syncthreads();
+  const int64_t b0 = (int64_t)blockIdx.x * per_block, b1 = (b0 + per_block < nk) ? b0 + per_block : nk;
+  for (int64_t chunk = b0; chunk < b1; chunk += 256) {
+    const int64_t i = chunk + threadIdx.x;
+    const int64_t f = i < b1 ? flags[i] : 0;
+    s[threadIdx.x] = f;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int64_t v = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0;
+      __syncthreads();
+      s[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (f) {
+      const int64_t o = base + s[threadIdx.x] - 1;
+      o_flo[o] = P.key_flo[i];
+      o_seq[o] = P.key_seq[i];
+      o_ref[o] = P.key_ref[i];
+      o_r[o] = P.key_r[i];
+      o_wmax[o] = P.key_wmax[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) base += s[255];
+    __syncthreads();
+  }
+}
+
+// real endpoints of boxes given as (row, child index)
+__global__ __launch_bounds__(256) void k_rows_out(const Params* __restrict__ PP, int64_t nb, const int32_t* __restrict__ ref,
+                                                  const int32_t* __restrict__ rr, double* __restrict__ lo,
+                                                  double* __restrict__ hi) {
+  round_up_mode();
+  const Params P = *PP;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int32_t row = ref[b], r = rr[b];
+    const ChildRow X{P.hist_n + (int64_t)row * P.n, P.hist_h + (int64_t)row * P.n, P.hist_mid + (int64_t)row * kMaxSplit,
+                     P.n, P.m, P.hist_cyc[row], r >= 0 ? P.hist_mask[row] : 0u, r >= 0 ? (uint32_t)r : 0u};
+    for (int i = threadIdx.x; i < P.n; i += 256) {
+      const I x = X.get(i);
+      lo[b * P.n + i] = neg(x.n);
+      hi[b * P.n + i] = x.h;
+    }
+  }
+}
+
+// elementwise interval operations (tests)
+__global__ void k_interval_op(int op, int64_t cnt, const double* __restrict__ a, const double* __restrict__ b,
+                              double* __restrict__ out) {
+  round_up_mode();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const I x{neg(a[2 * i]), a[2 * i + 1]};
+  const I y = b ? I{neg(b[2 * i]), b[2 * i + 1]} : I{0.0, 0.0};
+  I r;
+  switch (op) {
+    case 0: r = add(x, y); break;
+    case 1: r = sub(x, y); break;
+    case 2: r = mul(x, y); break;
+    case 3: r = div(x, y); break;
+    case 4: r = isqrt(x); break;
+    case 5: r = sqr(x); break;
+    case 6: r = iabs(x); break;
+    case 7: r = recip(x); break;
+    case 8: r = sincos2pi(x, true, false).c; break;
+    case 9: r = sincos2pi(x, false, true).s; break;
+    default: r = dabs(x); break;
+  }
+  if (__builtin_isnan(r.n) || __builtin_isnan(r.h)) r = entire();
+  out[2 * i] = neg(r.n);
+  out[2 * i + 1] = r.h;
+}
+
+__global__ void k_point_trig(int fn, int64_t cnt, const double* __restrict__ y, double* __restrict__ out) {
+  round_up_mode();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const TrigEnc e = sincos2pi_point(y[i]);
+  const I r = fn == 0 ? e.c : e.s;
+  out[2 * i] = neg(r.n);
+  out[2 * i + 1] = r.h;
+}
+
+// ===========================================================================
+// host side
+// ===========================================================================
+
+namespace {
+
+thread_local std::string g_err;
+
+ibb_status fail(ibb_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess) return fail(IBB_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// device memory through the caller's allocator, or stream-ordered hipMallocAsync
+struct Mem {
+  ibb_allocator alloc{};
+  bool have_alloc = false;
+  hipStream_t stream = nullptr;
+  struct Blk {
+    void* p;
+    size_t bytes;
+  };
+  std::vector<Blk> blocks;
+
+  void* get(size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    void* p = nullptr;
+    if (have_alloc) {
+      p = alloc.alloc(alloc.ctx, bytes, stream);
+    } else if (hipMallocAsync(&p, bytes, stream) != hipSuccess) {
+      p = nullptr;
+    }
+    if (p) blocks.push_back({p, bytes});
+    return p;
+  }
+  void put(void* p) {
+    for (size_t i = 0; i < blocks.size(); ++i)
+      if (blocks[i].p == p) {
+        if (have_alloc) alloc.free(alloc.ctx, p, blocks[i].bytes, stream);
+        else (void)hipFreeAsync(p, stream);
+        blocks.erase(blocks.begin() + i);
+        return;
+      }
+  }
+  void release_all() {
+    for (auto& b : blocks) {
+      if (have_alloc) alloc.free(alloc.ctx, b.p, b.bytes, stream);
+      else (void)hipFreeAsync(b.p, stream);
+    }
+    blocks.clear();
+  }
+};
+
+bool finite_bounded(double v) { return std::isfinite(v) && std::fabs(v) <= 1e15; }
+
+ibb_status validate(const ibb_problem* p) {
+  if (!p) return fail(IBB_E_INVALID, "problem is NULL");
+  if (p->family != IBB_SEP_COS && p->family != IBB_CHAIN && p->family != IBB_SEP_ABS_SIN2)
+    return fail(IBB_E_INVALID, "unknown family " + std::to_string(p->family));
+  if (p->n < 1 || p->n > (1 << 24)) return fail(IBB_E_INVALID, "n out of range");
+  if (p->family == IBB_CHAIN && p->n < 2) return fail(IBB_E_INVALID, "CHAIN needs n >= 2");
+  const int64_t need = p->family == IBB_CHAIN ? 2 * (int64_t)(p->n - 1) : 4 * (int64_t)p->n;
+  if (p->coef_len != need) return fail(IBB_E_INVALID, "coef_len must be " + std::to_string(need));
+  if (!p->coef || !p->lower || !p->upper) return fail(IBB_E_INVALID, "NULL array");
+  for (int64_t i = 0; i < need; ++i)
+    if (!finite_bounded(p->coef[i])) return fail(IBB_E_INVALID, "coefficient " + std::to_string(i) + " not finite or too large");
+  if (p->family != IBB_CHAIN)
+    for (int i = 0; i < p->n; ++i) {
+      const double k = p->coef[2 * (int64_t)p->n + i];
+      if (!(k >= 1.0) || k != std::floor(k) || k > 1e12) return fail(IBB_E_INVALID, "k must be a positive integer");
+    }
+  for (int i = 0; i < p->n; ++i) {
+    if (!finite_bounded(p->lower[i]) || !finite_bounded(p->upper[i])) return fail(IBB_E_INVALID, "bounds must be finite");
+    if (!(p->lower[i] < p->upper[i])) return fail(IBB_E_INVALID, "need lower < upper");
+  }
+  if (!(p->tol_f > 0.0) || !std::isfinite(p->tol_f)) return fail(IBB_E_INVALID, "tol_f must be > 0");
+  if (!(p->tol_x >= 0.0)) return fail(IBB_E_INVALID, "tol_x must be >= 0");
+  return IBB_OK;
+}
+
+template <typename T>
+T* dalloc(Mem& M, int64_t count) {
+  return static_cast<T*>(M.get((size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+}
+
+// coefficient tables and bounds on the device
+ibb_status upload_problem(Mem& M, const ibb_problem* p, Params& P) {
+  const int n = p->n;
+  P.family = p->family;
+  P.n = n;
+  std::vector<double> nl(n);
+  for (int i = 0; i < n; ++i) nl[i] = -p->lower[i];
+  double* d_nl = dalloc<double>(M, n);
+  double* d_u = dalloc<double>(M, n);
+  double* d_coef = dalloc<double>(M, p->coef_len);
+  if (!d_nl || !d_u || !d_coef) return fail(IBB_E_NOMEM, "device allocation failed");
+  HIPCHK(hipMemcpyAsync(d_nl, nl.data(), n * sizeof(double), hipMemcpyHostToDevice, M.stream));
+  HIPCHK(hipMemcpyAsync(d_u, p->upper, n * sizeof(double), hipMemcpyHostToDevice, M.stream));
+  HIPCHK(hipMemcpyAsync(d_coef, p->coef, p->coef_len * sizeof(double), hipMemcpyHostToDevice, M.stream));
+  P.nl = d_nl;
+  P.u = d_u;
+  P.sep = nullptr;
+  P.chain = nullptr;
+  const int blocks = (n + 255) / 256;
+  if (p->family == IBB_CHAIN) {
+    CoefChain* c = dalloc<CoefChain>(M, n);
+    if (!c) return fail(IBB_E_NOMEM, "device allocation failed");
+    hipLaunchKernelGGL(k_setup_chain, dim3(blocks), dim3(256), 0, M.stream, n, d_coef, c);
+    P.chain = c;
+  } else {
+    CoefSep* c = dalloc<CoefSep>(M, n);
+    if (!c) return fail(IBB_E_NOMEM, "device allocation failed");
+    hipLaunchKernelGGL(k_setup_sep, dim3(blocks), dim3(256), 0, M.stream, n, p->family, d_coef, c);
+    P.sep = c;
+  }
+  HIPCHK(hipGetLastError());
+  // nl (host) must outlive its copy; d_coef is not needed after the setup kernel
+  HIPCHK(hipStreamSynchronize(M.stream));
+  M.put(d_coef);
+  return IBB_OK;
+}
+
+template <typename F>
+void dispatch_family(int family, F&& f) {
+  if (family == IBB_SEP_COS) f(std::integral_constant<int, FAM_SEP_COS>{});
+  else if (family == IBB_CHAIN) f(std::integral_constant<int, FAM_CHAIN>{});
+  else f(std::integral_constant<int, FAM_SEP_ABS_SIN2>{});
+}
+
+}  // namespace
+
+// result object -------------------------------------------------------------
+struct ibb_result {
+  ibb_info info{};
+  Mem mem;
+  Params P{};
+  Params* dP = nullptr;
+  int64_t n_boxes = 0;
+  // compacted live keys
+  double* flo = nullptr;
+  int64_t* seq = nullptr;
+  int32_t* ref = nullptr;
+  int32_t* r = nullptr;
+  double* wmax = nullptr;
+  std::vector<double> tr_gub;
+  std::vector<int64_t> tr_nsurv, tr_nlive, tr_sel;
+};
+
+namespace {
+
+// grow an array on the device, keeping the first `keep` elements
+template <typename T>
+ibb_status grow(Mem& M, T*& ptr, int64_t keep, int64_t new_count) {
+  T* np = dalloc<T>(M, new_count);
+  if (!np) return fail(IBB_E_NOMEM, "device allocation failed while growing the box list");
+  if (keep > 0) HIPCHK(hipMemcpyAsync(np, ptr, keep * sizeof(T), hipMemcpyDeviceToDevice, M.stream));
+  M.put(ptr);
+  ptr = np;
+  return IBB_OK;
+}
+
+ibb_status push_params(Mem& M, const Params& P, Params* dP) {
+  HIPCHK(hipMemcpyAsync(dP, &P, sizeof(Params), hipMemcpyHostToDevice, M.stream));
+  return IBB_OK;
+}
+
+int sel_blocks_for(int64_t keys) {
+  int64_t b = (keys + kSelThreads * 4 - 1) / (kSelThreads * 4);
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), kMaxSelBlocks);
+}
+
+// stable compaction of keys with lower bound <= GUB into fresh arrays
+ibb_status compact_keys(Mem& M, Params& P, Params* dP, State* dS, int64_t nk, int64_t cap_out, double*& o_flo,
+                        int64_t*& o_seq, int32_t*& o_ref, int32_t*& o_r, double*& o_wmax, int64_t& kept) {
+  int64_t* flags = dalloc<int64_t>(M, nk);
+  const int64_t per_block = 4096;
+  const int nblocks = (int)std::max<int64_t>(1, (nk + per_block - 1) / per_block);
+  int64_t* bcnt = dalloc<int64_t>(M, nblocks);
+  o_flo = dalloc<double>(M, cap_out);
+  o_seq = dalloc<int64_t>(M, cap_out);
+  o_ref = dalloc<int32_t>(M, cap_out);
+  o_r = dalloc<int32_t>(M, cap_out);
+  o_wmax = dalloc<double>(M, cap_out);
+  if (!flags || !bcnt || !o_flo || !o_seq || !o_ref || !o_r || !o_wmax) return fail(IBB_E_NOMEM, "device allocation failed");
+  hipLaunchKernelGGL(k_count_live, dim3(sel_blocks_for(nk)), dim3(kSelThreads), 0, M.stream, dP, dS, flags);
+  hipLaunchKernelGGL(k_compact_count, dim3(nblocks), dim3(256), 0, M.stream, flags, nk, per_block, bcnt);
+  hipLaunchKernelGGL(k_compact_scatter, dim3(nblocks), dim3(256), 0, M.stream, dP, flags, nk, per_block, bcnt, nblocks,
+                     o_flo, o_seq, o_ref, o_r, o_wmax);
+  HIPCHK(hipGetLastError());
+  std::vector<int64_t> h(nblocks);
+  HIPCHK(hipMemcpyAsync(h.data(), bcnt, nblocks * sizeof(int64_t), hipMemcpyDeviceToHost, M.stream));
+  HIPCHK(hipStreamSynchronize(M.stream));
+  kept = 0;
+  for (auto v : h) kept += v;
+  M.put(flags);
+  M.put(bcnt);
+  return IBB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ibb_status ibb_options_default(ibb_options* o) {
+  if (!o) return fail(IBB_E_INVALID, "options is NULL");
+  o->precision = IBB_FP64;
+  o->split_dims = 10;
+  o->select_k = 1;
+  o->deterministic = 1;
+  o->max_sweeps = 1000000;
+  o->max_live_boxes = (int64_t)1 << 26;
+  o->time_limit_s = 0.0;
+  return IBB_OK;
+}
+
+const char* ibb_status_string(ibb_status s) {
+  switch (s) {
+    case IBB_OK: return "ok";
+    case IBB_NOT_CONVERGED: return "not converged (budget reached; enclosure still rigorous)";
+    case IBB_PENDING: return "pending";
+    case IBB_E_INVALID: return "invalid argument";
+    case IBB_E_NOMEM: return "out of memory";
+    case IBB_E_DEVICE: return "device error";
+    case IBB_E_CAPACITY: return "capacity exceeded";
+    case IBB_E_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* ibb_last_error(void) { return g_err.c_str(); }
+
+static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in, const ibb_allocator* alloc,
+                             void* hip_stream, ibb_result** out) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!out) return fail(IBB_E_INVALID, "out is NULL");
+  *out = nullptr;
+  ibb_status st = validate(prob);
+  if (st != IBB_OK) return st;
+  ibb_options opts;
+  if (opts_in) opts = *opts_in; else ibb_options_default(&opts);
+  if (opts.split_dims < 1 || opts.split_dims > kMaxSplit) return fail(IBB_E_INVALID, "split_dims must be in 1..16");
+  if (opts.select_k != 1) return fail(IBB_E_INVALID, "this build selects one box per sweep (select_k = 1)");
+  if (opts.precision != IBB_FP64) return fail(IBB_E_INVALID, "this build bounds in FP64 (precision = IBB_FP64)");
+  if (opts.max_sweeps < 0) return fail(IBB_E_INVALID, "max_sweeps must be >= 0");
+
+  ibb_result* R = new ibb_result();
+  Mem& M = R->mem;
+  M.stream = (hipStream_t)hip_stream;
+  if (alloc && alloc->alloc && alloc->free) { M.alloc = *alloc; M.have_alloc = true; }
+  auto bail = [&](ibb_status s) { (void)hipStreamSynchronize(M.stream); M.release_all(); delete R; return s; };
+
+  Params& P = R->P;
+  const int n = prob->n;
+  st = upload_problem(M, prob, P);
+  if (st != IBB_OK) return bail(st);
+  P.m = std::min(n, opts.split_dims);
+  P.nch = 1 << P.m;
+  P.tol_f = prob->tol_f;
+  P.tol_x = prob->tol_x;
+  P.max_sweeps = opts.max_sweeps;
+  P.max_live = opts.max_live_boxes;
+  P.trace_cap = std::min<int64_t>(opts.max_sweeps + 1, (int64_t)1 << 22);
+  P.key_cap = std::max<int64_t>(4096, 16 * (int64_t)P.nch);
+  P.hist_cap = 256;
+  P.key_flo = dalloc<double>(M, P.key_cap);
+  P.key_seq = dalloc<int64_t>(M, P.key_cap);
+  P.key_ref = dalloc<int32_t>(M, P.key_cap);
+  P.key_r = dalloc<int32_t>(M, P.key_cap);
+  P.key_wmax = dalloc<double>(M, P.key_cap);
+  P.hist_n = dalloc<double>(M, P.hist_cap * n);
+  P.hist_h = dalloc<double>(M, P.hist_cap * n);
+  P.hist_cyc = dalloc<int32_t>(M, P.hist_cap);
+  P.hist_mask = dalloc<uint32_t>(M, P.hist_cap);
+  P.hist_mid = dalloc<double>(M, P.hist_cap * kMaxSplit);
+  P.ch_flo = dalloc<double>(M, P.nch);
+  P.ch_flag = dalloc<uint8_t>(M, P.nch);
+  P.ch_wmax = dalloc<double>(M, P.nch);
+  P.part_flo = dalloc<double>(M, kMaxSelBlocks);
+  P.part_seq = dalloc<int64_t>(M, kMaxSelBlocks);
+  P.part_idx = dalloc<int64_t>(M, kMaxSelBlocks);
+  P.part_wmax = dalloc<double>(M, kMaxSelBlocks);
+  P.part_cnt = dalloc<int64_t>(M, kMaxSelBlocks);
+  P.tr_gub = dalloc<double>(M, P.trace_cap);
+  P.tr_nsurv = dalloc<int64_t>(M, P.trace_cap);
+  P.tr_nlive = dalloc<int64_t>(M, P.trace_cap);
+  P.tr_sel = dalloc<int64_t>(M, P.trace_cap);
+  Params* dP = dalloc<Params>(M, 1);
+  State* dS = dalloc<State>(M, 1);
+  if (!P.key_flo || !P.key_seq || !P.key_ref || !P.key_r || !P.key_wmax || !P.hist_n || !P.hist_h || !P.hist_cyc ||
+      !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.part_flo || !P.part_seq ||
+      !P.part_idx || !P.part_wmax || !P.part_cnt || !P.tr_gub || !P.tr_nsurv || !P.tr_nlive || !P.tr_sel || !dP || !dS)
+    return bail(fail(IBB_E_NOMEM, "device allocation failed"));
+  R->dP = dP;
+  // root row: (-l, u)
+  {
+    std::vector<double> nl(n);
+    for (int i = 0; i < n; ++i) nl[i] = -prob->lower[i];
+    if (hipMemcpyAsync(P.hist_n, nl.data(), n * sizeof(double), hipMemcpyHostToDevice, M.stream) != hipSuccess ||
+        hipMemcpyAsync(P.hist_h, prob->upper, n * sizeof(double), hipMemcpyHostToDevice, M.stream) != hipSuccess)
+      return bail(fail(IBB_E_DEVICE, "copy of the root box failed"));
+    if (hipMemsetAsync(dS, 0, sizeof(State), M.stream) != hipSuccess) return bail(fail(IBB_E_DEVICE, "memset failed"));
+    if (push_params(M, P, dP) != IBB_OK) return bail(IBB_E_DEVICE);
+    // nl must stay alive until the copy is done
+    if (hipStreamSynchronize(M.stream) != hipSuccess) return bail(fail(IBB_E_DEVICE, "sync failed"));
+  }
+  dispatch_family(P.family, [&](auto fam) {
+    hipLaunchKernelGGL(k_root<decltype(fam)::value>, dim3(1), dim3(kWave), 0, M.stream, dP, dS);
+  });
+  if (hipGetLastError() != hipSuccess) return bail(fail(IBB_E_DEVICE, "root launch failed"));
+
+  // ---- sweep loop, in chunks; the host reads the device state between chunks ----
+  State hs{};
+  int64_t n_keys = 1, sweeps = 0;
+  int chunk = 4;
+  const int bound_blocks = (P.nch + kBoundWaves - 1) / kBoundWaves;
+  for (;;) {
+    // capacity for this chunk: one row and at most nch keys per sweep
+    const int64_t need_rows = sweeps + chunk + 2;
+    if (need_rows > P.hist_cap) {
+      int64_t nc = std::max<int64_t>(2 * P.hist_cap, need_rows);
+      if (grow(M, P.hist_n, (sweeps + 1) * (int64_t)n, nc * n) != IBB_OK ||
+          grow(M, P.hist_h, (sweeps + 1) * (int64_t)n, nc * n) != IBB_OK ||
+          grow(M, P.hist_cyc, sweeps + 1, nc) != IBB_OK || grow(M, P.hist_mask, sweeps + 1, nc) != IBB_OK ||
+          grow(M, P.hist_mid, (sweeps + 1) * kMaxSplit, nc * kMaxSplit) != IBB_OK)
+        return bail(IBB_E_NOMEM);
+      P.hist_cap = nc;
+      if (push_params(M, P, dP) != IBB_OK) return bail(IBB_E_DEVICE);
+    }
+    const int64_t need_keys = n_keys + (int64_t)chunk * P.nch;
+    if (need_keys > P.key_cap) {
+      int64_t nc = std::max<int64_t>(2 * P.key_cap, need_keys);
+      if (grow(M, P.key_flo, n_keys, nc) != IBB_OK || grow(M, P.key_seq, n_keys, nc) != IBB_OK ||
+          grow(M, P.key_ref, n_keys, nc) != IBB_OK || grow(M, P.key_r, n_keys, nc) != IBB_OK ||
+          grow(M, P.key_wmax, n_keys, nc) != IBB_OK)
+        return bail(IBB_E_NOMEM);
+      P.key_cap = nc;
+      if (push_params(M, P, dP) != IBB_OK) return bail(IBB_E_DEVICE);
+    }
+    const int sb = sel_blocks_for(need_keys);
+    dispatch_family(P.family, [&](auto fam) {
+      for (int s = 0; s < chunk; ++s) {
+        hipLaunchKernelGGL(k_select, dim3(sb), dim3(kSelThreads), 0, M.stream, dP, dS);
+        hipLaunchKernelGGL(k_bound<decltype(fam)::value>, dim3(bound_blocks), dim3(kWave * kBoundWaves), 0, M.stream,
+                           dP, dS);
+      }
+    });
+    if (hipGetLastError() != hipSuccess) return bail(fail(IBB_E_DEVICE, "sweep launch failed"));
+    if (hipMemcpyAsync(&hs, dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
+        hipStreamSynchronize(M.stream) != hipSuccess)
+      return bail(fail(IBB_E_DEVICE, "sweep failed"));
+    n_keys = hs.n_keys;
+    sweeps = hs.sweeps;
+    if (hs.stop) break;
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (opts.time_limit_s > 0.0 && el > opts.time_limit_s) break;
+    chunk = std::min(chunk * 2, 256);
+    // drop removed keys when they dominate the list
+    if (n_keys > 4 * (hs.n_live + P.nch) && n_keys > (int64_t)1 << 16) {
+      double* f; int64_t* sq; int32_t* rf; int32_t* rr; double* wx; int64_t kept = 0;
+      if (compact_keys(M, P, dP, dS, n_keys, P.key_cap, f, sq, rf, rr, wx, kept) != IBB_OK) return bail(IBB_E_NOMEM);
+      M.put(P.key_flo); M.put(P.key_seq); M.put(P.key_ref); M.put(P.key_r); M.put(P.key_wmax);
+      P.key_flo = f; P.key_seq = sq; P.key_ref = rf; P.key_r = rr; P.key_wmax = wx;
+      if (push_params(M, P, dP) != IBB_OK) return bail(IBB_E_DEVICE);
+      if (hipMemcpyAsync(&dS->n_keys, &kept, sizeof(int64_t), hipMemcpyHostToDevice, M.stream) != hipSuccess ||
+          hipStreamSynchronize(M.stream) != hipSuccess)
+        return bail(fail(IBB_E_DEVICE, "compaction failed"));
+      n_keys = kept;
+    }
+  }
+
+  // ---- final list: keys with lower bound <= GUB, in insertion order ----
+  int64_t kept = 0;
+  if (compact_keys(M, P, dP, dS, n_keys, std::max<int64_t>(n_keys, 1), R->flo, R->seq, R->ref, R->r, R->wmax, kept) !=
+      IBB_OK)
+    return bail(IBB_E_NOMEM);
+  R->n_boxes = kept;
+  // GLB over the final list
+  std::vector<double> hflo(kept);
+  if (kept && hipMemcpy(hflo.data(), R->flo, kept * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return bail(fail(IBB_E_DEVICE, "copy failed"));
+  double glb = INFINITY;
+  for (double v : hflo) glb = std::min(glb, v);
+  // trace
+  const int64_t tn = std::min<int64_t>(hs.sweeps, P.trace_cap);
+  R->tr_gub.resize(tn); R->tr_nsurv.resize(tn); R->tr_nlive.resize(tn); R->tr_sel.resize(tn);
+  if (tn > 0) {
+    if (hipMemcpy(R->tr_gub.data(), P.tr_gub, tn * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(R->tr_nsurv.data(), P.tr_nsurv, tn * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(R->tr_nlive.data(), P.tr_nlive, tn * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(R->tr_sel.data(), P.tr_sel, tn * 8, hipMemcpyDeviceToHost) != hipSuccess)
+      return bail(fail(IBB_E_DEVICE, "trace copy failed"));
+    R->tr_nlive[tn - 1] = kept;
+  }
+  R->info.f_lo = glb;
+  R->info.f_hi = okey_inv(hs.gub_key);
+  R->info.n_boxes = kept;
+  R->info.sweeps = hs.sweeps;
+  R->info.boxes_evaluated = hs.evaluated;
+  R->info.fp32_pruned = 0;
+  R->info.fp64_confirmed = hs.evaluated;
+  R->info.status = hs.stop == STOP_CONVERGED ? IBB_OK : (hs.stop == STOP_EMPTY ? IBB_E_INTERNAL : IBB_NOT_CONVERGED);
+  R->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  if (R->info.status == IBB_E_INTERNAL) return bail(fail(IBB_E_INTERNAL, "the live list became empty"));
+  *out = R;
+  return (ibb_status)R->info.status;
+}
+
+ibb_status ibb_solve(const ibb_problem* prob, const ibb_options* opts, const ibb_allocator* alloc, void* hip_stream,
+                     ibb_result** out) {
+  try {
+    return solve_impl(prob, opts, alloc, hip_stream, out);
+  } catch (...) {
+    return fail(IBB_E_INTERNAL, "exception in ibb_solve");
+  }
+}
+
+ibb_status ibb_result_info(const ibb_result* res, ibb_info* info) {
+  if (!res || !info) return fail(IBB_E_INVALID, "NULL argument");
+  *info = res->info;
+  return IBB_OK;
+}
+
+ibb_status ibb_result_boxes(const ibb_result* res, double* lo, double* hi, double* f_lo_per_box, int64_t* seq,
+                            int64_t capacity, int64_t* written) {
+  if (!res || capacity < 0) return fail(IBB_E_INVALID, "bad argument");
+  ibb_result* R = const_cast<ibb_result*>(res);
+  const int64_t k = std::min(capacity, R->n_boxes);
+  if (written) *written = k;
+  if (k == 0) return IBB_OK;
+  Mem& M = R->mem;
+  const int n = R->P.n;
+  if (f_lo_per_box) HIPCHK(hipMemcpy(f_lo_per_box, R->flo, k * sizeof(double), hipMemcpyDeviceToHost));
+  if (seq) HIPCHK(hipMemcpy(seq, R->seq, k * sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (lo || hi) {
+    double* dlo = dalloc<double>(M, k * n);
+    double* dhi = dalloc<double>(M, k * n);
+    if (!dlo || !dhi) return fail(IBB_E_NOMEM, "device allocation failed");
+    hipLaunchKernelGGL(k_rows_out, dim3((unsigned)std::min<int64_t>(k, 65535)), dim3(256), 0, M.stream, R->dP, k, R->ref,
+                       R->r, dlo, dhi);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(M.stream));
+    if (lo) HIPCHK(hipMemcpy(lo, dlo, k * n * sizeof(double), hipMemcpyDeviceToHost));
+    if (hi) HIPCHK(hipMemcpy(hi, dhi, k * n * sizeof(double), hipMemcpyDeviceToHost));
+    M.put(dlo);
+    M.put(dhi);
+    HIPCHK(hipStreamSynchronize(M.stream));
+  }
+  return IBB_OK;
+}
+
+ibb_status ibb_result_trace(const ibb_result* res, double* gub, int64_t* n_inserted, int64_t* n_live,
+                            int64_t* selected_seq, int64_t capacity, int64_t* written) {
+  if (!res || capacity < 0) return fail(IBB_E_INVALID, "bad argument");
+  const int64_t k = std::min<int64_t>(capacity, (int64_t)res->tr_gub.size());
+  for (int64_t i = 0; i < k; ++i) {
+    if (gub) gub[i] = res->tr_gub[i];
+    if (n_inserted) n_inserted[i] = res->tr_nsurv[i];
+    if (n_live) n_live[i] = res->tr_nlive[i];
+    if (selected_seq) selected_seq[i] = res->tr_sel[i];
+  }
+  if (written) *written = k;
+  return IBB_OK;
+}
+
+void ibb_result_free(ibb_result* res) {
+  if (!res) return;
+  (void)hipStreamSynchronize(res->mem.stream);
+  res->mem.release_all();
+  (void)hipStreamSynchronize(res->mem.stream);
+  delete res;
+}
+
+ibb_status ibb_eval_boxes(const ibb_problem* prob, int32_t precision, int64_t nb, const double* d_lo, const double* d_hi,
+                          double* d_F, double* d_ub_mid, uint8_t* d_mono_prune, double* d_G, void* hip_stream) {
+  ibb_status st = validate(prob);
+  if (st != IBB_OK) return st;
+  if (precision != IBB_FP64) return fail(IBB_E_INVALID, "ibb_eval_boxes bounds in FP64 only");
+  if (nb < 0) return fail(IBB_E_INVALID, "nb < 0");
+  if (nb == 0) return IBB_OK;
+  if (!d_lo || !d_hi || !d_F || !d_ub_mid || !d_mono_prune) return fail(IBB_E_INVALID, "NULL device array");
+  Mem M;
+  M.stream = (hipStream_t)hip_stream;
+  Params P{};
+  st = upload_problem(M, prob, P);
+  if (st != IBB_OK) { M.release_all(); return st; }
+  Params* dP = dalloc<Params>(M, 1);
+  if (!dP) { M.release_all(); return fail(IBB_E_NOMEM, "device allocation failed"); }
+  if (hipMemcpyAsync(dP, &P, sizeof(Params), hipMemcpyHostToDevice, M.stream) != hipSuccess) {
+    M.release_all();
+    return fail(IBB_E_DEVICE, "copy failed");
+  }
+  const int64_t blocks = (nb + kBoundWaves - 1) / kBoundWaves;
+  if (blocks > 0x7fffffff) { M.release_all(); return fail(IBB_E_CAPACITY, "too many boxes"); }
+  dispatch_family(P.family, [&](auto fam) {
+    hipLaunchKernelGGL(k_eval_boxes<decltype(fam)::value>, dim3((unsigned)blocks), dim3(kWave * kBoundWaves), 0,
+                       M.stream, dP, nb, d_lo, d_hi, d_F, d_ub_mid, d_mono_prune, d_G);
+  });
+  hipError_t e = hipGetLastError();
+  // the host copy of P is gone after return; the device copy was enqueued before the kernel
+  (void)hipStreamSynchronize(M.stream);
+  M.release_all();
+  if (e != hipSuccess) return fail(IBB_E_DEVICE, std::string("eval launch: ") + hipGetErrorString(e));
+  return IBB_OK;
+}
+
+ibb_status ibb_interval_op(int32_t op, int64_t count, const double* d_a, const double* d_b, double* d_out,
+                           void* hip_stream) {
+  if (op < 0 || op > 10) return fail(IBB_E_INVALID, "unknown op");
+  if (count < 0) return fail(IBB_E_INVALID, "count < 0");
+  if (count == 0) return IBB_OK;
+  const bool binary = op <= 3;
+  if (!d_a || !d_out || (binary && !d_b)) return fail(IBB_E_INVALID, "NULL device array");
+  const int64_t blocks = (count + 255) / 256;
+  if (blocks > 0x7fffffff) return fail(IBB_E_CAPACITY, "count too large");
+  hipLaunchKernelGGL(k_interval_op, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream, op, count, d_a,
+                     binary ? d_b : nullptr, d_out);
+  HIPCHK(hipGetLastError());
+  return IBB_OK;
+}
+
+ibb_status ibb_point_trig(int32_t fn, int64_t count, const double* d_y, double* d_out, void* hip_stream) {
+  if (fn != 0 && fn != 1) return fail(IBB_E_INVALID, "fn must be 0 (cos) or 1 (sin)");
+  if (count < 0) return fail(IBB_E_INVALID, "count < 0");
+  if (count == 0) return IBB_OK;
+  if (!d_y || !d_out) return fail(IBB_E_INVALID, "NULL device array");
+  const int64_t blocks = (count + 255) / 256;
+  if (blocks > 0x7fffffff) return fail(IBB_E_CAPACITY, "count too large");
+  hipLaunchKernelGGL(k_point_trig, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream, fn, count, d_y, d_out);
+  HIPCHK(hipGetLastError());
+  return IBB_OK;
+}
+
+}  // extern "C"

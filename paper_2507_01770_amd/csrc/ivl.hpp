@@ -1,0 +1,356 @@
+// ivl.hpp -- outward-rounded interval arithmetic for gfx950 wavefronts.
+//
+// Every kernel that includes this header switches its wave to round-toward-+inf
+// (MODE.FP_ROUND = +inf for both f32 and f64) as its first statement, and
+// represents an interval [lo, hi] as the pair (n, h) = (-lo, hi).  Then every
+// endpoint is a single hardware operation rounded up:
+//   lower endpoint of a sum   RD(a + b)  = -RU((-a) + (-b))  ->  n = n_a + n_b
+//   upper endpoint            RU(a + b)                      ->  h = h_a + h_b
+// and a product whose lower endpoint needs RD(x*y) uses RU(-(x*y)), issued as
+// one multiply with a negated source operand.  This is the outward rounding of
+// Sec. 2.1 (lower endpoint rounded down, upper rounded up), with Eqs. (3)-(6)
+// written for the negated lower endpoint.
+//
+// The compiler assumes round-to-nearest and may legally move a negation across
+// a multiply (-(x*y) == (-x)*y under round-to-nearest, not under round-up).  So
+// no code here negates the result or an operand of a multiply, divide or fma in
+// plain C++: such negations go through the opaque helpers below (one VALU
+// instruction each, or a source modifier), and constants are hex literals.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ibb {
+
+// -------------------------------------------------------------------------
+// rounding mode and opaque helpers
+// -------------------------------------------------------------------------
+
+// MODE[3:0] = FP_ROUND: bits 1:0 f32, bits 3:2 f64/f16; 1 = toward +inf.
+__device__ __forceinline__ void round_up_mode() {
+  asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 0, 4), 5\n\ts_nop 3" ::: "memory");
+}
+
+// RU(-(a*b))
+__device__ __forceinline__ double mul_neg(double a, double b) {
+  double r;
+  asm("v_mul_f64 %0, -%1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+// -a, exact, invisible to the optimiser
+__device__ __forceinline__ double neg(double a) {
+  double r;
+  asm("v_mul_f64 %0, %1, -1.0" : "=v"(r) : "v"(a));
+  return r;
+}
+// RU(a*b - c); exact when the result is representable (residuals of products)
+__device__ __forceinline__ double fms(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, -%3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+// RU(c - a*b)
+__device__ __forceinline__ double fnma(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, -%1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+__device__ __forceinline__ double hexd(uint64_t u) { return __builtin_bit_cast(double, u); }
+__device__ __forceinline__ double dmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ double dmin(double a, double b) { return __builtin_fmin(a, b); }
+
+// next double up / down (finite arguments)
+__device__ __forceinline__ double next_up(double x) {
+  uint64_t u = __builtin_bit_cast(uint64_t, x);
+  if (x == 0.0) return hexd(1ull);
+  u = (int64_t)u >= 0 ? u + 1 : u - 1;
+  return __builtin_bit_cast(double, u);
+}
+__device__ __forceinline__ double next_down(double x) {
+  uint64_t u = __builtin_bit_cast(uint64_t, x);
+  if (x == 0.0) return hexd(0x8000000000000001ull);
+  u = (int64_t)u >= 0 ? u - 1 : u + 1;
+  return __builtin_bit_cast(double, u);
+}
+
+// -------------------------------------------------------------------------
+// intervals: I{n, h} is [-n, h]
+// -------------------------------------------------------------------------
+struct I {
+  double n, h;
+};
+
+__device__ __forceinline__ I point(double x) { return I{neg(x), x}; }
+__device__ __forceinline__ double lo_of(I a) { return neg(a.n); }
+
+// Eq. (3)
+__device__ __forceinline__ I add(I a, I b) { return I{a.n + b.n, a.h + b.h}; }
+// Eq. (4): [a.lo - b.hi, a.hi - b.lo]
+__device__ __forceinline__ I sub(I a, I b) { return I{a.n + b.h, a.h + b.n}; }
+// a - c for a scalar c
+__device__ __forceinline__ I sub_s(I a, double c) { return I{a.n + c, a.h - c}; }
+// c - a for a scalar c
+__device__ __forceinline__ I s_sub(double c, I a) { return I{a.h - c, c + a.n}; }
+
+// s * a for a scalar s (Eq. (5) with a degenerate first factor)
+__device__ __forceinline__ I scale(double s, I a) {
+  double as = __builtin_fabs(s);
+  double p = as * a.n, q = as * a.h;
+  return s >= 0.0 ? I{p, q} : I{q, p};
+}
+
+// Eq. (5): lower = min of the four products rounded down, upper = max rounded up
+__device__ __forceinline__ I mul(I a, I b) {
+  // products of (lo_a, hi_a) x (lo_b, hi_b) with lo = -n:
+  //   lo_a lo_b = n_a n_b,  lo_a hi_b = -(n_a h_b),  hi_a lo_b = -(h_a n_b),  hi_a hi_b
+  double hi = dmax(dmax(a.n * b.n, a.h * b.h), dmax(mul_neg(a.n, b.h), mul_neg(a.h, b.n)));
+  double nl = dmax(dmax(a.n * b.h, a.h * b.n), dmax(mul_neg(a.n, b.n), mul_neg(a.h, b.h)));
+  return I{nl, hi};
+}
+
+// x^2 as one operation
+__device__ __forceinline__ I sqr(I a) {
+  const bool nonneg = a.n <= 0.0;   // lo >= 0
+  const bool nonpos = a.h <= 0.0;   // hi <= 0
+  double p = nonneg ? a.n : a.h;    // endpoint nearest zero (up to sign)
+  double q = nonneg ? a.h : (nonpos ? a.n : dmax(a.n, a.h));
+  double nl = (nonneg || nonpos) ? mul_neg(p, p) : 0.0;
+  return I{nl, q * q};
+}
+
+__device__ __forceinline__ I iabs(I a) {
+  if (a.n <= 0.0) return a;                 // lo >= 0
+  if (a.h <= 0.0) return I{a.h, a.n};       // [-hi, -lo]
+  return I{0.0, dmax(a.n, a.h)};
+}
+
+// enclosure of the generalized derivative of |x|
+__device__ __forceinline__ I dabs(I a) {
+  if (a.n < 0.0) return I{-1.0, 1.0};       // lo > 0: {1}
+  if (a.h < 0.0) return I{1.0, -1.0};       // hi < 0: {-1}
+  return I{1.0, 1.0};                       // [-1, 1]
+}
+
+// --- division and square root (directed results by residual correction) ---
+
+// smallest double >= x / y  (y != 0, finite operands, no underflow)
+__device__ inline double div_ru(double x, double y) {
+  double q = x / y;
+  // residual r = x - q y (exact for q within an ulp); q < x/y  <=>  r / y > 0
+  for (int it = 0; it < 4; ++it) {
+    double r = fnma(q, y, x);
+    bool below = (y > 0.0) ? (r > 0.0) : (r < 0.0);
+    if (!below) break;
+    q = next_up(q);
+  }
+  for (int it = 0; it < 4; ++it) {
+    double p = next_down(q);
+    double r = fnma(p, y, x);
+    bool p_ok = (y > 0.0) ? (r <= 0.0) : (r >= 0.0);   // p >= x / y
+    if (!p_ok) break;
+    q = p;
+  }
+  return q;
+}
+// largest double <= x / y
+__device__ inline double div_rd(double x, double y) {
+  double q = x / y;
+  for (int it = 0; it < 4; ++it) {
+    double r = fnma(q, y, x);
+    bool above = (y > 0.0) ? (r < 0.0) : (r > 0.0);
+    if (!above) break;
+    q = next_down(q);
+  }
+  for (int it = 0; it < 4; ++it) {
+    double p = next_up(q);
+    double r = fnma(p, y, x);
+    bool p_ok = (y > 0.0) ? (r >= 0.0) : (r <= 0.0);   // p <= x / y
+    if (!p_ok) break;
+    q = p;
+  }
+  return q;
+}
+__device__ inline double sqrt_ru(double x) {
+  if (x <= 0.0) return 0.0;
+  double s = __builtin_sqrt(x);
+  for (int it = 0; it < 4; ++it) { if (!(fnma(s, s, x) > 0.0)) break; s = next_up(s); }
+  for (int it = 0; it < 4; ++it) { double p = next_down(s); if (!(p >= 0.0 && fnma(p, p, x) <= 0.0)) break; s = p; }
+  return s;
+}
+__device__ inline double sqrt_rd(double x) {
+  if (x <= 0.0) return 0.0;
+  double s = __builtin_sqrt(x);
+  for (int it = 0; it < 4; ++it) { if (!(fnma(s, s, x) < 0.0)) break; s = next_down(s); }
+  for (int it = 0; it < 4; ++it) { double p = next_up(s); if (!(fnma(p, p, x) >= 0.0)) break; s = p; }
+  return s;
+}
+
+__device__ __forceinline__ I entire() { return I{__builtin_inf(), __builtin_inf()}; }
+
+__device__ inline I recip(I b) {
+  if (!(b.n < 0.0 || b.h < 0.0)) return entire();     // 0 in b
+  double lo = div_rd(1.0, b.h), hi = div_ru(1.0, lo_of(b));
+  return I{neg(lo), hi};
+}
+// Eq. (6)
+__device__ inline I div(I a, I b) {
+  I r = recip(b);
+  if (r.n == __builtin_inf()) return r;
+  return mul(a, r);
+}
+__device__ inline I isqrt(I a) {
+  if (a.h < 0.0) return entire();
+  double lo = a.n < 0.0 ? sqrt_rd(lo_of(a)) : 0.0;
+  return I{neg(lo), sqrt_ru(a.h)};
+}
+
+// -------------------------------------------------------------------------
+// cos(2 pi y), sin(2 pi y)
+//
+// Reduction (exact): f = y - rint(y), a = |f|, and one reduced argument g with
+// |g| <= 1/8 serves both functions:
+//   a <= 1/8:        cos = C(a),          sin = sgn(f) S(a)
+//   1/8 < a <= 3/8:  cos = S(1/4 - a),    sin = sgn(f) C(1/4 - a)
+//   a > 3/8:         cos = -C(1/2 - a),   sin = sgn(f) S(1/2 - a)
+// with S(g) = sin(2 pi g), C(g) = cos(2 pi g).
+//
+// S(g) = A0 g + A1 g^3 + g^5 P(g^2), A_k = (-1)^k (2pi)^(2k+1) / (2k+1)!
+// C(g) = 1 + B1 g^2 + g^4 Q(g^2),    B_k = (-1)^k (2pi)^(2k) / (2k)!
+// The first two terms of each are carried as an unevaluated sum w + t (A0,
+// A1 and B1 split into two doubles, products split exactly with fma, the
+// rounding error of the leading addition recovered exactly by Sterbenz), the
+// tail in plain round-up arithmetic.  The result w + t is within about
+// 0.02 * 2^-52 |w| (S) or 0.07 * 2^-52 (C) of the true value, the Taylor
+// truncation (degree 17 / 18) below 2^-62.  The enclosure adds a margin E
+// (2^-55 |w| for S, 2^-54 for C) on each side and rounds outward, so it holds
+// the true value, holds any enclosure of the form [v - 2^-58 |v|, v + 2^-58 |v|]
+// with v within 2^-62 relative of the truth, and is at most two doubles wider
+// than that on each side.
+// -------------------------------------------------------------------------
+
+struct TrigEnc {
+  I c, s;   // enclosures of cos(2 pi y) and sin(2 pi y)
+};
+
+__device__ __forceinline__ TrigEnc sincos2pi_point(double y) {
+  const double f = y - __builtin_rint(y);          // exact
+  const double a = __builtin_fabs(f);
+  const bool oct0 = a <= 0.125, oct1 = a <= 0.375;
+  const double g = oct0 ? a : (oct1 ? 0.25 - a : 0.5 - a);   // exact, |g| <= 1/8
+  // exact square: z + zl = g^2
+  const double z = g * g;
+  const double zl = fms(g, g, z);
+
+  // ---- S(g) ----
+  const double A0h = hexd(0x401921fb54442d18ull), A0l = hexd(0x3cb1a62633145c07ull);
+  const double A1h = hexd(0xc054abbce625be53ull), A1l = hexd(0x3ce05511c68476a8ull);
+  // p + pe = A0h g exactly
+  const double p = A0h * g;
+  const double pe = fms(A0h, g, p);
+  // g^3 = r1 + r1e + g zl (r1 + r1e = g z exactly)
+  const double r1 = g * z;
+  const double r1e = fms(g, z, r1);
+  // A1 g^3 ~= q + qe + (A1h (r1e + g zl) + A1l r1)
+  const double q = A1h * r1;
+  const double qe = fms(A1h, r1, q);
+  // leading sum p + q, |q| <= 0.103 |p|, opposite signs: error recovered exactly
+  const double ws = p + q;
+  const double ds = q - (ws - p);
+  // tail A2 g^5 + ... + A8 g^17 = g z^2 (A2 + z (A3 + ...))
+  double ts = hexd(0x3fbaaec32af93359ull);                  // A8
+  ts = __builtin_fma(z, ts, hexd(0xbfe6fadb9f155744ull));   // A7
+  ts = __builtin_fma(z, ts, hexd(0x400e8f434d018d63ull));   // A6
+  ts = __builtin_fma(z, ts, hexd(0xc02e3074fde8871full));   // A5
+  ts = __builtin_fma(z, ts, hexd(0x40450783487ee782ull));   // A4
+  ts = __builtin_fma(z, ts, hexd(0xc0532d2cce62bd86ull));   // A3
+  ts = __builtin_fma(z, ts, hexd(0x405466bc6775aae2ull));   // A2
+  const double g5 = r1 * z;
+  double lo_s = ds + pe;
+  lo_s = lo_s + qe;
+  lo_s = __builtin_fma(A0l, g, lo_s);
+  lo_s = __builtin_fma(A1h, __builtin_fma(g, zl, r1e), lo_s);
+  lo_s = __builtin_fma(A1l, r1, lo_s);
+  lo_s = __builtin_fma(g5, ts, lo_s);
+  const double Es = __builtin_fabs(ws) * hexd(0x3c80000000000000ull);   // 2^-55 |w|
+  // enclosure: [w + t - E, w + t + E] rounded outward
+  I S{(Es - lo_s) - ws, ws + (lo_s + Es)};
+
+  // ---- C(g) ----
+  const double B1h = hexd(0xc033bd3cc9be45deull), B1l = hexd(0xbcd692b71366cc04ull);
+  // B1 g^2 ~= u + ue + (B1h zl + B1l z)
+  const double u = B1h * z;
+  const double ue = fms(B1h, z, u);
+  const double wc = 1.0 + u;                // in [0.69, 1]
+  const double dc = u - (wc - 1.0);         // exact
+  double tc = hexd(0xbfa2a0c591af8314ull);                   // B9
+  tc = __builtin_fma(z, tc, hexd(0x3fd20c62c2f2d7f5ull));    // B8
+  tc = __builtin_fma(z, tc, hexd(0xbffb6e24f44b128full));    // B7
+  tc = __builtin_fma(z, tc, hexd(0x401f9d38a3763cc3ull));    // B6
+  tc = __builtin_fma(z, tc, hexd(0xc03a6d1f2a204a8cull));    // B5
+  tc = __builtin_fma(z, tc, hexd(0x404e1f506891babbull));    // B4
+  tc = __builtin_fma(z, tc, hexd(0xc0555d3c7e3cbffaull));    // B3
+  tc = __builtin_fma(z, tc, hexd(0x40503c1f081b5ac4ull));    // B2
+  const double z2 = z * z;
+  double lo_c = dc + ue;
+  lo_c = __builtin_fma(B1h, zl, lo_c);
+  lo_c = __builtin_fma(B1l, z, lo_c);
+  lo_c = __builtin_fma(z2, tc, lo_c);
+  const double Ec = (g == 0.0) ? 0.0 : hexd(0x3c90000000000000ull);   // 2^-54
+  I C{(Ec - lo_c) - wc, wc + (lo_c + Ec)};
+
+  // ---- assemble by octant and sign ----
+  TrigEnc r;
+  // cos: C, S, or -C
+  r.c = oct0 ? C : (oct1 ? S : I{C.h, C.n});
+  // sin: sgn(f) * (S, C, S)
+  I sv = (oct0 || !oct1) ? S : C;
+  r.s = (f < 0.0) ? I{sv.h, sv.n} : sv;
+  // clamp to [-1, 1]
+  r.c.n = dmin(r.c.n, 1.0); r.c.h = dmin(r.c.h, 1.0);
+  r.s.n = dmin(r.s.n, 1.0); r.s.h = dmin(r.s.h, 1.0);
+  return r;
+}
+
+// does [-n, h] hold an integer?  ceil(lo) <= floor(hi)  <=>  floor(n) + floor(h) >= 0
+__device__ __forceinline__ bool has_int(double n, double h) {
+  return __builtin_floor(n) + __builtin_floor(h) >= 0.0;
+}
+
+// interval cos(2 pi Y) and sin(2 pi Y) together (they share the reduction)
+struct TrigIv {
+  I c, s;
+};
+__device__ __forceinline__ TrigIv sincos2pi(I y, bool want_cos, bool want_sin) {
+  TrigIv r;
+  const I whole{1.0, 1.0};
+  if (!(y.n + y.h < 1.0)) {                 // width (rounded up) >= 1 period, or NaN
+    r.c = whole; r.s = whole;
+    return r;
+  }
+  TrigEnc ea = sincos2pi_point(lo_of(y));
+  TrigEnc eb = sincos2pi_point(y.h);
+  r.c = I{dmax(ea.c.n, eb.c.n), dmax(ea.c.h, eb.c.h)};
+  r.s = I{dmax(ea.s.n, eb.s.n), dmax(ea.s.h, eb.s.h)};
+  if (want_cos) {
+    if (has_int(y.n, y.h)) r.c.h = 1.0;                       // max at y in Z
+    if (has_int(y.n + 0.5, y.h - 0.5)) r.c.n = 1.0;           // min at y in Z + 1/2
+  }
+  if (want_sin) {
+    if (has_int(y.n + 0.25, y.h - 0.25)) r.s.h = 1.0;         // max at y in Z + 1/4
+    if (has_int(y.n - 0.25, y.h + 0.25)) r.s.n = 1.0;         // min at y in Z - 1/4
+  }
+  return r;
+}
+
+// ordered 64-bit key of a double: key(x) < key(y) <=> x < y (for x, y not NaN, -0 < +0)
+__host__ __device__ __forceinline__ uint64_t okey(double x) {
+  uint64_t u = __builtin_bit_cast(uint64_t, x);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__host__ __device__ __forceinline__ double okey_inv(uint64_t k) {
+  uint64_t u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return __builtin_bit_cast(double, u);
+}
+
+}  // namespace ibb

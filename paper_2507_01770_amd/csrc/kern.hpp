@@ -1,0 +1,199 @@
+// kern.hpp -- device state and kernels of the branch-and-bound sweep.
+//
+// One sweep (Sec. 3.1, one iteration; Sec. 3.2, partition with variable cycling):
+//   k_select       stop test on [GLB, GUB]; pick the live box with the smallest
+//                  (lower bound, insertion number); rebuild its row from its
+//                  parent row and child index; fix its m split coordinates.
+//   k_bound<FAM>   one wavefront per child: F over the child, the first-order
+//                  test, then (unless F.lo already exceeds the running GUB) the
+//                  upper bound of f at the child midpoint -> atomicMin on GUB.
+//                  The last workgroup to finish applies the cutoff with the
+//                  final GUB and appends the survivors in child order.
+// Live boxes are kept compactly, as the paper's memory-limited list does
+// (Sec. 3.2: an index, the iteration it came from, the cycling index and the
+// lower bound): a key holds the lower bound, an insertion number, the row of
+// the selected parent it was cut from and its child index.  The rows of the
+// selected parents (one per sweep, 16 n bytes) stay in HBM.
+#pragma once
+#include "fam.hpp"
+
+namespace ibb {
+
+constexpr int kWave = 64;
+constexpr int kBoundWaves = 4;            // waves per workgroup in the bound kernels
+constexpr int kMaxSplit = 16;             // M <= 16
+constexpr int kSelThreads = 256;
+constexpr int kMaxSelBlocks = 1024;
+
+enum StopCode { RUNNING = 0, STOP_CONVERGED = 1, STOP_SWEEPS = 2, STOP_LIVE = 3, STOP_EMPTY = 4 };
+
+struct Params {
+  int32_t family, n, m, nch;              // nch = 2^m children per selected box
+  double tol_f, tol_x;
+  int64_t max_sweeps, max_live;
+  const CoefSep* sep;                     // [n] (separable families)
+  const CoefChain* chain;                 // [n] (CHAIN; entry n-1 is zero)
+  const double* nl;                       // [n] -l
+  const double* u;                        // [n]  u
+  // live-box keys
+  double* key_flo;
+  int64_t* key_seq;
+  int32_t* key_ref;                       // row of the parent the box was cut from
+  int32_t* key_r;                         // child index, or -1: the box is that row itself
+  double* key_wmax;                       // widest side of the box (rounded up)
+  int64_t key_cap;
+  // rows of selected boxes, stored as (-lo, hi)
+  double* hist_n;
+  double* hist_h;
+  int32_t* hist_cyc;                      // cycling index of the row
+  uint32_t* hist_mask;                    // bit j: coordinate (cyc + j) mod n is split
+  double* hist_mid;                       // [row][kMaxSplit] split points
+  int64_t hist_cap;
+  // per-sweep children
+  double* ch_flo;
+  uint8_t* ch_flag;                       // 0 not formed, 1 fails the first-order test, 2 candidate
+  double* ch_wmax;
+  // select partials
+  double* part_flo;
+  int64_t* part_seq;
+  int64_t* part_idx;
+  double* part_wmax;
+  int64_t* part_cnt;
+  // trace
+  double* tr_gub;
+  int64_t* tr_nsurv;
+  int64_t* tr_nlive;
+  int64_t* tr_sel;
+  int64_t trace_cap;
+};
+
+struct State {
+  uint64_t gub_key;                       // ordered key of GUB
+  int64_t n_keys, next_seq, sweeps, evaluated, n_live;
+  double glb, wmax;
+  int32_t stop;
+  uint32_t sel_done, bound_done;
+  int32_t sel_row, sel_cyc;
+  uint32_t sel_mask;
+  int64_t sel_seq;
+  double sel_mid[kMaxSplit];
+};
+
+// bisection point: 0.5 lo + 0.5 hi rounded up, kept inside [lo, hi]
+__device__ __forceinline__ double midpoint(I x) {
+  double m = mul_neg(0.5, x.n) + 0.5 * x.h;
+  m = dmax(m, neg(x.n));
+  return dmin(m, x.h);
+}
+
+// read access to the rows of boxes -------------------------------------------
+
+// a box given as real endpoints lo[i], hi[i]
+struct PlainRow {
+  const double* lo;
+  const double* hi;
+  __device__ __forceinline__ I get(int i) const { return I{neg(lo[i]), hi[i]}; }
+};
+
+// child r of a stored row: coordinate (cyc + j) mod n takes the upper half
+// [mid_j, hi] when bit j of r is set and the lower half [lo, mid_j] otherwise
+struct ChildRow {
+  const double* pn;
+  const double* ph;
+  const double* mid;
+  int n, m, cyc;
+  uint32_t mask, r;
+  __device__ __forceinline__ I get(int i) const {
+    I x{pn[i], ph[i]};
+    int j = i - cyc;
+    if (j < 0) j += n;
+    if (j < m && ((mask >> j) & 1u)) {
+      const double md = mid[j];
+      if ((r >> j) & 1u) x.n = neg(md); else x.h = md;
+    }
+    return x;
+  }
+};
+
+// wave-level helpers ---------------------------------------------------------
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int h = 32; h >= 1; h >>= 1) v = dmax(v, __shfl_xor(v, h, kWave));
+  return v;
+}
+
+// Canonical sum: lane s holds slot s (terms s, s+64, ... summed left to right);
+// slots are folded with strides 32, 16, ..., 1, slot s absorbing slot s + h.
+__device__ __forceinline__ I fold_slots(I acc, int lane) {
+  for (int h = 32; h >= 1; h >>= 1) {
+    const double on = __shfl_down(acc.n, h, kWave);
+    const double oh = __shfl_down(acc.h, h, kWave);
+    if (lane < h) acc = add(acc, I{on, oh});
+  }
+  return I{__shfl(acc.n, 0, kWave), __shfl(acc.h, 0, kWave)};
+}
+__device__ __forceinline__ double fold_slots_hi(double acc, int lane) {
+  for (int h = 32; h >= 1; h >>= 1) {
+    const double o = __shfl_down(acc, h, kWave);
+    if (lane < h) acc = acc + o;
+  }
+  return __shfl(acc, 0, kWave);
+}
+
+// F, first-order test and widest side of one box, by one wavefront
+template <int FAM, class Row>
+__device__ __forceinline__ void bound_box(const Params& P, const Row& X, int lane, I& F, bool& mono,
+                                          double& wmax, double* Gout) {
+  const int n = P.n;
+  I acc{0.0, 0.0};
+  bool mo = false;
+  double wm = 0.0;
+  if (FAM != FAM_CHAIN) {
+    for (int i = lane; i < n; i += kWave) {
+      const I x = X.get(i);
+      I t, G;
+      sep_box<FAM>(P.sep[i], x, t, G);
+      acc = add(acc, t);
+      mo |= (G.n < 0.0 && x.n != P.nl[i]) || (G.h < 0.0 && x.h != P.u[i]);
+      wm = dmax(wm, x.n + x.h);
+      if (Gout) { Gout[2 * i] = neg(G.n); Gout[2 * i + 1] = G.h; }
+    }
+  } else {
+    for (int i = lane; i < n; i += kWave) {
+      const I xi = X.get(i);
+      const bool has_prev = i > 0, has_next = i + 1 < n;
+      const I xp = has_prev ? X.get(i - 1) : xi;
+      const I xn = has_next ? X.get(i + 1) : xi;
+      if (has_next) {
+        I R, E;
+        acc = add(acc, chain_term(P.chain[i], xi, xn, R, E));
+      }
+      const I G = chain_grad(P.chain[has_prev ? i - 1 : i], P.chain[i], xp, xi, xn, has_prev, has_next);
+      mo |= (G.n < 0.0 && xi.n != P.nl[i]) || (G.h < 0.0 && xi.h != P.u[i]);
+      wm = dmax(wm, xi.n + xi.h);
+      if (Gout) { Gout[2 * i] = neg(G.n); Gout[2 * i + 1] = G.h; }
+    }
+  }
+  F = fold_slots(acc, lane);
+  mono = __any(mo);
+  wmax = wave_max(wm);
+}
+
+// upper bound of f at the box midpoint, by one wavefront
+template <int FAM, class Row>
+__device__ __forceinline__ double point_ub(const Params& P, const Row& X, int lane) {
+  const int n = P.n;
+  double acc = 0.0;
+  if (FAM != FAM_CHAIN) {
+    for (int i = lane; i < n; i += kWave) acc = acc + sep_point_hi<FAM>(P.sep[i], midpoint(X.get(i)));
+  } else {
+    for (int i = lane; i + 1 < n; i += kWave) {
+      I R, E;
+      const I t = chain_term(P.chain[i], point(midpoint(X.get(i))), point(midpoint(X.get(i + 1))), R, E);
+      acc = acc + t.h;
+    }
+  }
+  return fold_slots_hi(acc, lane);
+}
+
+}  // namespace ibb

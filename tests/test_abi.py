@@ -1,0 +1,65 @@
+"""The C ABI (include/ibb.h) without a GPU: every declared entry point is exported,
+and argument validation rejects bad problems before any device call."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2507_01770_amd as ibb
+from paper_2507_01770_amd import problems as PR
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ibb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ibb_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 11, names
+    L = ibb.lib()
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_options_default_and_status_strings():
+    L = ibb.lib()
+    o = ibb._Options()
+    assert L.ibb_options_default(C.byref(o)) == 0
+    assert (o.precision, o.split_dims, o.select_k, o.deterministic) == (0, 10, 1, 1)
+    for s in [0, 1, 2, -1, -2, -3, -4, -5]:
+        assert L.ibb_status_string(s)
+
+
+def _solve_rc(**kw):
+    p = PR.sep_cos(3, 1)
+    args = dict(family=p.family, coef=p.coef, lower=p.lower, upper=p.upper, tol_f=1e-6, tol_x=0.0)
+    args.update(kw)
+    k = ibb._ProblemKeep(args["family"], args["coef"], args["lower"], args["upper"], args["tol_f"], args["tol_x"])
+    o = ibb._Options()
+    ibb.lib().ibb_options_default(C.byref(o))
+    for key in ("split_dims", "select_k", "precision"):
+        if key in kw:
+            setattr(o, key, kw[key])
+    h = C.c_void_p()
+    rc = ibb.lib().ibb_solve(C.byref(k.s), C.byref(o), None, None, C.byref(h))
+    return rc, ibb.lib().ibb_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(family=7), "unknown family"),
+    (dict(coef=np.zeros(5)), "coef_len"),
+    (dict(lower=np.array([0.0, 0.0, 1.0]), upper=np.array([1.0, 1.0, 1.0])), "lower < upper"),
+    (dict(upper=np.array([1.0, np.inf, 1.0])), "finite"),
+    (dict(tol_f=0.0), "tol_f"),
+    (dict(coef=np.concatenate([np.ones(3), np.ones(3), [1.5, 1, 1], np.zeros(3)])), "positive integer"),
+    (dict(split_dims=17), "split_dims"),
+])
+def test_validation_rejects_before_touching_the_device(kw, msg):
+    rc, err = _solve_rc(**kw)
+    assert rc == -1 and msg in err, (rc, err)

@@ -1,0 +1,120 @@
+"""Whole iterations on the GPU (ibb_solve through the C ABI) against the oracle.
+
+CHAIN: every bound is bit-identical, so the two iterations must agree sweep for
+sweep (GUB after each sweep, children inserted, live count, selected box) and
+end with the same boxes.  Separable families: the GPU's trig enclosures may be
+a couple of doubles wider, so decisions can differ in rare ties; both runs must
+enclose the known minimum 0 at the stated width and keep the minimiser, and
+their traces must agree closely.  The workload sizes run on the GPU in full and
+are compared with a prefix of the oracle's iteration.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2507_01770_amd import problems as PR
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2507_01770_amd as ibb  # noqa: E402
+
+
+def inside_some_box(x, lo, hi):
+    return bool(np.any(np.all((lo <= x) & (x <= hi), axis=1)))
+
+
+def run_both(p, **kw):
+    print(f"case {p.name} {kw}", flush=True)
+    r = ibb.minimize(p, **kw)
+    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=p.tol_x,
+                max_sweeps=kw.get("max_sweeps", 100000))
+    return r, o
+
+
+# [-2, 2.3] keeps x* = 1 off the bisection points, so the runs take 40-50 sweeps;
+# n = 13 on [-2, 2] does not converge quickly and stops on the sweep budget
+@pytest.mark.parametrize("n,hi,budget", [(2, 2.0, 3000), (3, 2.3, 3000), (5, 2.3, 3000), (8, 2.3, 3000),
+                                         (12, 2.3, 3000), (13, 2.0, 150)])
+def test_chain_identical_iteration(n, hi, budget):
+    p = PR.chain(n, 505, hi=hi)
+    r, o = run_both(p, max_sweeps=budget)
+    assert r.status == o.status
+    assert r.sweeps == o.sweeps
+    assert np.array_equal(r.trace_gub, o.trace_gub)
+    assert np.array_equal(r.trace_nsurv, o.trace_nsurv)
+    assert np.array_equal(r.trace_nlive, o.trace_nlive)
+    assert np.array_equal(r.trace_sel, o.trace_sel)
+    assert r.f_lo == o.f_lo and r.f_hi == o.f_hi
+    assert np.array_equal(r.seq, o.seq) and np.array_equal(r.flo, o.flo)
+    assert np.array_equal(r.lo, o.lo) and np.array_equal(r.hi, o.hi)
+    assert boxes_equal_count(r, o)
+
+
+def boxes_equal_count(r, o):
+    return r.n_boxes == len(o.flo)
+
+
+@pytest.mark.parametrize("fam,n,seed", [(PR.SEP_COS, 1, 1), (PR.SEP_COS, 2, 101), (PR.SEP_COS, 9, 2),
+                                        (PR.SEP_ABS_SIN2, 2, 3), (PR.SEP_ABS_SIN2, 12, 4)])
+def test_separable_matches_oracle(fam, n, seed):
+    p = PR.make(fam, n, seed)
+    r, o = run_both(p, max_sweeps=20000)
+    assert r.status == ibb.OK and o.status == O.ST_OK
+    for res in (r, o):
+        assert res.f_lo <= 0.0 <= res.f_hi and res.f_hi - res.f_lo <= 1e-6
+        assert inside_some_box(p.x_star, res.lo, res.hi)
+    # same path up to last-bit differences of the bounds
+    assert abs(r.sweeps - o.sweeps) <= max(2, o.sweeps // 20)
+    k = min(len(r.trace_gub), len(o.trace_gub), 10)
+    assert np.allclose(r.trace_gub[:k], o.trace_gub[:k], rtol=1e-12, atol=1e-12)
+
+
+def test_budget_and_width_criterion():
+    p = PR.sep_cos(6, 9)
+    r = ibb.minimize(p, max_sweeps=4)
+    assert r.status == ibb.NOT_CONVERGED and r.sweeps == 4
+    assert r.f_lo <= 0.0 <= r.f_hi and inside_some_box(p.x_star, r.lo, r.hi)
+    p.tol_x = 1e-4
+    r = ibb.minimize(p, max_sweeps=20000)
+    assert r.status == ibb.OK and np.all(r.hi - r.lo < 1e-4)
+
+
+def test_workload0_full_parity():
+    p = PR.config(0)
+    r, o = run_both(p)
+    assert r.status == ibb.OK and r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6
+    assert r.sweeps == o.sweeps
+
+
+@pytest.mark.parametrize("cfg,prefix", [(1, 6), (2, 12)])
+def test_workload_full_run_and_prefix(cfg, prefix):
+    p = PR.config(cfg)
+    print(f"case workload {cfg} full", flush=True)
+    r = ibb.minimize(p, max_sweeps=200000, fetch_boxes=True, max_boxes_fetched=2000)
+    assert r.status == ibb.OK, r.status
+    assert r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6
+    assert inside_some_box(p.x_star, r.lo, r.hi) or r.n_boxes > 2000
+    print(f"case workload {cfg} oracle prefix {prefix}", flush=True)
+    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=prefix)
+    if p.family == PR.CHAIN:
+        assert np.array_equal(r.trace_gub[:prefix], o.trace_gub)
+        assert np.array_equal(r.trace_nsurv[:prefix], o.trace_nsurv)
+        assert np.array_equal(r.trace_sel[:prefix], o.trace_sel)
+    else:
+        assert np.allclose(r.trace_gub[:prefix], o.trace_gub, rtol=1e-12)
+        assert np.array_equal(r.trace_sel[:prefix], o.trace_sel)
+
+
+def test_workload3_capped_run():
+    # n = 10,000: the oracle needs about 30 s per sweep, so only invariants here
+    # (the bounds themselves are compared on sampled boxes in test_gpu_eval)
+    p = PR.config(3)
+    print("case workload 3 capped", flush=True)
+    r = ibb.minimize(p, max_sweeps=40, fetch_boxes=False)
+    assert r.status == ibb.NOT_CONVERGED and r.sweeps == 40
+    assert r.f_lo <= 0.0 <= r.f_hi
+    assert r.trace_sel[0] == 0 and np.all(np.diff(r.trace_gub) <= 0)
