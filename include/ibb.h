@@ -79,6 +79,8 @@ typedef struct {
   int64_t max_sweeps;    /* budget; default 1,000,000 */
   int64_t max_live_boxes;/* budget on the live list; default 1<<26 */
   double time_limit_s;   /* budget; <= 0 means none; default 0 */
+  int32_t profile;       /* 1: time every sweep kernel with HIP events (ibb_info t_* fields); default 0 */
+  int32_t reserved;
 } ibb_options;
 
 typedef struct {
@@ -96,6 +98,12 @@ typedef struct {
   int64_t fp64_confirmed;     /* children bounded in FP64 */
   double seconds;             /* wall time of ibb_solve */
   int32_t status;             /* IBB_OK or IBB_NOT_CONVERGED */
+  int32_t reserved;
+  int64_t ub_evaluated;       /* children whose midpoint upper bound was computed */
+  /* filled when options.profile = 1: summed kernel times (ms) and launch counts of
+     the sweeps that ran (launches after the stop are not counted) */
+  double t_bound_ms, t_select_ms;
+  int64_t n_bound_launches, n_select_launches;
 } ibb_info;
 
 typedef struct ibb_result ibb_result;

@@ -38,7 +38,7 @@ class _Problem(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("split_dims", C.c_int32), ("select_k", C.c_int32),
                 ("deterministic", C.c_int32), ("max_sweeps", C.c_int64), ("max_live_boxes", C.c_int64),
-                ("time_limit_s", C.c_double)]
+                ("time_limit_s", C.c_double), ("profile", C.c_int32), ("reserved", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -52,7 +52,9 @@ class _Allocator(C.Structure):
 class _Info(C.Structure):
     _fields_ = [("f_lo", C.c_double), ("f_hi", C.c_double), ("n_boxes", C.c_int64), ("sweeps", C.c_int64),
                 ("boxes_evaluated", C.c_int64), ("fp32_pruned", C.c_int64), ("fp64_confirmed", C.c_int64),
-                ("seconds", C.c_double), ("status", C.c_int32)]
+                ("seconds", C.c_double), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("ub_evaluated", C.c_int64), ("t_bound_ms", C.c_double), ("t_select_ms", C.c_double),
+                ("n_bound_launches", C.c_int64), ("n_select_launches", C.c_int64)]
 
 
 _lib = None
@@ -217,16 +219,21 @@ class Result:
     trace_nsurv: np.ndarray
     trace_nlive: np.ndarray
     trace_sel: np.ndarray
+    ub_evaluated: int = 0
+    t_bound_ms: float = 0.0        # summed k_bound time (profile=True)
+    t_select_ms: float = 0.0
+    n_bound_launches: int = 0
+    n_select_launches: int = 0
 
 
 def minimize(problem=None, *, family=None, coef=None, lower=None, upper=None, tol_f=None, tol_x=None,
              precision=FP64, split_dims=10, select_k=1, max_sweeps=1_000_000, max_live_boxes=1 << 26,
              time_limit_s=0.0, fetch_boxes=True, max_boxes_fetched=100_000, use_torch_allocator=True,
-             stream=None) -> Result:
+             profile=False, stream=None) -> Result:
     """Enclose min f over [lower, upper]; returns [f_lo, f_hi] and the surviving boxes."""
     k = _prob_args(problem, family, coef, lower, upper, tol_f, tol_x)
     L = lib()
-    opts = _Options(precision, split_dims, select_k, 1, max_sweeps, max_live_boxes, time_limit_s)
+    opts = _Options(precision, split_dims, select_k, 1, max_sweeps, max_live_boxes, time_limit_s, int(profile), 0)
     alloc = _TorchAllocator() if use_torch_allocator else None
     h = C.c_void_p()
     rc = L.ibb_solve(C.byref(k.s), C.byref(opts), C.byref(alloc.struct) if alloc else None, _stream_ptr(stream),
@@ -253,6 +260,7 @@ def minimize(problem=None, *, family=None, coef=None, lower=None, upper=None, to
         _check(L.ibb_result_trace(h, dp(tg), ip(tn), ip(tl), ip(tsel), ts, C.byref(w)))
         got = w.value
         return Result(info.f_lo, info.f_hi, info.status, info.sweeps, info.boxes_evaluated, nb, info.seconds,
-                      lo, hi, flo, seq, tg[:got], tn[:got], tl[:got], tsel[:got])
+                      lo, hi, flo, seq, tg[:got], tn[:got], tl[:got], tsel[:got], info.ub_evaluated,
+                      info.t_bound_ms, info.t_select_ms, info.n_bound_launches, info.n_select_launches)
     finally:
         L.ibb_result_free(h)

@@ -98,6 +98,7 @@ __global__ __launch_bounds__(kWave) void k_root(const Params* __restrict__ PP, S
     S->next_seq = 1;
     S->sweeps = 0;
     S->evaluated = 1;
+    S->ub_evaluated = 1;
     S->n_live = 1;
     S->stop = RUNNING;
     S->sel_done = 0u;
@@ -262,7 +263,10 @@ __global__ __launch_bounds__(kWave* kBoundWaves) void k_bound(const Params* __re
       if (!(flo > gcur)) {
         // a child whose lower bound exceeds the running GUB cannot lower GUB
         const double u = point_ub<FAM>(P, X, lane);
-        if (lane == 0) atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(u + 0.0));
+        if (lane == 0) {
+          atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(u + 0.0));
+          atomicAdd((unsigned long long*)&S->ub_evaluated, 1ull);
+        }
       }
       if (lane == 0) {
         P.ch_flo[c] = flo;
@@ -676,6 +680,8 @@ ibb_status ibb_options_default(ibb_options* o) {
   o->max_sweeps = 1000000;
   o->max_live_boxes = (int64_t)1 << 26;
   o->time_limit_s = 0.0;
+  o->profile = 0;
+  o->reserved = 0;
   return IBB_OK;
 }
 
@@ -777,6 +783,11 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
   // ---- sweep loop, in chunks; the host reads the device state between chunks ----
   State hs{};
   int64_t n_keys = 1, sweeps = 0;
+  struct Events {
+    std::vector<hipEvent_t> v;
+    ~Events() { for (auto e : v) (void)hipEventDestroy(e); }
+  } evs;
+  auto& ev = evs.v;
   int chunk = 4;
   const int bound_blocks = (P.nch + kBoundWaves - 1) / kBoundWaves;
   for (;;) {
@@ -803,17 +814,42 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
       if (push_params(M, P, dP) != IBB_OK) return bail(IBB_E_DEVICE);
     }
     const int sb = sel_blocks_for(need_keys);
+    const bool prof = opts.profile != 0;
+    if (prof && (int)ev.size() < 4 * chunk) {
+      const size_t old_n = ev.size();
+      ev.resize(4 * chunk);
+      for (size_t e = old_n; e < ev.size(); ++e)
+        if (hipEventCreate(&ev[e]) != hipSuccess) return bail(fail(IBB_E_DEVICE, "hipEventCreate failed"));
+    }
     dispatch_family(P.family, [&](auto fam) {
       for (int s = 0; s < chunk; ++s) {
+        if (prof) (void)hipEventRecord(ev[4 * s + 0], M.stream);
         hipLaunchKernelGGL(k_select, dim3(sb), dim3(kSelThreads), 0, M.stream, dP, dS);
+        if (prof) (void)hipEventRecord(ev[4 * s + 1], M.stream);
         hipLaunchKernelGGL(k_bound<decltype(fam)::value>, dim3(bound_blocks), dim3(kWave * kBoundWaves), 0, M.stream,
                            dP, dS);
+        if (prof) (void)hipEventRecord(ev[4 * s + 2], M.stream);
       }
     });
     if (hipGetLastError() != hipSuccess) return bail(fail(IBB_E_DEVICE, "sweep launch failed"));
     if (hipMemcpyAsync(&hs, dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
         hipStreamSynchronize(M.stream) != hipSuccess)
       return bail(fail(IBB_E_DEVICE, "sweep failed"));
+    if (prof) {
+      // sweeps that ran in this chunk; the select of the stopping sweep ran too
+      const int64_t ran = hs.sweeps - sweeps;
+      for (int s = 0; s < chunk; ++s) {
+        float ms = 0.f;
+        if (s < ran || (s == ran && hs.stop)) {
+          if (hipEventElapsedTime(&ms, ev[4 * s + 0], ev[4 * s + 1]) == hipSuccess) R->info.t_select_ms += ms;
+          R->info.n_select_launches++;
+        }
+        if (s < ran) {
+          if (hipEventElapsedTime(&ms, ev[4 * s + 1], ev[4 * s + 2]) == hipSuccess) R->info.t_bound_ms += ms;
+          R->info.n_bound_launches++;
+        }
+      }
+    }
     n_keys = hs.n_keys;
     sweeps = hs.sweeps;
     if (hs.stop) break;
@@ -864,6 +900,7 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
   R->info.boxes_evaluated = hs.evaluated;
   R->info.fp32_pruned = 0;
   R->info.fp64_confirmed = hs.evaluated;
+  R->info.ub_evaluated = hs.ub_evaluated;
   R->info.status = hs.stop == STOP_CONVERGED ? IBB_OK : (hs.stop == STOP_EMPTY ? IBB_E_INTERNAL : IBB_NOT_CONVERGED);
   R->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   if (R->info.status == IBB_E_INTERNAL) return bail(fail(IBB_E_INTERNAL, "the live list became empty"));

@@ -208,11 +208,11 @@ __device__ inline I isqrt(I a) {
 // -------------------------------------------------------------------------
 // cos(2 pi y), sin(2 pi y)
 //
-// Reduction (exact): f = y - rint(y), a = |f|, and one reduced argument g with
-// |g| <= 1/8 serves both functions:
-//   a <= 1/8:        cos = C(a),          sin = sgn(f) S(a)
-//   1/8 < a <= 3/8:  cos = S(1/4 - a),    sin = sgn(f) C(1/4 - a)
-//   a > 3/8:         cos = -C(1/2 - a),   sin = sgn(f) S(1/2 - a)
+// Reduction (exact): f = |y| - nearest integer (via floor), a = |f|, and one
+// reduced argument g with |g| <= 1/8 serves both functions:
+//   a <= 1/8:        cos = C(a),          sin = sgn(y) sgn(f) S(a)
+//   1/8 < a <= 3/8:  cos = S(1/4 - a),    sin = sgn(y) sgn(f) C(1/4 - a)
+//   a > 3/8:         cos = -C(1/2 - a),   sin = sgn(y) sgn(f) S(1/2 - a)
 // with S(g) = sin(2 pi g), C(g) = cos(2 pi g).
 //
 // S(g) = A0 g + A1 g^3 + g^5 P(g^2), A_k = (-1)^k (2pi)^(2k+1) / (2k+1)!
@@ -234,7 +234,11 @@ struct TrigEnc {
 };
 
 __device__ __forceinline__ TrigEnc sincos2pi_point(double y) {
-  const double f = y - __builtin_rint(y);          // exact
+  // reduce |y| with floor (exact, independent of the rounding mode):
+  // fr in [0, 1), f in (-1/2, 1/2];  cos is even, sin odd in y
+  const double ay = __builtin_fabs(y);
+  const double fr = ay - __builtin_floor(ay);
+  const double f = fr > 0.5 ? fr - 1.0 : fr;
   const double a = __builtin_fabs(f);
   const bool oct0 = a <= 0.125, oct1 = a <= 0.375;
   const double g = oct0 ? a : (oct1 ? 0.25 - a : 0.5 - a);   // exact, |g| <= 1/8
@@ -244,7 +248,7 @@ __device__ __forceinline__ TrigEnc sincos2pi_point(double y) {
 
   // ---- S(g) ----
   const double A0h = hexd(0x401921fb54442d18ull), A0l = hexd(0x3cb1a62633145c07ull);
-  const double A1h = hexd(0xc054abbce625be53ull), A1l = hexd(0x3ce05511c68476a8ull);
+  const double A1h = hexd(0xc044abbce625be53ull), A1l = hexd(0x3ce05511c68476a8ull);
   // p + pe = A0h g exactly
   const double p = A0h * g;
   const double pe = fms(A0h, g, p);
@@ -275,6 +279,15 @@ __device__ __forceinline__ TrigEnc sincos2pi_point(double y) {
   const double Es = __builtin_fabs(ws) * hexd(0x3c80000000000000ull);   // 2^-55 |w|
   // enclosure: [w + t - E, w + t + E] rounded outward
   I S{(Es - lo_s) - ws, ws + (lo_s + Es)};
+  // |g| < 2^-900: the split products above are no longer exact near the
+  // subnormal range; there 2 pi g (1 - 2^-54) < sin(2 pi g) <= 2 pi g, so
+  // [RD(PI2_LO g), RU(PI2_HI g)] (g >= 0; odd for g < 0) encloses S
+  if (__builtin_fabs(g) < hexd(0x07b0000000000000ull)) {
+    const double ag = __builtin_fabs(g);
+    const double lo_m = mul_neg(hexd(0x401921fb54442d18ull), ag);   // -RD(PI2_LO |g|)
+    const double hi_m = hexd(0x401921fb54442d19ull) * ag;            //  RU(PI2_HI |g|)
+    S = g >= 0.0 ? I{lo_m, hi_m} : I{hi_m, lo_m};
+  }
 
   // ---- C(g) ----
   const double B1h = hexd(0xc033bd3cc9be45deull), B1l = hexd(0xbcd692b71366cc04ull);
@@ -305,7 +318,7 @@ __device__ __forceinline__ TrigEnc sincos2pi_point(double y) {
   r.c = oct0 ? C : (oct1 ? S : I{C.h, C.n});
   // sin: sgn(f) * (S, C, S)
   I sv = (oct0 || !oct1) ? S : C;
-  r.s = (f < 0.0) ? I{sv.h, sv.n} : sv;
+  r.s = ((f < 0.0) != (y < 0.0)) ? I{sv.h, sv.n} : sv;
   // clamp to [-1, 1]
   r.c.n = dmin(r.c.n, 1.0); r.c.h = dmin(r.c.h, 1.0);
   r.s.n = dmin(r.s.n, 1.0); r.s.h = dmin(r.s.h, 1.0);

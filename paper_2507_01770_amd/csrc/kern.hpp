@@ -69,7 +69,7 @@ struct Params {
 
 struct State {
   uint64_t gub_key;                       // ordered key of GUB
-  int64_t n_keys, next_seq, sweeps, evaluated, n_live;
+  int64_t n_keys, next_seq, sweeps, evaluated, ub_evaluated, n_live;
   double glb, wmax;
   int32_t stop;
   uint32_t sel_done, bound_done;

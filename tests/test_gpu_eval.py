@@ -72,7 +72,7 @@ def test_separable_contains_oracle(fam, n):
 def test_workload_sizes_sampled(cfg):
     p = PR.config(cfg)
     nb = 6 if cfg == 3 else 16
-    (F, ub, mono, G), (gF, gub, gmono, gG) = both(p, nb, seed=cfg, grad=False)
+    (F, ub, mono), (gF, gub, gmono) = both(p, nb, seed=cfg, grad=False)
     if p.family == PR.CHAIN:
         assert np.array_equal(gF, F) and np.array_equal(gub, ub) and np.array_equal(gmono, mono)
     else:

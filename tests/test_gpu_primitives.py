@@ -78,15 +78,26 @@ def test_bit_exact_div_sqrt(op):
     assert idx.size == 0, (op, got[idx[:3]], ref[idx[:3]])
 
 
-def ulps_beyond(outer, inner):
-    """how many doubles outer's endpoints lie beyond inner's (per side; <0 = not containing)"""
-    lo_o, hi_o, lo_i, hi_i = outer[:, 0], outer[:, 1], inner[:, 0], inner[:, 1]
+def _okey(x):
+    """ordered integer key of doubles: key(a) < key(b) <=> a < b, -0 == +0"""
+    b = np.ascontiguousarray(x).view(np.int64)
+    return np.where(b < 0, -(b & 0x7fffffffffffffff), b)
 
-    def steps(a, b):  # number of doubles from a up to b (a <= b), via ordered integer keys
-        ka = np.where(a < 0, -(a.view(np.int64) & 0x7fffffffffffffff), a.view(np.int64)).astype(np.int64)
-        kb = np.where(b < 0, -(b.view(np.int64) & 0x7fffffffffffffff), b.view(np.int64)).astype(np.int64)
-        return kb - ka
-    return steps(lo_o, lo_i), steps(hi_i, hi_o)
+
+def ulps_beyond(outer, inner):
+    """how many doubles outer's endpoints lie beyond inner's (per side; <0 = not containing).
+    Differences are clipped to +-2^40 so that far-apart values cannot overflow."""
+    def steps(a, b):  # number of doubles from a up to b
+        ka, kb = _okey(a), _okey(b)
+        same_sign = (ka >= 0) == (kb >= 0)
+        d = np.where(same_sign, kb - ka, np.sign(kb - ka.astype(np.float64)) * 2 ** 40)
+        return np.clip(d, -2 ** 40, 2 ** 40).astype(np.int64)
+    return steps(outer[:, 0], inner[:, 0]), steps(inner[:, 1], outer[:, 1])
+
+
+def report(y, got, ref, dl, dh, limit=5):
+    bad = np.argwhere((dl < 0) | (dh < 0) | (dl > 2) | (dh > 2)).ravel()
+    return [(float(y[i]).hex(), got[i].tolist(), ref[i].tolist(), int(dl[i]), int(dh[i])) for i in bad[:limit]]
 
 
 def trig_points(seed, cnt):
@@ -106,8 +117,8 @@ def test_point_trig_contains_oracle_within_two_ulps(fn):
     ref = O.point_trig(fn, y)
     got = ibb.point_trig(fn, torch.from_numpy(y).cuda()).cpu().numpy()
     dl, dh = ulps_beyond(got, ref)
-    assert dl.min() >= 0 and dh.min() >= 0, "GPU enclosure must contain the oracle's"
-    assert dl.max() <= 2 and dh.max() <= 2, (dl.max(), dh.max())
+    assert dl.min() >= 0 and dh.min() >= 0, ("GPU enclosure must contain the oracle's", report(y, got, ref, dl, dh))
+    assert dl.max() <= 2 and dh.max() <= 2, report(y, got, ref, dl, dh)
     # and the true value (a sample, at 200 bits)
     mpmath.mp.prec = 200
     for i in np.random.default_rng(1).choice(y.size, 400, replace=False):
@@ -127,5 +138,5 @@ def test_interval_trig_contains_oracle_within_two_ulps(fn):
     ref = O.iv_op(fn, Y)
     got = gpu_op(fn, Y)
     dl, dh = ulps_beyond(got, ref)
-    assert dl.min() >= 0 and dh.min() >= 0
-    assert dl.max() <= 2 and dh.max() <= 2, (dl.max(), dh.max())
+    assert dl.min() >= 0 and dh.min() >= 0, report(Y[:, 0], got, ref, dl, dh)
+    assert dl.max() <= 2 and dh.max() <= 2, report(Y[:, 0], got, ref, dl, dh)
