@@ -1,4 +1,5 @@
 // ibb.hip -- libibb: kernels, host driver and the C ABI declared in include/ibb.h.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -101,6 +102,7 @@ __global__ __launch_bounds__(kWave) void k_root(const Params* __restrict__ PP, S
     S->ub_evaluated = 1;
     S->n_live = 1;
     S->stop = RUNNING;
+    S->pending = 0;
     S->sel_done = 0u;
     S->bound_done = 0u;
   }
@@ -114,118 +116,161 @@ struct Cand {
 __device__ __forceinline__ bool better(const Cand& a, const Cand& b) {  // a before b
   return a.f < b.f || (a.f == b.f && a.s < b.s);
 }
+// running reduction of the selection scan: best key, widest box, live count
+struct SelAcc {
+  Cand best;
+  double wm;
+  int64_t cnt;
+};
+__device__ __forceinline__ SelAcc sel_merge(SelAcc a, const SelAcc& b) {
+  if (better(b.best, a.best)) a.best = b.best;
+  a.wm = dmax(a.wm, b.wm);
+  a.cnt += b.cnt;
+  return a;
+}
+__device__ __forceinline__ SelAcc sel_empty() { return SelAcc{Cand{__builtin_inf(), INT64_MAX, -1}, 0.0, 0}; }
 
-// Stop test and selection of the next box to partition.
-__global__ __launch_bounds__(kSelThreads) void k_select(const Params* __restrict__ PP, State* __restrict__ S) {
-  round_up_mode();
-  if (S->stop) return;
-  const Params P = *PP;
-  const int64_t nk = S->n_keys;
-  const double gub = okey_inv(S->gub_key);
-  Cand best{__builtin_inf(), INT64_MAX, -1};
-  double wm = 0.0;
-  int64_t cnt = 0;
-  for (int64_t i = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; i < nk; i += (int64_t)gridDim.x * kSelThreads) {
-    const double f = P.key_flo[i];
-    if (!(f <= gub)) continue;   // removed (+inf) or above GUB
-    cnt++;
-    wm = dmax(wm, P.key_wmax[i]);
-    const Cand c{f, P.key_seq[i], i};
-    if (better(c, best)) best = c;
-  }
-  // wave reduce
+// reduce over a workgroup of NT threads; the result is returned to every thread
+template <int NT>
+__device__ __forceinline__ SelAcc sel_block_reduce(SelAcc v) {
   for (int h = 32; h >= 1; h >>= 1) {
-    Cand o{__shfl_xor(best.f, h, kWave), (int64_t)__shfl_xor((long long)best.s, h, kWave),
-           (int64_t)__shfl_xor((long long)best.idx, h, kWave)};
-    if (better(o, best)) best = o;
-    wm = dmax(wm, __shfl_xor(wm, h, kWave));
-    cnt += (int64_t)__shfl_xor((long long)cnt, h, kWave);
+    SelAcc o;
+    o.best.f = __shfl_xor(v.best.f, h, kWave);
+    o.best.s = (int64_t)__shfl_xor((long long)v.best.s, h, kWave);
+    o.best.idx = (int64_t)__shfl_xor((long long)v.best.idx, h, kWave);
+    o.wm = __shfl_xor(v.wm, h, kWave);
+    o.cnt = (int64_t)__shfl_xor((long long)v.cnt, h, kWave);
+    v = sel_merge(v, o);
   }
-  __shared__ Cand sc[kSelThreads / kWave];
-  __shared__ double sw[kSelThreads / kWave];
-  __shared__ int64_t sn[kSelThreads / kWave];
-  __shared__ bool last;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) { sc[w] = best; sw[w] = wm; sn[w] = cnt; }
+  __shared__ SelAcc part[NT / kWave];
+  const int w = threadIdx.x >> 6;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 1; k < kSelThreads / kWave; ++k) {
-      if (better(sc[k], best)) best = sc[k];
-      wm = dmax(wm, sw[k]);
-      cnt += sn[k];
+  if ((threadIdx.x & 63) == 0) part[w] = v;
+  __syncthreads();
+  SelAcc r = part[0];
+  for (int k = 1; k < NT / kWave; ++k) r = sel_merge(r, part[k]);
+  return r;
+}
+
+// Insert the survivors of the previous sweep's children (lower bound <= the
+// final GUB of that sweep, first-order test passed), in child order, and fold
+// them into the running selection.  One workgroup of NT threads.
+template <int NT>
+__device__ void insert_children(const Params& P, State* S, double gub, SelAcc& acc) {
+  __shared__ int scan[NT];
+  __shared__ int sformed[NT];
+  const int per = (P.nch + NT - 1) / NT;
+  const int c0 = threadIdx.x * per, c1 = min(P.nch, c0 + per);
+  int mine = 0, nformed = 0;
+  for (int k = c0; k < c1; ++k) {
+    const uint8_t fl = P.ch_flag[k];
+    nformed += fl != 0;
+    mine += (fl == 2 && !(P.ch_flo[k] > gub));
+  }
+  scan[threadIdx.x] = mine;
+  sformed[threadIdx.x] = nformed;
+  __syncthreads();
+  for (int off = 1; off < NT; off <<= 1) {   // inclusive scan
+    const int v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
+    const int f2 = threadIdx.x >= (unsigned)off ? sformed[threadIdx.x - off] : 0;
+    __syncthreads();
+    scan[threadIdx.x] += v;
+    sformed[threadIdx.x] += f2;
+    __syncthreads();
+  }
+  const int total = scan[NT - 1];
+  const int64_t base = S->n_keys;
+  const int64_t seq0 = S->next_seq;
+  const int row = S->sel_row;
+  int64_t o = base + (scan[threadIdx.x] - mine);
+  SelAcc a = sel_empty();
+  for (int k = c0; k < c1; ++k) {
+    const double f = P.ch_flo[k];
+    if (P.ch_flag[k] == 2 && !(f > gub)) {
+      const int64_t sq = seq0 + (o - base);
+      P.key_flo[o] = f;
+      P.key_seq[o] = sq;
+      P.key_ref[o] = row;
+      P.key_r[o] = k;
+      P.key_wmax[o] = P.ch_wmax[k];
+      a.cnt++;
+      a.wm = dmax(a.wm, P.ch_wmax[k]);
+      const Cand cd{f, sq, o};
+      if (better(cd, a.best)) a.best = cd;
+      ++o;
     }
-    P.part_flo[blockIdx.x] = best.f;
-    P.part_seq[blockIdx.x] = best.s;
-    P.part_idx[blockIdx.x] = best.idx;
-    P.part_wmax[blockIdx.x] = wm;
-    P.part_cnt[blockIdx.x] = cnt;
-    __threadfence();
-    const uint32_t prev = atomicAdd(&S->sel_done, 1u);
-    last = prev == gridDim.x - 1;
+  }
+  a = sel_block_reduce<NT>(a);
+  acc = sel_merge(acc, a);
+  if (threadIdx.x == 0) {
+    const int64_t t = S->sweeps;
+    if (t < P.trace_cap) {
+      P.tr_gub[t] = gub;
+      P.tr_nsurv[t] = total;
+      P.tr_sel[t] = S->sel_seq;
+    }
+    S->n_keys = base + total;
+    S->next_seq = seq0 + total;
+    S->evaluated += sformed[NT - 1];
+    S->sweeps = t + 1;
+    S->pending = 0;
   }
   __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // ---- the last workgroup: merge partials ----
-  __shared__ Cand fbest;
+}
+
+// One workgroup: stop test on [GLB, GUB]; if running, remove the best key from the
+// list and build its row (child r of row ref) and the split points of that row.
+template <int NT>
+__device__ void select_finish(const Params& P, State* S, const SelAcc& tot, double gub) {
   __shared__ int32_t go;
   if (threadIdx.x == 0) {
-    Cand b{__builtin_inf(), INT64_MAX, -1};
-    double wmx = 0.0;
-    int64_t total = 0;
-    for (uint32_t k = 0; k < gridDim.x; ++k) {
-      const Cand c{P.part_flo[k], P.part_seq[k], P.part_idx[k]};
-      if (better(c, b)) b = c;
-      wmx = dmax(wmx, P.part_wmax[k]);
-      total += P.part_cnt[k];
-    }
-    S->sel_done = 0u;
+    const Cand b = tot.best;
     const int64_t t = S->sweeps;
-    if (t > 0 && t - 1 < P.trace_cap) P.tr_nlive[t - 1] = total;
-    S->n_live = total;
+    if (t > 0 && t - 1 < P.trace_cap) P.tr_nlive[t - 1] = tot.cnt;
+    S->n_live = tot.cnt;
     S->glb = b.f;
-    S->wmax = wmx;
+    S->wmax = tot.wm;
     int32_t stop = RUNNING;
-    if (total == 0) stop = STOP_EMPTY;
-    else if (gub - b.f <= P.tol_f && (P.tol_x <= 0.0 || wmx < P.tol_x)) stop = STOP_CONVERGED;
+    if (tot.cnt == 0) stop = STOP_EMPTY;
+    else if (gub - b.f <= P.tol_f && (P.tol_x <= 0.0 || tot.wm < P.tol_x)) stop = STOP_CONVERGED;
     else if (t >= P.max_sweeps) stop = STOP_SWEEPS;
-    else if (P.max_live > 0 && total > P.max_live) stop = STOP_LIVE;
+    else if (P.max_live > 0 && tot.cnt > P.max_live) stop = STOP_LIVE;
     if (stop) S->stop = stop;
     go = stop == RUNNING;
-    fbest = b;
     if (go) {
       P.key_flo[b.idx] = __builtin_inf();     // removed from the list
       S->sel_seq = b.s;
+      S->pending = 1;                         // the bound kernel will produce children
     }
   }
   __syncthreads();
   if (!go) return;
-  // ---- build the selected box's row ----
   const int64_t row = S->sweeps + 1;
-  const int32_t ref = P.key_ref[fbest.idx];
-  const int32_t r = P.key_r[fbest.idx];
+  const int32_t ref = P.key_ref[tot.best.idx];
+  const int32_t r = P.key_r[tot.best.idx];
   const int n = P.n;
   const int pcyc = P.hist_cyc[ref];
   const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
                      n, P.m, pcyc, r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
   double* dn = P.hist_n + row * n;
   double* dh = P.hist_h + row * n;
-  for (int i = threadIdx.x; i < n; i += kSelThreads) {
+  for (int i = threadIdx.x; i < n; i += NT) {
     const I x = src.get(i);
     dn[i] = x.n;
     dh[i] = x.h;
   }
   const int cyc = r >= 0 ? (int)(((int64_t)pcyc + P.m) % n) : pcyc;
-  __syncthreads();
-  __threadfence_block();
-  if (threadIdx.x < (unsigned)P.m) {
+  if (threadIdx.x < (unsigned)kWave) {
     const int j = threadIdx.x;
-    const int d = (int)(((int64_t)cyc + j) % n);
-    const I x{dn[d], dh[d]};
-    const double md = midpoint(x);
-    const bool ok = neg(x.n) < md && md < x.h;
-    P.hist_mid[row * kMaxSplit + j] = md;
-    S->sel_mid[j] = md;
+    bool ok = false;
+    if (j < P.m) {
+      const int d = (int)(((int64_t)cyc + j) % n);
+      const I x = src.get(d);                 // same values as the row just written
+      const double md = midpoint(x);
+      ok = neg(x.n) < md && md < x.h;
+      P.hist_mid[row * kMaxSplit + j] = md;
+      S->sel_mid[j] = md;
+    }
     const unsigned long long bal = __ballot(ok);
     if (j == 0) {
       const uint32_t mask = (uint32_t)bal & ((P.m >= 32) ? 0xffffffffu : ((1u << P.m) - 1u));
@@ -238,104 +283,243 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const Params* __restrict
   }
 }
 
-// Bound the children of the selected box; the last workgroup inserts survivors.
-template <int FAM>
+// scan of keys [lo, hi) with lower bound <= GUB into a running selection
+__device__ __forceinline__ void scan_keys(const Params& P, double gub, int64_t i0, int64_t i1, int64_t stride,
+                                          SelAcc& a) {
+  const bool need_w = P.tol_x > 0.0;
+  for (int64_t i = i0; i < i1; i += stride) {
+    const double f = P.key_flo[i];
+    if (!(f <= gub)) continue;   // removed (+inf) or above GUB
+    a.cnt++;
+    if (need_w) a.wm = dmax(a.wm, P.key_wmax[i]);
+    if (f <= a.best.f) {         // only a candidate needs its insertion number
+      const Cand c{f, P.key_seq[i], i};
+      if (better(c, a.best)) a.best = c;
+    }
+  }
+}
+
+// Large lists: every workgroup scans a stretch of the keys and writes a partial.
+__global__ __launch_bounds__(kSelThreads) void k_select_part(const Params* __restrict__ PP, State* __restrict__ S) {
+  if (S->stop) return;
+  const Params P = *PP;
+  const double gub = okey_inv(S->gub_key);
+  SelAcc a = sel_empty();
+  scan_keys(P, gub, (int64_t)blockIdx.x * kSelThreads + threadIdx.x, S->n_keys, (int64_t)gridDim.x * kSelThreads, a);
+  a = sel_block_reduce<kSelThreads>(a);
+  if (threadIdx.x == 0) {
+    P.part_flo[blockIdx.x] = a.best.f;
+    P.part_seq[blockIdx.x] = a.best.s;
+    P.part_idx[blockIdx.x] = a.best.idx;
+    P.part_wmax[blockIdx.x] = a.wm;
+    P.part_cnt[blockIdx.x] = a.cnt;
+  }
+}
+
+// One workgroup per sweep: insert the previous sweep's survivors, take the
+// smallest key over the list (its own scan, or the partials of k_select_part),
+// test the stopping criteria and select the next box.  Kernel boundaries make
+// the children written by k_bound and the partials visible: no device-scope
+// fences are needed.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_select(const Params* __restrict__ PP, State* __restrict__ S, int nparts,
+                                               int host_stop) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params P = *PP;
+  const double gub = okey_inv(S->gub_key);
+  SelAcc a = sel_empty();
+  if (nparts == 0) {
+    scan_keys(P, gub, threadIdx.x, S->n_keys, NT, a);
+  } else {
+    for (int k = threadIdx.x; k < nparts; k += NT) {
+      const SelAcc o{Cand{P.part_flo[k], P.part_seq[k], P.part_idx[k]}, P.part_wmax[k], P.part_cnt[k]};
+      a = sel_merge(a, o);
+    }
+  }
+  a = sel_block_reduce<NT>(a);
+  if (S->pending) insert_children<NT>(P, S, gub, a);
+  if (host_stop) {   // the host ends the run here (time limit): keep the inserted list
+    if (threadIdx.x == 0) {
+      const int64_t t = S->sweeps;
+      if (t > 0 && t - 1 < P.trace_cap) P.tr_nlive[t - 1] = a.cnt;
+      S->n_live = a.cnt;
+      S->stop = STOP_HOST;
+    }
+    return;
+  }
+  select_finish<NT>(P, S, a, gub);
+}
+
+// Bound the children of the selected box.
+//
+// W "box" wavefronts share one child: in round rd, wave w computes the terms of
+// coordinate chunk rd*W + w (64 coordinates, one per lane) and parks them in
+// LDS; wave 0 adds the W chunks to its slot sums in chunk order, so slot s
+// still sums t_s, t_{s+64}, t_{s+128}, ... left to right and the bound is the
+// same bit for bit whatever W is.
+//
+// CONC = 1 (latency mode, few children): W more wavefronts per child compute
+// the midpoint upper bound at the same time, for every formed child.
+// CONC = 0 (throughput mode): the same wavefronts compute the midpoint bound
+// afterwards, and only when F.lo does not exceed the running GUB (a child whose
+// lower bound exceeds GUB cannot lower it).  Both give the same GUB.
+template <int FAM, int W, int CONC>
 __global__ __launch_bounds__(kWave* kBoundWaves) void k_bound(const Params* __restrict__ PP, State* __restrict__ S) {
   round_up_mode();
   if (S->stop) return;
   const Params P = *PP;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int c = blockIdx.x * kBoundWaves + (threadIdx.x >> 6);
+  constexpr int WPC = CONC ? 2 * W : W;     // wavefronts per child
+  constexpr int CPB = kBoundWaves / WPC;    // children per workgroup
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int local = wid / WPC, role_w = wid % WPC;
+  const bool mid_role = CONC && role_w >= W;
+  const int w = role_w % W;
+  const int first = local * WPC + (mid_role ? W : 0);   // wave slot of this role's wave 0
+  const int c = blockIdx.x * CPB + local;
   const int row = S->sel_row;
   const uint32_t mask = S->sel_mask;
-  if (c < P.nch) {
-    if (((uint32_t)c & ~mask) != 0u) {
-      if (lane == 0) P.ch_flag[c] = 0;   // splits a coordinate that cannot be split
+  const bool formed = c < P.nch && (((uint32_t)c & ~mask) == 0u);
+  const ChildRow X{P.hist_n + (int64_t)row * P.n, P.hist_h + (int64_t)row * P.n, P.hist_mid + (int64_t)row * kMaxSplit,
+                   P.n, P.m, S->sel_cyc, mask, (uint32_t)(c < P.nch ? c : 0)};
+  const int n = P.n;
+  const int rounds = ((n + kWave - 1) / kWave + W - 1) / W;
+  __shared__ double ln[kBoundWaves][kWave], lh[kBoundWaves][kWave];
+  __shared__ int s_flag[kBoundWaves];
+  __shared__ double s_wm[kBoundWaves];
+
+  I acc{0.0, 0.0};
+  double hacc = 0.0;
+  bool mo = false;
+  double wm = 0.0;
+  // ---- pass 1: F, first-order test, widest side (box waves); midpoint bound (mid waves) ----
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int i = (rd * W + w) * kWave + lane;
+    I t{0.0, 0.0};
+    if (formed && i < n) {
+      if (mid_role) {
+        if (FAM != FAM_CHAIN) t.h = sep_point_hi<FAM>(P.sep[i], midpoint(X.get(i)));
+        else if (i + 1 < n) {
+          I R, E;
+          t.h = chain_term(P.chain[i], point(midpoint(X.get(i))), point(midpoint(X.get(i + 1))), R, E).h;
+        }
+      } else if (FAM != FAM_CHAIN) {
+        const I x = X.get(i);
+        I G;
+        sep_box<FAM>(P.sep[i], x, t, G);
+        mo |= (G.n < 0.0 && x.n != P.nl[i]) || (G.h < 0.0 && x.h != P.u[i]);
+        wm = dmax(wm, x.n + x.h);
+      } else {
+        const I xi = X.get(i);
+        const bool has_prev = i > 0, has_next = i + 1 < n;
+        const I xp = has_prev ? X.get(i - 1) : xi;
+        const I xn = has_next ? X.get(i + 1) : xi;
+        if (has_next) {
+          I R, E;
+          t = chain_term(P.chain[i], xi, xn, R, E);
+        }
+        const I G = chain_grad(P.chain[has_prev ? i - 1 : i], P.chain[i], xp, xi, xn, has_prev, has_next);
+        mo |= (G.n < 0.0 && xi.n != P.nl[i]) || (G.h < 0.0 && xi.h != P.u[i]);
+        wm = dmax(wm, xi.n + xi.h);
+      }
+    }
+    if (WPC == 1) {
+      acc = add(acc, t);
     } else {
-      const ChildRow X{P.hist_n + (int64_t)row * P.n, P.hist_h + (int64_t)row * P.n, P.hist_mid + (int64_t)row * kMaxSplit,
-                       P.n, P.m, S->sel_cyc, mask, (uint32_t)c};
-      I F;
-      bool mo;
-      double wm;
-      bound_box<FAM>(P, X, lane, F, mo, wm, nullptr);
-      const double flo = neg(F.n);
+      ln[wid][lane] = t.n;
+      lh[wid][lane] = t.h;
+      __syncthreads();
+      if (w == 0) {
+        if (mid_role)
+          for (int k = 0; k < W; ++k) hacc = hacc + lh[first + k][lane];
+        else
+          for (int k = 0; k < W; ++k) acc = add(acc, I{ln[first + k][lane], lh[first + k][lane]});
+      }
+      __syncthreads();
+    }
+  }
+  const bool any_mo = __any(mo);
+  const double wmx = wave_max(wm);
+  if (W > 1) {
+    if (lane == 0) { s_flag[wid] = any_mo; s_wm[wid] = wmx; }
+    __syncthreads();
+  }
+  double flo = 0.0, cwm = wmx;
+  bool cmo = any_mo;
+  if (!mid_role && w == 0) {
+    const I F = fold_slots(acc, lane);
+    flo = neg(F.n);
+    for (int k = 1; k < W; ++k) { cmo = cmo || s_flag[first + k]; cwm = dmax(cwm, s_wm[first + k]); }
+  }
+
+  if (!CONC) {
+    // ---- pass 2 (throughput mode): midpoint bound unless F.lo exceeds the running GUB ----
+    bool do_ub;
+    if (W > 1) {
+      __syncthreads();
+      if (w == 0 && lane == 0) {
+        const double gcur = okey_inv(__hip_atomic_load(&S->gub_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        s_flag[local] = formed && !(flo > gcur);
+      }
+      __syncthreads();
+      do_ub = s_flag[local] != 0;
+    } else {
       const double gcur = okey_inv(__hip_atomic_load(&S->gub_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      if (!(flo > gcur)) {
-        // a child whose lower bound exceeds the running GUB cannot lower GUB
-        const double u = point_ub<FAM>(P, X, lane);
-        if (lane == 0) {
-          atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(u + 0.0));
-          atomicAdd((unsigned long long*)&S->ub_evaluated, 1ull);
+      do_ub = formed && !(flo > gcur);
+    }
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int i = (rd * W + w) * kWave + lane;
+      double th = 0.0;
+      if (do_ub && i < n) {
+        if (FAM != FAM_CHAIN) {
+          th = sep_point_hi<FAM>(P.sep[i], midpoint(X.get(i)));
+        } else if (i + 1 < n) {
+          I R, E;
+          th = chain_term(P.chain[i], point(midpoint(X.get(i))), point(midpoint(X.get(i + 1))), R, E).h;
         }
       }
-      if (lane == 0) {
-        P.ch_flo[c] = flo;
-        P.ch_flag[c] = mo ? 1 : 2;
-        P.ch_wmax[c] = wm;
+      if (W == 1) {
+        hacc = hacc + th;
+      } else {
+        lh[wid][lane] = th;
+        __syncthreads();
+        if (w == 0)
+          for (int k = 0; k < W; ++k) hacc = hacc + lh[local * W + k][lane];
+        __syncthreads();
       }
     }
-  }
-  __shared__ bool last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t prev = atomicAdd(&S->bound_done, 1u);
-    last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // ---- the last workgroup: cutoff with the final GUB, insert survivors in child order ----
-  const int T = kWave * kBoundWaves;
-  const double gub = okey_inv(__hip_atomic_load(&S->gub_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  const int per = (P.nch + T - 1) / T;
-  const int c0 = threadIdx.x * per, c1 = min(P.nch, c0 + per);
-  int mine = 0, formed = 0;
-  for (int k = c0; k < c1; ++k) {
-    const uint8_t fl = P.ch_flag[k];
-    formed += fl != 0;
-    mine += (fl == 2 && !(P.ch_flo[k] > gub));
-  }
-  __shared__ int scan[kWave * kBoundWaves];
-  __shared__ int sformed[kWave * kBoundWaves];
-  scan[threadIdx.x] = mine;
-  sformed[threadIdx.x] = formed;
-  __syncthreads();
-  for (int off = 1; off < T; off <<= 1) {   // inclusive scan
-    const int v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
-    const int f2 = threadIdx.x >= (unsigned)off ? sformed[threadIdx.x - off] : 0;
-    __syncthreads();
-    scan[threadIdx.x] += v;
-    sformed[threadIdx.x] += f2;
-    __syncthreads();
-  }
-  const int total = scan[T - 1];
-  const int64_t base = S->n_keys;
-  const int64_t seq0 = S->next_seq;
-  int64_t o = base + (scan[threadIdx.x] - mine);
-  for (int k = c0; k < c1; ++k) {
-    if (P.ch_flag[k] == 2 && !(P.ch_flo[k] > gub)) {
-      P.key_flo[o] = P.ch_flo[k];
-      P.key_seq[o] = seq0 + (o - base);
-      P.key_ref[o] = row;
-      P.key_r[o] = k;
-      P.key_wmax[o] = P.ch_wmax[k];
-      ++o;
+    if (w == 0) {
+      const double u = fold_slots_hi(hacc, lane);
+      if (lane == 0 && c < P.nch) {
+        if (formed) {
+          if (do_ub) {
+            atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(u + 0.0));
+            atomicAdd((unsigned long long*)&S->ub_evaluated, 1ull);
+          }
+          P.ch_flo[c] = flo;
+          P.ch_flag[c] = cmo ? 1 : 2;
+          P.ch_wmax[c] = cwm;
+        } else {
+          P.ch_flag[c] = 0;   // takes the upper half of a coordinate that cannot be split
+        }
+      }
     }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int64_t t = S->sweeps;
-    if (t < P.trace_cap) {
-      P.tr_gub[t] = gub;
-      P.tr_nsurv[t] = total;
-      P.tr_sel[t] = S->sel_seq;
+  } else if (w == 0) {
+    if (mid_role) {
+      const double u = fold_slots_hi(hacc, lane);
+      if (lane == 0 && formed) {
+        atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(u + 0.0));
+        atomicAdd((unsigned long long*)&S->ub_evaluated, 1ull);
+      }
+    } else if (lane == 0 && c < P.nch) {
+      if (formed) {
+        P.ch_flo[c] = flo;
+        P.ch_flag[c] = cmo ? 1 : 2;
+        P.ch_wmax[c] = cwm;
+      } else {
+        P.ch_flag[c] = 0;
+      }
     }
-    S->n_keys = base + total;
-    S->next_seq = seq0 + total;
-    S->evaluated += sformed[T - 1];
-    S->sweeps = t + 1;
-    S->bound_done = 0u;
   }
 }
 
@@ -634,9 +818,11 @@ ibb_status push_params(Mem& M, const Params& P, Params* dP) {
   return IBB_OK;
 }
 
+// one workgroup up to 4 Ki keys (no partials kernel), else ~8 keys per thread
 int sel_blocks_for(int64_t keys) {
-  int64_t b = (keys + kSelThreads * 4 - 1) / (kSelThreads * 4);
-  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), kMaxSelBlocks);
+  if (keys <= 4096) return 1;
+  int64_t b = (keys + kSelThreads * 8 - 1) / (kSelThreads * 8);
+  return (int)std::min<int64_t>(std::max<int64_t>(b, 2), kMaxSelBlocks);
 }
 
 // stable compaction of keys with lower bound <= GUB into fresh arrays
@@ -783,13 +969,21 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
   // ---- sweep loop, in chunks; the host reads the device state between chunks ----
   State hs{};
   int64_t n_keys = 1, sweeps = 0;
+  bool pending = false;
   struct Events {
     std::vector<hipEvent_t> v;
     ~Events() { for (auto e : v) (void)hipEventDestroy(e); }
   } evs;
   auto& ev = evs.v;
   int chunk = 4;
-  const int bound_blocks = (P.nch + kBoundWaves - 1) / kBoundWaves;
+  // bound kernel shape: with few children the GPU is latency-bound, so the midpoint
+  // bound runs in its own wavefronts (variants 0, 1: 1 or 2 box waves + as many
+  // midpoint waves per child); with many coordinate chunks per child, 4 waves per
+  // child compute F then the midpoint bound (variant 2).  All give the same bits.
+  const int nchunks = (n + kWave - 1) / kWave;
+  const int bound_variant = nchunks <= 1 ? 0 : (nchunks <= 4 ? 1 : 2);
+  const int waves_per_child = bound_variant == 0 ? 2 : 4;
+  const int bound_blocks = (P.nch + kBoundWaves / waves_per_child - 1) / (kBoundWaves / waves_per_child);
   for (;;) {
     // capacity for this chunk: one row and at most nch keys per sweep
     const int64_t need_rows = sweeps + chunk + 2;
@@ -803,7 +997,7 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
       P.hist_cap = nc;
       if (push_params(M, P, dP) != IBB_OK) return bail(IBB_E_DEVICE);
     }
-    const int64_t need_keys = n_keys + (int64_t)chunk * P.nch;
+    const int64_t need_keys = n_keys + (int64_t)(chunk + 1) * P.nch;   // +1: children pending from the last chunk
     if (need_keys > P.key_cap) {
       int64_t nc = std::max<int64_t>(2 * P.key_cap, need_keys);
       if (grow(M, P.key_flo, n_keys, nc) != IBB_OK || grow(M, P.key_seq, n_keys, nc) != IBB_OK ||
@@ -822,13 +1016,19 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
         if (hipEventCreate(&ev[e]) != hipSuccess) return bail(fail(IBB_E_DEVICE, "hipEventCreate failed"));
     }
     dispatch_family(P.family, [&](auto fam) {
+      constexpr int FAM = decltype(fam)::value;
       for (int s = 0; s < chunk; ++s) {
-        if (prof) (void)hipEventRecord(ev[4 * s + 0], M.stream);
-        hipLaunchKernelGGL(k_select, dim3(sb), dim3(kSelThreads), 0, M.stream, dP, dS);
-        if (prof) (void)hipEventRecord(ev[4 * s + 1], M.stream);
-        hipLaunchKernelGGL(k_bound<decltype(fam)::value>, dim3(bound_blocks), dim3(kWave * kBoundWaves), 0, M.stream,
-                           dP, dS);
-        if (prof) (void)hipEventRecord(ev[4 * s + 2], M.stream);
+        if (sb > 1)
+          hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
+                                nullptr, 0, dP, dS);
+        hipExtLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
+                              (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, dP, dS,
+                              sb > 1 ? sb : 0, 0);
+        hipEvent_t e0 = prof ? ev[4 * s + 1] : nullptr, e1 = prof ? ev[4 * s + 2] : nullptr;
+        const dim3 g(bound_blocks), b(kWave * kBoundWaves);
+        if (bound_variant == 0) hipExtLaunchKernelGGL((k_bound<FAM, 1, 1>), g, b, 0, M.stream, e0, e1, 0, dP, dS);
+        else if (bound_variant == 1) hipExtLaunchKernelGGL((k_bound<FAM, 2, 1>), g, b, 0, M.stream, e0, e1, 0, dP, dS);
+        else hipExtLaunchKernelGGL((k_bound<FAM, 4, 0>), g, b, 0, M.stream, e0, e1, 0, dP, dS);
       }
     });
     if (hipGetLastError() != hipSuccess) return bail(fail(IBB_E_DEVICE, "sweep launch failed"));
@@ -836,12 +1036,12 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
         hipStreamSynchronize(M.stream) != hipSuccess)
       return bail(fail(IBB_E_DEVICE, "sweep failed"));
     if (prof) {
-      // sweeps that ran in this chunk; the select of the stopping sweep ran too
-      const int64_t ran = hs.sweeps - sweeps;
+      // bound launches that did work in this chunk; the select of the stopping sweep ran too
+      const int64_t ran = (hs.sweeps + (hs.pending ? 1 : 0)) - (sweeps + (pending ? 1 : 0));
       for (int s = 0; s < chunk; ++s) {
         float ms = 0.f;
         if (s < ran || (s == ran && hs.stop)) {
-          if (hipEventElapsedTime(&ms, ev[4 * s + 0], ev[4 * s + 1]) == hipSuccess) R->info.t_select_ms += ms;
+          if (hipEventElapsedTime(&ms, ev[4 * s + 0], ev[4 * s + 3]) == hipSuccess) R->info.t_select_ms += ms;
           R->info.n_select_launches++;
         }
         if (s < ran) {
@@ -852,9 +1052,22 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
     }
     n_keys = hs.n_keys;
     sweeps = hs.sweeps;
+    pending = hs.pending != 0;
     if (hs.stop) break;
     const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-    if (opts.time_limit_s > 0.0 && el > opts.time_limit_s) break;
+    if (opts.time_limit_s > 0.0 && el > opts.time_limit_s) {
+      // insert the last sweep's children, then stop
+      const int sbf = sel_blocks_for(n_keys);
+      if (sbf > 1) hipLaunchKernelGGL(k_select_part, dim3(sbf), dim3(kSelThreads), 0, M.stream, dP, dS);
+      hipLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, dP, dS,
+                         sbf > 1 ? sbf : 0, 1);
+      if (hipMemcpyAsync(&hs, dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
+          hipStreamSynchronize(M.stream) != hipSuccess)
+        return bail(fail(IBB_E_DEVICE, "final insert failed"));
+      n_keys = hs.n_keys;
+      sweeps = hs.sweeps;
+      break;
+    }
     chunk = std::min(chunk * 2, 256);
     // drop removed keys when they dominate the list
     if (n_keys > 4 * (hs.n_live + P.nch) && n_keys > (int64_t)1 << 16) {

@@ -1,14 +1,15 @@
 // kern.hpp -- device state and kernels of the branch-and-bound sweep.
 //
 // One sweep (Sec. 3.1, one iteration; Sec. 3.2, partition with variable cycling):
-//   k_select       stop test on [GLB, GUB]; pick the live box with the smallest
-//                  (lower bound, insertion number); rebuild its row from its
-//                  parent row and child index; fix its m split coordinates.
-//   k_bound<FAM>   one wavefront per child: F over the child, the first-order
+//   k_select       (one workgroup) insert the previous sweep's surviving
+//                  children (cutoff with that sweep's final GUB, first-order
+//                  test), stop test on [GLB, GUB], pick the live box with the
+//                  smallest (lower bound, insertion number), rebuild its row from
+//                  its parent row and child index, fix its m split coordinates.
+//                  Large lists are scanned first by k_select_part.
+//   k_bound<FAM,W> W wavefronts per child: F over the child, the first-order
 //                  test, then (unless F.lo already exceeds the running GUB) the
 //                  upper bound of f at the child midpoint -> atomicMin on GUB.
-//                  The last workgroup to finish applies the cutoff with the
-//                  final GUB and appends the survivors in child order.
 // Live boxes are kept compactly, as the paper's memory-limited list does
 // (Sec. 3.2: an index, the iteration it came from, the cycling index and the
 // lower bound): a key holds the lower bound, an insertion number, the row of
@@ -23,9 +24,10 @@ constexpr int kWave = 64;
 constexpr int kBoundWaves = 4;            // waves per workgroup in the bound kernels
 constexpr int kMaxSplit = 16;             // M <= 16
 constexpr int kSelThreads = 256;
+constexpr int kSelSingleThreads = 1024;   // the one-workgroup selection
 constexpr int kMaxSelBlocks = 1024;
 
-enum StopCode { RUNNING = 0, STOP_CONVERGED = 1, STOP_SWEEPS = 2, STOP_LIVE = 3, STOP_EMPTY = 4 };
+enum StopCode { RUNNING = 0, STOP_CONVERGED = 1, STOP_SWEEPS = 2, STOP_LIVE = 3, STOP_EMPTY = 4, STOP_HOST = 5 };
 
 struct Params {
   int32_t family, n, m, nch;              // nch = 2^m children per selected box
@@ -72,6 +74,7 @@ struct State {
   int64_t n_keys, next_seq, sweeps, evaluated, ub_evaluated, n_live;
   double glb, wmax;
   int32_t stop;
+  int32_t pending;                        // children of the last selected box await insertion
   uint32_t sel_done, bound_done;
   int32_t sel_row, sel_cyc;
   uint32_t sel_mask;

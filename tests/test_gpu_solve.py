@@ -36,9 +36,11 @@ def run_both(p, **kw):
 
 
 # [-2, 2.3] keeps x* = 1 off the bisection points, so the runs take 40-50 sweeps;
-# n = 13 on [-2, 2] does not converge quickly and stops on the sweep budget
+# n = 13 on [-2, 2] does not converge quickly and stops on the sweep budget.
+# n = 70 and 100 use two wavefronts per child, n = 200 four.
 @pytest.mark.parametrize("n,hi,budget", [(2, 2.0, 3000), (3, 2.3, 3000), (5, 2.3, 3000), (8, 2.3, 3000),
-                                         (12, 2.3, 3000), (13, 2.0, 150)])
+                                         (12, 2.3, 3000), (13, 2.0, 150), (70, 2.0, 3000), (100, 2.3, 30),
+                                         (200, 2.3, 20)])
 def test_chain_identical_iteration(n, hi, budget):
     p = PR.chain(n, 505, hi=hi)
     r, o = run_both(p, max_sweeps=budget)
@@ -78,6 +80,11 @@ def test_budget_and_width_criterion():
     r = ibb.minimize(p, max_sweeps=4)
     assert r.status == ibb.NOT_CONVERGED and r.sweeps == 4
     assert r.f_lo <= 0.0 <= r.f_hi and inside_some_box(p.x_star, r.lo, r.hi)
+    # a time limit stops on the host between chunks; the last children are still inserted
+    r = ibb.minimize(p, time_limit_s=1e-9)
+    assert r.status == ibb.NOT_CONVERGED and r.sweeps >= 1
+    assert r.f_lo <= 0.0 <= r.f_hi and inside_some_box(p.x_star, r.lo, r.hi)
+    assert r.trace_nsurv.sum() + 1 - r.sweeps >= r.n_boxes
     p.tol_x = 1e-4
     r = ibb.minimize(p, max_sweeps=20000)
     assert r.status == ibb.OK and np.all(r.hi - r.lo < 1e-4)
