@@ -42,10 +42,16 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--cpu-sweeps", type=int, default=30, help="oracle prefix for the CPU baseline (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=128, help="requests in the serving trace (0 = skip)")
+    ap.add_argument("--fp32-steps", type=int, default=5, help="solves of the same workload with the FP32 filter (0 = skip)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates the HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: this library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         return 2
+    if args.copy_probe > 0:
+        return copy_probe(args.copy_probe)
 
     import numpy as np
     import torch
@@ -92,6 +98,26 @@ def main() -> int:
                "sample": f"first {o.sweeps} sweeps of the same workload ({o.boxes_evaluated} boxes, {tcpu:.1f} s, "
                          f"single thread, fesetround per endpoint operation)"}
 
+    fp32 = None
+    if args.fp32_steps > 0:
+        ibb.minimize(p, fetch_boxes=False, precision="fp32_bulk")
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r32 = [ibb.minimize(p, fetch_boxes=False, precision="fp32_bulk", profile=True) for _ in range(args.fp32_steps)]
+        torch.cuda.synchronize()
+        d32 = time.perf_counter() - t2
+        for r in r32:
+            assert r.status == ibb.OK and r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6, (r.f_lo, r.f_hi)
+        q = r32[-1]
+        fp32 = {"boxes_per_s": round(sum(r.boxes_evaluated for r in r32) / d32, 1),
+                "ms_per_solve": round(d32 / args.fp32_steps * 1e3, 4),
+                "sweeps": q.sweeps, "boxes_per_solve": q.boxes_evaluated,
+                "fp32_pruned": q.fp32_pruned, "fp64_confirmed": q.fp64_confirmed, "fp32_sweeps": q.fp32_sweeps,
+                "bound_avg_launch_us": round(q.t_bound_ms * 1e3 / max(1, q.n_bound_launches), 3),
+                "enclosure": [q.f_lo, q.f_hi]}
+
+    serving = serve_bench(args.serve_requests) if args.serve_requests > 0 else None
+
     line = {
         "metric": "boxes/sec and time-to-enclosure (width 1e-6); served problems/sec + p50/p99",
         "value": round(boxes / dt, 1),
@@ -111,12 +137,97 @@ def main() -> int:
             "time_to_enclosure_ms": round(float(np.median([r.seconds for r in res])) * 1e3, 4),
             "sweeps": r0.sweeps, "boxes_per_solve": r0.boxes_evaluated,
             "enclosure": [r0.f_lo, r0.f_hi],
+            "fp32_bulk": fp32,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def copy_probe(mib: int) -> int:
+    """A plain device-to-device copy of `mib` MiB, for scaling the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4}), flush=True)
+    return 0
+
+
+SERVE_MAX_SWEEPS = 500     # per-request sweep budget (some chained requests do not converge quickly)
+
+
+def serve_bench(count: int) -> dict:
+    """Serving workload: `count` requests (n log-uniform in [2, 2000], family uniform over the
+    three, seeded coefficients), enclosure width 1e-6, at most SERVE_MAX_SWEEPS sweeps each.
+    1) closed loop: all requests submitted at once -> capacity mu (problems/s);
+    2) Poisson arrivals at 0.8 mu through the continuous-batching server -> problems/s, p50/p99
+       of completion - arrival;
+    3) the same arrivals served one at a time, FIFO, by ibb_solve (plain FP64, no batching)."""
+    import numpy as np
+    import paper_2507_01770_amd as ibb
+    from paper_2507_01770_amd import problems as PR
+
+    reqs = PR.serving_trace(count=count, seed=105, rate=1.0)
+    probs = [p for _, p in reqs]
+    gaps = np.array([t for t, _ in reqs])
+    gaps = np.diff(np.concatenate([[0.0], gaps]))          # unit-rate exponential gaps
+
+    def run_server(arrivals):
+        with ibb.Server(mem_budget_bytes=64 << 30, max_slots=64) as srv:
+            t0 = time.perf_counter()
+            tickets, t_arr, done = [], [], {}
+            i = 0
+            while len(done) < len(probs):
+                now = time.perf_counter() - t0
+                while i < len(probs) and arrivals[i] <= now:
+                    tickets.append(srv.submit(probs[i], max_sweeps=SERVE_MAX_SWEEPS))
+                    t_arr.append(arrivals[i])
+                    i += 1
+                for k, t in enumerate(tickets):
+                    if t not in done:
+                        r = srv.poll(t)
+                        if r is not None:
+                            done[t] = (time.perf_counter() - t0, r.status)
+                time.sleep(0.0002)
+            st = srv.stats()
+        lat = np.array([done[t][0] - a for t, a in zip(tickets, t_arr)])
+        makespan = max(v[0] for v in done.values()) - arrivals[0]
+        ok = sum(v[1] == ibb.OK for v in done.values())
+        return lat, makespan, ok, st
+
+    lat0, span0, ok0, st0 = run_server(np.zeros(len(probs)))
+    mu = len(probs) / span0
+    lam = 0.8 * mu
+    arrivals = np.cumsum(gaps) / lam
+    lat, span, ok, st = run_server(arrivals)
+    # one at a time, FIFO, same arrivals
+    t0 = time.perf_counter()
+    free_at, lat1 = 0.0, []
+    for a, p in zip(arrivals, probs):
+        start = max(a, free_at)
+        while time.perf_counter() - t0 < start:
+            time.sleep(0.0002)
+        ibb.minimize(p, max_sweeps=SERVE_MAX_SWEEPS, fetch_boxes=False)
+        free_at = time.perf_counter() - t0
+        lat1.append(free_at - a)
+    lat1 = np.array(lat1)
+    span1 = free_at - arrivals[0]
+    return {
+        "requests": len(probs), "max_sweeps_per_request": SERVE_MAX_SWEEPS, "converged": int(ok),
+        "capacity_problems_per_s": round(mu, 2), "arrival_rate": round(lam, 2),
+        "problems_per_s": round(len(probs) / span, 2),
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2), "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+        "max_concurrent": st["max_active"],
+        "one_at_a_time": {"problems_per_s": round(len(probs) / span1, 2),
+                          "p50_ms": round(float(np.percentile(lat1, 50)) * 1e3, 2),
+                          "p99_ms": round(float(np.percentile(lat1, 99)) * 1e3, 2)},
+    }
 
 
 if __name__ == "__main__":

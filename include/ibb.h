@@ -58,6 +58,20 @@ typedef enum {
  * (or k/2 (x - c)), so the argument reduction is exact. */
 typedef enum { IBB_SEP_COS = 1, IBB_CHAIN = 2, IBB_SEP_ABS_SIN2 = 3 } ibb_family;
 
+/* IBB_FP64: every box is bounded in double precision, as in the paper's
+ * experiments (Sec. 4).
+ * IBB_FP32_BULK (an addition to the paper's method): a single-precision filter
+ * runs first on each child while it pays: the child's box is enclosed in
+ * floats, F and the first-order test are evaluated in single precision with
+ * outward rounding, and a child whose float lower bound exceeds the GUB at the
+ * start of the sweep, or that fails the float first-order test, is discarded
+ * without its double-precision bound.  Other children are bounded in FP64 as
+ * usual, and midpoint upper bounds are always FP64.  The filter runs in a sweep
+ * only while it discards at least half of the children (after a sweep where it
+ * discarded less it is off for 2, 4, ..., 64 sweeps, and it is turned on when
+ * half of an FP64 sweep's children were discarded); it stays off for problems
+ * whose magnitudes could overflow single precision.  Results remain rigorous
+ * and deterministic but are not the FP64 run's bit for bit. */
 typedef enum { IBB_FP64 = 0, IBB_FP32_BULK = 1 } ibb_precision;
 
 typedef struct {
@@ -80,7 +94,11 @@ typedef struct {
   int64_t max_live_boxes;/* budget on the live list; default 1<<26 */
   double time_limit_s;   /* budget; <= 0 means none; default 0 */
   int32_t profile;       /* 1: time every sweep kernel with HIP events (ibb_info t_* fields); default 0 */
-  int32_t reserved;
+  int32_t bound_shape;   /* 0 (default): the autotuner picks the bound kernel's shape; k = 1..5 forces
+                            shape k-1 (W waves per child, concurrent midpoint waves or not):
+                            0 {1, yes}, 1 {2, yes}, 2 {1, no}, 3 {2, no}, 4 {4, no}.  Every shape gives
+                            the same results; IBB_E_INVALID for a shape with concurrent midpoint
+                            waves under IBB_FP32_BULK or with W above ceil(n / 64) */
 } ibb_options;
 
 typedef struct {
@@ -94,16 +112,18 @@ typedef struct {
   int64_t n_boxes;            /* live boxes at the end (lower bound <= GUB) */
   int64_t sweeps;             /* iterations run */
   int64_t boxes_evaluated;    /* children bounded, plus the root */
-  int64_t fp32_pruned;        /* children discarded by the FP32 filter */
-  int64_t fp64_confirmed;     /* children bounded in FP64 */
+  int64_t fp32_pruned;        /* children discarded by the FP32 filter (no FP64 bound formed) */
+  int64_t fp64_confirmed;     /* boxes bounded in FP64 (boxes_evaluated - fp32_pruned) */
   double seconds;             /* wall time of ibb_solve */
   int32_t status;             /* IBB_OK or IBB_NOT_CONVERGED */
-  int32_t reserved;
+  int32_t fp32_sweeps;        /* sweeps in which the FP32 filter ran */
   int64_t ub_evaluated;       /* children whose midpoint upper bound was computed */
   /* filled when options.profile = 1: summed kernel times (ms) and launch counts of
      the sweeps that ran (launches after the stop are not counted) */
   double t_bound_ms, t_select_ms;
   int64_t n_bound_launches, n_select_launches;
+  int32_t bound_shape;        /* shape of the bound kernel used (0..4, see ibb_options) */
+  int32_t pad;
 } ibb_info;
 
 typedef struct ibb_result ibb_result;
@@ -141,8 +161,10 @@ void ibb_result_free(ibb_result* res);
  * bound of f at the box midpoint (0.5 lo + 0.5 hi rounded up), d_mono_prune[nb]
  * 1 when the first-order test of Sec. 3.1 discards the box (some DLB_j > 0 with
  * x_j^lo != l_j, or some DUB_j < 0 with x_j^hi != u_j), and d_G (may be NULL)
- * [nb][n][2] the enclosures of the partial derivatives.  precision must be
- * IBB_FP64 here. */
+ * [nb][n][2] the enclosures of the partial derivatives.  With precision
+ * IBB_FP32_BULK, F, the test and G are the single-precision filter's (over the
+ * box enclosed in floats, converted exactly to double) and d_ub_mid stays FP64;
+ * IBB_E_INVALID if the magnitudes could overflow single precision. */
 ibb_status ibb_eval_boxes(const ibb_problem* prob, int32_t precision, int64_t nb, const double* d_lo,
                           const double* d_hi, double* d_F, double* d_ub_mid, uint8_t* d_mono_prune,
                           double* d_G, void* hip_stream);
@@ -159,6 +181,56 @@ ibb_status ibb_interval_op(int32_t op, int64_t count, const double* d_a, const d
 /* Point enclosures: d_out[count][2] receives [lo, hi] around cos(2 pi y)
  * (fn = 0) or sin(2 pi y) (fn = 1) for each double d_y[i]. */
 ibb_status ibb_point_trig(int32_t fn, int64_t count, const double* d_y, double* d_out, void* hip_stream);
+
+/* Single-precision counterparts, for testing the FP32 filter's arithmetic
+ * (round-up mode on the negated lower endpoint, so +, -, x and sqr give the
+ * tightest float enclosure).  d_a, d_b, d_out: device float [count][2] (lo, hi).
+ * op as in ibb_interval_op, restricted to 0 add, 1 sub, 2 mul, 5 sqr, 6 abs,
+ * 8 cos(2 pi a), 9 sin(2 pi a), 10 derivative of |.| (others: IBB_E_INVALID). */
+ibb_status ibb_interval_op32(int32_t op, int64_t count, const float* d_a, const float* d_b, float* d_out,
+                             void* hip_stream);
+/* d_out[count][2] (float) receives [lo, hi] around cos(2 pi y) (fn = 0) or
+ * sin(2 pi y) (fn = 1) for each float d_y[i]. */
+ibb_status ibb_point_trig32(int32_t fn, int64_t count, const float* d_y, float* d_out, void* hip_stream);
+
+/* ---- many problems at once ------------------------------------------------
+ * Problems solved together share each sweep's two kernel launches: the
+ * selection runs one workgroup per problem, the bounds one wavefront per child
+ * of every problem (any mix of families and sizes).  Each problem keeps its own
+ * list, rows and GUB and follows exactly the iteration ibb_solve runs for it,
+ * so its result is the same bit for bit alone or in any mix. */
+
+/* Solve count problems together.  outs[i] receives problem i's result (NULL if
+ * it failed; free each with ibb_result_free) and statuses[i] its status
+ * (IBB_OK, IBB_NOT_CONVERGED or an error).  The call returns IBB_OK unless the
+ * batch itself could not run; it synchronises hip_stream. */
+ibb_status ibb_solve_batch(const ibb_problem* probs, int32_t count, const ibb_options* opts,
+                           const ibb_allocator* alloc, void* hip_stream, ibb_result** outs, int32_t* statuses);
+
+/* Continuous-batching server.  A host thread owned by the server runs batched
+ * sweeps over the admitted problems in chunks of 8 sweeps (each chunk replayed
+ * as a captured HIP graph while the set of problems is unchanged).  Between
+ * chunks it retires finished problems and admits queued ones while a slot is
+ * free (at most max_slots at once) and the device memory in use plus the new
+ * problem's starting footprint stays within mem_budget_bytes.  All device work
+ * goes to hip_stream (the caller keeps it alive until ibb_server_destroy and
+ * until the last result from this server is freed). */
+typedef struct ibb_server ibb_server;
+ibb_status ibb_server_create(size_t mem_budget_bytes, int32_t max_slots, const ibb_allocator* alloc,
+                             void* hip_stream, ibb_server** out);
+/* Copy a problem into the queue; *ticket identifies it.  Per-problem time limits
+ * are not applied by the server (sweep and list budgets are).  IBB_E_CAPACITY if
+ * the problem alone exceeds the memory budget. */
+ibb_status ibb_server_submit(ibb_server* srv, const ibb_problem* prob, const ibb_options* opts, uint64_t* ticket);
+/* IBB_PENDING while the problem is queued or running; once it has finished, the
+ * call hands over the result (*out, owned by the caller) and returns its status;
+ * a ticket is handed over once. */
+ibb_status ibb_server_poll(ibb_server* srv, uint64_t ticket, ibb_result** out);
+/* Counters: problems admitted, completed, the largest number run at once, queued now. */
+ibb_status ibb_server_stats(ibb_server* srv, int64_t* admitted, int64_t* completed, int64_t* max_active,
+                            int64_t* queued);
+/* Stop the thread, drop problems still queued or running, free unclaimed results. */
+ibb_status ibb_server_destroy(ibb_server* srv);
 
 const char* ibb_status_string(ibb_status s);
 const char* ibb_last_error(void);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libibb.so")
 
 SEP_COS, CHAIN, SEP_ABS_SIN2 = 1, 2, 3
 FP64, FP32_BULK = 0, 1
-OK, NOT_CONVERGED = 0, 1
+OK, NOT_CONVERGED, PENDING = 0, 1, 2
 OPS = dict(add=0, sub=1, mul=2, div=3, sqrt=4, sqr=5, abs=6, recip=7, cos2pi=8, sin2pi=9, dabs=10)
 
 
@@ -38,7 +38,7 @@ class _Problem(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("split_dims", C.c_int32), ("select_k", C.c_int32),
                 ("deterministic", C.c_int32), ("max_sweeps", C.c_int64), ("max_live_boxes", C.c_int64),
-                ("time_limit_s", C.c_double), ("profile", C.c_int32), ("reserved", C.c_int32)]
+                ("time_limit_s", C.c_double), ("profile", C.c_int32), ("bound_shape", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -52,9 +52,10 @@ class _Allocator(C.Structure):
 class _Info(C.Structure):
     _fields_ = [("f_lo", C.c_double), ("f_hi", C.c_double), ("n_boxes", C.c_int64), ("sweeps", C.c_int64),
                 ("boxes_evaluated", C.c_int64), ("fp32_pruned", C.c_int64), ("fp64_confirmed", C.c_int64),
-                ("seconds", C.c_double), ("status", C.c_int32), ("reserved", C.c_int32),
+                ("seconds", C.c_double), ("status", C.c_int32), ("fp32_sweeps", C.c_int32),
                 ("ub_evaluated", C.c_int64), ("t_bound_ms", C.c_double), ("t_select_ms", C.c_double),
-                ("n_bound_launches", C.c_int64), ("n_select_launches", C.c_int64)]
+                ("n_bound_launches", C.c_int64), ("n_select_launches", C.c_int64),
+                ("bound_shape", C.c_int32), ("pad", C.c_int32)]
 
 
 _lib = None
@@ -79,14 +80,32 @@ def lib():
     L.ibb_eval_boxes.argtypes = [C.POINTER(_Problem), i32, i64, vp, vp, vp, vp, vp, vp, vp]
     L.ibb_interval_op.argtypes = [i32, i64, vp, vp, vp, vp]
     L.ibb_point_trig.argtypes = [i32, i64, vp, vp, vp]
+    L.ibb_interval_op32.argtypes = [i32, i64, vp, vp, vp, vp]
+    L.ibb_point_trig32.argtypes = [i32, i64, vp, vp, vp]
     L.ibb_status_string.restype = C.c_char_p
     L.ibb_status_string.argtypes = [C.c_int]
     L.ibb_last_error.restype = C.c_char_p
+    L.ibb_solve_batch.argtypes = [C.POINTER(_Problem), i32, C.POINTER(_Options), C.POINTER(_Allocator), vp,
+                                  C.POINTER(vp), C.POINTER(i32)]
+    L.ibb_server_create.argtypes = [C.c_size_t, i32, C.POINTER(_Allocator), vp, C.POINTER(vp)]
+    L.ibb_server_submit.argtypes = [vp, C.POINTER(_Problem), C.POINTER(_Options), C.POINTER(C.c_uint64)]
+    L.ibb_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
+    L.ibb_server_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.ibb_server_destroy.argtypes = [vp]
     for f in ["ibb_options_default", "ibb_solve", "ibb_result_info", "ibb_result_boxes", "ibb_result_trace",
-              "ibb_eval_boxes", "ibb_interval_op", "ibb_point_trig"]:
+              "ibb_eval_boxes", "ibb_interval_op", "ibb_point_trig", "ibb_interval_op32", "ibb_point_trig32",
+              "ibb_solve_batch", "ibb_server_create",
+              "ibb_server_submit", "ibb_server_poll", "ibb_server_stats", "ibb_server_destroy"]:
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
+
+
+def _prec(p) -> int:
+    """precision as FP64 / FP32_BULK or the names 'fp64' / 'fp32_bulk'."""
+    if isinstance(p, str):
+        return {"fp64": FP64, "fp32_bulk": FP32_BULK}[p]
+    return int(p)
 
 
 def _check(rc: int, ok=(OK,)):
@@ -180,9 +199,31 @@ def point_trig(fn: str, y, stream=None):
     return out
 
 
-def eval_boxes(problem, lo, hi, want_grad=False, stream=None):
+def interval_op32(op: str, a, b=None, stream=None):
+    """Single-precision interval op on device float tensors [count, 2] (lo, hi)."""
+    torch = _torch()
+    a = a.to(device="cuda", dtype=torch.float32).contiguous()
+    bb = None if b is None else b.to(device="cuda", dtype=torch.float32).contiguous()
+    out = torch.empty_like(a)
+    _check(lib().ibb_interval_op32(OPS[op], a.shape[0], C.c_void_p(a.data_ptr()),
+                                   None if bb is None else C.c_void_p(bb.data_ptr()), C.c_void_p(out.data_ptr()),
+                                   _stream_ptr(stream)))
+    return out
+
+
+def point_trig32(fn: str, y, stream=None):
+    """Float [lo, hi] around cos(2 pi y) or sin(2 pi y) for a device float tensor y."""
+    torch = _torch()
+    y = y.to(device="cuda", dtype=torch.float32).contiguous().reshape(-1)
+    out = torch.empty((y.shape[0], 2), dtype=torch.float32, device="cuda")
+    _check(lib().ibb_point_trig32(0 if fn == "cos2pi" else 1, y.shape[0], C.c_void_p(y.data_ptr()),
+                                  C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def eval_boxes(problem, lo, hi, want_grad=False, precision=FP64, stream=None):
     """Bound boxes lo, hi ([nb, n] device tensors).  Returns F [nb,2], ub [nb], mono [nb] (bool)
-    and, when want_grad, G [nb, n, 2]."""
+    and, when want_grad, G [nb, n, 2].  precision='fp32_bulk' gives the FP32 filter's F, test and G."""
     torch = _torch()
     k = _prob_args(problem)
     lo = lo.to(device="cuda", dtype=torch.float64).contiguous()
@@ -193,7 +234,7 @@ def eval_boxes(problem, lo, hi, want_grad=False, stream=None):
     mono = torch.empty(nb, dtype=torch.uint8, device="cuda")
     G = torch.empty((nb, lo.shape[1], 2), dtype=torch.float64, device="cuda") if want_grad else None
     vp = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
-    _check(lib().ibb_eval_boxes(C.byref(k.s), FP64, nb, vp(lo), vp(hi), vp(F), vp(ub), vp(mono),
+    _check(lib().ibb_eval_boxes(C.byref(k.s), _prec(precision), nb, vp(lo), vp(hi), vp(F), vp(ub), vp(mono),
                                 None if G is None else vp(G), _stream_ptr(stream)))
     return (F, ub, mono.bool(), G) if want_grad else (F, ub, mono.bool())
 
@@ -224,25 +265,35 @@ class Result:
     t_select_ms: float = 0.0
     n_bound_launches: int = 0
     n_select_launches: int = 0
+    fp32_pruned: int = 0           # children discarded by the FP32 filter
+    fp64_confirmed: int = 0        # boxes bounded in FP64
+    fp32_sweeps: int = 0           # sweeps in which the FP32 filter ran
+    bound_shape: int = -1          # shape of the bound kernel (0..4), picked by the autotuner unless forced
 
 
 def minimize(problem=None, *, family=None, coef=None, lower=None, upper=None, tol_f=None, tol_x=None,
              precision=FP64, split_dims=10, select_k=1, max_sweeps=1_000_000, max_live_boxes=1 << 26,
              time_limit_s=0.0, fetch_boxes=True, max_boxes_fetched=100_000, use_torch_allocator=True,
-             profile=False, stream=None) -> Result:
+             profile=False, bound_shape=None, stream=None) -> Result:
     """Enclose min f over [lower, upper]; returns [f_lo, f_hi] and the surviving boxes."""
     k = _prob_args(problem, family, coef, lower, upper, tol_f, tol_x)
     L = lib()
-    opts = _Options(precision, split_dims, select_k, 1, max_sweeps, max_live_boxes, time_limit_s, int(profile), 0)
+    opts = _Options(_prec(precision), split_dims, select_k, 1, max_sweeps, max_live_boxes, time_limit_s,
+                    int(profile), 0 if bound_shape is None else int(bound_shape) + 1)
     alloc = _TorchAllocator() if use_torch_allocator else None
     h = C.c_void_p()
     rc = L.ibb_solve(C.byref(k.s), C.byref(opts), C.byref(alloc.struct) if alloc else None, _stream_ptr(stream),
                      C.byref(h))
     _check(rc, ok=(OK, NOT_CONVERGED))
+    return _take_result(h, k.lower.shape[0], fetch_boxes, max_boxes_fetched)
+
+
+def _take_result(h, n, fetch_boxes=True, max_boxes_fetched=100_000) -> Result:
+    """Copy a result out of the library and free it."""
+    L = lib()
     try:
         info = _Info()
         _check(L.ibb_result_info(h, C.byref(info)))
-        n = k.lower.shape[0]
         nb = info.n_boxes
         nf = min(nb, max_boxes_fetched) if fetch_boxes else 0
         flo = np.empty(nb)
@@ -261,6 +312,76 @@ def minimize(problem=None, *, family=None, coef=None, lower=None, upper=None, to
         got = w.value
         return Result(info.f_lo, info.f_hi, info.status, info.sweeps, info.boxes_evaluated, nb, info.seconds,
                       lo, hi, flo, seq, tg[:got], tn[:got], tl[:got], tsel[:got], info.ub_evaluated,
-                      info.t_bound_ms, info.t_select_ms, info.n_bound_launches, info.n_select_launches)
+                      info.t_bound_ms, info.t_select_ms, info.n_bound_launches, info.n_select_launches,
+                      info.fp32_pruned, info.fp64_confirmed, info.fp32_sweeps, info.bound_shape)
     finally:
         L.ibb_result_free(h)
+
+
+def _options(precision=FP64, split_dims=10, select_k=1, max_sweeps=1_000_000, max_live_boxes=1 << 26,
+             time_limit_s=0.0):
+    return _Options(_prec(precision), split_dims, select_k, 1, max_sweeps, max_live_boxes, time_limit_s, 0, 0)
+
+
+def solve_batch(problems, *, fetch_boxes=True, max_boxes_fetched=100_000, stream=None, **opts) -> list:
+    """Solve several problems together (their sweeps share kernel launches).  Returns a
+    list of Result (or an IbbError instance for a problem that failed)."""
+    L = lib()
+    keeps = [_prob_args(p) for p in problems]
+    arr = (_Problem * len(keeps))(*[k.s for k in keeps])
+    o = _options(**opts)
+    outs = (C.c_void_p * len(keeps))()
+    sts = (C.c_int32 * len(keeps))()
+    _check(L.ibb_solve_batch(arr, len(keeps), C.byref(o), None, _stream_ptr(stream), outs, sts))
+    res = []
+    for i, k in enumerate(keeps):
+        if sts[i] in (OK, NOT_CONVERGED) and outs[i]:
+            res.append(_take_result(C.c_void_p(outs[i]), k.lower.shape[0], fetch_boxes, max_boxes_fetched))
+        else:
+            res.append(IbbError(f"problem {i}: {L.ibb_status_string(sts[i]).decode()}"))
+    return res
+
+
+class Server:
+    """Continuous-batching server (C++ thread inside libibb).  submit() returns a
+    ticket; poll() returns None while the problem is pending, else its Result."""
+
+    def __init__(self, mem_budget_bytes=8 << 30, max_slots=64, stream=None):
+        torch = _torch()
+        self._stream = stream if stream is not None else torch.cuda.Stream()
+        self._h = C.c_void_p()
+        _check(lib().ibb_server_create(int(mem_budget_bytes), int(max_slots), None,
+                                       C.c_void_p(self._stream.cuda_stream), C.byref(self._h)))
+        self._n = {}
+
+    def submit(self, problem, **opts) -> int:
+        k = _prob_args(problem)
+        o = _options(**opts)
+        t = C.c_uint64()
+        _check(lib().ibb_server_submit(self._h, C.byref(k.s), C.byref(o), C.byref(t)))
+        self._n[t.value] = k.lower.shape[0]
+        return t.value
+
+    def poll(self, ticket, fetch_boxes=False, max_boxes_fetched=100_000):
+        out = C.c_void_p()
+        rc = lib().ibb_server_poll(self._h, C.c_uint64(ticket), C.byref(out))
+        if rc == PENDING:
+            return None
+        _check(rc, ok=(OK, NOT_CONVERGED))
+        return _take_result(out, self._n.pop(ticket), fetch_boxes, max_boxes_fetched)
+
+    def stats(self) -> dict:
+        v = [C.c_int64() for _ in range(4)]
+        _check(lib().ibb_server_stats(self._h, *[C.byref(x) for x in v]))
+        return dict(admitted=v[0].value, completed=v[1].value, max_active=v[2].value, queued=v[3].value)
+
+    def close(self):
+        if self._h:
+            _check(lib().ibb_server_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

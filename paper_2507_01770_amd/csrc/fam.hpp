@@ -90,3 +90,55 @@ __device__ __forceinline__ I chain_grad(const CoefChain& cprev, const CoefChain&
 }
 
 }  // namespace ibb
+
+// ---- the same trees in single precision (the FP32 filter) --------------------
+// Coefficients are enclosed in float intervals once per problem; k and k/2 are
+// exact (the filter is used only when every k_i <= 2^24).
+namespace ibb {
+
+struct alignas(16) CoefSep32 {
+  J a, b, c, pkb;      // [a] (or [s]), [b], [c], [2 pi k b] (or [pi k b])
+  float k, hk;         // k, k/2
+  float pad0, pad1;
+};
+struct alignas(16) CoefChain32 {
+  J al, be;            // [alpha_i], [beta_i] (zero past the last term)
+};
+
+template <int FAM>
+__device__ __forceinline__ void sep_box32(const CoefSep32& cf, J X, J& t, J& G) {
+  const J D = sub32(X, cf.c);
+  if (FAM == FAM_SEP_COS) {
+    const TrigIv32 cs = sincos2pi32(scale32(cf.k, D), true, true);
+    t = add32(mul32(cf.a, sqr32(D)), mul32(cf.b, s_sub32(1.0f, cs.c)));
+    G = add32(mul32(scale32(2.0f, cf.a), D), mul32(cf.pkb, cs.s));
+  } else {
+    const TrigIv32 sh = sincos2pi32(scale32(cf.hk, D), false, true);
+    t = add32(mul32(cf.a, abs32(D)), mul32(cf.b, sqr32(sh.s)));
+    const TrigIv32 sy = sincos2pi32(scale32(cf.k, D), false, true);
+    G = add32(mul32(cf.a, dabs32(D)), mul32(cf.pkb, sy.s));
+  }
+}
+
+__device__ __forceinline__ J chain_term32(const CoefChain32& cf, J Xi, J Xi1) {
+  const J R = sub32(Xi1, sqr32(Xi));
+  const J E = add32(Xi, J{1.0f, -1.0f});
+  return add32(mul32(cf.al, sqr32(R)), mul32(cf.be, sqr32(E)));
+}
+
+__device__ __forceinline__ J chain_grad32(const CoefChain32& cprev, const CoefChain32& cj, J Xp, J Xj, J Xn,
+                                          bool has_prev, bool has_next) {
+  J g{0.0f, 0.0f};
+  if (has_next) {
+    const J R = sub32(Xn, sqr32(Xj));
+    const J E = add32(Xj, J{1.0f, -1.0f});
+    g = add32(mul32(mul32(scale32(-4.0f, cj.al), Xj), R), mul32(scale32(2.0f, cj.be), E));
+  }
+  if (has_prev) {
+    const J B = mul32(scale32(2.0f, cprev.al), sub32(Xj, sqr32(Xp)));
+    g = has_next ? add32(g, B) : B;
+  }
+  return g;
+}
+
+}  // namespace ibb

@@ -6,9 +6,15 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <type_traits>
+#include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "ibb.h"
@@ -21,7 +27,8 @@ using namespace ibb;
 // ===========================================================================
 
 // per-coordinate coefficient records; [c pi k b] = [RD(c PI_LO k), RU(c PI_HI k)] * b
-__global__ void k_setup_sep(int n, int family, const double* __restrict__ coef, CoefSep* __restrict__ out) {
+__global__ void k_setup_sep(int n, int family, const double* __restrict__ coef, CoefSep* __restrict__ out,
+                            CoefSep32* __restrict__ out32) {
   round_up_mode();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -36,15 +43,29 @@ __global__ void k_setup_sep(int n, int family, const double* __restrict__ coef, 
   const I pk{mul_neg(sc * pl, r.k), (sc * ph) * r.k};
   r.pkb = mul(pk, point(r.b));
   out[i] = r;
+  if (out32) {
+    CoefSep32 q;
+    q.a = to32(point(r.a));
+    q.b = to32(point(r.b));
+    q.c = to32(point(r.c));
+    q.pkb = to32(r.pkb);
+    q.k = (float)r.k;        // exact: the filter is enabled only for k <= 2^24
+    q.hk = 0.5f * q.k;
+    q.pad0 = q.pad1 = 0.0f;
+    out32[i] = q;
+  }
 }
 
-__global__ void k_setup_chain(int n, const double* __restrict__ coef, CoefChain* __restrict__ out) {
+__global__ void k_setup_chain(int n, const double* __restrict__ coef, CoefChain* __restrict__ out,
+                              CoefChain32* __restrict__ out32) {
+  round_up_mode();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   CoefChain r;
   r.al = i < n - 1 ? coef[i] : 0.0;
   r.be = i < n - 1 ? coef[(n - 1) + i] : 0.0;
   out[i] = r;
+  if (out32) out32[i] = CoefChain32{to32(point(r.al)), to32(point(r.be))};
 }
 
 // bound nb boxes given by their real endpoints (one wavefront per box)
@@ -69,6 +90,39 @@ __global__ __launch_bounds__(kWave* kBoundWaves) void k_eval_boxes(const Params*
   if (lane == 0) {
     F[2 * b] = neg(Fb.n);
     F[2 * b + 1] = Fb.h;
+    ub[b] = u;
+    mono[b] = mo ? 1 : 0;
+  }
+}
+
+// the FP32 filter's bounds of nb boxes: F and the first-order test in single
+// precision over the FP32-enclosing box, the midpoint upper bound in FP64
+template <int FAM>
+__global__ __launch_bounds__(kWave* kBoundWaves) void k_eval_boxes32(const Params* __restrict__ PP, int64_t nb,
+                                                                    const double* __restrict__ lo,
+                                                                    const double* __restrict__ hi,
+                                                                    double* __restrict__ F, double* __restrict__ ub,
+                                                                    uint8_t* __restrict__ mono,
+                                                                    double* __restrict__ G) {
+  round_up_mode();
+  const Params P = *PP;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t b = (int64_t)blockIdx.x * kBoundWaves + (threadIdx.x >> 6);
+  if (b >= nb) return;
+  const PlainRow X{lo + b * P.n, hi + b * P.n};
+  J a32{0.0f, 0.0f};
+  bool m32 = false;
+  for (int i = lane; i < P.n; i += kWave) {
+    J t;
+    filter32_coord<FAM>(P, X, i, t, m32, G ? G + b * 2 * P.n : nullptr);
+    a32 = add32(a32, t);
+  }
+  const J F32 = fold32(a32, lane);
+  const bool mo = __any(m32);
+  const double u = point_ub<FAM>(P, X, lane);
+  if (lane == 0) {
+    F[2 * b] = (double)neg32(F32.n);
+    F[2 * b + 1] = (double)F32.h;
     ub[b] = u;
     mono[b] = mo ? 1 : 0;
   }
@@ -159,14 +213,19 @@ template <int NT>
 __device__ void insert_children(const Params& P, State* S, double gub, SelAcc& acc) {
   __shared__ int scan[NT];
   __shared__ int sformed[NT];
+  __shared__ int s_n32;
+  if (threadIdx.x == 0) s_n32 = 0;
+  __syncthreads();
   const int per = (P.nch + NT - 1) / NT;
   const int c0 = threadIdx.x * per, c1 = min(P.nch, c0 + per);
-  int mine = 0, nformed = 0;
+  int mine = 0, nformed = 0, n32 = 0;
   for (int k = c0; k < c1; ++k) {
     const uint8_t fl = P.ch_flag[k];
     nformed += fl != 0;
+    n32 += fl == 3;
     mine += (fl == 2 && !(P.ch_flo[k] > gub));
   }
+  if (n32) atomicAdd(&s_n32, n32);
   scan[threadIdx.x] = mine;
   sformed[threadIdx.x] = nformed;
   __syncthreads();
@@ -211,9 +270,27 @@ __device__ void insert_children(const Params& P, State* S, double gub, SelAcc& a
     }
     S->n_keys = base + total;
     S->next_seq = seq0 + total;
-    S->evaluated += sformed[NT - 1];
+    const int formed = sformed[NT - 1];
+    S->evaluated += formed;
     S->sweeps = t + 1;
     S->pending = 0;
+    if (P.prec32) {
+      // FP32 filter switch, from counts only (so the same for every run): keep it
+      // while it discards at least half of the children; after a sweep where it
+      // discarded less, turn it off for 2, 4, ..., 64 sweeps; turn it on when at
+      // least half of an FP64 sweep's children were discarded
+      if (S->use32) {
+        S->fp32_sweeps += 1;
+        S->fp32_pruned += s_n32;
+        if (2 * s_n32 < formed) {
+          S->use32 = 0;
+          S->p32_fails = min(S->p32_fails + 1, 6);
+          S->p32_resume = t + 1 + (1 << S->p32_fails);
+        }
+      } else if (t + 1 >= S->p32_resume && formed > 0 && 2 * (formed - total) >= formed) {
+        S->use32 = 1;
+      }
+    }
   }
   __syncthreads();
 }
@@ -240,6 +317,7 @@ __device__ void select_finish(const Params& P, State* S, const SelAcc& tot, doub
     if (go) {
       P.key_flo[b.idx] = __builtin_inf();     // removed from the list
       S->sel_seq = b.s;
+      S->gub_start = gub;
       S->pending = 1;                         // the bound kernel will produce children
     }
   }
@@ -322,11 +400,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_part(const Params* __res
 // the children written by k_bound and the partials visible: no device-scope
 // fences are needed.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_select(const Params* __restrict__ PP, State* __restrict__ S, int nparts,
-                                               int host_stop) {
-  round_up_mode();
-  if (S->stop) return;
-  const Params P = *PP;
+__device__ void select_body(const Params& P, State* S, int nparts, int host_stop) {
   const double gub = okey_inv(S->gub_key);
   SelAcc a = sel_empty();
   if (nparts == 0) {
@@ -351,6 +425,15 @@ __global__ __launch_bounds__(NT) void k_select(const Params* __restrict__ PP, St
   select_finish<NT>(P, S, a, gub);
 }
 
+template <int NT>
+__global__ __launch_bounds__(NT) void k_select(const Params* __restrict__ PP, State* __restrict__ S, int nparts,
+                                               int host_stop) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params P = *PP;
+  select_body<NT>(P, S, nparts, host_stop);
+}
+
 // Bound the children of the selected box.
 //
 // W "box" wavefronts share one child: in round rd, wave w computes the terms of
@@ -365,18 +448,14 @@ __global__ __launch_bounds__(NT) void k_select(const Params* __restrict__ PP, St
 // afterwards, and only when F.lo does not exceed the running GUB (a child whose
 // lower bound exceeds GUB cannot lower it).  Both give the same GUB.
 template <int FAM, int W, int CONC>
-__global__ __launch_bounds__(kWave* kBoundWaves) void k_bound(const Params* __restrict__ PP, State* __restrict__ S) {
-  round_up_mode();
-  if (S->stop) return;
-  const Params P = *PP;
+__device__ void bound_body(const Params& P, State* S, int cbase) {
   constexpr int WPC = CONC ? 2 * W : W;     // wavefronts per child
-  constexpr int CPB = kBoundWaves / WPC;    // children per workgroup
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
   const int local = wid / WPC, role_w = wid % WPC;
   const bool mid_role = CONC && role_w >= W;
   const int w = role_w % W;
   const int first = local * WPC + (mid_role ? W : 0);   // wave slot of this role's wave 0
-  const int c = blockIdx.x * CPB + local;
+  const int c = cbase + local;
   const int row = S->sel_row;
   const uint32_t mask = S->sel_mask;
   const bool formed = c < P.nch && (((uint32_t)c & ~mask) == 0u);
@@ -388,6 +467,53 @@ __global__ __launch_bounds__(kWave* kBoundWaves) void k_bound(const Params* __re
   __shared__ int s_flag[kBoundWaves];
   __shared__ double s_wm[kBoundWaves];
 
+  // ---- pass 0 (FP32 filter, throughput mode only): a single-precision lower
+  // bound over the FP32-enclosing box and the first-order test.  r32 = 2: the
+  // bound exceeds the GUB at the start of the sweep (no FP64 work at all);
+  // r32 = 1: the first-order test discards the child (FP64 midpoint bound only);
+  // r32 = 0: bound the child in FP64 as usual.
+  int r32 = 0;
+  if (!CONC && P.prec32 && S->use32) {
+    // same canonical order as the FP64 sum (slot = lane, rounds left to right,
+    // then the wave fold), so the filter's decisions do not depend on W
+    __shared__ float l32n[kBoundWaves][kWave], l32h[kBoundWaves][kWave];
+    __shared__ int s_r32[kBoundWaves];
+    J a32{0.0f, 0.0f};
+    bool m32 = false;
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int i = (rd * W + w) * kWave + lane;
+      J t{0.0f, 0.0f};
+      if (formed && i < n) filter32_coord<FAM>(P, X, i, t, m32);
+      if (W == 1) {
+        a32 = add32(a32, t);
+      } else {
+        l32n[wid][lane] = t.n;
+        l32h[wid][lane] = t.h;
+        __syncthreads();
+        if (w == 0)
+          for (int k = 0; k < W; ++k) a32 = add32(a32, J{l32n[first + k][lane], l32h[first + k][lane]});
+        __syncthreads();
+      }
+    }
+    const bool any32 = __any(m32);
+    if (W == 1) {
+      const J F32 = fold32(a32, lane);
+      if (formed) r32 = ((double)neg32(F32.n) > S->gub_start) ? 2 : (any32 ? 1 : 0);
+    } else {
+      if (lane == 0) s_flag[wid] = any32;
+      __syncthreads();
+      if (w == 0) {
+        const J F32 = fold32(a32, lane);
+        bool any = false;
+        for (int k = 0; k < W; ++k) any = any || s_flag[first + k];
+        if (lane == 0) s_r32[local] = formed ? (((double)neg32(F32.n) > S->gub_start) ? 2 : (any ? 1 : 0)) : 0;
+      }
+      __syncthreads();
+      r32 = s_r32[local];
+    }
+  }
+  const bool run64 = formed && r32 == 0;
+
   I acc{0.0, 0.0};
   double hacc = 0.0;
   bool mo = false;
@@ -396,7 +522,7 @@ __global__ __launch_bounds__(kWave* kBoundWaves) void k_bound(const Params* __re
   for (int rd = 0; rd < rounds; ++rd) {
     const int i = (rd * W + w) * kWave + lane;
     I t{0.0, 0.0};
-    if (formed && i < n) {
+    if ((mid_role ? formed : run64) && i < n) {
       if (mid_role) {
         if (FAM != FAM_CHAIN) t.h = sep_point_hi<FAM>(P.sep[i], midpoint(X.get(i)));
         else if (i + 1 < n) {
@@ -459,13 +585,13 @@ __global__ __launch_bounds__(kWave* kBoundWaves) void k_bound(const Params* __re
       __syncthreads();
       if (w == 0 && lane == 0) {
         const double gcur = okey_inv(__hip_atomic_load(&S->gub_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        s_flag[local] = formed && !(flo > gcur);
+        s_flag[local] = formed && (r32 == 1 || (r32 == 0 && !(flo > gcur)));
       }
       __syncthreads();
       do_ub = s_flag[local] != 0;
     } else {
       const double gcur = okey_inv(__hip_atomic_load(&S->gub_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      do_ub = formed && !(flo > gcur);
+      do_ub = formed && (r32 == 1 || (r32 == 0 && !(flo > gcur)));
     }
     for (int rd = 0; rd < rounds; ++rd) {
       const int i = (rd * W + w) * kWave + lane;
@@ -496,9 +622,13 @@ __global__ __launch_bounds__(kWave* kBoundWaves) void k_bound(const Params* __re
             atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(u + 0.0));
             atomicAdd((unsigned long long*)&S->ub_evaluated, 1ull);
           }
-          P.ch_flo[c] = flo;
-          P.ch_flag[c] = cmo ? 1 : 2;
-          P.ch_wmax[c] = cwm;
+          if (r32) {
+            P.ch_flag[c] = 3;
+          } else {
+            P.ch_flo[c] = flo;
+            P.ch_flag[c] = cmo ? 1 : 2;
+            P.ch_wmax[c] = cwm;
+          }
         } else {
           P.ch_flag[c] = 0;   // takes the upper half of a coordinate that cannot be split
         }
@@ -521,6 +651,15 @@ __global__ __launch_bounds__(kWave* kBoundWaves) void k_bound(const Params* __re
       }
     }
   }
+}
+
+template <int FAM, int W, int CONC>
+__global__ __launch_bounds__(kWave* kBoundWaves) void k_bound(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  if (S->stop) return;
+  constexpr int CPB = kBoundWaves / (CONC ? 2 * W : W);   // children per workgroup
+  const Params P = *PP;
+  bound_body<FAM, W, CONC>(P, S, blockIdx.x * CPB);
 }
 
 // count live keys (lower bound <= GUB) and the smallest lower bound
@@ -636,6 +775,38 @@ __global__ void k_interval_op(int op, int64_t cnt, const double* __restrict__ a,
   out[2 * i + 1] = r.h;
 }
 
+__global__ void k_interval_op32(int op, int64_t cnt, const float* __restrict__ a, const float* __restrict__ b,
+                                float* __restrict__ out) {
+  round_up_mode();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const J x{neg32(a[2 * i]), a[2 * i + 1]};
+  const J y = b ? J{neg32(b[2 * i]), b[2 * i + 1]} : J{0.0f, 0.0f};
+  J r;
+  switch (op) {
+    case 0: r = add32(x, y); break;
+    case 1: r = sub32(x, y); break;
+    case 2: r = mul32(x, y); break;
+    case 5: r = sqr32(x); break;
+    case 6: r = abs32(x); break;
+    case 8: r = sincos2pi32(x, true, false).c; break;
+    case 9: r = sincos2pi32(x, false, true).s; break;
+    default: r = dabs32(x); break;
+  }
+  out[2 * i] = neg32(r.n);
+  out[2 * i + 1] = r.h;
+}
+
+__global__ void k_point_trig32(int fn, int64_t cnt, const float* __restrict__ y, float* __restrict__ out) {
+  round_up_mode();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const TrigEnc32 e = sincos2pi_point32(y[i]);
+  const J r = fn == 0 ? e.c : e.s;
+  out[2 * i] = neg32(r.n);
+  out[2 * i + 1] = r.h;
+}
+
 __global__ void k_point_trig(int fn, int64_t cnt, const double* __restrict__ y, double* __restrict__ out) {
   round_up_mode();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -737,8 +908,34 @@ T* dalloc(Mem& M, int64_t count) {
   return static_cast<T*>(M.get((size_t)std::max<int64_t>(count, 1) * sizeof(T)));
 }
 
-// coefficient tables and bounds on the device
-ibb_status upload_problem(Mem& M, const ibb_problem* p, Params& P) {
+// Whether single-precision evaluation cannot overflow: every intermediate of the
+// FP32 trees, bounded from the coefficient and domain magnitudes, stays below
+// 2^120 (and k_i <= 2^24 is exact in float).  Otherwise the filter stays off.
+bool fp32_safe(const ibb_problem* p) {
+  const int n = p->n;
+  double B = 0.0;
+  for (int i = 0; i < n; ++i) B = std::max(B, std::max(std::fabs(p->lower[i]), std::fabs(p->upper[i])));
+  const double lim = std::ldexp(1.0, 120) / (4.0 * n + 4.0);
+  double worst = 0.0;
+  if (p->family == IBB_CHAIN) {
+    for (int i = 0; i < n - 1; ++i) {
+      const double al = std::fabs(p->coef[i]), be = std::fabs(p->coef[(n - 1) + i]);
+      const double R = B + B * B, E = B + 1.0;
+      worst = std::max({worst, al * R * R + be * E * E, 4.0 * al * B * R + 2.0 * be * E + 2.0 * al * R, R * R});
+    }
+  } else {
+    for (int i = 0; i < n; ++i) {
+      const double a = std::fabs(p->coef[i]), b = std::fabs(p->coef[n + i]), k = p->coef[2 * n + i];
+      const double D = B + std::fabs(p->coef[3 * n + i]);
+      if (k > 16777216.0) return false;
+      worst = std::max({worst, a * D * D + a * D + 2.0 * b, 2.0 * a * D + 7.0 * k * b, k * D, D * D});
+    }
+  }
+  return worst < lim;
+}
+
+// coefficient tables and bounds on the device; the float tables only with want32
+ibb_status upload_problem(Mem& M, const ibb_problem* p, Params& P, bool want32 = false) {
   const int n = p->n;
   P.family = p->family;
   P.n = n;
@@ -755,17 +952,25 @@ ibb_status upload_problem(Mem& M, const ibb_problem* p, Params& P) {
   P.u = d_u;
   P.sep = nullptr;
   P.chain = nullptr;
+  P.sep32 = nullptr;
+  P.chain32 = nullptr;
+  P.prec32 = want32 ? 1 : 0;
+  P.pad32 = 0;
   const int blocks = (n + 255) / 256;
   if (p->family == IBB_CHAIN) {
     CoefChain* c = dalloc<CoefChain>(M, n);
-    if (!c) return fail(IBB_E_NOMEM, "device allocation failed");
-    hipLaunchKernelGGL(k_setup_chain, dim3(blocks), dim3(256), 0, M.stream, n, d_coef, c);
+    CoefChain32* c32 = want32 ? dalloc<CoefChain32>(M, n) : nullptr;
+    if (!c || (want32 && !c32)) return fail(IBB_E_NOMEM, "device allocation failed");
+    hipLaunchKernelGGL(k_setup_chain, dim3(blocks), dim3(256), 0, M.stream, n, d_coef, c, c32);
     P.chain = c;
+    P.chain32 = c32;
   } else {
     CoefSep* c = dalloc<CoefSep>(M, n);
-    if (!c) return fail(IBB_E_NOMEM, "device allocation failed");
-    hipLaunchKernelGGL(k_setup_sep, dim3(blocks), dim3(256), 0, M.stream, n, p->family, d_coef, c);
+    CoefSep32* c32 = want32 ? dalloc<CoefSep32>(M, n) : nullptr;
+    if (!c || (want32 && !c32)) return fail(IBB_E_NOMEM, "device allocation failed");
+    hipLaunchKernelGGL(k_setup_sep, dim3(blocks), dim3(256), 0, M.stream, n, p->family, d_coef, c, c32);
     P.sep = c;
+    P.sep32 = c32;
   }
   HIPCHK(hipGetLastError());
   // nl (host) must outlive its copy; d_coef is not needed after the setup kernel
@@ -855,71 +1060,39 @@ ibb_status compact_keys(Mem& M, Params& P, Params* dP, State* dS, int64_t nk, in
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-ibb_status ibb_options_default(ibb_options* o) {
-  if (!o) return fail(IBB_E_INVALID, "options is NULL");
-  o->precision = IBB_FP64;
-  o->split_dims = 10;
-  o->select_k = 1;
-  o->deterministic = 1;
-  o->max_sweeps = 1000000;
-  o->max_live_boxes = (int64_t)1 << 26;
-  o->time_limit_s = 0.0;
-  o->profile = 0;
-  o->reserved = 0;
-  return IBB_OK;
-}
+// One problem in flight: its result object (which owns the device memory), where
+// its Params and State live on the device, and the host's view of its progress.
+struct Run {
+  ibb_result* R = nullptr;
+  Params* dP = nullptr;
+  State* dS = nullptr;
+  ibb_options opts{};
+  int64_t n_keys = 1, sweeps = 0;
+  bool pending = false;
+  State hs{};
+  std::chrono::steady_clock::time_point t0;
+};
 
-const char* ibb_status_string(ibb_status s) {
-  switch (s) {
-    case IBB_OK: return "ok";
-    case IBB_NOT_CONVERGED: return "not converged (budget reached; enclosure still rigorous)";
-    case IBB_PENDING: return "pending";
-    case IBB_E_INVALID: return "invalid argument";
-    case IBB_E_NOMEM: return "out of memory";
-    case IBB_E_DEVICE: return "device error";
-    case IBB_E_CAPACITY: return "capacity exceeded";
-    case IBB_E_INTERNAL: return "internal error";
-  }
-  return "unknown status";
-}
-
-const char* ibb_last_error(void) { return g_err.c_str(); }
-
-static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in, const ibb_allocator* alloc,
-                             void* hip_stream, ibb_result** out) {
-  const auto t_start = std::chrono::steady_clock::now();
-  if (!out) return fail(IBB_E_INVALID, "out is NULL");
-  *out = nullptr;
-  ibb_status st = validate(prob);
-  if (st != IBB_OK) return st;
-  ibb_options opts;
-  if (opts_in) opts = *opts_in; else ibb_options_default(&opts);
-  if (opts.split_dims < 1 || opts.split_dims > kMaxSplit) return fail(IBB_E_INVALID, "split_dims must be in 1..16");
-  if (opts.select_k != 1) return fail(IBB_E_INVALID, "this build selects one box per sweep (select_k = 1)");
-  if (opts.precision != IBB_FP64) return fail(IBB_E_INVALID, "this build bounds in FP64 (precision = IBB_FP64)");
-  if (opts.max_sweeps < 0) return fail(IBB_E_INVALID, "max_sweeps must be >= 0");
-
-  ibb_result* R = new ibb_result();
+// Allocate the problem's arrays, upload it and enqueue its root box (Sec. 3.1,
+// Initialization).  dP/dS must already point to device storage.
+ibb_status run_setup(Run& U, const ibb_problem* prob) {
+  ibb_result* R = U.R;
   Mem& M = R->mem;
-  M.stream = (hipStream_t)hip_stream;
-  if (alloc && alloc->alloc && alloc->free) { M.alloc = *alloc; M.have_alloc = true; }
-  auto bail = [&](ibb_status s) { (void)hipStreamSynchronize(M.stream); M.release_all(); delete R; return s; };
-
   Params& P = R->P;
   const int n = prob->n;
-  st = upload_problem(M, prob, P);
-  if (st != IBB_OK) return bail(st);
-  P.m = std::min(n, opts.split_dims);
+  ibb_status st = upload_problem(M, prob, P, U.opts.precision == IBB_FP32_BULK && fp32_safe(prob));
+  if (st != IBB_OK) return st;
+  P.m = std::min(n, U.opts.split_dims);
   P.nch = 1 << P.m;
   P.tol_f = prob->tol_f;
   P.tol_x = prob->tol_x;
-  P.max_sweeps = opts.max_sweeps;
-  P.max_live = opts.max_live_boxes;
-  P.trace_cap = std::min<int64_t>(opts.max_sweeps + 1, (int64_t)1 << 22);
-  P.key_cap = std::max<int64_t>(4096, 16 * (int64_t)P.nch);
-  P.hist_cap = 256;
+  P.max_sweeps = U.opts.max_sweeps;
+  P.max_live = U.opts.max_live_boxes;
+  P.trace_cap = std::min<int64_t>(U.opts.max_sweeps + 1, (int64_t)1 << 17);
+  P.key_cap = std::max<int64_t>(4096, 4 * (int64_t)P.nch);
+  P.hist_cap = 64;
   P.key_flo = dalloc<double>(M, P.key_cap);
   P.key_seq = dalloc<int64_t>(M, P.key_cap);
   P.key_ref = dalloc<int32_t>(M, P.key_cap);
@@ -942,73 +1115,318 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
   P.tr_nsurv = dalloc<int64_t>(M, P.trace_cap);
   P.tr_nlive = dalloc<int64_t>(M, P.trace_cap);
   P.tr_sel = dalloc<int64_t>(M, P.trace_cap);
-  Params* dP = dalloc<Params>(M, 1);
-  State* dS = dalloc<State>(M, 1);
   if (!P.key_flo || !P.key_seq || !P.key_ref || !P.key_r || !P.key_wmax || !P.hist_n || !P.hist_h || !P.hist_cyc ||
       !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.part_flo || !P.part_seq ||
-      !P.part_idx || !P.part_wmax || !P.part_cnt || !P.tr_gub || !P.tr_nsurv || !P.tr_nlive || !P.tr_sel || !dP || !dS)
-    return bail(fail(IBB_E_NOMEM, "device allocation failed"));
-  R->dP = dP;
+      !P.part_idx || !P.part_wmax || !P.part_cnt || !P.tr_gub || !P.tr_nsurv || !P.tr_nlive || !P.tr_sel)
+    return fail(IBB_E_NOMEM, "device allocation failed");
   // root row: (-l, u)
-  {
-    std::vector<double> nl(n);
-    for (int i = 0; i < n; ++i) nl[i] = -prob->lower[i];
-    if (hipMemcpyAsync(P.hist_n, nl.data(), n * sizeof(double), hipMemcpyHostToDevice, M.stream) != hipSuccess ||
-        hipMemcpyAsync(P.hist_h, prob->upper, n * sizeof(double), hipMemcpyHostToDevice, M.stream) != hipSuccess)
-      return bail(fail(IBB_E_DEVICE, "copy of the root box failed"));
-    if (hipMemsetAsync(dS, 0, sizeof(State), M.stream) != hipSuccess) return bail(fail(IBB_E_DEVICE, "memset failed"));
-    if (push_params(M, P, dP) != IBB_OK) return bail(IBB_E_DEVICE);
-    // nl must stay alive until the copy is done
-    if (hipStreamSynchronize(M.stream) != hipSuccess) return bail(fail(IBB_E_DEVICE, "sync failed"));
-  }
+  std::vector<double> nl(n);
+  for (int i = 0; i < n; ++i) nl[i] = -prob->lower[i];
+  HIPCHK(hipMemcpyAsync(P.hist_n, nl.data(), n * sizeof(double), hipMemcpyHostToDevice, M.stream));
+  HIPCHK(hipMemcpyAsync(P.hist_h, prob->upper, n * sizeof(double), hipMemcpyHostToDevice, M.stream));
+  HIPCHK(hipMemsetAsync(U.dS, 0, sizeof(State), M.stream));
+  st = push_params(M, P, U.dP);
+  if (st != IBB_OK) return st;
+  HIPCHK(hipStreamSynchronize(M.stream));   // nl must outlive its copy
   dispatch_family(P.family, [&](auto fam) {
-    hipLaunchKernelGGL(k_root<decltype(fam)::value>, dim3(1), dim3(kWave), 0, M.stream, dP, dS);
+    hipLaunchKernelGGL(k_root<decltype(fam)::value>, dim3(1), dim3(kWave), 0, M.stream, U.dP, U.dS);
   });
-  if (hipGetLastError() != hipSuccess) return bail(fail(IBB_E_DEVICE, "root launch failed"));
+  HIPCHK(hipGetLastError());
+  U.n_keys = 1;
+  U.sweeps = 0;
+  U.pending = false;
+  return IBB_OK;
+}
 
-  // ---- sweep loop, in chunks; the host reads the device state between chunks ----
-  State hs{};
-  int64_t n_keys = 1, sweeps = 0;
-  bool pending = false;
+// room for `chunk` more sweeps: one row and at most nch keys per sweep
+ibb_status run_capacity(Run& U, int chunk) {
+  Mem& M = U.R->mem;
+  Params& P = U.R->P;
+  const int n = P.n;
+  bool changed = false;
+  const int64_t need_rows = U.sweeps + chunk + 2;
+  if (need_rows > P.hist_cap) {
+    const int64_t nc = std::max<int64_t>(2 * P.hist_cap, need_rows);
+    const int64_t keep = U.sweeps + 2;
+    ibb_status st = IBB_OK;
+    if ((st = grow(M, P.hist_n, keep * n, nc * n)) != IBB_OK || (st = grow(M, P.hist_h, keep * n, nc * n)) != IBB_OK ||
+        (st = grow(M, P.hist_cyc, keep, nc)) != IBB_OK || (st = grow(M, P.hist_mask, keep, nc)) != IBB_OK ||
+        (st = grow(M, P.hist_mid, keep * kMaxSplit, nc * kMaxSplit)) != IBB_OK)
+      return st;
+    P.hist_cap = nc;
+    changed = true;
+  }
+  const int64_t need_keys = U.n_keys + (int64_t)(chunk + 1) * P.nch;   // +1: children pending from the last chunk
+  if (need_keys > P.key_cap) {
+    const int64_t nc = std::max<int64_t>(2 * P.key_cap, need_keys);
+    ibb_status st = IBB_OK;
+    if ((st = grow(M, P.key_flo, U.n_keys, nc)) != IBB_OK || (st = grow(M, P.key_seq, U.n_keys, nc)) != IBB_OK ||
+        (st = grow(M, P.key_ref, U.n_keys, nc)) != IBB_OK || (st = grow(M, P.key_r, U.n_keys, nc)) != IBB_OK ||
+        (st = grow(M, P.key_wmax, U.n_keys, nc)) != IBB_OK)
+      return st;
+    P.key_cap = nc;
+    changed = true;
+  }
+  if (changed) return push_params(M, P, U.dP);
+  return IBB_OK;
+}
+
+// after a chunk: take the device counters, drop removed keys when they dominate
+ibb_status run_after_chunk(Run& U) {
+  U.n_keys = U.hs.n_keys;
+  U.sweeps = U.hs.sweeps;
+  U.pending = U.hs.pending != 0;
+  Params& P = U.R->P;
+  if (!U.hs.stop && U.n_keys > 4 * (U.hs.n_live + P.nch) && U.n_keys > (int64_t)1 << 16) {
+    Mem& M = U.R->mem;
+    double* f; int64_t* sq; int32_t* rf; int32_t* rr; double* wx; int64_t kept = 0;
+    ibb_status st = compact_keys(M, P, U.dP, U.dS, U.n_keys, P.key_cap, f, sq, rf, rr, wx, kept);
+    if (st != IBB_OK) return st;
+    M.put(P.key_flo); M.put(P.key_seq); M.put(P.key_ref); M.put(P.key_r); M.put(P.key_wmax);
+    P.key_flo = f; P.key_seq = sq; P.key_ref = rf; P.key_r = rr; P.key_wmax = wx;
+    st = push_params(M, P, U.dP);
+    if (st != IBB_OK) return st;
+    HIPCHK(hipMemcpyAsync(&U.dS->n_keys, &kept, sizeof(int64_t), hipMemcpyHostToDevice, M.stream));
+    HIPCHK(hipStreamSynchronize(M.stream));
+    U.n_keys = kept;
+  }
+  return IBB_OK;
+}
+
+// final list (keys with lower bound <= GUB, in insertion order), trace, info
+ibb_status run_finish(Run& U) {
+  ibb_result* R = U.R;
+  Mem& M = R->mem;
+  Params& P = R->P;
+  const State& hs = U.hs;
+  int64_t kept = 0;
+  ibb_status st = compact_keys(M, P, U.dP, U.dS, U.n_keys, std::max<int64_t>(U.n_keys, 1), R->flo, R->seq, R->ref, R->r,
+                               R->wmax, kept);
+  if (st != IBB_OK) return st;
+  R->n_boxes = kept;
+  std::vector<double> hflo(kept);
+  if (kept) HIPCHK(hipMemcpy(hflo.data(), R->flo, kept * sizeof(double), hipMemcpyDeviceToHost));
+  double glb = INFINITY;
+  for (double v : hflo) glb = std::min(glb, v);
+  const int64_t tn = std::min<int64_t>(hs.sweeps, P.trace_cap);
+  R->tr_gub.resize(tn); R->tr_nsurv.resize(tn); R->tr_nlive.resize(tn); R->tr_sel.resize(tn);
+  if (tn > 0) {
+    HIPCHK(hipMemcpy(R->tr_gub.data(), P.tr_gub, tn * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(R->tr_nsurv.data(), P.tr_nsurv, tn * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(R->tr_nlive.data(), P.tr_nlive, tn * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(R->tr_sel.data(), P.tr_sel, tn * 8, hipMemcpyDeviceToHost));
+    if (hs.sweeps <= P.trace_cap) R->tr_nlive[tn - 1] = kept;
+  }
+  R->info.f_lo = glb;
+  R->info.f_hi = okey_inv(hs.gub_key);
+  R->info.n_boxes = kept;
+  R->info.sweeps = hs.sweeps;
+  R->info.boxes_evaluated = hs.evaluated;
+  R->info.fp32_pruned = hs.fp32_pruned;
+  R->info.fp64_confirmed = hs.evaluated - hs.fp32_pruned;
+  R->info.fp32_sweeps = (int32_t)std::min<int64_t>(hs.fp32_sweeps, INT32_MAX);
+  R->info.ub_evaluated = hs.ub_evaluated;
+  R->info.status = hs.stop == STOP_CONVERGED ? IBB_OK : (hs.stop == STOP_EMPTY ? IBB_E_INTERNAL : IBB_NOT_CONVERGED);
+  R->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - U.t0).count();
+  if (R->info.status == IBB_E_INTERNAL) return fail(IBB_E_INTERNAL, "the live list became empty");
+  return IBB_OK;
+}
+
+ibb_status check_options(const ibb_options& o) {
+  if (o.split_dims < 1 || o.split_dims > kMaxSplit) return fail(IBB_E_INVALID, "split_dims must be in 1..16");
+  if (o.select_k != 1) return fail(IBB_E_INVALID, "this build selects one box per sweep (select_k = 1)");
+  if (o.precision != IBB_FP64 && o.precision != IBB_FP32_BULK) return fail(IBB_E_INVALID, "unknown precision");
+  if (o.max_sweeps < 0) return fail(IBB_E_INVALID, "max_sweeps must be >= 0");
+  return IBB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// bound kernel shapes and the autotuner
+//
+// A shape is W wavefronts per child over the coordinate tiles (W = 1, 2, 4), in
+// latency mode (CONC = 1: W more wavefronts per child compute the midpoint bound
+// at the same time) or throughput mode (CONC = 0: F first, then the midpoint
+// bound unless F.lo already exceeds the GUB; the FP32 filter runs only here).
+// A workgroup holds 4 wavefronts, so 4 / (W (1 + CONC)) children.
+struct BoundShape {
+  int w, conc;
+};
+constexpr int kNumBoundShapes = 5;
+constexpr BoundShape kBoundShapes[kNumBoundShapes] = {{1, 1}, {2, 1}, {1, 0}, {2, 0}, {4, 0}};
+
+template <int FAM>
+void launch_bound(int shape, int nch, hipStream_t stream, hipEvent_t e0, hipEvent_t e1, Params* dP, State* dS) {
+  const BoundShape bs = kBoundShapes[shape];
+  const int cpb = kBoundWaves / (bs.w * (1 + bs.conc));
+  const dim3 g((nch + cpb - 1) / cpb), b(kWave * kBoundWaves);
+  switch (shape) {
+    case 0: hipExtLaunchKernelGGL((k_bound<FAM, 1, 1>), g, b, 0, stream, e0, e1, 0, dP, dS); break;
+    case 1: hipExtLaunchKernelGGL((k_bound<FAM, 2, 1>), g, b, 0, stream, e0, e1, 0, dP, dS); break;
+    case 2: hipExtLaunchKernelGGL((k_bound<FAM, 1, 0>), g, b, 0, stream, e0, e1, 0, dP, dS); break;
+    case 3: hipExtLaunchKernelGGL((k_bound<FAM, 2, 0>), g, b, 0, stream, e0, e1, 0, dP, dS); break;
+    default: hipExtLaunchKernelGGL((k_bound<FAM, 4, 0>), g, b, 0, stream, e0, e1, 0, dP, dS); break;
+  }
+}
+
+std::mutex g_tune_mu;
+std::unordered_map<uint64_t, int> g_tuned;
+
+int tuned_shape(uint64_t key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(key);
+  return it == g_tuned.end() ? -1 : it->second;
+}
+void store_tuned_shape(uint64_t key, int shape) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = shape;
+}
+
+// Time every admissible shape on the first sweep of this problem and return the
+// fastest.  The first sweep's selection runs as usual; its bound kernel then runs
+// once per shape to warm up and 3 times per shape under HIP events.  Repeating it
+// is harmless: every run writes the same child records, and the GUB is a minimum
+// of the same upper bounds; the counters are restored from the state after the
+// first run.  The solve then continues with the next sweep's selection.
+ibb_status autotune_bound(Run& U, int n_tiles, int& best) {
+  ibb_result* R = U.R;
+  Mem& M = R->mem;
+  Params& P = R->P;
+  best = P.prec32 ? (n_tiles <= 1 ? 2 : (n_tiles <= 4 ? 3 : 4)) : (n_tiles <= 1 ? 0 : (n_tiles <= 4 ? 1 : 4));
+  hipLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS, 0, 0);
+  HIPCHK(hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream));
+  HIPCHK(hipStreamSynchronize(M.stream));
+  U.sweeps = U.hs.sweeps;
+  U.pending = U.hs.pending != 0;
+  if (U.hs.stop || !U.hs.pending) return IBB_OK;   // nothing to bound: keep the default shape
+  hipEvent_t ev[2];
+  HIPCHK(hipEventCreate(&ev[0]));
+  if (hipEventCreate(&ev[1]) != hipSuccess) { (void)hipEventDestroy(ev[0]); return fail(IBB_E_DEVICE, "hipEventCreate failed"); }
+  State after{};
+  float best_ms = 0.0f;
+  ibb_status st = IBB_OK;
+  dispatch_family(P.family, [&](auto fam) {
+    constexpr int FAM = decltype(fam)::value;
+    bool first = true;
+    for (int v = 0; v < kNumBoundShapes && st == IBB_OK; ++v) {
+      if (P.prec32 && kBoundShapes[v].conc) continue;
+      if (kBoundShapes[v].w > 1 && kBoundShapes[v].w > n_tiles) continue;   // idle waves
+      launch_bound<FAM>(v, P.nch, M.stream, nullptr, nullptr, U.dP, U.dS);
+      if (first) {
+        if (hipMemcpyAsync(&after, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
+            hipStreamSynchronize(M.stream) != hipSuccess) { st = fail(IBB_E_DEVICE, "autotune copy failed"); break; }
+        first = false;
+      }
+      float tot = 0.0f;
+      for (int r = 0; r < 3; ++r) {
+        float ms = 0.0f;
+        launch_bound<FAM>(v, P.nch, M.stream, ev[0], ev[1], U.dP, U.dS);
+        if (hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) {
+          st = fail(IBB_E_DEVICE, "autotune timing failed");
+          break;
+        }
+        tot += ms;
+      }
+      if (st == IBB_OK && (best_ms == 0.0f || tot < best_ms)) { best_ms = tot; best = v; }
+    }
+  });
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (st != IBB_OK) return st;
+  if (hipGetLastError() != hipSuccess) return fail(IBB_E_DEVICE, "autotune launch failed");
+  HIPCHK(hipMemcpyAsync(U.dS, &after, sizeof(State), hipMemcpyHostToDevice, M.stream));
+  HIPCHK(hipStreamSynchronize(M.stream));
+  U.hs = after;
+  return IBB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ibb_status ibb_options_default(ibb_options* o) {
+  if (!o) return fail(IBB_E_INVALID, "options is NULL");
+  o->precision = IBB_FP64;
+  o->split_dims = 10;
+  o->select_k = 1;
+  o->deterministic = 1;
+  o->max_sweeps = 1000000;
+  o->max_live_boxes = (int64_t)1 << 26;
+  o->time_limit_s = 0.0;
+  o->profile = 0;
+  o->bound_shape = 0;
+  return IBB_OK;
+}
+
+const char* ibb_status_string(ibb_status s) {
+  switch (s) {
+    case IBB_OK: return "ok";
+    case IBB_NOT_CONVERGED: return "not converged (budget reached; enclosure still rigorous)";
+    case IBB_PENDING: return "pending";
+    case IBB_E_INVALID: return "invalid argument";
+    case IBB_E_NOMEM: return "out of memory";
+    case IBB_E_DEVICE: return "device error";
+    case IBB_E_CAPACITY: return "capacity exceeded";
+    case IBB_E_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* ibb_last_error(void) { return g_err.c_str(); }
+
+static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in, const ibb_allocator* alloc,
+                             void* hip_stream, ibb_result** out) {
+  if (!out) return fail(IBB_E_INVALID, "out is NULL");
+  *out = nullptr;
+  ibb_status st = validate(prob);
+  if (st != IBB_OK) return st;
+  Run U;
+  U.t0 = std::chrono::steady_clock::now();
+  if (opts_in) U.opts = *opts_in; else ibb_options_default(&U.opts);
+  if ((st = check_options(U.opts)) != IBB_OK) return st;
+
+  ibb_result* R = new ibb_result();
+  U.R = R;
+  Mem& M = R->mem;
+  M.stream = (hipStream_t)hip_stream;
+  if (alloc && alloc->alloc && alloc->free) { M.alloc = *alloc; M.have_alloc = true; }
+  auto bail = [&](ibb_status s) { (void)hipStreamSynchronize(M.stream); M.release_all(); delete R; return s; };
+  U.dP = dalloc<Params>(M, 1);
+  U.dS = dalloc<State>(M, 1);
+  if (!U.dP || !U.dS) return bail(fail(IBB_E_NOMEM, "device allocation failed"));
+  R->dP = U.dP;
+  if ((st = run_setup(U, prob)) != IBB_OK) return bail(st);
+  Params& P = R->P;
+  const int n = P.n;
+
+  // bound kernel shape (children per workgroup x waves per child), picked by the
+  // autotuner below unless the caller forces one; every shape gives the same bits
+  int bound_variant = -1;
+  if (U.opts.bound_shape > 0) {
+    bound_variant = U.opts.bound_shape - 1;
+    if (bound_variant >= kNumBoundShapes || (P.prec32 && kBoundShapes[bound_variant].conc) ||
+        (kBoundShapes[bound_variant].w > 1 && kBoundShapes[bound_variant].w > (n + kWave - 1) / kWave))
+      return bail(fail(IBB_E_INVALID, "forced bound shape not available for this precision"));
+  }
+  const int n_tiles = (n + kWave - 1) / kWave;
+  const uint64_t tune_key = ((uint64_t)P.family << 40) | ((uint64_t)std::min(n_tiles, 1 << 20) << 8) |
+                            ((uint64_t)P.m << 1) | (uint64_t)(P.prec32 != 0);
+  if (bound_variant < 0) bound_variant = tuned_shape(tune_key);
+  if (bound_variant < 0) {
+    st = autotune_bound(U, n_tiles, bound_variant);
+    if (st != IBB_OK) return bail(st);
+    store_tuned_shape(tune_key, bound_variant);
+  }
+  R->info.bound_shape = bound_variant;
   struct Events {
     std::vector<hipEvent_t> v;
     ~Events() { for (auto e : v) (void)hipEventDestroy(e); }
   } evs;
   auto& ev = evs.v;
   int chunk = 4;
-  // bound kernel shape: with few children the GPU is latency-bound, so the midpoint
-  // bound runs in its own wavefronts (variants 0, 1: 1 or 2 box waves + as many
-  // midpoint waves per child); with many coordinate chunks per child, 4 waves per
-  // child compute F then the midpoint bound (variant 2).  All give the same bits.
-  const int nchunks = (n + kWave - 1) / kWave;
-  const int bound_variant = nchunks <= 1 ? 0 : (nchunks <= 4 ? 1 : 2);
-  const int waves_per_child = bound_variant == 0 ? 2 : 4;
-  const int bound_blocks = (P.nch + kBoundWaves / waves_per_child - 1) / (kBoundWaves / waves_per_child);
   for (;;) {
-    // capacity for this chunk: one row and at most nch keys per sweep
-    const int64_t need_rows = sweeps + chunk + 2;
-    if (need_rows > P.hist_cap) {
-      int64_t nc = std::max<int64_t>(2 * P.hist_cap, need_rows);
-      if (grow(M, P.hist_n, (sweeps + 1) * (int64_t)n, nc * n) != IBB_OK ||
-          grow(M, P.hist_h, (sweeps + 1) * (int64_t)n, nc * n) != IBB_OK ||
-          grow(M, P.hist_cyc, sweeps + 1, nc) != IBB_OK || grow(M, P.hist_mask, sweeps + 1, nc) != IBB_OK ||
-          grow(M, P.hist_mid, (sweeps + 1) * kMaxSplit, nc * kMaxSplit) != IBB_OK)
-        return bail(IBB_E_NOMEM);
-      P.hist_cap = nc;
-      if (push_params(M, P, dP) != IBB_OK) return bail(IBB_E_DEVICE);
-    }
-    const int64_t need_keys = n_keys + (int64_t)(chunk + 1) * P.nch;   // +1: children pending from the last chunk
-    if (need_keys > P.key_cap) {
-      int64_t nc = std::max<int64_t>(2 * P.key_cap, need_keys);
-      if (grow(M, P.key_flo, n_keys, nc) != IBB_OK || grow(M, P.key_seq, n_keys, nc) != IBB_OK ||
-          grow(M, P.key_ref, n_keys, nc) != IBB_OK || grow(M, P.key_r, n_keys, nc) != IBB_OK ||
-          grow(M, P.key_wmax, n_keys, nc) != IBB_OK)
-        return bail(IBB_E_NOMEM);
-      P.key_cap = nc;
-      if (push_params(M, P, dP) != IBB_OK) return bail(IBB_E_DEVICE);
-    }
-    const int sb = sel_blocks_for(need_keys);
-    const bool prof = opts.profile != 0;
+    if ((st = run_capacity(U, chunk)) != IBB_OK) return bail(st);
+    const int sb = sel_blocks_for(U.n_keys + (int64_t)(chunk + 1) * P.nch);
+    const bool prof = U.opts.profile != 0;
     if (prof && (int)ev.size() < 4 * chunk) {
       const size_t old_n = ev.size();
       ev.resize(4 * chunk);
@@ -1020,27 +1438,24 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
       for (int s = 0; s < chunk; ++s) {
         if (sb > 1)
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
-                                nullptr, 0, dP, dS);
+                                nullptr, 0, U.dP, U.dS);
         hipExtLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
-                              (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, dP, dS,
-                              sb > 1 ? sb : 0, 0);
-        hipEvent_t e0 = prof ? ev[4 * s + 1] : nullptr, e1 = prof ? ev[4 * s + 2] : nullptr;
-        const dim3 g(bound_blocks), b(kWave * kBoundWaves);
-        if (bound_variant == 0) hipExtLaunchKernelGGL((k_bound<FAM, 1, 1>), g, b, 0, M.stream, e0, e1, 0, dP, dS);
-        else if (bound_variant == 1) hipExtLaunchKernelGGL((k_bound<FAM, 2, 1>), g, b, 0, M.stream, e0, e1, 0, dP, dS);
-        else hipExtLaunchKernelGGL((k_bound<FAM, 4, 0>), g, b, 0, M.stream, e0, e1, 0, dP, dS);
+                              (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
+                              U.dS, sb > 1 ? sb : 0, 0);
+        launch_bound<FAM>(bound_variant, P.nch, M.stream, prof ? ev[4 * s + 1] : nullptr, prof ? ev[4 * s + 2] : nullptr,
+                          U.dP, U.dS);
       }
     });
     if (hipGetLastError() != hipSuccess) return bail(fail(IBB_E_DEVICE, "sweep launch failed"));
-    if (hipMemcpyAsync(&hs, dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
+    if (hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
         hipStreamSynchronize(M.stream) != hipSuccess)
       return bail(fail(IBB_E_DEVICE, "sweep failed"));
     if (prof) {
       // bound launches that did work in this chunk; the select of the stopping sweep ran too
-      const int64_t ran = (hs.sweeps + (hs.pending ? 1 : 0)) - (sweeps + (pending ? 1 : 0));
+      const int64_t ran = (U.hs.sweeps + (U.hs.pending ? 1 : 0)) - (U.sweeps + (U.pending ? 1 : 0));
       for (int s = 0; s < chunk; ++s) {
         float ms = 0.f;
-        if (s < ran || (s == ran && hs.stop)) {
+        if (s < ran || (s == ran && U.hs.stop)) {
           if (hipEventElapsedTime(&ms, ev[4 * s + 0], ev[4 * s + 3]) == hipSuccess) R->info.t_select_ms += ms;
           R->info.n_select_launches++;
         }
@@ -1050,73 +1465,25 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
         }
       }
     }
-    n_keys = hs.n_keys;
-    sweeps = hs.sweeps;
-    pending = hs.pending != 0;
-    if (hs.stop) break;
-    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-    if (opts.time_limit_s > 0.0 && el > opts.time_limit_s) {
+    if (U.hs.stop) { if ((st = run_after_chunk(U)) != IBB_OK) return bail(st); break; }
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - U.t0).count();
+    if (U.opts.time_limit_s > 0.0 && el > U.opts.time_limit_s) {
       // insert the last sweep's children, then stop
-      const int sbf = sel_blocks_for(n_keys);
-      if (sbf > 1) hipLaunchKernelGGL(k_select_part, dim3(sbf), dim3(kSelThreads), 0, M.stream, dP, dS);
-      hipLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, dP, dS,
+      const int sbf = sel_blocks_for(U.hs.n_keys);
+      if (sbf > 1) hipLaunchKernelGGL(k_select_part, dim3(sbf), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+      hipLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS,
                          sbf > 1 ? sbf : 0, 1);
-      if (hipMemcpyAsync(&hs, dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
+      if (hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
           hipStreamSynchronize(M.stream) != hipSuccess)
         return bail(fail(IBB_E_DEVICE, "final insert failed"));
-      n_keys = hs.n_keys;
-      sweeps = hs.sweeps;
+      U.n_keys = U.hs.n_keys;
+      U.sweeps = U.hs.sweeps;
       break;
     }
+    if ((st = run_after_chunk(U)) != IBB_OK) return bail(st);
     chunk = std::min(chunk * 2, 256);
-    // drop removed keys when they dominate the list
-    if (n_keys > 4 * (hs.n_live + P.nch) && n_keys > (int64_t)1 << 16) {
-      double* f; int64_t* sq; int32_t* rf; int32_t* rr; double* wx; int64_t kept = 0;
-      if (compact_keys(M, P, dP, dS, n_keys, P.key_cap, f, sq, rf, rr, wx, kept) != IBB_OK) return bail(IBB_E_NOMEM);
-      M.put(P.key_flo); M.put(P.key_seq); M.put(P.key_ref); M.put(P.key_r); M.put(P.key_wmax);
-      P.key_flo = f; P.key_seq = sq; P.key_ref = rf; P.key_r = rr; P.key_wmax = wx;
-      if (push_params(M, P, dP) != IBB_OK) return bail(IBB_E_DEVICE);
-      if (hipMemcpyAsync(&dS->n_keys, &kept, sizeof(int64_t), hipMemcpyHostToDevice, M.stream) != hipSuccess ||
-          hipStreamSynchronize(M.stream) != hipSuccess)
-        return bail(fail(IBB_E_DEVICE, "compaction failed"));
-      n_keys = kept;
-    }
   }
-
-  // ---- final list: keys with lower bound <= GUB, in insertion order ----
-  int64_t kept = 0;
-  if (compact_keys(M, P, dP, dS, n_keys, std::max<int64_t>(n_keys, 1), R->flo, R->seq, R->ref, R->r, R->wmax, kept) !=
-      IBB_OK)
-    return bail(IBB_E_NOMEM);
-  R->n_boxes = kept;
-  // GLB over the final list
-  std::vector<double> hflo(kept);
-  if (kept && hipMemcpy(hflo.data(), R->flo, kept * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-    return bail(fail(IBB_E_DEVICE, "copy failed"));
-  double glb = INFINITY;
-  for (double v : hflo) glb = std::min(glb, v);
-  // trace
-  const int64_t tn = std::min<int64_t>(hs.sweeps, P.trace_cap);
-  R->tr_gub.resize(tn); R->tr_nsurv.resize(tn); R->tr_nlive.resize(tn); R->tr_sel.resize(tn);
-  if (tn > 0) {
-    if (hipMemcpy(R->tr_gub.data(), P.tr_gub, tn * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(R->tr_nsurv.data(), P.tr_nsurv, tn * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(R->tr_nlive.data(), P.tr_nlive, tn * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(R->tr_sel.data(), P.tr_sel, tn * 8, hipMemcpyDeviceToHost) != hipSuccess)
-      return bail(fail(IBB_E_DEVICE, "trace copy failed"));
-    R->tr_nlive[tn - 1] = kept;
-  }
-  R->info.f_lo = glb;
-  R->info.f_hi = okey_inv(hs.gub_key);
-  R->info.n_boxes = kept;
-  R->info.sweeps = hs.sweeps;
-  R->info.boxes_evaluated = hs.evaluated;
-  R->info.fp32_pruned = 0;
-  R->info.fp64_confirmed = hs.evaluated;
-  R->info.ub_evaluated = hs.ub_evaluated;
-  R->info.status = hs.stop == STOP_CONVERGED ? IBB_OK : (hs.stop == STOP_EMPTY ? IBB_E_INTERNAL : IBB_NOT_CONVERGED);
-  R->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-  if (R->info.status == IBB_E_INTERNAL) return bail(fail(IBB_E_INTERNAL, "the live list became empty"));
+  if ((st = run_finish(U)) != IBB_OK) return bail(st);
   *out = R;
   return (ibb_status)R->info.status;
 }
@@ -1190,14 +1557,17 @@ ibb_status ibb_eval_boxes(const ibb_problem* prob, int32_t precision, int64_t nb
                           double* d_F, double* d_ub_mid, uint8_t* d_mono_prune, double* d_G, void* hip_stream) {
   ibb_status st = validate(prob);
   if (st != IBB_OK) return st;
-  if (precision != IBB_FP64) return fail(IBB_E_INVALID, "ibb_eval_boxes bounds in FP64 only");
+  if (precision != IBB_FP64 && precision != IBB_FP32_BULK) return fail(IBB_E_INVALID, "unknown precision");
+  const bool p32 = precision == IBB_FP32_BULK;
+  if (p32 && !fp32_safe(prob))
+    return fail(IBB_E_INVALID, "coefficient or domain magnitudes too large for single-precision bounds");
   if (nb < 0) return fail(IBB_E_INVALID, "nb < 0");
   if (nb == 0) return IBB_OK;
   if (!d_lo || !d_hi || !d_F || !d_ub_mid || !d_mono_prune) return fail(IBB_E_INVALID, "NULL device array");
   Mem M;
   M.stream = (hipStream_t)hip_stream;
   Params P{};
-  st = upload_problem(M, prob, P);
+  st = upload_problem(M, prob, P, p32);
   if (st != IBB_OK) { M.release_all(); return st; }
   Params* dP = dalloc<Params>(M, 1);
   if (!dP) { M.release_all(); return fail(IBB_E_NOMEM, "device allocation failed"); }
@@ -1208,8 +1578,12 @@ ibb_status ibb_eval_boxes(const ibb_problem* prob, int32_t precision, int64_t nb
   const int64_t blocks = (nb + kBoundWaves - 1) / kBoundWaves;
   if (blocks > 0x7fffffff) { M.release_all(); return fail(IBB_E_CAPACITY, "too many boxes"); }
   dispatch_family(P.family, [&](auto fam) {
-    hipLaunchKernelGGL(k_eval_boxes<decltype(fam)::value>, dim3((unsigned)blocks), dim3(kWave * kBoundWaves), 0,
-                       M.stream, dP, nb, d_lo, d_hi, d_F, d_ub_mid, d_mono_prune, d_G);
+    if (p32)
+      hipLaunchKernelGGL(k_eval_boxes32<decltype(fam)::value>, dim3((unsigned)blocks), dim3(kWave * kBoundWaves), 0,
+                         M.stream, dP, nb, d_lo, d_hi, d_F, d_ub_mid, d_mono_prune, d_G);
+    else
+      hipLaunchKernelGGL(k_eval_boxes<decltype(fam)::value>, dim3((unsigned)blocks), dim3(kWave * kBoundWaves), 0,
+                         M.stream, dP, nb, d_lo, d_hi, d_F, d_ub_mid, d_mono_prune, d_G);
   });
   hipError_t e = hipGetLastError();
   // the host copy of P is gone after return; the device copy was enqueued before the kernel
@@ -1246,4 +1620,35 @@ ibb_status ibb_point_trig(int32_t fn, int64_t count, const double* d_y, double* 
   return IBB_OK;
 }
 
+ibb_status ibb_interval_op32(int32_t op, int64_t count, const float* d_a, const float* d_b, float* d_out,
+                             void* hip_stream) {
+  if (!(op == 0 || op == 1 || op == 2 || op == 5 || op == 6 || op == 8 || op == 9 || op == 10))
+    return fail(IBB_E_INVALID, "op not available in single precision");
+  if (count < 0) return fail(IBB_E_INVALID, "count < 0");
+  if (count == 0) return IBB_OK;
+  const bool binary = op <= 2;
+  if (!d_a || !d_out || (binary && !d_b)) return fail(IBB_E_INVALID, "NULL device array");
+  const int64_t blocks = (count + 255) / 256;
+  if (blocks > 0x7fffffff) return fail(IBB_E_CAPACITY, "count too large");
+  hipLaunchKernelGGL(k_interval_op32, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream, op, count, d_a,
+                     binary ? d_b : nullptr, d_out);
+  HIPCHK(hipGetLastError());
+  return IBB_OK;
+}
+
+ibb_status ibb_point_trig32(int32_t fn, int64_t count, const float* d_y, float* d_out, void* hip_stream) {
+  if (fn != 0 && fn != 1) return fail(IBB_E_INVALID, "fn must be 0 (cos) or 1 (sin)");
+  if (count < 0) return fail(IBB_E_INVALID, "count < 0");
+  if (count == 0) return IBB_OK;
+  if (!d_y || !d_out) return fail(IBB_E_INVALID, "NULL device array");
+  const int64_t blocks = (count + 255) / 256;
+  if (blocks > 0x7fffffff) return fail(IBB_E_CAPACITY, "count too large");
+  hipLaunchKernelGGL(k_point_trig32, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream, fn, count, d_y,
+                     d_out);
+  HIPCHK(hipGetLastError());
+  return IBB_OK;
+}
+
 }  // extern "C"
+
+#include "serve.inc"

@@ -367,3 +367,140 @@ __host__ __device__ __forceinline__ double okey_inv(uint64_t k) {
 }
 
 }  // namespace ibb
+
+// =========================================================================
+// Single precision: the FP32 filter.  Same representation [-n, h] and the same
+// round-up MODE (its f32 field is set too).  A double interval is enclosed in
+// single precision with the conversion's rounding checked, so the enclosure
+// holds whatever rounding the conversion used.
+// =========================================================================
+namespace ibb {
+
+__device__ __forceinline__ float mul_neg32(float a, float b) {
+  float r;
+  asm("v_mul_f32 %0, -%1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ float neg32(float a) {
+  float r;
+  asm("v_mul_f32 %0, %1, -1.0" : "=v"(r) : "v"(a));
+  return r;
+}
+__device__ __forceinline__ float next_up32(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  if (x == 0.0f) return __builtin_bit_cast(float, 1u);
+  u = (int32_t)u >= 0 ? u + 1 : u - 1;
+  return __builtin_bit_cast(float, u);
+}
+__device__ __forceinline__ float f32max(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ float f32min(float a, float b) { return __builtin_fminf(a, b); }
+
+struct J {
+  float n, h;
+};
+
+// smallest float >= x (checked after the conversion)
+__device__ __forceinline__ float up32(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = next_up32(f);
+  return f;
+}
+__device__ __forceinline__ J to32(I x) { return J{up32(x.n), up32(x.h)}; }
+
+__device__ __forceinline__ J add32(J a, J b) { return J{a.n + b.n, a.h + b.h}; }
+__device__ __forceinline__ J sub32(J a, J b) { return J{a.n + b.h, a.h + b.n}; }
+__device__ __forceinline__ J s_sub32(float c, J a) { return J{a.h - c, c + a.n}; }   // exact scalar c
+__device__ __forceinline__ J scale32(float s, J a) {                                // exact scalar s
+  const float as = __builtin_fabsf(s);
+  const float p = as * a.n, q = as * a.h;
+  return s >= 0.0f ? J{p, q} : J{q, p};
+}
+__device__ __forceinline__ J mul32(J a, J b) {
+  const float hi = f32max(f32max(a.n * b.n, a.h * b.h), f32max(mul_neg32(a.n, b.h), mul_neg32(a.h, b.n)));
+  const float nl = f32max(f32max(a.n * b.h, a.h * b.n), f32max(mul_neg32(a.n, b.n), mul_neg32(a.h, b.h)));
+  return J{nl, hi};
+}
+__device__ __forceinline__ J sqr32(J a) {
+  const bool nonneg = a.n <= 0.0f, nonpos = a.h <= 0.0f;
+  const float p = nonneg ? a.n : a.h;
+  const float q = nonneg ? a.h : (nonpos ? a.n : f32max(a.n, a.h));
+  const float nl = (nonneg || nonpos) ? mul_neg32(p, p) : 0.0f;
+  return J{nl, q * q};
+}
+__device__ __forceinline__ J abs32(J a) {
+  if (a.n <= 0.0f) return a;
+  if (a.h <= 0.0f) return J{a.h, a.n};
+  return J{0.0f, f32max(a.n, a.h)};
+}
+__device__ __forceinline__ J dabs32(J a) {
+  if (a.n < 0.0f) return J{-1.0f, 1.0f};
+  if (a.h < 0.0f) return J{1.0f, -1.0f};
+  return J{1.0f, 1.0f};
+}
+
+// cos(2 pi y), sin(2 pi y) at a float y: the exact reduction of sincos2pi_point,
+// then degree-9 / degree-10 Taylor polynomials in single precision (round-up).
+// Their rounding error is below 3 * 2^-23 relative (sine) and absolute (cosine),
+// the truncation below 2^-28; the enclosure adds a margin of 2^-19 (plus 2^-126
+// absolute on the sine, which covers a subnormal product).
+struct TrigEnc32 {
+  J c, s;
+};
+__device__ __forceinline__ TrigEnc32 sincos2pi_point32(float y) {
+  const float ay = __builtin_fabsf(y);
+  const float fr = ay - __builtin_floorf(ay);
+  const float f = fr > 0.5f ? fr - 1.0f : fr;
+  const float a = __builtin_fabsf(f);
+  const bool oct0 = a <= 0.125f, oct1 = a <= 0.375f;
+  const float g = oct0 ? a : (oct1 ? 0.25f - a : 0.5f - a);
+  const float z = g * g;
+  // A_k = (-1)^k (2pi)^(2k+1)/(2k+1)!,  B_k = (-1)^k (2pi)^(2k)/(2k)!  (rounded to float)
+  float ps = __builtin_bit_cast(float, 0x42283c1au);            // A4  42.06
+  ps = __builtin_fmaf(z, ps, __builtin_bit_cast(float, 0xc2996966u));   // A3 -76.71
+  ps = __builtin_fmaf(z, ps, __builtin_bit_cast(float, 0x42a335e3u));   // A2  81.61
+  ps = __builtin_fmaf(z, ps, __builtin_bit_cast(float, 0xc2255de7u));   // A1 -41.34
+  ps = __builtin_fmaf(z, ps, __builtin_bit_cast(float, 0x40c90fdbu));   // A0   6.283
+  const float sv = g * ps;
+  float pc = __builtin_bit_cast(float, 0xc1d368f9u);            // B5 -26.43
+  pc = __builtin_fmaf(z, pc, __builtin_bit_cast(float, 0x4270fa83u));   // B4  60.24
+  pc = __builtin_fmaf(z, pc, __builtin_bit_cast(float, 0xc2aae9e4u));   // B3 -85.46
+  pc = __builtin_fmaf(z, pc, __builtin_bit_cast(float, 0x4281e0f8u));   // B2  64.94
+  pc = __builtin_fmaf(z, pc, __builtin_bit_cast(float, 0xc19de9e6u));   // B1 -19.74
+  const float cv = __builtin_fmaf(z, pc, 1.0f);
+  const float Es = __builtin_fmaf(__builtin_fabsf(sv), 0x1p-19f, 0x1p-126f);
+  const float Ec = g == 0.0f ? 0.0f : 0x1p-19f;
+  const J S{Es - sv, sv + Es};
+  const J C{Ec - cv, cv + Ec};
+  TrigEnc32 r;
+  r.c = oct0 ? C : (oct1 ? S : J{C.h, C.n});
+  const J sv2 = (oct0 || !oct1) ? S : C;
+  r.s = ((f < 0.0f) != (y < 0.0f)) ? J{sv2.h, sv2.n} : sv2;
+  r.c.n = f32min(r.c.n, 1.0f); r.c.h = f32min(r.c.h, 1.0f);
+  r.s.n = f32min(r.s.n, 1.0f); r.s.h = f32min(r.s.h, 1.0f);
+  return r;
+}
+__device__ __forceinline__ bool has_int32(float n, float h) { return __builtin_floorf(n) + __builtin_floorf(h) >= 0.0f; }
+
+struct TrigIv32 {
+  J c, s;
+};
+__device__ __forceinline__ TrigIv32 sincos2pi32(J y, bool want_cos, bool want_sin) {
+  TrigIv32 r;
+  const J whole{1.0f, 1.0f};
+  if (!(y.n + y.h < 1.0f)) { r.c = whole; r.s = whole; return r; }
+  const TrigEnc32 ea = sincos2pi_point32(neg32(y.n));
+  const TrigEnc32 eb = sincos2pi_point32(y.h);
+  r.c = J{f32max(ea.c.n, eb.c.n), f32max(ea.c.h, eb.c.h)};
+  r.s = J{f32max(ea.s.n, eb.s.n), f32max(ea.s.h, eb.s.h)};
+  if (want_cos) {
+    if (has_int32(y.n, y.h)) r.c.h = 1.0f;
+    if (has_int32(y.n + 0.5f, y.h - 0.5f)) r.c.n = 1.0f;
+  }
+  if (want_sin) {
+    if (has_int32(y.n + 0.25f, y.h - 0.25f)) r.s.h = 1.0f;
+    if (has_int32(y.n - 0.25f, y.h + 0.25f)) r.s.n = 1.0f;
+  }
+  return r;
+}
+
+}  // namespace ibb

@@ -35,6 +35,9 @@ struct Params {
   int64_t max_sweeps, max_live;
   const CoefSep* sep;                     // [n] (separable families)
   const CoefChain* chain;                 // [n] (CHAIN; entry n-1 is zero)
+  int32_t prec32, pad32;                  // 1: the FP32 filter may run (the sweep's State.use32 decides)
+  const CoefSep32* sep32;                 // [n] float enclosures of the coefficients (filter only)
+  const CoefChain32* chain32;             // [n]
   const double* nl;                       // [n] -l
   const double* u;                        // [n]  u
   // live-box keys
@@ -53,7 +56,8 @@ struct Params {
   int64_t hist_cap;
   // per-sweep children
   double* ch_flo;
-  uint8_t* ch_flag;                       // 0 not formed, 1 fails the first-order test, 2 candidate
+  uint8_t* ch_flag;                       // 0 not formed, 1 fails the first-order test, 2 candidate,
+                                          // 3 discarded by the FP32 filter
   double* ch_wmax;
   // select partials
   double* part_flo;
@@ -80,6 +84,12 @@ struct State {
   uint32_t sel_mask;
   int64_t sel_seq;
   double sel_mid[kMaxSplit];
+  // FP32 filter: GUB when the sweep's bound kernel starts (the filter's cutoff,
+  // so that its decisions do not depend on the order of the GUB updates), the
+  // switch for the next sweep, back-off after sweeps where it pruned too little
+  double gub_start;
+  int32_t use32, p32_fails;
+  int64_t p32_resume, fp32_pruned, fp32_sweeps;
 };
 
 // bisection point: 0.5 lo + 0.5 hi rounded up, kept inside [lo, hi]
@@ -141,6 +151,38 @@ __device__ __forceinline__ double fold_slots_hi(double acc, int lane) {
     if (lane < h) acc = acc + o;
   }
   return __shfl(acc, 0, kWave);
+}
+
+// wave sum of single-precision intervals (fixed order, any lane holds the result)
+__device__ __forceinline__ J fold32(J acc, int lane) {
+  for (int h = 32; h >= 1; h >>= 1) {
+    const float on = __shfl_down(acc.n, h, kWave);
+    const float oh = __shfl_down(acc.h, h, kWave);
+    if (lane < h) acc = add32(acc, J{on, oh});
+  }
+  return J{__shfl(acc.n, 0, kWave), __shfl(acc.h, 0, kWave)};
+}
+
+// FP32 filter, coordinate i of a box: its term of f (CHAIN: term i, zero for the
+// last coordinate) and the first-order test on its gradient component
+template <int FAM, class Row>
+__device__ __forceinline__ void filter32_coord(const Params& P, const Row& X, int i, J& t, bool& mono,
+                                               double* Gout = nullptr) {
+  const int n = P.n;
+  const I x = X.get(i);
+  J G;
+  if (FAM != FAM_CHAIN) {
+    sep_box32<FAM>(P.sep32[i], to32(x), t, G);
+  } else {
+    const bool has_prev = i > 0, has_next = i + 1 < n;
+    const J x32 = to32(x);
+    const J xp = has_prev ? to32(X.get(i - 1)) : x32;
+    const J xn = has_next ? to32(X.get(i + 1)) : x32;
+    t = has_next ? chain_term32(P.chain32[i], x32, xn) : J{0.0f, 0.0f};
+    G = chain_grad32(P.chain32[has_prev ? i - 1 : i], P.chain32[i], xp, x32, xn, has_prev, has_next);
+  }
+  mono |= (G.n < 0.0f && x.n != P.nl[i]) || (G.h < 0.0f && x.h != P.u[i]);
+  if (Gout) { Gout[2 * i] = (double)neg32(G.n); Gout[2 * i + 1] = (double)G.h; }
 }
 
 // F, first-order test and widest side of one box, by one wavefront

@@ -1,0 +1,117 @@
+"""Batched solves and the continuous-batching server (C ABI) on the GPU.
+
+Each problem keeps its own list and GUB and follows exactly the iteration that
+ibb_solve runs for it alone, so every result must be the same bit for bit alone,
+in a batch, and in the server's mix (whatever else was admitted next to it and
+whenever it arrived).
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2507_01770_amd import problems as PR
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2507_01770_amd as ibb  # noqa: E402
+
+
+def mix():
+    return [PR.sep_cos(2, 101), PR.sep_cos(9, 2), PR.chain(5, 505, hi=2.3), PR.sep_abs_sin2(12, 4),
+            PR.chain(13, 505), PR.sep_cos(100, 102), PR.sep_abs_sin2(130, 7), PR.chain(70, 505),
+            PR.chain(200, 505, hi=2.3)]
+
+
+BUDGET = dict(max_sweeps=400)
+
+
+def same(a, b):
+    assert a.status == b.status and a.sweeps == b.sweeps
+    assert a.f_lo == b.f_lo and a.f_hi == b.f_hi
+    assert a.boxes_evaluated == b.boxes_evaluated and a.n_boxes == b.n_boxes
+    assert np.array_equal(a.trace_gub, b.trace_gub) and np.array_equal(a.trace_nsurv, b.trace_nsurv)
+    assert np.array_equal(a.trace_nlive, b.trace_nlive) and np.array_equal(a.trace_sel, b.trace_sel)
+    assert np.array_equal(a.flo, b.flo) and np.array_equal(a.seq, b.seq)
+    if a.lo is not None and b.lo is not None:
+        assert np.array_equal(a.lo, b.lo) and np.array_equal(a.hi, b.hi)
+
+
+@pytest.fixture(scope="module")
+def alone():
+    out = []
+    for p in mix():
+        print(f"case alone {p.name}", flush=True)
+        out.append(ibb.minimize(p, max_boxes_fetched=500, **BUDGET))
+    return out
+
+
+def test_batch_equals_alone(alone):
+    print("case batch of all", flush=True)
+    got = ibb.solve_batch(mix(), max_boxes_fetched=500, **BUDGET)
+    for a, b in zip(alone, got):
+        same(a, b)
+
+
+def test_batch_subsets_equal_alone(alone):
+    ps = mix()
+    for idx in ([0], [8, 1], [5, 6, 2]):
+        print(f"case batch subset {idx}", flush=True)
+        got = ibb.solve_batch([ps[i] for i in idx], max_boxes_fetched=500, **BUDGET)
+        for i, b in zip(idx, got):
+            same(alone[i], b)
+
+
+def test_server_mix_equals_alone(alone):
+    ps = mix()
+    with ibb.Server(mem_budget_bytes=4 << 30, max_slots=4) as srv:
+        tickets = []
+        for p in ps:                      # staggered arrivals while others run
+            print(f"case server submit {p.name}", flush=True)
+            tickets.append(srv.submit(p, **BUDGET))
+            time.sleep(0.002)
+        res = {}
+        t0 = time.time()
+        while len(res) < len(tickets) and time.time() - t0 < 120:
+            for t in tickets:
+                if t not in res:
+                    r = srv.poll(t, fetch_boxes=True, max_boxes_fetched=500)
+                    if r is not None:
+                        res[t] = r
+            time.sleep(0.001)
+        st = srv.stats()
+    assert len(res) == len(tickets)
+    for t, a in zip(tickets, alone):
+        same(a, res[t])
+    assert st["completed"] == len(ps) and 2 <= st["max_active"] <= 4
+
+
+def test_server_respects_memory_budget():
+    ps = [PR.sep_cos(100, 11 + i) for i in range(6)]
+    # about 0.35 MB each at the start: a 1 MB budget admits at most three at once
+    with ibb.Server(mem_budget_bytes=1 << 20, max_slots=8) as srv:
+        pending = {srv.submit(p, max_sweeps=300) for p in ps}
+        t0 = time.time()
+        while pending and time.time() - t0 < 120:
+            for t in list(pending):
+                if srv.poll(t) is not None:
+                    pending.discard(t)
+            time.sleep(0.002)
+        st = srv.stats()
+    assert not pending and st["completed"] == len(ps)
+    assert st["max_active"] <= 3
+
+
+def test_server_rejects_invalid():
+    with ibb.Server(mem_budget_bytes=1 << 30, max_slots=2) as srv:
+        p = PR.sep_cos(3, 1)
+        p.lower = p.lower.copy()
+        p.lower[0] = p.upper[0]
+        with pytest.raises(ibb.IbbError):
+            srv.submit(p)
+        with pytest.raises(ibb.IbbError):
+            srv.poll(12345)

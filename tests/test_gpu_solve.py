@@ -125,3 +125,39 @@ def test_workload3_capped_run():
     assert r.status == ibb.NOT_CONVERGED and r.sweeps == 40
     assert r.f_lo <= 0.0 <= r.f_hi
     assert r.trace_sel[0] == 0 and np.all(np.diff(r.trace_gub) <= 0)
+
+
+def _same_run(a, b):
+    assert (a.status, a.f_lo, a.f_hi, a.sweeps, a.boxes_evaluated, a.n_boxes) == \
+        (b.status, b.f_lo, b.f_hi, b.sweeps, b.boxes_evaluated, b.n_boxes)
+    assert np.array_equal(a.trace_gub, b.trace_gub) and np.array_equal(a.trace_nsurv, b.trace_nsurv)
+    assert np.array_equal(a.flo, b.flo) and np.array_equal(a.seq, b.seq)
+
+
+@pytest.mark.parametrize("p,shapes", [(PR.sep_cos(100, 102), [0, 1, 2, 3]), (PR.chain(300, 505, hi=2.3), [0, 1, 2, 3, 4]),
+                                      (PR.sep_abs_sin2(40, 9), [0, 2])])
+def test_every_bound_shape_gives_the_same_run(p, shapes):
+    # the autotuner may pick any shape: all must follow the same iteration bit for bit
+    runs = []
+    for s in shapes:
+        print(f"case shape {s} {p.name}", flush=True)
+        r = ibb.minimize(p, max_sweeps=60, bound_shape=s, fetch_boxes=False)
+        assert r.bound_shape == s
+        runs.append(r)
+    auto = ibb.minimize(p, max_sweeps=60, fetch_boxes=False)
+    assert auto.bound_shape in shapes
+    for r in runs[1:] + [auto]:
+        _same_run(runs[0], r)
+    # and in FP32 mode (throughput shapes only) the filter's decisions agree too
+    f32 = [ibb.minimize(p, max_sweeps=60, bound_shape=s, precision="fp32_bulk", fetch_boxes=False)
+           for s in shapes if s >= 2]
+    for r in f32[1:]:
+        _same_run(f32[0], r)
+        assert r.fp32_pruned == f32[0].fp32_pruned
+
+
+def test_forced_shape_rejected_when_not_admissible():
+    with pytest.raises(ibb.IbbError):
+        ibb.minimize(PR.sep_cos(100, 102), max_sweeps=5, bound_shape=4)          # 4 waves, 2 tiles
+    with pytest.raises(ibb.IbbError):
+        ibb.minimize(PR.sep_cos(9, 2), max_sweeps=5, bound_shape=0, precision="fp32_bulk")
