@@ -4,9 +4,11 @@
 
 One step = one whole solve (every sweep of the hot path until GUB - GLB <= 1e-6),
 so ms_per_step is the time-to-enclosure and value is boxes bounded per second.
-Prints one JSON line.  Also reports the roofline of the dominant kernel
-(k_bound, timed with HIP events inside the library on the solve's stream) and
-the CPU oracle's rate on a bounded prefix of the same workload.
+Prints one JSON line.  The headline uses incremental child bounds (the default);
+the same workload also runs with full bounds and with the FP32 filter.  Each
+roofline is that of the dominant kernel, timed with HIP events inside the library
+on the solve's stream.  The CPU oracle's rate is taken on a bounded prefix of the
+same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
 """
@@ -33,6 +35,18 @@ sys.path.insert(0, ROOT)
 BOX_OPS_PER_COORD = 172
 MID_OPS_PER_COORD = 142
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 (fma) x 2.4 GHz
+# separable cosine, F of one term alone (no gradient): interval D, Y, sqr, scalings, 1 - C,
+# sum (14) + two point evaluations of cos/sin (126) + extremum tests (2)
+TERM_OPS_PER_COORD = 142
+
+
+def incremental_ops_per_sweep(n: int, m: int) -> float:
+    """Algorithmic FP64 operations of one sweep with incremental bounds (separable cosine):
+    the n - m shared terms (F and the midpoint bound), both halves of the m split
+    coordinates (F, G and the midpoint bound), and per child m interval additions for F
+    (2 ops) and m additions for the midpoint bound (1 op)."""
+    return (n - m) * (TERM_OPS_PER_COORD + MID_OPS_PER_COORD) + 2 * m * (BOX_OPS_PER_COORD + MID_OPS_PER_COORD) \
+        + (1 << m) * m * 3
 
 
 def main() -> int:
@@ -44,6 +58,7 @@ def main() -> int:
     ap.add_argument("--cpu-sweeps", type=int, default=30, help="oracle prefix for the CPU baseline (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=128, help="requests in the serving trace (0 = skip)")
     ap.add_argument("--fp32-steps", type=int, default=5, help="solves of the same workload with the FP32 filter (0 = skip)")
+    ap.add_argument("--full-steps", type=int, default=5, help="solves of the same workload with full bounds (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM traffic counters) and exit")
     args = ap.parse_args()
@@ -59,55 +74,66 @@ def main() -> int:
     from paper_2507_01770_amd import problems as PR
 
     p = PR.config(1)
-    torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        ibb.minimize(p, fetch_boxes=False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = [ibb.minimize(p, fetch_boxes=False, profile=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = t1 - t0
-    boxes = sum(r.boxes_evaluated for r in res)
-    for r in res:
-        assert r.status == ibb.OK and r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6, (r.f_lo, r.f_hi)
 
-    # roofline of k_bound: algorithmic FP64 ops over the summed kernel time
+    def timed(steps, warmup, **kw):
+        for _ in range(warmup):
+            ibb.minimize(p, fetch_boxes=False, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = [ibb.minimize(p, fetch_boxes=False, profile=True, **kw) for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        for r in rs:
+            assert r.status == ibb.OK and r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6, (r.f_lo, r.f_hi)
+        return rs, dt
+
+    # headline: incremental child bounds (the default)
+    res, dt = timed(args.steps, args.warmup)
+    boxes = sum(r.boxes_evaluated for r in res)
     r0 = res[-1]
-    formed = r0.boxes_evaluated - 1          # children (the root is bounded by another kernel)
-    ub_children = r0.ub_evaluated - 1
-    ops = p.n * (formed * BOX_OPS_PER_COORD + ub_children * MID_OPS_PER_COORD) * 1.0
-    t_bound = r0.t_bound_ms * 1e-3
-    achieved = ops / t_bound / 1e12 if t_bound > 0 else 0.0
+    # dominant kernel: the selection kernel, which also bounds the children
+    ib_ops = incremental_ops_per_sweep(p.n, min(p.n, 10)) * r0.sweeps
+    t_sel = r0.t_select_ms * 1e-3
+    ach = ib_ops / t_sel / 1e12 if t_sel > 0 else 0.0
     roofline = {
-        "bound": "alu", "kernel": "k_bound<SEP_COS>", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
-        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 5), "traffic": None,
-        "avg_launch_us": round(r0.t_bound_ms * 1e3 / max(1, r0.n_bound_launches), 3),
-        "launches_per_solve": r0.n_bound_launches,
-        "flops_per_launch": round(ops / max(1, r0.n_bound_launches)),
-        "select_avg_launch_us": round(r0.t_select_ms * 1e3 / max(1, r0.n_select_launches), 3),
+        "bound": "alu", "kernel": "k_select_ib<SEP_COS> (one workgroup per sweep)", "achieved": round(ach, 6),
+        "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 8), "traffic": None,
+        "avg_launch_us": round(r0.t_select_ms * 1e3 / max(1, r0.n_select_launches), 3),
+        "launches_per_solve": r0.n_select_launches,
+        "flops_per_launch": round(ib_ops / max(1, r0.n_select_launches)),
     }
+
+    # the same workload with full bounds (every child over all n terms): k_bound's roofline
+    full = None
+    if args.full_steps > 0:
+        rf, df = timed(args.full_steps, 1, incremental=False)
+        q = rf[-1]
+        formed = q.boxes_evaluated - 1          # children (the root is bounded by another kernel)
+        ops = p.n * (formed * BOX_OPS_PER_COORD + (q.ub_evaluated - 1) * MID_OPS_PER_COORD) * 1.0
+        tb = q.t_bound_ms * 1e-3
+        a = ops / tb / 1e12 if tb > 0 else 0.0
+        full = {"boxes_per_s": round(sum(r.boxes_evaluated for r in rf) / df, 1),
+                "ms_per_solve": round(df / args.full_steps * 1e3, 4), "sweeps": q.sweeps,
+                "bound_shape": q.bound_shape,
+                "roofline": {"bound": "alu", "kernel": "k_bound<SEP_COS>", "achieved": round(a, 4),
+                             "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(a / PEAK_FP64_TFLOPS, 5),
+                             "avg_launch_us": round(q.t_bound_ms * 1e3 / max(1, q.n_bound_launches), 3),
+                             "flops_per_launch": round(ops / max(1, q.n_bound_launches))},
+                "select_avg_launch_us": round(q.t_select_ms * 1e3 / max(1, q.n_select_launches), 3)}
 
     cpu = None
     if args.cpu_sweeps > 0:
         from oracle import oracle as O
         tc = time.perf_counter()
-        o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=args.cpu_sweeps)
+        o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=args.cpu_sweeps, incremental=True)
         tcpu = time.perf_counter() - tc
         cpu = {"value": round(o.boxes_evaluated / tcpu, 2), "unit": "boxes/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {o.sweeps} sweeps of the same workload ({o.boxes_evaluated} boxes, {tcpu:.1f} s, "
-                         f"single thread, fesetround per endpoint operation)"}
+               "sample": f"first {o.sweeps} sweeps of the same workload with incremental child bounds "
+                         f"({o.boxes_evaluated} boxes, {tcpu:.1f} s, single thread, fesetround per endpoint operation)"}
 
     fp32 = None
     if args.fp32_steps > 0:
-        ibb.minimize(p, fetch_boxes=False, precision="fp32_bulk")
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        r32 = [ibb.minimize(p, fetch_boxes=False, precision="fp32_bulk", profile=True) for _ in range(args.fp32_steps)]
-        torch.cuda.synchronize()
-        d32 = time.perf_counter() - t2
-        for r in r32:
-            assert r.status == ibb.OK and r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6, (r.f_lo, r.f_hi)
+        r32, d32 = timed(args.fp32_steps, 1, precision="fp32_bulk")
         q = r32[-1]
         fp32 = {"boxes_per_s": round(sum(r.boxes_evaluated for r in r32) / d32, 1),
                 "ms_per_solve": round(d32 / args.fp32_steps * 1e3, 4),
@@ -136,8 +162,9 @@ def main() -> int:
             "precision": args.precision, "select_k": 1, "split_dims": 10,
             "time_to_enclosure_ms": round(float(np.median([r.seconds for r in res])) * 1e3, 4),
             "sweeps": r0.sweeps, "boxes_per_solve": r0.boxes_evaluated,
-            "enclosure": [r0.f_lo, r0.f_hi],
-            "fp32_bulk": fp32,
+            "enclosure": [r0.f_lo, r0.f_hi], "bounds": "incremental",
+            "full_bounds": full,
+            "fp32_bulk_full_bounds": fp32,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

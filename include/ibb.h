@@ -98,7 +98,18 @@ typedef struct {
                             shape k-1 (W waves per child, concurrent midpoint waves or not):
                             0 {1, yes}, 1 {2, yes}, 2 {1, no}, 3 {2, no}, 4 {4, no}.  Every shape gives
                             the same results; IBB_E_INVALID for a shape with concurrent midpoint
-                            waves under IBB_FP32_BULK or with W above ceil(n / 64) */
+                            waves under IBB_FP32_BULK or with W above ceil(n / 64).
+                            Applies to full bounds only (incremental = 0) */
+  int32_t incremental;   /* 1 (default): incremental child bounds.  A child differs from the selected
+                            box only on the split coordinates, so every term of f that involves none
+                            of them is shared: the selection workgroup sums those once per sweep (in
+                            the canonical slot order, the others left out) and bounds each child as
+                            that sum plus its affected terms in increasing index; the midpoint upper
+                            bound likewise.  The same enclosures up to the order of the additions,
+                            O(n + 2^m m) work per sweep instead of O(2^m n).  0: every child is
+                            bounded over all n terms (the FP32 filter and bound_shape apply only here;
+                            IBB_E_INVALID for incremental = 1 with IBB_FP32_BULK or a bound_shape) */
+  int32_t reserved;      /* 0 */
 } ibb_options;
 
 typedef struct {
@@ -122,7 +133,7 @@ typedef struct {
      the sweeps that ran (launches after the stop are not counted) */
   double t_bound_ms, t_select_ms;
   int64_t n_bound_launches, n_select_launches;
-  int32_t bound_shape;        /* shape of the bound kernel used (0..4, see ibb_options) */
+  int32_t bound_shape;        /* shape of the bound kernel used (0..4, see ibb_options; -1: incremental) */
   int32_t pad;
 } ibb_info;
 
@@ -139,6 +150,15 @@ ibb_status ibb_options_default(ibb_options* opts);
  * of range. */
 ibb_status ibb_solve(const ibb_problem* prob, const ibb_options* opts, const ibb_allocator* alloc,
                      void* hip_stream, ibb_result** out);
+
+/* Continue a run: up to n_sweeps more sweeps (Sec. 3.1) on the state that res
+ * keeps on the device, for instance after ibb_solve stopped at max_sweeps or the
+ * time limit.  The list, GUB, rows and trace continue exactly where they were,
+ * so ibb_solve with budget a then ibb_sweep(b) gives the same run as ibb_solve
+ * with budget a + b.  Updates res (info, boxes, trace) and returns its status:
+ * IBB_OK once converged (a converged result is left as it is), else
+ * IBB_NOT_CONVERGED.  Runs on hip_stream and synchronises it. */
+ibb_status ibb_sweep(ibb_result* res, int64_t n_sweeps, void* hip_stream);
 
 ibb_status ibb_result_info(const ibb_result* res, ibb_info* info);
 

@@ -322,12 +322,13 @@ static iv grad(const orc_problem* P, const iv* X, int64_t j) {
  * (slot s absorbs slot s + h); absent slots are skipped.  This order is part
  * of the definition of the enclosure F (the paper does not fix one).
  */
-static iv canonical_sum(const orc_problem* P, const iv* X) {
+static iv canonical_sum_except(const orc_problem* P, const iv* X, const unsigned char* leave_out) {
   iv slot[64];
   int present[64];
   int64_t T = n_terms(P);
   for (int s = 0; s < 64; ++s) present[s] = 0;
   for (int64_t i = 0; i < T; ++i) {
+    if (leave_out && leave_out[i]) continue;
     int s = (int)(i % 64);
     iv t = term(P, X, i);
     slot[s] = present[s] ? iv_add(slot[s], t) : t;
@@ -341,6 +342,8 @@ static iv canonical_sum(const orc_problem* P, const iv* X) {
       }
   return present[0] ? slot[0] : mk(0.0, 0.0);
 }
+
+static iv canonical_sum(const orc_problem* P, const iv* X) { return canonical_sum_except(P, X, NULL); }
 
 /* bisection point of [lo, hi]: 0.5 lo + 0.5 hi rounded up, kept inside */
 static double midpoint(double lo, double hi) {
@@ -378,7 +381,61 @@ static box_eval eval_box(const orc_problem* P, const double* lo, const double* h
 /* the iteration                                                             */
 /* ------------------------------------------------------------------------- */
 
-typedef struct { int32_t split_dims, select_k; int64_t max_sweeps, max_live_boxes; } orc_options;
+typedef struct {
+  int32_t split_dims, select_k; int64_t max_sweeps, max_live_boxes;
+  int32_t incremental;   /* 1: children bounded from their parent's shared terms (see child_bounds) */
+  int32_t reserved;
+} orc_options;
+
+/*
+ * Incremental bounds of the children of one selected box (an option; the
+ * paper bounds every subregion from scratch and fixes no summation order).
+ * A child differs from its parent only on the split coordinates, so a term t_i
+ * that involves none of them (SEP: i not split; CHAIN: neither i nor i+1
+ * split) is the parent's.  The canonical sum of those terms (the order of
+ * canonical_sum, affected terms left out) is formed once per parent; a child's
+ * F is that sum plus its affected terms, added one at a time in increasing i.
+ * The midpoint upper bound is formed the same way, from the terms at the
+ * midpoints (the midpoint of an unsplit coordinate is the parent's).  The
+ * first-order test and the widest side are unchanged: they do not depend on an
+ * order of summation.
+ */
+typedef struct {
+  unsigned char* affected;  /* [n_terms] */
+  iv base_F;
+  double base_ub;
+} parent_base;
+
+static void parent_base_form(const orc_problem* P, const double* lo, const double* hi, const int* split_dim,
+                             int n_split, iv* X, parent_base* B) {
+  const int64_t n = P->n, T = n_terms(P);
+  for (int64_t i = 0; i < T; ++i) B->affected[i] = 0;
+  for (int q = 0; q < n_split; ++q) {
+    const int64_t d = split_dim[q];
+    if (d < T) B->affected[d] = 1;                                  /* t_d involves x_d */
+    if (P->family == FAM_CHAIN && d >= 1) B->affected[d - 1] = 1;   /* t_{d-1} involves x_d */
+  }
+  for (int64_t i = 0; i < n; ++i) X[i] = mk(lo[i], hi[i]);
+  B->base_F = canonical_sum_except(P, X, B->affected);
+  for (int64_t i = 0; i < n; ++i) { double m = midpoint(lo[i], hi[i]); X[i] = mk(m, m); }
+  B->base_ub = canonical_sum_except(P, X, B->affected).hi;
+}
+
+/* F and the midpoint upper bound of a child from its parent's base */
+static void child_bounds(const orc_problem* P, const parent_base* B, const double* lo, const double* hi, iv* X,
+                         iv* F, double* ub) {
+  const int64_t n = P->n, T = n_terms(P);
+  for (int64_t i = 0; i < n; ++i) X[i] = mk(lo[i], hi[i]);
+  iv f = B->base_F;
+  for (int64_t i = 0; i < T; ++i)
+    if (B->affected[i]) f = iv_add(f, term(P, X, i));
+  for (int64_t i = 0; i < n; ++i) { double m = midpoint(lo[i], hi[i]); X[i] = mk(m, m); }
+  double u = B->base_ub;
+  for (int64_t i = 0; i < T; ++i)
+    if (B->affected[i]) u = up_add(u, term(P, X, i).hi);
+  *F = f;
+  *ub = u;
+}
 typedef struct { double f_lo, f_hi; int64_t n_boxes, sweeps, boxes_evaluated; int32_t status; } orc_info;
 
 enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_INVALID = -1, ST_NOMEM = -2, ST_INTERNAL = -5 };
@@ -451,6 +508,8 @@ void* orc_solve(const orc_problem* P, const orc_options* O, int64_t trace_cap) {
   box* par = (box*)malloc((size_t)K * sizeof(box));
   double* clo = (double*)malloc((size_t)n * sizeof(double));
   double* chi = (double*)malloc((size_t)n * sizeof(double));
+  parent_base pb;
+  pb.affected = (unsigned char*)malloc((size_t)(n > 0 ? n : 1));
 
   /* Initialization (Sec. 3.1): L = { whole domain } */
   box root;
@@ -499,11 +558,14 @@ void* orc_solve(const orc_problem* P, const orc_options* O, int64_t trace_cap) {
     double gub_new = S->gub;
     for (int p = 0; p < kk; ++p) {
       int dim[64]; double mid[64]; int split[64];
+      int split_dim[64], n_split = 0;
       for (int j = 0; j < m; ++j) {
         dim[j] = (int)(((int64_t)par[p].cyc + j) % n);
         mid[j] = midpoint(par[p].lo[dim[j]], par[p].hi[dim[j]]);
         split[j] = par[p].lo[dim[j]] < mid[j] && mid[j] < par[p].hi[dim[j]];
+        if (split[j]) split_dim[n_split++] = dim[j];
       }
+      if (O->incremental) parent_base_form(P, par[p].lo, par[p].hi, split_dim, n_split, X, &pb);
       for (int64_t r = 0; r < nch; ++r) {
         int64_t c = (int64_t)p * nch + r;
         ch_ok[c] = 0;
@@ -517,6 +579,7 @@ void* orc_solve(const orc_problem* P, const orc_options* O, int64_t trace_cap) {
           if ((r >> j) & 1) clo[dim[j]] = mid[j]; else chi[dim[j]] = mid[j];
         }
         box_eval e = eval_box(P, clo, chi, X, NULL);
+        if (O->incremental) child_bounds(P, &pb, clo, chi, X, &e.F, &e.ub);
         S->info.boxes_evaluated++;
         ch_flo[c] = e.F.lo;
         ch_ub[c] = e.ub;
@@ -580,7 +643,7 @@ done:
     S->info.f_lo = glb;
   }
   qsort(S->live, (size_t)S->n_live, sizeof(box), cmp_seq);
-  free(X); free(par); free(clo); free(chi);
+  free(X); free(par); free(clo); free(chi); free(pb.affected);
   return S;
 }
 

@@ -48,7 +48,8 @@ class _Problem(C.Structure):
 
 class _Options(C.Structure):
     _fields_ = [("split_dims", C.c_int32), ("select_k", C.c_int32),
-                ("max_sweeps", C.c_int64), ("max_live_boxes", C.c_int64)]
+                ("max_sweeps", C.c_int64), ("max_live_boxes", C.c_int64),
+                ("incremental", C.c_int32), ("reserved", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -157,12 +158,14 @@ class SolveResult:
 
 
 def solve(family, coef, lower, upper, tol_f=1e-6, tol_x=0.0, split_dims=10, select_k=1,
-          max_sweeps=100000, max_live_boxes=0, trace_cap=None) -> SolveResult:
+          max_sweeps=100000, max_live_boxes=0, trace_cap=None, incremental=False) -> SolveResult:
+    """The iteration of Sec. 3.1-3.2.  incremental=True bounds each child from its
+    parent's shared terms (same enclosures up to the order of the additions)."""
     k = _Keep(family, coef, lower, upper, tol_f, tol_x)
     n = k.lower.shape[0]
     if trace_cap is None:
         trace_cap = max_sweeps
-    opts = _Options(split_dims, select_k, max_sweeps, max_live_boxes)
+    opts = _Options(split_dims, select_k, max_sweeps, max_live_boxes, int(bool(incremental)), 0)
     L = lib()
     h = L.orc_solve(C.byref(k.p), C.byref(opts), trace_cap)
     if not h:

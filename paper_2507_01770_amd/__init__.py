@@ -38,7 +38,8 @@ class _Problem(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("split_dims", C.c_int32), ("select_k", C.c_int32),
                 ("deterministic", C.c_int32), ("max_sweeps", C.c_int64), ("max_live_boxes", C.c_int64),
-                ("time_limit_s", C.c_double), ("profile", C.c_int32), ("bound_shape", C.c_int32)]
+                ("time_limit_s", C.c_double), ("profile", C.c_int32), ("bound_shape", C.c_int32),
+                ("incremental", C.c_int32), ("reserved", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -68,6 +69,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise IbbError(f"{LIB_PATH} is missing: build it with `python paper_2507_01770_amd/build.py`")
+    # torch first: its HIP runtime (soname libamdhip64.so.7) is then the one the library
+    # binds to, so device memory and streams from torch are valid in the library
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
     L.ibb_options_default.argtypes = [C.POINTER(_Options)]
@@ -76,6 +80,7 @@ def lib():
     L.ibb_result_boxes.argtypes = [vp, dp, dp, dp, C.POINTER(i64), i64, C.POINTER(i64)]
     L.ibb_result_trace.argtypes = [vp, dp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), i64, C.POINTER(i64)]
     L.ibb_result_free.argtypes = [vp]
+    L.ibb_sweep.argtypes = [vp, i64, vp]
     L.ibb_result_free.restype = None
     L.ibb_eval_boxes.argtypes = [C.POINTER(_Problem), i32, i64, vp, vp, vp, vp, vp, vp, vp]
     L.ibb_interval_op.argtypes = [i32, i64, vp, vp, vp, vp]
@@ -92,7 +97,7 @@ def lib():
     L.ibb_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
     L.ibb_server_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.ibb_server_destroy.argtypes = [vp]
-    for f in ["ibb_options_default", "ibb_solve", "ibb_result_info", "ibb_result_boxes", "ibb_result_trace",
+    for f in ["ibb_options_default", "ibb_solve", "ibb_sweep", "ibb_result_info", "ibb_result_boxes", "ibb_result_trace",
               "ibb_eval_boxes", "ibb_interval_op", "ibb_point_trig", "ibb_interval_op32", "ibb_point_trig32",
               "ibb_solve_batch", "ibb_server_create",
               "ibb_server_submit", "ibb_server_poll", "ibb_server_stats", "ibb_server_destroy"]:
@@ -274,12 +279,12 @@ class Result:
 def minimize(problem=None, *, family=None, coef=None, lower=None, upper=None, tol_f=None, tol_x=None,
              precision=FP64, split_dims=10, select_k=1, max_sweeps=1_000_000, max_live_boxes=1 << 26,
              time_limit_s=0.0, fetch_boxes=True, max_boxes_fetched=100_000, use_torch_allocator=True,
-             profile=False, bound_shape=None, stream=None) -> Result:
+             profile=False, bound_shape=None, incremental=None, stream=None) -> Result:
     """Enclose min f over [lower, upper]; returns [f_lo, f_hi] and the surviving boxes."""
     k = _prob_args(problem, family, coef, lower, upper, tol_f, tol_x)
     L = lib()
-    opts = _Options(_prec(precision), split_dims, select_k, 1, max_sweeps, max_live_boxes, time_limit_s,
-                    int(profile), 0 if bound_shape is None else int(bound_shape) + 1)
+    opts = _options(precision, split_dims, select_k, max_sweeps, max_live_boxes, time_limit_s, profile, bound_shape,
+                    incremental)
     alloc = _TorchAllocator() if use_torch_allocator else None
     h = C.c_void_p()
     rc = L.ibb_solve(C.byref(k.s), C.byref(opts), C.byref(alloc.struct) if alloc else None, _stream_ptr(stream),
@@ -290,37 +295,85 @@ def minimize(problem=None, *, family=None, coef=None, lower=None, upper=None, to
 
 def _take_result(h, n, fetch_boxes=True, max_boxes_fetched=100_000) -> Result:
     """Copy a result out of the library and free it."""
-    L = lib()
     try:
-        info = _Info()
-        _check(L.ibb_result_info(h, C.byref(info)))
-        nb = info.n_boxes
-        nf = min(nb, max_boxes_fetched) if fetch_boxes else 0
-        flo = np.empty(nb)
-        seq = np.empty(nb, dtype=np.int64)
-        lo = np.empty((nf, n)) if fetch_boxes else None
-        hi = np.empty((nf, n)) if fetch_boxes else None
-        w = C.c_int64()
-        dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
-        ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))  # noqa: E731
-        _check(L.ibb_result_boxes(h, None, None, dp(flo), ip(seq), nb, C.byref(w)))
-        if fetch_boxes and nf:
-            _check(L.ibb_result_boxes(h, dp(lo), dp(hi), None, None, nf, C.byref(w)))
-        ts = info.sweeps
-        tg, tn, tl, tsel = np.empty(ts), np.empty(ts, np.int64), np.empty(ts, np.int64), np.empty(ts, np.int64)
-        _check(L.ibb_result_trace(h, dp(tg), ip(tn), ip(tl), ip(tsel), ts, C.byref(w)))
-        got = w.value
-        return Result(info.f_lo, info.f_hi, info.status, info.sweeps, info.boxes_evaluated, nb, info.seconds,
-                      lo, hi, flo, seq, tg[:got], tn[:got], tl[:got], tsel[:got], info.ub_evaluated,
-                      info.t_bound_ms, info.t_select_ms, info.n_bound_launches, info.n_select_launches,
-                      info.fp32_pruned, info.fp64_confirmed, info.fp32_sweeps, info.bound_shape)
+        return _read_result(h, n, fetch_boxes, max_boxes_fetched)
     finally:
-        L.ibb_result_free(h)
+        lib().ibb_result_free(h)
+
+
+def _read_result(h, n, fetch_boxes=True, max_boxes_fetched=100_000) -> Result:
+    """Copy a result out of the library (the handle stays valid)."""
+    L = lib()
+    info = _Info()
+    _check(L.ibb_result_info(h, C.byref(info)))
+    nb = info.n_boxes
+    nf = min(nb, max_boxes_fetched) if fetch_boxes else 0
+    flo = np.empty(nb)
+    seq = np.empty(nb, dtype=np.int64)
+    lo = np.empty((nf, n)) if fetch_boxes else None
+    hi = np.empty((nf, n)) if fetch_boxes else None
+    w = C.c_int64()
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+    ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))  # noqa: E731
+    _check(L.ibb_result_boxes(h, None, None, dp(flo), ip(seq), nb, C.byref(w)))
+    if fetch_boxes and nf:
+        _check(L.ibb_result_boxes(h, dp(lo), dp(hi), None, None, nf, C.byref(w)))
+    ts = info.sweeps
+    tg, tn, tl, tsel = np.empty(ts), np.empty(ts, np.int64), np.empty(ts, np.int64), np.empty(ts, np.int64)
+    _check(L.ibb_result_trace(h, dp(tg), ip(tn), ip(tl), ip(tsel), ts, C.byref(w)))
+    got = w.value
+    return Result(info.f_lo, info.f_hi, info.status, info.sweeps, info.boxes_evaluated, nb, info.seconds,
+                  lo, hi, flo, seq, tg[:got], tn[:got], tl[:got], tsel[:got], info.ub_evaluated,
+                  info.t_bound_ms, info.t_select_ms, info.n_bound_launches, info.n_select_launches,
+                  info.fp32_pruned, info.fp64_confirmed, info.fp32_sweeps, info.bound_shape)
+
+
+class Run:
+    """A run kept on the device: ``Run(problem, max_sweeps=a)`` solves with budget a,
+    ``sweep(b)`` continues it for up to b more sweeps (ibb_sweep), ``result()`` reads
+    it, ``close()`` frees it."""
+
+    def __init__(self, problem, *, stream=None, **opts):
+        self._k = _prob_args(problem)
+        self._stream = stream
+        o = _options(**opts)
+        self._h = C.c_void_p()
+        _check(lib().ibb_solve(C.byref(self._k.s), C.byref(o), None, _stream_ptr(stream), C.byref(self._h)),
+               ok=(OK, NOT_CONVERGED))
+
+    def sweep(self, n_sweeps: int) -> int:
+        return _check(lib().ibb_sweep(self._h, int(n_sweeps), _stream_ptr(self._stream)), ok=(OK, NOT_CONVERGED))
+
+    def result(self, fetch_boxes=True, max_boxes_fetched=100_000) -> Result:
+        return _read_result(self._h, self._k.lower.shape[0], fetch_boxes, max_boxes_fetched)
+
+    def close(self):
+        if self._h:
+            lib().ibb_result_free(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _options(precision=FP64, split_dims=10, select_k=1, max_sweeps=1_000_000, max_live_boxes=1 << 26,
-             time_limit_s=0.0):
-    return _Options(_prec(precision), split_dims, select_k, 1, max_sweeps, max_live_boxes, time_limit_s, 0, 0)
+             time_limit_s=0.0, profile=False, bound_shape=None, incremental=None):
+    """incremental=None: incremental child bounds unless the FP32 filter or a bound shape
+    (both about full bounds) is asked for."""
+    prec = _prec(precision)
+    if incremental is None:
+        incremental = prec == FP64 and bound_shape is None
+    return _Options(prec, split_dims, select_k, 1, max_sweeps, max_live_boxes, time_limit_s, int(profile),
+                    0 if bound_shape is None else int(bound_shape) + 1, int(bool(incremental)), 0)
 
 
 def solve_batch(problems, *, fetch_boxes=True, max_boxes_fetched=100_000, stream=None, **opts) -> list:

@@ -50,6 +50,19 @@ __device__ __forceinline__ void sep_box(const CoefSep& cf, I X, I& t, I& G) {
   }
 }
 
+// t_i alone (the same operations as in sep_box)
+template <int FAM>
+__device__ __forceinline__ I sep_term(const CoefSep& cf, I X) {
+  const I D = sub_s(X, cf.c);
+  if (FAM == FAM_SEP_COS) {
+    const TrigIv cs = sincos2pi(scale(cf.k, D), true, false);
+    return add(scale(cf.a, sqr(D)), scale(cf.b, s_sub(1.0, cs.c)));
+  } else {
+    const TrigIv sh = sincos2pi(scale(0.5 * cf.k, D), false, true);
+    return add(scale(cf.a, iabs(D)), scale(cf.b, sqr(sh.s)));
+  }
+}
+
 // upper endpoint of t_i at the point x (the point interval [x, x])
 template <int FAM>
 __device__ __forceinline__ double sep_point_hi(const CoefSep& cf, double x) {

@@ -298,7 +298,7 @@ __device__ void insert_children(const Params& P, State* S, double gub, SelAcc& a
 // One workgroup: stop test on [GLB, GUB]; if running, remove the best key from the
 // list and build its row (child r of row ref) and the split points of that row.
 template <int NT>
-__device__ void select_finish(const Params& P, State* S, const SelAcc& tot, double gub) {
+__device__ bool select_finish(const Params& P, State* S, const SelAcc& tot, double gub) {
   __shared__ int32_t go;
   if (threadIdx.x == 0) {
     const Cand b = tot.best;
@@ -322,7 +322,7 @@ __device__ void select_finish(const Params& P, State* S, const SelAcc& tot, doub
     }
   }
   __syncthreads();
-  if (!go) return;
+  if (!go) return false;
   const int64_t row = S->sweeps + 1;
   const int32_t ref = P.key_ref[tot.best.idx];
   const int32_t r = P.key_r[tot.best.idx];
@@ -359,6 +359,7 @@ __device__ void select_finish(const Params& P, State* S, const SelAcc& tot, doub
       S->sel_row = (int32_t)row;
     }
   }
+  return true;
 }
 
 // scan of keys [lo, hi) with lower bound <= GUB into a running selection
@@ -400,7 +401,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_part(const Params* __res
 // the children written by k_bound and the partials visible: no device-scope
 // fences are needed.
 template <int NT>
-__device__ void select_body(const Params& P, State* S, int nparts, int host_stop) {
+__device__ bool select_body(const Params& P, State* S, int nparts, int host_stop) {
   const double gub = okey_inv(S->gub_key);
   SelAcc a = sel_empty();
   if (nparts == 0) {
@@ -420,9 +421,225 @@ __device__ void select_body(const Params& P, State* S, int nparts, int host_stop
       S->n_live = a.cnt;
       S->stop = STOP_HOST;
     }
-    return;
+    return false;
   }
-  select_finish<NT>(P, S, a, gub);
+  return select_finish<NT>(P, S, a, gub);
+}
+
+// ---------------------------------------------------------------------------
+// Incremental bounds (an option): the children of the selected box share every
+// term that involves none of its split coordinates.  The selection workgroup
+// forms the canonical sum of those terms once (slot order, the affected terms
+// left out), the terms of each half of each split coordinate (separable
+// families), and then bounds every child in one thread: F = base + the affected
+// terms in increasing index, the midpoint upper bound likewise, the first-order
+// test on the coordinates whose derivative involves a split coordinate (the
+// parent passed it on every other one, with the same intervals), the widest
+// side from the parent's unsplit sides.  GUB takes the minimum of the children's
+// midpoint bounds (this workgroup is the only writer of the problem's GUB here).
+template <int NT>
+struct IbLds {
+  double tfn[NT], tfh[NT], tu[NT];
+  double red[NT / kWave];
+  int cnt[NT / kWave];
+  double base_n, base_h, base_u;
+  double tf_n[kMaxSplit][2], tf_h[kMaxSplit][2], t_u[kMaxSplit][2], w[kMaxSplit][2];
+  int mono[kMaxSplit][2];
+  int ord[kMaxSplit];
+  int aff[2 * kMaxSplit], naff;   // CHAIN: affected terms, increasing
+  int gc[3 * kMaxSplit], ngc;     // CHAIN: affected derivative coordinates
+};
+
+template <int NT, int FAM>
+__device__ void ib_children(const Params& P, State* S, IbLds<NT>& L) {
+  static_assert(NT % kWave == 0, "whole wavefronts");
+  double* const tfn = L.tfn;
+  double* const tfh = L.tfh;
+  double* const tu = L.tu;
+  double* const s_red = L.red;
+  int* const s_cnt = L.cnt;
+  double& s_base_n = L.base_n;
+  double& s_base_h = L.base_h;
+  double& s_base_u = L.base_u;
+  auto& s_tfn = L.tf_n;
+  auto& s_tfh = L.tf_h;
+  auto& s_tu = L.t_u;
+  auto& s_w = L.w;
+  auto& s_mono = L.mono;
+  int* const s_ord = L.ord;
+  int* const s_aff = L.aff;
+  int& s_naff = L.naff;
+  int* const s_gc = L.gc;
+  int& s_ngc = L.ngc;
+  __syncthreads();   // the selected row, its split points and mask were written by other threads
+  const int n = P.n, m = P.m, lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  const int row = S->sel_row, cyc = S->sel_cyc;
+  const uint32_t mask = S->sel_mask;
+  const double* rn = P.hist_n + (int64_t)row * n;
+  const double* rh = P.hist_h + (int64_t)row * n;
+  const double* mid = P.hist_mid + (int64_t)row * kMaxSplit;
+  auto split_of = [&](int i) -> int {   // j if coordinate i is split, else -1
+    int j = i - cyc;
+    if (j < 0) j += n;
+    return (j < m && ((mask >> j) & 1u)) ? j : -1;
+  };
+  const int T = FAM == FAM_CHAIN ? n - 1 : n;
+
+  // 1. base sums over the terms no split coordinate touches; widest unsplit side
+  I acc{0.0, 0.0};
+  double uacc = 0.0, wb = 0.0;
+  for (int c0 = 0; c0 < n; c0 += NT) {
+    const int i = c0 + (int)threadIdx.x;
+    I t{0.0, 0.0};
+    double u = 0.0;
+    if (i < n && split_of(i) < 0) {
+      const I x{rn[i], rh[i]};
+      wb = dmax(wb, x.n + x.h);
+      if (i < T && !(FAM == FAM_CHAIN && split_of(i + 1) >= 0)) {
+        if (FAM != FAM_CHAIN) {
+          t = sep_term<FAM>(P.sep[i], x);
+          u = sep_point_hi<FAM>(P.sep[i], midpoint(x));
+        } else {
+          const I xn{rn[i + 1], rh[i + 1]};
+          I R, E;
+          t = chain_term(P.chain[i], x, xn, R, E);
+          u = chain_term(P.chain[i], point(midpoint(x)), point(midpoint(xn)), R, E).h;
+        }
+      }
+    }
+    tfn[threadIdx.x] = t.n;
+    tfh[threadIdx.x] = t.h;
+    tu[threadIdx.x] = u;
+    __syncthreads();
+    if (wid == 0)   // slot = lane: terms c0 + q*64 + lane in increasing order
+      for (int q = 0; q < NT / kWave; ++q) {
+        acc = add(acc, I{tfn[q * kWave + lane], tfh[q * kWave + lane]});
+        uacc = uacc + tu[q * kWave + lane];
+      }
+    __syncthreads();
+  }
+  wb = wave_max(wb);
+  if (lane == 0) s_red[wid] = wb;
+  if (wid == 0) {
+    const I F = fold_slots(acc, lane);
+    const double U = fold_slots_hi(uacc, lane);
+    if (lane == 0) { s_base_n = F.n; s_base_h = F.h; s_base_u = U; }
+  }
+  // 2. per split coordinate and half (separable families); order of the split
+  //    coordinates by index; affected CHAIN terms and derivative coordinates
+  if (FAM != FAM_CHAIN && (int)threadIdx.x < 2 * m) {
+    const int j = threadIdx.x >> 1, b = threadIdx.x & 1;
+    if ((mask >> j) & 1u) {
+      const int d = (int)(((int64_t)cyc + j) % n);
+      const double md = mid[j];
+      const I half = b ? I{neg(md), rh[d]} : I{rn[d], md};
+      I tt, G;
+      sep_box<FAM>(P.sep[d], half, tt, G);
+      s_tfn[j][b] = tt.n;
+      s_tfh[j][b] = tt.h;
+      s_mono[j][b] = (G.n < 0.0 && half.n != P.nl[d]) || (G.h < 0.0 && half.h != P.u[d]);
+      s_tu[j][b] = sep_point_hi<FAM>(P.sep[d], midpoint(half));
+      s_w[j][b] = half.n + half.h;
+    }
+  }
+  if (threadIdx.x == 0) {
+    const int start = (n - cyc < m) ? n - cyc : 0;   // first j whose coordinate wrapped to the front
+    for (int k = 0; k < m; ++k) s_ord[k] = (start + k) % m;
+    if (FAM == FAM_CHAIN) {
+      int na = 0, ng = 0, last_a = -1, last_g = -1;
+      for (int k = 0; k < m; ++k) {
+        const int j = s_ord[k];
+        if (!((mask >> j) & 1u)) continue;
+        const int d = (int)(((int64_t)cyc + j) % n);
+        for (int a = d - 1; a <= d; ++a)
+          if (a >= 0 && a <= n - 2 && a > last_a) { s_aff[na++] = a; last_a = a; }
+        for (int g = d - 1; g <= d + 1; ++g)
+          if (g >= 0 && g <= n - 1 && g > last_g) { s_gc[ng++] = g; last_g = g; }
+      }
+      s_naff = na;
+      s_ngc = ng;
+    }
+  }
+  __syncthreads();
+  double wbase = 0.0;
+  for (int k = 0; k < NT / kWave; ++k) wbase = dmax(wbase, s_red[k]);
+  const I base{s_base_n, s_base_h};
+  const double base_u = s_base_u;
+  __syncthreads();   // s_red is reused below
+
+  // 3. the children, one thread each
+  double umin = __builtin_inf();
+  int cnt = 0;
+  for (int c = threadIdx.x; c < P.nch; c += NT) {
+    if (((uint32_t)c & ~mask) != 0u) { P.ch_flag[c] = 0; continue; }
+    I F = base;
+    double u = base_u, wm = wbase;
+    bool mo = false;
+    if (FAM != FAM_CHAIN) {
+      for (int k = 0; k < m; ++k) {
+        const int j = s_ord[k];
+        if (!((mask >> j) & 1u)) continue;
+        const int b = (c >> j) & 1;
+        F = add(F, I{s_tfn[j][b], s_tfh[j][b]});
+        u = u + s_tu[j][b];
+        mo = mo || s_mono[j][b];
+        wm = dmax(wm, s_w[j][b]);
+      }
+    } else {
+      const ChildRow X{rn, rh, mid, n, m, cyc, mask, (uint32_t)c};
+      for (int k = 0; k < s_naff; ++k) {
+        const int a = s_aff[k];
+        const I xa = X.get(a), xb = X.get(a + 1);
+        I R, E;
+        F = add(F, chain_term(P.chain[a], xa, xb, R, E));
+        u = u + chain_term(P.chain[a], point(midpoint(xa)), point(midpoint(xb)), R, E).h;
+      }
+      for (int k = 0; k < s_ngc; ++k) {
+        const int g = s_gc[k];
+        const bool has_prev = g > 0, has_next = g + 1 < n;
+        const I xg = X.get(g);
+        const I xp = has_prev ? X.get(g - 1) : xg;
+        const I xq = has_next ? X.get(g + 1) : xg;
+        const I G = chain_grad(P.chain[has_prev ? g - 1 : g], P.chain[g], xp, xg, xq, has_prev, has_next);
+        mo = mo || (G.n < 0.0 && xg.n != P.nl[g]) || (G.h < 0.0 && xg.h != P.u[g]);
+      }
+      for (int j = 0; j < m; ++j)
+        if ((mask >> j) & 1u) {
+          const I x = X.get((int)(((int64_t)cyc + j) % n));
+          wm = dmax(wm, x.n + x.h);
+        }
+    }
+    P.ch_flo[c] = neg(F.n);
+    P.ch_flag[c] = mo ? 1 : 2;
+    P.ch_wmax[c] = wm;
+    umin = dmin(umin, u + 0.0);
+    ++cnt;
+  }
+  // 4. GUB = min(GUB, children's midpoint bounds)
+  for (int h = 32; h >= 1; h >>= 1) {
+    umin = dmin(umin, __shfl_xor(umin, h, kWave));
+    cnt += __shfl_xor(cnt, h, kWave);
+  }
+  if (lane == 0) { s_red[wid] = umin; s_cnt[wid] = cnt; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mn = s_red[0];
+    int64_t tot = s_cnt[0];
+    for (int k = 1; k < NT / kWave; ++k) { mn = dmin(mn, s_red[k]); tot += s_cnt[k]; }
+    const uint64_t key = okey(mn);
+    if (tot > 0 && key < S->gub_key) S->gub_key = key;
+    S->ub_evaluated += tot;
+  }
+}
+
+template <int NT, int FAM>
+__global__ __launch_bounds__(NT) void k_select_ib(const Params* __restrict__ PP, State* __restrict__ S, int nparts,
+                                                  int host_stop) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params P = *PP;
+  __shared__ IbLds<NT> lds;
+  if (select_body<NT>(P, S, nparts, host_stop)) ib_children<NT, FAM>(P, S, lds);
 }
 
 template <int NT>
@@ -955,7 +1172,7 @@ ibb_status upload_problem(Mem& M, const ibb_problem* p, Params& P, bool want32 =
   P.sep32 = nullptr;
   P.chain32 = nullptr;
   P.prec32 = want32 ? 1 : 0;
-  P.pad32 = 0;
+  P.incremental = 0;
   const int blocks = (n + 255) / 256;
   if (p->family == IBB_CHAIN) {
     CoefChain* c = dalloc<CoefChain>(M, n);
@@ -994,6 +1211,8 @@ struct ibb_result {
   Mem mem;
   Params P{};
   Params* dP = nullptr;
+  State* dS = nullptr;                  // device state, kept so that ibb_sweep can continue the run
+  ibb_options opts{};
   int64_t n_boxes = 0;
   // compacted live keys
   double* flo = nullptr;
@@ -1084,6 +1303,7 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   const int n = prob->n;
   ibb_status st = upload_problem(M, prob, P, U.opts.precision == IBB_FP32_BULK && fp32_safe(prob));
   if (st != IBB_OK) return st;
+  P.incremental = U.opts.incremental ? 1 : 0;
   P.m = std::min(n, U.opts.split_dims);
   P.nch = 1 << P.m;
   P.tol_f = prob->tol_f;
@@ -1167,6 +1387,17 @@ ibb_status run_capacity(Run& U, int chunk) {
     P.key_cap = nc;
     changed = true;
   }
+  const int64_t need_tr = std::min<int64_t>(U.sweeps + chunk + 1, (int64_t)1 << 17);
+  if (need_tr > P.trace_cap) {   // a run continued by ibb_sweep past its first budget
+    const int64_t nc = std::min<int64_t>(std::max<int64_t>(2 * P.trace_cap, need_tr), (int64_t)1 << 17);
+    const int64_t keep = std::min<int64_t>(U.sweeps, P.trace_cap);
+    ibb_status st = IBB_OK;
+    if ((st = grow(M, P.tr_gub, keep, nc)) != IBB_OK || (st = grow(M, P.tr_nsurv, keep, nc)) != IBB_OK ||
+        (st = grow(M, P.tr_nlive, keep, nc)) != IBB_OK || (st = grow(M, P.tr_sel, keep, nc)) != IBB_OK)
+      return st;
+    P.trace_cap = nc;
+    changed = true;
+  }
   if (changed) return push_params(M, P, U.dP);
   return IBB_OK;
 }
@@ -1236,6 +1467,11 @@ ibb_status check_options(const ibb_options& o) {
   if (o.split_dims < 1 || o.split_dims > kMaxSplit) return fail(IBB_E_INVALID, "split_dims must be in 1..16");
   if (o.select_k != 1) return fail(IBB_E_INVALID, "this build selects one box per sweep (select_k = 1)");
   if (o.precision != IBB_FP64 && o.precision != IBB_FP32_BULK) return fail(IBB_E_INVALID, "unknown precision");
+  if (o.incremental != 0 && o.incremental != 1) return fail(IBB_E_INVALID, "incremental must be 0 or 1");
+  if (o.incremental && o.precision == IBB_FP32_BULK)
+    return fail(IBB_E_INVALID, "the FP32 filter works on full bounds: set incremental = 0 with IBB_FP32_BULK");
+  if (o.incremental && o.bound_shape != 0)
+    return fail(IBB_E_INVALID, "bound_shape applies to full bounds (incremental = 0)");
   if (o.max_sweeps < 0) return fail(IBB_E_INVALID, "max_sweeps must be >= 0");
   return IBB_OK;
 }
@@ -1339,6 +1575,88 @@ ibb_status autotune_bound(Run& U, int n_tiles, int& best) {
   return IBB_OK;
 }
 
+// Run sweeps in chunks (4, 8, ..., 256 sweeps enqueued between two reads of the
+// device state) until the stop test or the time limit ends the iteration.
+ibb_status run_sweeps(Run& U, int bound_shape) {
+  ibb_result* R = U.R;
+  Mem& M = R->mem;
+  Params& P = R->P;
+  ibb_status st = IBB_OK;
+  struct Events {
+    std::vector<hipEvent_t> v;
+    ~Events() { for (auto e : v) (void)hipEventDestroy(e); }
+  } evs;
+  auto& ev = evs.v;
+  int chunk = 4;
+  for (;;) {
+    if ((st = run_capacity(U, chunk)) != IBB_OK) return st;
+    const int sb = sel_blocks_for(U.n_keys + (int64_t)(chunk + 1) * P.nch);
+    const bool prof = U.opts.profile != 0;
+    if (prof && (int)ev.size() < 4 * chunk) {
+      const size_t old_n = ev.size();
+      ev.resize(4 * chunk);
+      for (size_t e = old_n; e < ev.size(); ++e)
+        if (hipEventCreate(&ev[e]) != hipSuccess) return (fail(IBB_E_DEVICE, "hipEventCreate failed"));
+    }
+    dispatch_family(P.family, [&](auto fam) {
+      constexpr int FAM = decltype(fam)::value;
+      for (int s = 0; s < chunk; ++s) {
+        if (sb > 1)
+          hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
+                                nullptr, 0, U.dP, U.dS);
+        if (P.incremental) {   // selection and the children's bounds in one workgroup
+          hipExtLaunchKernelGGL((k_select_ib<kSelSingleThreads, FAM>), dim3(1), dim3(kSelSingleThreads), 0, M.stream,
+                                (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
+                                U.dS, sb > 1 ? sb : 0, 0);
+          continue;
+        }
+        hipExtLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
+                              (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
+                              U.dS, sb > 1 ? sb : 0, 0);
+        launch_bound<FAM>(bound_shape, P.nch, M.stream, prof ? ev[4 * s + 1] : nullptr, prof ? ev[4 * s + 2] : nullptr,
+                          U.dP, U.dS);
+      }
+    });
+    if (hipGetLastError() != hipSuccess) return (fail(IBB_E_DEVICE, "sweep launch failed"));
+    if (hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
+        hipStreamSynchronize(M.stream) != hipSuccess)
+      return (fail(IBB_E_DEVICE, "sweep failed"));
+    if (prof) {
+      // bound launches that did work in this chunk; the select of the stopping sweep ran too
+      const int64_t ran = (U.hs.sweeps + (U.hs.pending ? 1 : 0)) - (U.sweeps + (U.pending ? 1 : 0));
+      for (int s = 0; s < chunk; ++s) {
+        float ms = 0.f;
+        if (s < ran || (s == ran && U.hs.stop)) {
+          if (hipEventElapsedTime(&ms, ev[4 * s + 0], ev[4 * s + 3]) == hipSuccess) R->info.t_select_ms += ms;
+          R->info.n_select_launches++;
+        }
+        if (s < ran && !P.incremental) {
+          if (hipEventElapsedTime(&ms, ev[4 * s + 1], ev[4 * s + 2]) == hipSuccess) R->info.t_bound_ms += ms;
+          R->info.n_bound_launches++;
+        }
+      }
+    }
+    if (U.hs.stop) { if ((st = run_after_chunk(U)) != IBB_OK) return st; break; }
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - U.t0).count();
+    if (U.opts.time_limit_s > 0.0 && el > U.opts.time_limit_s) {
+      // insert the last sweep's children, then stop
+      const int sbf = sel_blocks_for(U.hs.n_keys);
+      if (sbf > 1) hipLaunchKernelGGL(k_select_part, dim3(sbf), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+      hipLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS,
+                         sbf > 1 ? sbf : 0, 1);
+      if (hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
+          hipStreamSynchronize(M.stream) != hipSuccess)
+        return (fail(IBB_E_DEVICE, "final insert failed"));
+      U.n_keys = U.hs.n_keys;
+      U.sweeps = U.hs.sweeps;
+      break;
+    }
+    if ((st = run_after_chunk(U)) != IBB_OK) return st;
+    chunk = std::min(chunk * 2, 256);
+  }
+  return IBB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1354,6 +1672,8 @@ ibb_status ibb_options_default(ibb_options* o) {
   o->time_limit_s = 0.0;
   o->profile = 0;
   o->bound_shape = 0;
+  o->incremental = 1;
+  o->reserved = 0;
   return IBB_OK;
 }
 
@@ -1394,6 +1714,8 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
   U.dS = dalloc<State>(M, 1);
   if (!U.dP || !U.dS) return bail(fail(IBB_E_NOMEM, "device allocation failed"));
   R->dP = U.dP;
+  R->dS = U.dS;
+  R->opts = U.opts;
   if ((st = run_setup(U, prob)) != IBB_OK) return bail(st);
   Params& P = R->P;
   const int n = P.n;
@@ -1410,79 +1732,15 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
   const int n_tiles = (n + kWave - 1) / kWave;
   const uint64_t tune_key = ((uint64_t)P.family << 40) | ((uint64_t)std::min(n_tiles, 1 << 20) << 8) |
                             ((uint64_t)P.m << 1) | (uint64_t)(P.prec32 != 0);
-  if (bound_variant < 0) bound_variant = tuned_shape(tune_key);
-  if (bound_variant < 0) {
+  if (P.incremental) bound_variant = -1;
+  else if (bound_variant < 0) bound_variant = tuned_shape(tune_key);
+  if (!P.incremental && bound_variant < 0) {
     st = autotune_bound(U, n_tiles, bound_variant);
     if (st != IBB_OK) return bail(st);
     store_tuned_shape(tune_key, bound_variant);
   }
   R->info.bound_shape = bound_variant;
-  struct Events {
-    std::vector<hipEvent_t> v;
-    ~Events() { for (auto e : v) (void)hipEventDestroy(e); }
-  } evs;
-  auto& ev = evs.v;
-  int chunk = 4;
-  for (;;) {
-    if ((st = run_capacity(U, chunk)) != IBB_OK) return bail(st);
-    const int sb = sel_blocks_for(U.n_keys + (int64_t)(chunk + 1) * P.nch);
-    const bool prof = U.opts.profile != 0;
-    if (prof && (int)ev.size() < 4 * chunk) {
-      const size_t old_n = ev.size();
-      ev.resize(4 * chunk);
-      for (size_t e = old_n; e < ev.size(); ++e)
-        if (hipEventCreate(&ev[e]) != hipSuccess) return bail(fail(IBB_E_DEVICE, "hipEventCreate failed"));
-    }
-    dispatch_family(P.family, [&](auto fam) {
-      constexpr int FAM = decltype(fam)::value;
-      for (int s = 0; s < chunk; ++s) {
-        if (sb > 1)
-          hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
-                                nullptr, 0, U.dP, U.dS);
-        hipExtLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
-                              (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
-                              U.dS, sb > 1 ? sb : 0, 0);
-        launch_bound<FAM>(bound_variant, P.nch, M.stream, prof ? ev[4 * s + 1] : nullptr, prof ? ev[4 * s + 2] : nullptr,
-                          U.dP, U.dS);
-      }
-    });
-    if (hipGetLastError() != hipSuccess) return bail(fail(IBB_E_DEVICE, "sweep launch failed"));
-    if (hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
-        hipStreamSynchronize(M.stream) != hipSuccess)
-      return bail(fail(IBB_E_DEVICE, "sweep failed"));
-    if (prof) {
-      // bound launches that did work in this chunk; the select of the stopping sweep ran too
-      const int64_t ran = (U.hs.sweeps + (U.hs.pending ? 1 : 0)) - (U.sweeps + (U.pending ? 1 : 0));
-      for (int s = 0; s < chunk; ++s) {
-        float ms = 0.f;
-        if (s < ran || (s == ran && U.hs.stop)) {
-          if (hipEventElapsedTime(&ms, ev[4 * s + 0], ev[4 * s + 3]) == hipSuccess) R->info.t_select_ms += ms;
-          R->info.n_select_launches++;
-        }
-        if (s < ran) {
-          if (hipEventElapsedTime(&ms, ev[4 * s + 1], ev[4 * s + 2]) == hipSuccess) R->info.t_bound_ms += ms;
-          R->info.n_bound_launches++;
-        }
-      }
-    }
-    if (U.hs.stop) { if ((st = run_after_chunk(U)) != IBB_OK) return bail(st); break; }
-    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - U.t0).count();
-    if (U.opts.time_limit_s > 0.0 && el > U.opts.time_limit_s) {
-      // insert the last sweep's children, then stop
-      const int sbf = sel_blocks_for(U.hs.n_keys);
-      if (sbf > 1) hipLaunchKernelGGL(k_select_part, dim3(sbf), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
-      hipLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS,
-                         sbf > 1 ? sbf : 0, 1);
-      if (hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
-          hipStreamSynchronize(M.stream) != hipSuccess)
-        return bail(fail(IBB_E_DEVICE, "final insert failed"));
-      U.n_keys = U.hs.n_keys;
-      U.sweeps = U.hs.sweeps;
-      break;
-    }
-    if ((st = run_after_chunk(U)) != IBB_OK) return bail(st);
-    chunk = std::min(chunk * 2, 256);
-  }
+  if ((st = run_sweeps(U, bound_variant)) != IBB_OK) return bail(st);
   if ((st = run_finish(U)) != IBB_OK) return bail(st);
   *out = R;
   return (ibb_status)R->info.status;
@@ -1494,6 +1752,44 @@ ibb_status ibb_solve(const ibb_problem* prob, const ibb_options* opts, const ibb
     return solve_impl(prob, opts, alloc, hip_stream, out);
   } catch (...) {
     return fail(IBB_E_INTERNAL, "exception in ibb_solve");
+  }
+}
+
+ibb_status ibb_sweep(ibb_result* R, int64_t n_sweeps, void* hip_stream) {
+  try {
+    if (!R) return fail(IBB_E_INVALID, "result is NULL");
+    if (n_sweeps < 0) return fail(IBB_E_INVALID, "n_sweeps < 0");
+    if (!R->dS || !R->dP) return fail(IBB_E_INVALID, "result holds no device state");
+    Run U;
+    U.R = R;
+    U.dP = R->dP;
+    U.dS = R->dS;
+    U.opts = R->opts;
+    Mem& M = R->mem;
+    M.stream = (hipStream_t)hip_stream;
+    Params& P = R->P;
+    HIPCHK(hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream));
+    HIPCHK(hipStreamSynchronize(M.stream));
+    if (n_sweeps == 0 || U.hs.stop == STOP_CONVERGED || U.hs.stop == STOP_EMPTY) return (ibb_status)R->info.status;
+    const double before = R->info.seconds;
+    U.t0 = std::chrono::steady_clock::now();
+    U.n_keys = U.hs.n_keys;
+    U.sweeps = U.hs.sweeps;
+    U.pending = U.hs.pending != 0;
+    P.max_sweeps = U.hs.sweeps + n_sweeps;
+    ibb_status st = push_params(M, P, U.dP);
+    if (st != IBB_OK) return st;
+    const int32_t running = RUNNING;
+    HIPCHK(hipMemcpyAsync(&U.dS->stop, &running, sizeof(int32_t), hipMemcpyHostToDevice, M.stream));
+    HIPCHK(hipStreamSynchronize(M.stream));
+    if ((st = run_sweeps(U, R->info.bound_shape)) != IBB_OK) return st;
+    M.put(R->flo); M.put(R->seq); M.put(R->ref); M.put(R->r); M.put(R->wmax);
+    R->flo = nullptr; R->seq = nullptr; R->ref = nullptr; R->r = nullptr; R->wmax = nullptr;
+    if ((st = run_finish(U)) != IBB_OK) return st;
+    R->info.seconds += before;
+    return (ibb_status)R->info.status;
+  } catch (...) {
+    return fail(IBB_E_INTERNAL, "exception in ibb_sweep");
   }
 }
 

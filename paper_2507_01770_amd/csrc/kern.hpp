@@ -35,7 +35,9 @@ struct Params {
   int64_t max_sweeps, max_live;
   const CoefSep* sep;                     // [n] (separable families)
   const CoefChain* chain;                 // [n] (CHAIN; entry n-1 is zero)
-  int32_t prec32, pad32;                  // 1: the FP32 filter may run (the sweep's State.use32 decides)
+  int32_t prec32;                         // 1: the FP32 filter may run (the sweep's State.use32 decides)
+  int32_t incremental;                    // 1: children are bounded by the selection workgroup from the
+                                          //    parent's shared terms (no bound kernel)
   const CoefSep32* sep32;                 // [n] float enclosures of the coefficients (filter only)
   const CoefChain32* chain32;             // [n]
   const double* nl;                       // [n] -l

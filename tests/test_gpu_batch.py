@@ -115,3 +115,37 @@ def test_server_rejects_invalid():
             srv.submit(p)
         with pytest.raises(ibb.IbbError):
             srv.poll(12345)
+
+
+def test_server_on_the_null_stream(alone):
+    # the legacy null stream cannot be captured: the engine then runs on a stream of its own
+    ps = mix()[:3]
+    with ibb.Server(mem_budget_bytes=1 << 30, max_slots=2, stream=torch.cuda.default_stream()) as srv:
+        tickets = [srv.submit(p, **BUDGET) for p in ps]
+        res = {}
+        t0 = time.time()
+        while len(res) < len(tickets) and time.time() - t0 < 120:
+            for t in tickets:
+                if t not in res:
+                    r = srv.poll(t, fetch_boxes=True, max_boxes_fetched=500)
+                    if r is not None:
+                        res[t] = r
+            time.sleep(0.001)
+    assert len(res) == len(tickets)
+    for t, a in zip(tickets, alone[:3]):
+        same(a, res[t])
+
+
+def test_batch_full_bounds_equals_alone():
+    # children bounded over all n terms by the batched bound kernel (one wavefront each);
+    # the solves alone run one after another in this process, so later ones get
+    # recycled device memory from the caching allocator
+    ps = mix()
+    print("case batch full bounds", flush=True)
+    alone = []
+    for p in ps:
+        print(f"case alone full bounds {p.name}", flush=True)
+        alone.append(ibb.minimize(p, max_boxes_fetched=500, incremental=False, **BUDGET))
+    got = ibb.solve_batch(ps, max_boxes_fetched=500, incremental=False, **BUDGET)
+    for a, b in zip(alone, got):
+        same(a, b)

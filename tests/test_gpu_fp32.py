@@ -233,7 +233,7 @@ def test_fp32_filter_off_equals_fp64():
     p = _with(p, coef=np.concatenate([np.full(6, 1e15), p.coef[6:]]))
     print("case fp32 off", flush=True)
     a = ibb.minimize(p, precision="fp32_bulk", max_sweeps=40)
-    b = ibb.minimize(p, precision="fp64", max_sweeps=40)
+    b = ibb.minimize(p, precision="fp64", max_sweeps=40, incremental=False)
     assert a.fp32_sweeps == 0 and a.fp32_pruned == 0
     assert (a.f_lo, a.f_hi, a.sweeps, a.boxes_evaluated) == (b.f_lo, b.f_hi, b.sweeps, b.boxes_evaluated)
     assert np.array_equal(a.trace_gub, b.trace_gub) and np.array_equal(a.flo, b.flo)

@@ -27,23 +27,29 @@ def inside_some_box(x, lo, hi):
     return bool(np.any(np.all((lo <= x) & (x <= hi), axis=1)))
 
 
-def run_both(p, **kw):
-    print(f"case {p.name} {kw}", flush=True)
-    r = ibb.minimize(p, **kw)
+def run_both(p, incremental, **kw):
+    """The same iteration on the GPU and in the oracle, with full or incremental child bounds."""
+    print(f"case {p.name} incremental={incremental} {kw}", flush=True)
+    r = ibb.minimize(p, incremental=incremental, **kw)
     o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=p.tol_x,
-                max_sweeps=kw.get("max_sweeps", 100000))
+                max_sweeps=kw.get("max_sweeps", 100000), incremental=incremental)
     return r, o
+
+
+MODES = [False, True]
 
 
 # [-2, 2.3] keeps x* = 1 off the bisection points, so the runs take 40-50 sweeps;
 # n = 13 on [-2, 2] does not converge quickly and stops on the sweep budget.
 # n = 70 and 100 use two wavefronts per child, n = 200 four.
+# n = 13 runs 300 sweeps: the row arrays grow past 256 rows on the way.
 @pytest.mark.parametrize("n,hi,budget", [(2, 2.0, 3000), (3, 2.3, 3000), (5, 2.3, 3000), (8, 2.3, 3000),
-                                         (12, 2.3, 3000), (13, 2.0, 150), (70, 2.0, 3000), (100, 2.3, 30),
+                                         (12, 2.3, 3000), (13, 2.0, 300), (70, 2.0, 3000), (100, 2.3, 30),
                                          (200, 2.3, 20)])
-def test_chain_identical_iteration(n, hi, budget):
+@pytest.mark.parametrize("incremental", MODES)
+def test_chain_identical_iteration(n, hi, budget, incremental):
     p = PR.chain(n, 505, hi=hi)
-    r, o = run_both(p, max_sweeps=budget)
+    r, o = run_both(p, incremental, max_sweeps=budget)
     assert r.status == o.status
     assert r.sweeps == o.sweeps
     assert np.array_equal(r.trace_gub, o.trace_gub)
@@ -62,9 +68,10 @@ def boxes_equal_count(r, o):
 
 @pytest.mark.parametrize("fam,n,seed", [(PR.SEP_COS, 1, 1), (PR.SEP_COS, 2, 101), (PR.SEP_COS, 9, 2),
                                         (PR.SEP_ABS_SIN2, 2, 3), (PR.SEP_ABS_SIN2, 12, 4)])
-def test_separable_matches_oracle(fam, n, seed):
+@pytest.mark.parametrize("incremental", MODES)
+def test_separable_matches_oracle(fam, n, seed, incremental):
     p = PR.make(fam, n, seed)
-    r, o = run_both(p, max_sweeps=20000)
+    r, o = run_both(p, incremental, max_sweeps=20000)
     assert r.status == ibb.OK and o.status == O.ST_OK
     for res in (r, o):
         assert res.f_lo <= 0.0 <= res.f_hi and res.f_hi - res.f_lo <= 1e-6
@@ -75,38 +82,41 @@ def test_separable_matches_oracle(fam, n, seed):
     assert np.allclose(r.trace_gub[:k], o.trace_gub[:k], rtol=1e-12, atol=1e-12)
 
 
-def test_budget_and_width_criterion():
+@pytest.mark.parametrize("incremental", MODES)
+def test_budget_and_width_criterion(incremental):
     p = PR.sep_cos(6, 9)
-    r = ibb.minimize(p, max_sweeps=4)
+    r = ibb.minimize(p, max_sweeps=4, incremental=incremental)
     assert r.status == ibb.NOT_CONVERGED and r.sweeps == 4
     assert r.f_lo <= 0.0 <= r.f_hi and inside_some_box(p.x_star, r.lo, r.hi)
     # a time limit stops on the host between chunks; the last children are still inserted
-    r = ibb.minimize(p, time_limit_s=1e-9)
+    r = ibb.minimize(p, time_limit_s=1e-9, incremental=incremental)
     assert r.status == ibb.NOT_CONVERGED and r.sweeps >= 1
     assert r.f_lo <= 0.0 <= r.f_hi and inside_some_box(p.x_star, r.lo, r.hi)
     assert r.trace_nsurv.sum() + 1 - r.sweeps >= r.n_boxes
     p.tol_x = 1e-4
-    r = ibb.minimize(p, max_sweeps=20000)
+    r = ibb.minimize(p, max_sweeps=20000, incremental=incremental)
     assert r.status == ibb.OK and np.all(r.hi - r.lo < 1e-4)
 
 
-def test_workload0_full_parity():
+@pytest.mark.parametrize("incremental", MODES)
+def test_workload0_full_parity(incremental):
     p = PR.config(0)
-    r, o = run_both(p)
+    r, o = run_both(p, incremental)
     assert r.status == ibb.OK and r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6
     assert r.sweeps == o.sweeps
 
 
 @pytest.mark.parametrize("cfg,prefix", [(1, 6), (2, 12)])
-def test_workload_full_run_and_prefix(cfg, prefix):
+@pytest.mark.parametrize("incremental", MODES)
+def test_workload_full_run_and_prefix(cfg, prefix, incremental):
     p = PR.config(cfg)
-    print(f"case workload {cfg} full", flush=True)
-    r = ibb.minimize(p, max_sweeps=200000, fetch_boxes=True, max_boxes_fetched=2000)
+    print(f"case workload {cfg} full incremental={incremental}", flush=True)
+    r = ibb.minimize(p, max_sweeps=200000, fetch_boxes=True, max_boxes_fetched=2000, incremental=incremental)
     assert r.status == ibb.OK, r.status
     assert r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6
     assert inside_some_box(p.x_star, r.lo, r.hi) or r.n_boxes > 2000
     print(f"case workload {cfg} oracle prefix {prefix}", flush=True)
-    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=prefix)
+    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=prefix, incremental=incremental)
     if p.family == PR.CHAIN:
         assert np.array_equal(r.trace_gub[:prefix], o.trace_gub)
         assert np.array_equal(r.trace_nsurv[:prefix], o.trace_nsurv)
@@ -116,13 +126,14 @@ def test_workload_full_run_and_prefix(cfg, prefix):
         assert np.array_equal(r.trace_sel[:prefix], o.trace_sel)
 
 
-def test_workload3_capped_run():
+@pytest.mark.parametrize("incremental,budget", [(False, 40), (True, 400)])
+def test_workload3_capped_run(incremental, budget):
     # n = 10,000: the oracle needs about 30 s per sweep, so only invariants here
     # (the bounds themselves are compared on sampled boxes in test_gpu_eval)
     p = PR.config(3)
-    print("case workload 3 capped", flush=True)
-    r = ibb.minimize(p, max_sweeps=40, fetch_boxes=False)
-    assert r.status == ibb.NOT_CONVERGED and r.sweeps == 40
+    print(f"case workload 3 capped incremental={incremental}", flush=True)
+    r = ibb.minimize(p, max_sweeps=budget, fetch_boxes=False, incremental=incremental)
+    assert r.status == ibb.NOT_CONVERGED and r.sweeps == budget
     assert r.f_lo <= 0.0 <= r.f_hi
     assert r.trace_sel[0] == 0 and np.all(np.diff(r.trace_gub) <= 0)
 
@@ -144,7 +155,7 @@ def test_every_bound_shape_gives_the_same_run(p, shapes):
         r = ibb.minimize(p, max_sweeps=60, bound_shape=s, fetch_boxes=False)
         assert r.bound_shape == s
         runs.append(r)
-    auto = ibb.minimize(p, max_sweeps=60, fetch_boxes=False)
+    auto = ibb.minimize(p, max_sweeps=60, fetch_boxes=False, incremental=False)
     assert auto.bound_shape in shapes
     for r in runs[1:] + [auto]:
         _same_run(runs[0], r)
@@ -161,3 +172,28 @@ def test_forced_shape_rejected_when_not_admissible():
         ibb.minimize(PR.sep_cos(100, 102), max_sweeps=5, bound_shape=4)          # 4 waves, 2 tiles
     with pytest.raises(ibb.IbbError):
         ibb.minimize(PR.sep_cos(9, 2), max_sweeps=5, bound_shape=0, precision="fp32_bulk")
+
+
+@pytest.mark.parametrize("p", [PR.sep_cos(100, 102), PR.chain(70, 505), PR.sep_abs_sin2(12, 4)])
+@pytest.mark.parametrize("incremental", MODES)
+def test_sweep_continues_the_same_run(p, incremental):
+    # budget a, then ibb_sweep in pieces == one run with the summed budget, and a
+    # run continued to convergence == the unbudgeted solve
+    print(f"case ibb_sweep {p.name} incremental={incremental}", flush=True)
+    whole = ibb.minimize(p, max_sweeps=38, fetch_boxes=False, incremental=incremental)   # 3 + 5 x 7
+    with ibb.Run(p, max_sweeps=3, incremental=incremental) as r:
+        assert r.result(fetch_boxes=False).sweeps == 3
+        for _ in range(5):
+            r.sweep(7)
+        got = r.result(fetch_boxes=False)
+        assert r.sweep(0) == got.status             # no sweep: the status as it was
+    _same_run(whole, got)
+    full = ibb.minimize(p, max_sweeps=5000, fetch_boxes=False, incremental=incremental)
+    with ibb.Run(p, max_sweeps=10, incremental=incremental) as r:
+        st = r.sweep(5000)
+        got = r.result(fetch_boxes=False)
+        assert st == full.status == got.status
+        assert r.sweep(10) == got.status            # a converged run stays as it is
+        again = r.result(fetch_boxes=False)
+    _same_run(full, got)
+    _same_run(full, again)
