@@ -223,7 +223,9 @@ ibb_status ibb_point_trig32(int32_t fn, int64_t count, const float* d_y, float* 
 /* Solve count problems together.  outs[i] receives problem i's result (NULL if
  * it failed; free each with ibb_result_free) and statuses[i] its status
  * (IBB_OK, IBB_NOT_CONVERGED or an error).  The call returns IBB_OK unless the
- * batch itself could not run; it synchronises hip_stream. */
+ * batch itself could not run.  The work runs on a stream of its own, ordered
+ * after the work enqueued on hip_stream; the call returns when it is done and the
+ * results are bound to hip_stream. */
 ibb_status ibb_solve_batch(const ibb_problem* probs, int32_t count, const ibb_options* opts,
                            const ibb_allocator* alloc, void* hip_stream, ibb_result** outs, int32_t* statuses);
 
@@ -232,9 +234,11 @@ ibb_status ibb_solve_batch(const ibb_problem* probs, int32_t count, const ibb_op
  * as a captured HIP graph while the set of problems is unchanged).  Between
  * chunks it retires finished problems and admits queued ones while a slot is
  * free (at most max_slots at once) and the device memory in use plus the new
- * problem's starting footprint stays within mem_budget_bytes.  All device work
- * goes to hip_stream (the caller keeps it alive until ibb_server_destroy and
- * until the last result from this server is freed). */
+ * problem's starting footprint stays within mem_budget_bytes.  The server's
+ * device work runs on a stream of its own, ordered after the work enqueued on
+ * hip_stream when the server is created; results are handed over bound to
+ * hip_stream (the caller keeps it alive until the last result from this server
+ * is freed). */
 typedef struct ibb_server ibb_server;
 ibb_status ibb_server_create(size_t mem_budget_bytes, int32_t max_slots, const ibb_allocator* alloc,
                              void* hip_stream, ibb_server** out);

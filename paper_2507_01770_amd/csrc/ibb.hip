@@ -211,11 +211,9 @@ __device__ __forceinline__ SelAcc sel_block_reduce(SelAcc v) {
 // them into the running selection.  One workgroup of NT threads.
 template <int NT>
 __device__ void insert_children(const Params& P, State* S, double gub, SelAcc& acc) {
-  __shared__ int scan[NT];
-  __shared__ int sformed[NT];
-  __shared__ int s_n32;
-  if (threadIdx.x == 0) s_n32 = 0;
-  __syncthreads();
+  constexpr int NW = NT / kWave;
+  __shared__ int w_ins[NW], w_form[NW], w_n32[NW];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
   const int per = (P.nch + NT - 1) / NT;
   const int c0 = threadIdx.x * per, c1 = min(P.nch, c0 + per);
   int mine = 0, nformed = 0, n32 = 0;
@@ -225,23 +223,43 @@ __device__ void insert_children(const Params& P, State* S, double gub, SelAcc& a
     n32 += fl == 3;
     mine += (fl == 2 && !(P.ch_flo[k] > gub));
   }
-  if (n32) atomicAdd(&s_n32, n32);
-  scan[threadIdx.x] = mine;
-  sformed[threadIdx.x] = nformed;
-  __syncthreads();
-  for (int off = 1; off < NT; off <<= 1) {   // inclusive scan
-    const int v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
-    const int f2 = threadIdx.x >= (unsigned)off ? sformed[threadIdx.x - off] : 0;
-    __syncthreads();
-    scan[threadIdx.x] += v;
-    sformed[threadIdx.x] += f2;
-    __syncthreads();
+  // prefix of the survivor counts: inclusive scan inside the wavefront, then
+  // the wavefront totals through LDS (children stay in child order)
+  int incl = mine;
+  for (int h = 1; h < kWave; h <<= 1) {
+    const int o = __shfl_up(incl, h, kWave);
+    if (lane >= h) incl += o;
   }
-  const int total = scan[NT - 1];
+  for (int h = 32; h >= 1; h >>= 1) {
+    nformed += __shfl_xor(nformed, h, kWave);
+    n32 += __shfl_xor(n32, h, kWave);
+  }
+  __shared__ int w_tot[3];
+  __syncthreads();   // the LDS arrays may still be read by a previous call
+  if (lane == kWave - 1) w_ins[wid] = incl;
+  if (lane == 0) { w_form[wid] = nformed; w_n32[wid] = n32; }
+  __syncthreads();
+  if (wid == 0) {    // exclusive prefix of the wavefront totals, and the sums
+    const int v = lane < NW ? w_ins[lane] : 0;
+    int f = lane < NW ? w_form[lane] : 0, q = lane < NW ? w_n32[lane] : 0, x = v;
+    for (int h = 1; h < kWave; h <<= 1) {
+      const int o = __shfl_up(x, h, kWave);
+      if (lane >= h) x += o;
+    }
+    for (int h = 32; h >= 1; h >>= 1) {
+      f += __shfl_xor(f, h, kWave);
+      q += __shfl_xor(q, h, kWave);
+    }
+    if (lane < NW) w_ins[lane] = x - v;
+    if (lane == kWave - 1) w_tot[0] = x;
+    if (lane == 0) { w_tot[1] = f; w_tot[2] = q; }
+  }
+  __syncthreads();
+  const int before = w_ins[wid], total = w_tot[0], formed = w_tot[1], s_n32 = w_tot[2];
   const int64_t base = S->n_keys;
   const int64_t seq0 = S->next_seq;
   const int row = S->sel_row;
-  int64_t o = base + (scan[threadIdx.x] - mine);
+  int64_t o = base + (before + incl - mine);
   SelAcc a = sel_empty();
   for (int k = c0; k < c1; ++k) {
     const double f = P.ch_flo[k];
@@ -270,7 +288,6 @@ __device__ void insert_children(const Params& P, State* S, double gub, SelAcc& a
     }
     S->n_keys = base + total;
     S->next_seq = seq0 + total;
-    const int formed = sformed[NT - 1];
     S->evaluated += formed;
     S->sweeps = t + 1;
     S->pending = 0;
@@ -630,6 +647,27 @@ __device__ void ib_children(const Params& P, State* S, IbLds<NT>& L) {
     if (tot > 0 && key < S->gub_key) S->gub_key = key;
     S->ub_evaluated += tot;
   }
+}
+
+// Up to `iters` whole sweeps with incremental bounds in one workgroup: the
+// selection scans the list itself, the children are bounded and GUB updated,
+// and the next iteration inserts the survivors.  Problems are independent, so
+// one workgroup per problem loops without any grid-wide barrier.
+template <int NT, int FAM>
+__device__ void sweeps_ib(const Params& P, State* S, IbLds<NT>& lds, int iters) {
+  if (S->stop) return;
+  for (int it = 0; it < iters; ++it) {
+    if (!select_body<NT>(P, S, 0, 0)) return;   // stopped (the flag is set)
+    ib_children<NT, FAM>(P, S, lds);
+    __syncthreads();   // GUB, counters and child records are read by the next selection
+  }
+}
+
+template <int NT, int FAM>
+__global__ __launch_bounds__(NT) void k_sweeps_ib(const Params* __restrict__ PP, State* __restrict__ S, int iters) {
+  round_up_mode();
+  __shared__ IbLds<NT> lds;
+  sweeps_ib<NT, FAM>(*PP, S, lds, iters);   // parameters read where used: nothing held across the loop
 }
 
 template <int NT, int FAM>
@@ -1598,8 +1636,16 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
       for (size_t e = old_n; e < ev.size(); ++e)
         if (hipEventCreate(&ev[e]) != hipSuccess) return (fail(IBB_E_DEVICE, "hipEventCreate failed"));
     }
+    // incremental bounds on a list one workgroup scans quickly: the whole chunk of
+    // sweeps in one launch
+    const bool persist = P.incremental && U.n_keys + (int64_t)(chunk + 1) * P.nch <= kPersistentMaxKeys;
     dispatch_family(P.family, [&](auto fam) {
       constexpr int FAM = decltype(fam)::value;
+      if (persist) {
+        hipExtLaunchKernelGGL((k_sweeps_ib<kSweepThreads, FAM>), dim3(1), dim3(kSweepThreads), 0, M.stream,
+                              prof ? ev[0] : nullptr, prof ? ev[3] : nullptr, 0, U.dP, U.dS, chunk);
+        return;
+      }
       for (int s = 0; s < chunk; ++s) {
         if (sb > 1)
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
@@ -1621,7 +1667,13 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
     if (hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
         hipStreamSynchronize(M.stream) != hipSuccess)
       return (fail(IBB_E_DEVICE, "sweep failed"));
-    if (prof) {
+    if (prof && persist) {
+      // one launch for the chunk: its time over the selections it made
+      const int64_t ran = (U.hs.sweeps + (U.hs.pending ? 1 : 0)) - (U.sweeps + (U.pending ? 1 : 0));
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[0], ev[3]) == hipSuccess) R->info.t_select_ms += ms;
+      R->info.n_select_launches += ran + (U.hs.stop ? 1 : 0);
+    } else if (prof) {
       // bound launches that did work in this chunk; the select of the stopping sweep ran too
       const int64_t ran = (U.hs.sweeps + (U.hs.pending ? 1 : 0)) - (U.sweeps + (U.pending ? 1 : 0));
       for (int s = 0; s < chunk; ++s) {

@@ -25,7 +25,9 @@ constexpr int kBoundWaves = 4;            // waves per workgroup in the bound ke
 constexpr int kMaxSplit = 16;             // M <= 16
 constexpr int kSelThreads = 256;
 constexpr int kSelSingleThreads = 1024;   // the one-workgroup selection
+constexpr int kSweepThreads = 512;        // persistent sweeps (room for 256 registers per lane)
 constexpr int kMaxSelBlocks = 1024;
+constexpr int64_t kPersistentMaxKeys = (int64_t)1 << 17;   // one workgroup scans at most this many keys per sweep
 
 enum StopCode { RUNNING = 0, STOP_CONVERGED = 1, STOP_SWEEPS = 2, STOP_LIVE = 3, STOP_EMPTY = 4, STOP_HOST = 5 };
 

@@ -149,3 +149,38 @@ def test_batch_full_bounds_equals_alone():
     got = ibb.solve_batch(ps, max_boxes_fetched=500, incremental=False, **BUDGET)
     for a, b in zip(alone, got):
         same(a, b)
+
+
+def test_server_results_freed_while_it_runs():
+    # the caller receives and frees results while the server thread keeps capturing
+    # and replaying graphs of the remaining problems: frees must never land on the
+    # stream being captured (regression test)
+    reqs = PR.serving_trace(count=48, seed=105, rate=1.0)
+    ps = [q for _, q in reqs]
+    picks = [0, 7, 19, 31, 47]
+    ref = {i: ibb.minimize(ps[i], max_sweeps=200, fetch_boxes=False) for i in picks}
+    with ibb.Server(mem_budget_bytes=1 << 30, max_slots=8) as srv:
+        tickets = []
+        got = {}
+        t0 = time.time()
+        for i, q in enumerate(ps):
+            tickets.append(srv.submit(q, max_sweeps=200))
+            for j, t in enumerate(tickets):         # poll (and so free) while submitting
+                if j not in got:
+                    r = srv.poll(t)
+                    if r is not None:
+                        got[j] = r
+        while len(got) < len(ps) and time.time() - t0 < 150:
+            for j, t in enumerate(tickets):
+                if j not in got:
+                    r = srv.poll(t)
+                    if r is not None:
+                        got[j] = r
+            time.sleep(0.0005)
+        st = srv.stats()
+    assert len(got) == len(ps) and st["completed"] == len(ps)
+    for i in picks:
+        a, b = ref[i], got[i]
+        assert (a.status, a.f_lo, a.f_hi, a.sweeps, a.boxes_evaluated) == (b.status, b.f_lo, b.f_hi, b.sweeps,
+                                                                             b.boxes_evaluated)
+        assert np.array_equal(a.trace_gub, b.trace_gub) and np.array_equal(a.flo, b.flo)
