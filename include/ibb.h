@@ -214,11 +214,14 @@ ibb_status ibb_interval_op32(int32_t op, int64_t count, const float* d_a, const 
 ibb_status ibb_point_trig32(int32_t fn, int64_t count, const float* d_y, float* d_out, void* hip_stream);
 
 /* ---- many problems at once ------------------------------------------------
- * Problems solved together share each sweep's two kernel launches: the
- * selection runs one workgroup per problem, the bounds one wavefront per child
- * of every problem (any mix of families and sizes).  Each problem keeps its own
- * list, rows and GUB and follows exactly the iteration ibb_solve runs for it,
- * so its result is the same bit for bit alone or in any mix. */
+ * Problems solved together share kernel launches: with incremental bounds (the
+ * default) one persistent workgroup per problem runs a whole chunk of its
+ * sweeps in one launch; with full bounds each sweep is two launches (selection,
+ * one workgroup per problem; bounds, one wavefront per child of every problem,
+ * any mix of families and sizes).  ibb_solve_batch captures a chunk as a HIP
+ * graph and replays it while the set of problems is unchanged.  Each problem
+ * keeps its own list, rows and GUB and follows exactly the iteration ibb_solve
+ * runs for it, so its result is the same bit for bit alone or in any mix. */
 
 /* Solve count problems together.  outs[i] receives problem i's result (NULL if
  * it failed; free each with ibb_result_free) and statuses[i] its status
@@ -230,8 +233,8 @@ ibb_status ibb_solve_batch(const ibb_problem* probs, int32_t count, const ibb_op
                            const ibb_allocator* alloc, void* hip_stream, ibb_result** outs, int32_t* statuses);
 
 /* Continuous-batching server.  A host thread owned by the server runs batched
- * sweeps over the admitted problems in chunks of 8 sweeps (each chunk replayed
- * as a captured HIP graph while the set of problems is unchanged).  Between
+ * sweeps over the admitted problems in chunks of 8 sweeps (launched directly,
+ * not captured: the caller's threads use the device meanwhile).  Between
  * chunks it retires finished problems and admits queued ones while a slot is
  * free (at most max_slots at once) and the device memory in use plus the new
  * problem's starting footprint stays within mem_budget_bytes.  The server's

@@ -210,7 +210,7 @@ __device__ __forceinline__ SelAcc sel_block_reduce(SelAcc v) {
 // final GUB of that sweep, first-order test passed), in child order, and fold
 // them into the running selection.  One workgroup of NT threads.
 template <int NT>
-__device__ void insert_children(const Params& P, State* S, double gub, SelAcc& acc) {
+__device__ __forceinline__ void insert_children(const Params& P, State* S, double gub, SelAcc& acc) {
   constexpr int NW = NT / kWave;
   __shared__ int w_ins[NW], w_form[NW], w_n32[NW];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
@@ -315,7 +315,7 @@ __device__ void insert_children(const Params& P, State* S, double gub, SelAcc& a
 // One workgroup: stop test on [GLB, GUB]; if running, remove the best key from the
 // list and build its row (child r of row ref) and the split points of that row.
 template <int NT>
-__device__ bool select_finish(const Params& P, State* S, const SelAcc& tot, double gub) {
+__device__ __forceinline__ bool select_finish(const Params& P, State* S, const SelAcc& tot, double gub) {
   __shared__ int32_t go;
   if (threadIdx.x == 0) {
     const Cand b = tot.best;
@@ -379,20 +379,30 @@ __device__ bool select_finish(const Params& P, State* S, const SelAcc& tot, doub
   return true;
 }
 
-// scan of keys [lo, hi) with lower bound <= GUB into a running selection
+// scan of keys [lo, hi) with lower bound <= GUB into a running selection (four
+// keys per step, loaded together; the result does not depend on the order)
+__device__ __forceinline__ void scan_key(const Params& P, double gub, bool need_w, int64_t i, double f, SelAcc& a) {
+  if (!(f <= gub)) return;   // removed (+inf) or above GUB
+  a.cnt++;
+  if (need_w) a.wm = dmax(a.wm, P.key_wmax[i]);
+  if (f <= a.best.f) {       // only a candidate needs its insertion number
+    const Cand c{f, P.key_seq[i], i};
+    if (better(c, a.best)) a.best = c;
+  }
+}
 __device__ __forceinline__ void scan_keys(const Params& P, double gub, int64_t i0, int64_t i1, int64_t stride,
                                           SelAcc& a) {
   const bool need_w = P.tol_x > 0.0;
-  for (int64_t i = i0; i < i1; i += stride) {
-    const double f = P.key_flo[i];
-    if (!(f <= gub)) continue;   // removed (+inf) or above GUB
-    a.cnt++;
-    if (need_w) a.wm = dmax(a.wm, P.key_wmax[i]);
-    if (f <= a.best.f) {         // only a candidate needs its insertion number
-      const Cand c{f, P.key_seq[i], i};
-      if (better(c, a.best)) a.best = c;
-    }
+  int64_t i = i0;
+  for (; i + 3 * stride < i1; i += 4 * stride) {
+    const double f0 = P.key_flo[i], f1 = P.key_flo[i + stride], f2 = P.key_flo[i + 2 * stride],
+                 f3 = P.key_flo[i + 3 * stride];
+    scan_key(P, gub, need_w, i, f0, a);
+    scan_key(P, gub, need_w, i + stride, f1, a);
+    scan_key(P, gub, need_w, i + 2 * stride, f2, a);
+    scan_key(P, gub, need_w, i + 3 * stride, f3, a);
   }
+  for (; i < i1; i += stride) scan_key(P, gub, need_w, i, P.key_flo[i], a);
 }
 
 // Large lists: every workgroup scans a stretch of the keys and writes a partial.
@@ -418,7 +428,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_part(const Params* __res
 // the children written by k_bound and the partials visible: no device-scope
 // fences are needed.
 template <int NT>
-__device__ bool select_body(const Params& P, State* S, int nparts, int host_stop) {
+__device__ __forceinline__ bool select_body(const Params& P, State* S, int nparts, int host_stop) {
   const double gub = okey_inv(S->gub_key);
   SelAcc a = sel_empty();
   if (nparts == 0) {
@@ -447,47 +457,54 @@ __device__ bool select_body(const Params& P, State* S, int nparts, int host_stop
 // Incremental bounds (an option): the children of the selected box share every
 // term that involves none of its split coordinates.  The selection workgroup
 // forms the canonical sum of those terms once (slot order, the affected terms
-// left out), the terms of each half of each split coordinate (separable
-// families), and then bounds every child in one thread: F = base + the affected
-// terms in increasing index, the midpoint upper bound likewise, the first-order
-// test on the coordinates whose derivative involves a split coordinate (the
-// parent passed it on every other one, with the same intervals), the widest
-// side from the parent's unsplit sides.  GUB takes the minimum of the children's
-// midpoint bounds (this workgroup is the only writer of the problem's GUB here).
+// left out) and a table of the affected terms for every combination of halves
+// of the split coordinates they involve; a child is then bounded in one thread:
+// F = base + its affected terms in increasing index, the midpoint upper bound
+// likewise, the first-order test on the coordinates whose derivative involves a
+// split coordinate (the parent passed it on every other one, with the same
+// intervals), the widest side from the parent's unsplit sides.  GUB takes the
+// minimum of the children's midpoint bounds (this workgroup is the only writer
+// of the problem's GUB here).
+//
+// Tables: for an affected term a the halves of its coordinates (a; a and a + 1
+// for the chained family) index 2 or 4 entries; for an affected derivative
+// coordinate g of the chained family, the halves of g - 1, g, g + 1 index 8
+// test results.  A coordinate that is not split has a single "half", the
+// parent's interval, so its bit is taken as 0.
+constexpr int kIbChunkTerms = 2048;  // base terms evaluated by the workgroup between two barriers
+constexpr int kIbMaxTerms = kMaxSplit + 1;
+constexpr int kIbCacheChildren = 1024;   // children whose bounds are kept in LDS between the two passes
+constexpr int kIbMaxGrad = kMaxSplit + 2;
+
 template <int NT>
 struct IbLds {
-  double tfn[NT], tfh[NT], tu[NT];
+  static constexpr int CH = kIbChunkTerms / NT;   // terms per thread between two barriers
+  double tfn[kIbChunkTerms], tfh[kIbChunkTerms], tu[kIbChunkTerms];
   double red[NT / kWave];
-  int cnt[NT / kWave];
-  double base_n, base_h, base_u;
-  double tf_n[kMaxSplit][2], tf_h[kMaxSplit][2], t_u[kMaxSplit][2], w[kMaxSplit][2];
-  int mono[kMaxSplit][2];
-  int ord[kMaxSplit];
-  int aff[2 * kMaxSplit], naff;   // CHAIN: affected terms, increasing
-  int gc[3 * kMaxSplit], ngc;     // CHAIN: affected derivative coordinates
+  int cnt[NT / kWave], ins[NT / kWave];
+  double base_n, base_h, base_u, wbase, gub;
+  int naff, ngc, tot;
+  int aff[kIbMaxTerms];                 // affected terms, increasing
+  int aj[kIbMaxTerms][2];               // split index of the term's coordinates (-1: not split)
+  double t_n[kIbMaxTerms][4], t_h[kIbMaxTerms][4], t_u[kIbMaxTerms][4];
+  double c_flo[kIbCacheChildren], c_wm[kIbCacheChildren];   // the children's bounds (nch <= kIbCacheChildren)
+  int8_t c_keep[kIbCacheChildren];      // 1: first-order test passed
+  int gc[kIbMaxGrad];                  // CHAIN: affected derivative coordinates, increasing
+  int gj[kIbMaxGrad][3];                // CHAIN: split index of g - 1, g, g + 1 (-1: not split / absent)
+  int gmono[kIbMaxGrad][8];             // first-order test failed, per combination of halves
+  double w[kMaxSplit][2];               // width of each half of each split coordinate
 };
 
+// the interval of coordinate i of the selected row for half b of split index j
+__device__ __forceinline__ I ib_half(const double* rn, const double* rh, const double* mid, int i, int j, int b) {
+  if (j < 0) return I{rn[i], rh[i]};
+  const double md = mid[j];
+  return b ? I{neg(md), rh[i]} : I{rn[i], md};
+}
+
 template <int NT, int FAM>
-__device__ void ib_children(const Params& P, State* S, IbLds<NT>& L) {
+__device__ __forceinline__ void ib_prepare(const Params& P, State* S, IbLds<NT>& L) {
   static_assert(NT % kWave == 0, "whole wavefronts");
-  double* const tfn = L.tfn;
-  double* const tfh = L.tfh;
-  double* const tu = L.tu;
-  double* const s_red = L.red;
-  int* const s_cnt = L.cnt;
-  double& s_base_n = L.base_n;
-  double& s_base_h = L.base_h;
-  double& s_base_u = L.base_u;
-  auto& s_tfn = L.tf_n;
-  auto& s_tfh = L.tf_h;
-  auto& s_tu = L.t_u;
-  auto& s_w = L.w;
-  auto& s_mono = L.mono;
-  int* const s_ord = L.ord;
-  int* const s_aff = L.aff;
-  int& s_naff = L.naff;
-  int* const s_gc = L.gc;
-  int& s_ngc = L.ngc;
   __syncthreads();   // the selected row, its split points and mask were written by other threads
   const int n = P.n, m = P.m, lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
   const int row = S->sel_row, cyc = S->sel_cyc;
@@ -496,170 +513,357 @@ __device__ void ib_children(const Params& P, State* S, IbLds<NT>& L) {
   const double* rh = P.hist_h + (int64_t)row * n;
   const double* mid = P.hist_mid + (int64_t)row * kMaxSplit;
   auto split_of = [&](int i) -> int {   // j if coordinate i is split, else -1
+    if (i < 0 || i >= n) return -1;
     int j = i - cyc;
     if (j < 0) j += n;
     return (j < m && ((mask >> j) & 1u)) ? j : -1;
   };
   const int T = FAM == FAM_CHAIN ? n - 1 : n;
 
-  // 1. base sums over the terms no split coordinate touches; widest unsplit side
-  I acc{0.0, 0.0};
-  double uacc = 0.0, wb = 0.0;
-  for (int c0 = 0; c0 < n; c0 += NT) {
-    const int i = c0 + (int)threadIdx.x;
-    I t{0.0, 0.0};
-    double u = 0.0;
-    if (i < n && split_of(i) < 0) {
-      const I x{rn[i], rh[i]};
-      wb = dmax(wb, x.n + x.h);
-      if (i < T && !(FAM == FAM_CHAIN && split_of(i + 1) >= 0)) {
-        if (FAM != FAM_CHAIN) {
-          t = sep_term<FAM>(P.sep[i], x);
-          u = sep_point_hi<FAM>(P.sep[i], midpoint(x));
+  // 1. lists of affected terms and derivative coordinates, in increasing index
+  if (threadIdx.x == 0) {
+    const int start = (n - cyc < m) ? n - cyc : 0;   // first j whose coordinate wrapped to the front
+    int na = 0, ng = 0, last_a = -1, last_g = -1;
+    for (int k = 0; k < m; ++k) {
+      const int j = (start + k) % m;
+      if (!((mask >> j) & 1u)) continue;
+      const int d = (int)(((int64_t)cyc + j) % n);
+      const int a0 = FAM == FAM_CHAIN ? d - 1 : d;
+      for (int a = a0; a <= d; ++a)
+        if (a >= 0 && a < T && a > last_a) {
+          L.aff[na] = a;
+          L.aj[na][0] = split_of(a);
+          L.aj[na][1] = FAM == FAM_CHAIN ? split_of(a + 1) : -1;
+          ++na;
+          last_a = a;
+        }
+      if (FAM == FAM_CHAIN)
+        for (int g = d - 1; g <= d + 1; ++g)
+          if (g >= 0 && g < n && g > last_g) {
+            L.gc[ng] = g;
+            L.gj[ng][0] = split_of(g - 1);
+            L.gj[ng][1] = split_of(g);
+            L.gj[ng][2] = split_of(g + 1);
+            ++ng;
+            last_g = g;
+          }
+    }
+    L.naff = na;
+    L.ngc = ng;
+  }
+  __syncthreads();
+
+  // 2. the tables (threads from the top down, so that they overlap the base sums
+  //    of the first chunk when n is small) and the widths of the halves
+  static_assert(NT >= 4 * kIbMaxTerms + 8 * kIbMaxGrad, "one thread per table entry");
+  {
+    const int q = NT - 1 - (int)threadIdx.x;
+    const int na = L.naff, ng = L.ngc;
+    if (FAM != FAM_CHAIN) {                     // separable: F, midpoint bound, first-order test of each half
+      if (q < 6 * na) {
+        const int part = q / (2 * na), r = q % (2 * na), k = r >> 1, b = r & 1;
+        const int a = L.aff[k];
+        const I x = ib_half(rn, rh, mid, a, L.aj[k][0], b);
+        if (part == 0) {
+          const I t = sep_term<FAM>(P.sep[a], x);
+          L.t_n[k][b] = t.n;
+          L.t_h[k][b] = t.h;
+        } else if (part == 1) {
+          L.t_u[k][b] = sep_point_hi<FAM>(P.sep[a], midpoint(x));
         } else {
-          const I xn{rn[i + 1], rh[i + 1]};
-          I R, E;
-          t = chain_term(P.chain[i], x, xn, R, E);
-          u = chain_term(P.chain[i], point(midpoint(x)), point(midpoint(xn)), R, E).h;
+          I t, G;
+          sep_box<FAM>(P.sep[a], x, t, G);
+          L.gmono[k][b] = (G.n < 0.0 && x.n != P.nl[a]) || (G.h < 0.0 && x.h != P.u[a]);
         }
       }
+    } else if (q < 4 * na) {                    // chained: affected term, combination of halves
+      const int k = q >> 2, cb = q & 3;
+      const int a = L.aff[k];
+      const int ja = L.aj[k][0], jb = L.aj[k][1];
+      if ((ja >= 0 || !(cb & 1)) && (jb >= 0 || !(cb & 2))) {
+        const I xa = ib_half(rn, rh, mid, a, ja, cb & 1);
+        const I xb = ib_half(rn, rh, mid, a + 1, jb, (cb >> 1) & 1);
+        I R, E;
+        const I t = chain_term(P.chain[a], xa, xb, R, E);
+        L.t_n[k][cb] = t.n;
+        L.t_h[k][cb] = t.h;
+        L.t_u[k][cb] = chain_term(P.chain[a], point(midpoint(xa)), point(midpoint(xb)), R, E).h;
+      }
+    } else if (q < 4 * na + 8 * ng) {           // chained: test per combination of halves of g - 1, g, g + 1
+      const int k = (q - 4 * na) >> 3, cb = (q - 4 * na) & 7;
+      const int g = L.gc[k];
+      const int j0 = L.gj[k][0], j1 = L.gj[k][1], j2 = L.gj[k][2];
+      int mo = 0;
+      if ((j0 >= 0 || !(cb & 1)) && (j1 >= 0 || !(cb & 2)) && (j2 >= 0 || !(cb & 4))) {
+        const bool has_prev = g > 0, has_next = g + 1 < n;
+        const I xg = ib_half(rn, rh, mid, g, j1, (cb >> 1) & 1);
+        const I xp = has_prev ? ib_half(rn, rh, mid, g - 1, j0, cb & 1) : xg;
+        const I xq = has_next ? ib_half(rn, rh, mid, g + 1, j2, (cb >> 2) & 1) : xg;
+        const I G = chain_grad(P.chain[has_prev ? g - 1 : g], P.chain[g], xp, xg, xq, has_prev, has_next);
+        mo = (G.n < 0.0 && xg.n != P.nl[g]) || (G.h < 0.0 && xg.h != P.u[g]);
+      }
+      L.gmono[k][cb] = mo;
     }
-    tfn[threadIdx.x] = t.n;
-    tfh[threadIdx.x] = t.h;
-    tu[threadIdx.x] = u;
+  }
+  if ((int)threadIdx.x < 2 * m) {              // widths of the halves
+    const int j = threadIdx.x >> 1, b = threadIdx.x & 1;
+    if ((mask >> j) & 1u) {
+      const I x = ib_half(rn, rh, mid, (int)(((int64_t)cyc + j) % n), j, b);
+      L.w[j][b] = x.n + x.h;
+    }
+  }
+
+  // 3. base sums over the terms no split coordinate touches; widest unsplit side
+  I acc{0.0, 0.0};
+  double uacc = 0.0, wb = 0.0;
+  constexpr int CH = IbLds<NT>::CH;
+  for (int c0 = 0; c0 < n; c0 += CH * NT) {
+    for (int r = 0; r < CH; ++r) {
+      const int i = c0 + r * NT + (int)threadIdx.x;
+      I t{0.0, 0.0};
+      double u = 0.0;
+      if (i < n && split_of(i) < 0) {
+        const I x{rn[i], rh[i]};
+        wb = dmax(wb, x.n + x.h);
+        if (i < T && !(FAM == FAM_CHAIN && split_of(i + 1) >= 0)) {
+          if (FAM != FAM_CHAIN) {
+            t = sep_term<FAM>(P.sep[i], x);
+            u = sep_point_hi<FAM>(P.sep[i], midpoint(x));
+          } else {
+            const I xn{rn[i + 1], rh[i + 1]};
+            I R, E;
+            t = chain_term(P.chain[i], x, xn, R, E);
+            u = chain_term(P.chain[i], point(midpoint(x)), point(midpoint(xn)), R, E).h;
+          }
+        }
+      }
+      L.tfn[r * NT + threadIdx.x] = t.n;
+      L.tfh[r * NT + threadIdx.x] = t.h;
+      L.tu[r * NT + threadIdx.x] = u;
+    }
     __syncthreads();
     if (wid == 0)   // slot = lane: terms c0 + q*64 + lane in increasing order
-      for (int q = 0; q < NT / kWave; ++q) {
-        acc = add(acc, I{tfn[q * kWave + lane], tfh[q * kWave + lane]});
-        uacc = uacc + tu[q * kWave + lane];
+      for (int q = 0; q < CH * NT / kWave; ++q) {
+        acc = add(acc, I{L.tfn[q * kWave + lane], L.tfh[q * kWave + lane]});
+        uacc = uacc + L.tu[q * kWave + lane];
       }
     __syncthreads();
   }
   wb = wave_max(wb);
-  if (lane == 0) s_red[wid] = wb;
+  if (lane == 0) L.red[wid] = wb;
   if (wid == 0) {
     const I F = fold_slots(acc, lane);
     const double U = fold_slots_hi(uacc, lane);
-    if (lane == 0) { s_base_n = F.n; s_base_h = F.h; s_base_u = U; }
-  }
-  // 2. per split coordinate and half (separable families); order of the split
-  //    coordinates by index; affected CHAIN terms and derivative coordinates
-  if (FAM != FAM_CHAIN && (int)threadIdx.x < 2 * m) {
-    const int j = threadIdx.x >> 1, b = threadIdx.x & 1;
-    if ((mask >> j) & 1u) {
-      const int d = (int)(((int64_t)cyc + j) % n);
-      const double md = mid[j];
-      const I half = b ? I{neg(md), rh[d]} : I{rn[d], md};
-      I tt, G;
-      sep_box<FAM>(P.sep[d], half, tt, G);
-      s_tfn[j][b] = tt.n;
-      s_tfh[j][b] = tt.h;
-      s_mono[j][b] = (G.n < 0.0 && half.n != P.nl[d]) || (G.h < 0.0 && half.h != P.u[d]);
-      s_tu[j][b] = sep_point_hi<FAM>(P.sep[d], midpoint(half));
-      s_w[j][b] = half.n + half.h;
-    }
-  }
-  if (threadIdx.x == 0) {
-    const int start = (n - cyc < m) ? n - cyc : 0;   // first j whose coordinate wrapped to the front
-    for (int k = 0; k < m; ++k) s_ord[k] = (start + k) % m;
-    if (FAM == FAM_CHAIN) {
-      int na = 0, ng = 0, last_a = -1, last_g = -1;
-      for (int k = 0; k < m; ++k) {
-        const int j = s_ord[k];
-        if (!((mask >> j) & 1u)) continue;
-        const int d = (int)(((int64_t)cyc + j) % n);
-        for (int a = d - 1; a <= d; ++a)
-          if (a >= 0 && a <= n - 2 && a > last_a) { s_aff[na++] = a; last_a = a; }
-        for (int g = d - 1; g <= d + 1; ++g)
-          if (g >= 0 && g <= n - 1 && g > last_g) { s_gc[ng++] = g; last_g = g; }
-      }
-      s_naff = na;
-      s_ngc = ng;
-    }
+    if (lane == 0) { L.base_n = F.n; L.base_h = F.h; L.base_u = U; }
   }
   __syncthreads();
-  double wbase = 0.0;
-  for (int k = 0; k < NT / kWave; ++k) wbase = dmax(wbase, s_red[k]);
-  const I base{s_base_n, s_base_h};
-  const double base_u = s_base_u;
-  __syncthreads();   // s_red is reused below
+  if (threadIdx.x == 0) {
+    double w = 0.0;
+    for (int k = 0; k < NT / kWave; ++k) w = dmax(w, L.red[k]);
+    L.wbase = w;
+  }
+  __syncthreads();
+}
 
-  // 3. the children, one thread each
+// bounds of child c from the tables: lower bound, first-order test failed,
+// widest side, midpoint upper bound
+template <int NT, int FAM>
+__device__ __forceinline__ void ib_child(const Params& P, const IbLds<NT>& L, uint32_t mask, int m, uint32_t c,
+                                         double& flo, bool& mo, double& wm, double& u) {
+  I F{L.base_n, L.base_h};
+  u = L.base_u;
+  wm = L.wbase;
+  mo = false;
+  const int na = L.naff;
+  for (int k = 0; k < na; ++k) {
+    const int ja = L.aj[k][0], jb = L.aj[k][1];
+    const int cb = (ja >= 0 ? (int)((c >> ja) & 1u) : 0) | (jb >= 0 ? (int)((c >> jb) & 1u) << 1 : 0);
+    F = add(F, I{L.t_n[k][cb], L.t_h[k][cb]});
+    u = u + L.t_u[k][cb];
+    if (FAM != FAM_CHAIN) mo = mo || L.gmono[k][cb];
+  }
+  if (FAM == FAM_CHAIN) {
+    const int ng = L.ngc;
+    for (int k = 0; k < ng; ++k) {
+      const int j0 = L.gj[k][0], j1 = L.gj[k][1], j2 = L.gj[k][2];
+      const int cb = (j0 >= 0 ? (int)((c >> j0) & 1u) : 0) | (j1 >= 0 ? (int)((c >> j1) & 1u) << 1 : 0) |
+                     (j2 >= 0 ? (int)((c >> j2) & 1u) << 2 : 0);
+      mo = mo || L.gmono[k][cb];
+    }
+  }
+  for (int j = 0; j < m; ++j)
+    if ((mask >> j) & 1u) wm = dmax(wm, L.w[j][(c >> j) & 1u]);
+  flo = neg(F.n);
+}
+
+// GUB = min(GUB, the children's midpoint bounds); returns the new GUB to every thread
+template <int NT, int FAM>
+__device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  const uint32_t mask = S->sel_mask;
   double umin = __builtin_inf();
   int cnt = 0;
+  const bool cache = P.nch <= kIbCacheChildren;
   for (int c = threadIdx.x; c < P.nch; c += NT) {
-    if (((uint32_t)c & ~mask) != 0u) { P.ch_flag[c] = 0; continue; }
-    I F = base;
-    double u = base_u, wm = wbase;
-    bool mo = false;
-    if (FAM != FAM_CHAIN) {
-      for (int k = 0; k < m; ++k) {
-        const int j = s_ord[k];
-        if (!((mask >> j) & 1u)) continue;
-        const int b = (c >> j) & 1;
-        F = add(F, I{s_tfn[j][b], s_tfh[j][b]});
-        u = u + s_tu[j][b];
-        mo = mo || s_mono[j][b];
-        wm = dmax(wm, s_w[j][b]);
-      }
-    } else {
-      const ChildRow X{rn, rh, mid, n, m, cyc, mask, (uint32_t)c};
-      for (int k = 0; k < s_naff; ++k) {
-        const int a = s_aff[k];
-        const I xa = X.get(a), xb = X.get(a + 1);
-        I R, E;
-        F = add(F, chain_term(P.chain[a], xa, xb, R, E));
-        u = u + chain_term(P.chain[a], point(midpoint(xa)), point(midpoint(xb)), R, E).h;
-      }
-      for (int k = 0; k < s_ngc; ++k) {
-        const int g = s_gc[k];
-        const bool has_prev = g > 0, has_next = g + 1 < n;
-        const I xg = X.get(g);
-        const I xp = has_prev ? X.get(g - 1) : xg;
-        const I xq = has_next ? X.get(g + 1) : xg;
-        const I G = chain_grad(P.chain[has_prev ? g - 1 : g], P.chain[g], xp, xg, xq, has_prev, has_next);
-        mo = mo || (G.n < 0.0 && xg.n != P.nl[g]) || (G.h < 0.0 && xg.h != P.u[g]);
-      }
-      for (int j = 0; j < m; ++j)
-        if ((mask >> j) & 1u) {
-          const I x = X.get((int)(((int64_t)cyc + j) % n));
-          wm = dmax(wm, x.n + x.h);
-        }
+    if (((uint32_t)c & ~mask) != 0u) continue;
+    double flo, wm, u;
+    bool mo;
+    ib_child<NT, FAM>(P, L, mask, P.m, (uint32_t)c, flo, mo, wm, u);
+    if (cache) {
+      L.c_flo[c] = flo;
+      L.c_wm[c] = wm;
+      L.c_keep[c] = mo ? 0 : 1;
     }
-    P.ch_flo[c] = neg(F.n);
-    P.ch_flag[c] = mo ? 1 : 2;
-    P.ch_wmax[c] = wm;
     umin = dmin(umin, u + 0.0);
     ++cnt;
   }
-  // 4. GUB = min(GUB, children's midpoint bounds)
   for (int h = 32; h >= 1; h >>= 1) {
     umin = dmin(umin, __shfl_xor(umin, h, kWave));
     cnt += __shfl_xor(cnt, h, kWave);
   }
-  if (lane == 0) { s_red[wid] = umin; s_cnt[wid] = cnt; }
+  if (lane == 0) { L.red[wid] = umin; L.cnt[wid] = cnt; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double mn = s_red[0];
-    int64_t tot = s_cnt[0];
-    for (int k = 1; k < NT / kWave; ++k) { mn = dmin(mn, s_red[k]); tot += s_cnt[k]; }
+    double mn = L.red[0];
+    int tot = L.cnt[0];
+    for (int k = 1; k < NT / kWave; ++k) { mn = dmin(mn, L.red[k]); tot += L.cnt[k]; }
     const uint64_t key = okey(mn);
-    if (tot > 0 && key < S->gub_key) S->gub_key = key;
+    uint64_t g = S->gub_key;
+    if (tot > 0 && key < g) {
+      g = key;
+      S->gub_key = key;
+    }
     S->ub_evaluated += tot;
+    L.gub = okey_inv(g);
+    L.tot = tot;
+  }
+  __syncthreads();
+  return L.gub;
+}
+
+// The survivors (first-order test passed, lower bound <= the new GUB) are
+// appended right away, in child order, exactly as the next selection would
+// insert them from child records (the full-bound path): no records round-trip
+// through device memory
+template <int NT, int FAM>
+__device__ __forceinline__ void ib_children_insert(const Params& P, State* S, IbLds<NT>& L) {
+  ib_prepare<NT, FAM>(P, S, L);
+  const double gub = ib_gub<NT, FAM>(P, S, L);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  const uint32_t mask = S->sel_mask;
+  const int64_t base = S->n_keys, seq0 = S->next_seq;
+  const int row = S->sel_row;
+  int64_t done = 0;
+  for (int c0 = 0; c0 < P.nch; c0 += NT) {
+    const int c = c0 + (int)threadIdx.x;
+    double flo = 0.0, wm = 0.0, u;
+    bool mo = true;
+    const bool formed = c < P.nch && (((uint32_t)c & ~mask) == 0u);
+    if (formed) {
+      if (P.nch <= kIbCacheChildren) {
+        flo = L.c_flo[c];
+        wm = L.c_wm[c];
+        mo = L.c_keep[c] == 0;
+      } else {
+        ib_child<NT, FAM>(P, L, mask, P.m, (uint32_t)c, flo, mo, wm, u);
+      }
+    }
+    const int keep = formed && !mo && !(flo > gub);
+    int incl = keep;
+    for (int h = 1; h < kWave; h <<= 1) {
+      const int o = __shfl_up(incl, h, kWave);
+      if (lane >= h) incl += o;
+    }
+    if (lane == kWave - 1) L.ins[wid] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < NT / kWave; ++k) {
+      const int v = L.ins[k];
+      before += k < wid ? v : 0;
+      total += v;
+    }
+    if (keep) {
+      const int64_t o = done + before + incl - 1;
+      P.key_flo[base + o] = flo;
+      P.key_seq[base + o] = seq0 + o;
+      P.key_ref[base + o] = row;
+      P.key_r[base + o] = c;
+      P.key_wmax[base + o] = wm;
+    }
+    done += total;
+    __syncthreads();   // L.ins is rewritten by the next round
+  }
+  if (threadIdx.x == 0) {
+    const int64_t t = S->sweeps;
+    if (t < P.trace_cap) {
+      P.tr_gub[t] = gub;
+      P.tr_nsurv[t] = done;
+      P.tr_sel[t] = S->sel_seq;
+    }
+    S->n_keys = base + done;
+    S->next_seq = seq0 + done;
+    S->evaluated += L.tot;
+    S->sweeps = t + 1;
+    S->pending = 0;
   }
 }
 
 // Up to `iters` whole sweeps with incremental bounds in one workgroup: the
-// selection scans the list itself, the children are bounded and GUB updated,
-// and the next iteration inserts the survivors.  Problems are independent, so
-// one workgroup per problem loops without any grid-wide barrier.
+// selection scans the list itself, the children are bounded, GUB updated and
+// the survivors inserted.  Problems are independent, so one workgroup per
+// problem loops without any grid-wide barrier.
+// Stable in-place compaction of the keys by one workgroup: keys whose lower
+// bound exceeds GUB (and removed keys, +inf) are dropped; the order, and so the
+// insertion numbers and every later selection, are unchanged.  Each chunk of NT
+// keys is read completely before any of it is written, and a key only moves to
+// a lower index, so no key is overwritten before it has been read.
+template <int NT>
+__device__ __forceinline__ void compact_in_place(const Params& P, State* S, IbLds<NT>& L) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  const double gub = okey_inv(S->gub_key);
+  const int64_t nk = S->n_keys;
+  int64_t kept = 0;
+  for (int64_t c0 = 0; c0 < nk; c0 += NT) {
+    const int64_t i = c0 + threadIdx.x;
+    double f = __builtin_inf(), w = 0.0;
+    int64_t sq = 0;
+    int32_t rf = 0, rr = 0;
+    const bool in = i < nk;
+    if (in) { f = P.key_flo[i]; sq = P.key_seq[i]; rf = P.key_ref[i]; rr = P.key_r[i]; w = P.key_wmax[i]; }
+    const int keep = in && f <= gub;
+    int incl = keep;
+    for (int h = 1; h < kWave; h <<= 1) {
+      const int o = __shfl_up(incl, h, kWave);
+      if (lane >= h) incl += o;
+    }
+    if (lane == kWave - 1) L.ins[wid] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < NT / kWave; ++k) {
+      const int v = L.ins[k];
+      before += k < wid ? v : 0;
+      total += v;
+    }
+    if (keep) {
+      const int64_t o = kept + before + incl - 1;
+      P.key_flo[o] = f; P.key_seq[o] = sq; P.key_ref[o] = rf; P.key_r[o] = rr; P.key_wmax[o] = w;
+    }
+    kept += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) S->n_keys = kept;
+  __syncthreads();
+}
+
 template <int NT, int FAM>
-__device__ void sweeps_ib(const Params& P, State* S, IbLds<NT>& lds, int iters) {
+__device__ __forceinline__ void sweeps_ib(const Params& P, State* S, IbLds<NT>& lds, int iters) {
   if (S->stop) return;
   for (int it = 0; it < iters; ++it) {
+    // dead keys dominate the list: drop them before the scan
+    if (S->n_keys > 4 * (S->n_live + P.nch) && S->n_keys > 4096) compact_in_place<NT>(P, S, lds);
     if (!select_body<NT>(P, S, 0, 0)) return;   // stopped (the flag is set)
-    ib_children<NT, FAM>(P, S, lds);
-    __syncthreads();   // GUB, counters and child records are read by the next selection
+    ib_children_insert<NT, FAM>(P, S, lds);
+    __syncthreads();   // keys and counters are read by the next selection
   }
 }
 
@@ -677,7 +881,7 @@ __global__ __launch_bounds__(NT) void k_select_ib(const Params* __restrict__ PP,
   if (S->stop) return;
   const Params P = *PP;
   __shared__ IbLds<NT> lds;
-  if (select_body<NT>(P, S, nparts, host_stop)) ib_children<NT, FAM>(P, S, lds);
+  if (select_body<NT>(P, S, nparts, host_stop)) ib_children_insert<NT, FAM>(P, S, lds);
 }
 
 template <int NT>
@@ -1080,6 +1284,11 @@ namespace {
 
 thread_local std::string g_err;
 
+// Held while a graph is being captured (batched solves) and while results are
+// read back or freed: HIP refuses some operations in one thread while another
+// thread captures.
+std::mutex g_capture_mu;
+
 ibb_status fail(ibb_status s, const std::string& msg) {
   g_err = msg;
   return s;
@@ -1446,7 +1655,7 @@ ibb_status run_after_chunk(Run& U) {
   U.sweeps = U.hs.sweeps;
   U.pending = U.hs.pending != 0;
   Params& P = U.R->P;
-  if (!U.hs.stop && U.n_keys > 4 * (U.hs.n_live + P.nch) && U.n_keys > (int64_t)1 << 16) {
+  if (!U.hs.stop && U.n_keys > 4 * (U.hs.n_live + P.nch) && U.n_keys > (int64_t)1 << 14) {
     Mem& M = U.R->mem;
     double* f; int64_t* sq; int32_t* rf; int32_t* rr; double* wx; int64_t kept = 0;
     ibb_status st = compact_keys(M, P, U.dP, U.dS, U.n_keys, P.key_cap, f, sq, rf, rr, wx, kept);
@@ -1638,12 +1847,13 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
     }
     // incremental bounds on a list one workgroup scans quickly: the whole chunk of
     // sweeps in one launch
-    const bool persist = P.incremental && U.n_keys + (int64_t)(chunk + 1) * P.nch <= kPersistentMaxKeys;
+    const bool persist = P.incremental && U.n_keys <= kPersistentMaxKeys;
     dispatch_family(P.family, [&](auto fam) {
       constexpr int FAM = decltype(fam)::value;
       if (persist) {
         hipExtLaunchKernelGGL((k_sweeps_ib<kSweepThreads, FAM>), dim3(1), dim3(kSweepThreads), 0, M.stream,
-                              prof ? ev[0] : nullptr, prof ? ev[3] : nullptr, 0, U.dP, U.dS, chunk);
+                              prof ? ev[0] : nullptr, prof ? ev[3] : nullptr, 0, U.dP, U.dS,
+                              std::min(chunk, kPersistentChunk));
         return;
       }
       for (int s = 0; s < chunk; ++s) {
@@ -1860,8 +2070,11 @@ ibb_status ibb_result_boxes(const ibb_result* res, double* lo, double* hi, doubl
   if (k == 0) return IBB_OK;
   Mem& M = R->mem;
   const int n = R->P.n;
-  if (f_lo_per_box) HIPCHK(hipMemcpy(f_lo_per_box, R->flo, k * sizeof(double), hipMemcpyDeviceToHost));
-  if (seq) HIPCHK(hipMemcpy(seq, R->seq, k * sizeof(int64_t), hipMemcpyDeviceToHost));
+  // copies on the result's own stream (never a legacy-stream copy: another
+  // thread of the process may be capturing a graph), serialised with captures
+  std::lock_guard<std::mutex> lk(g_capture_mu);
+  if (f_lo_per_box) HIPCHK(hipMemcpyAsync(f_lo_per_box, R->flo, k * sizeof(double), hipMemcpyDeviceToHost, M.stream));
+  if (seq) HIPCHK(hipMemcpyAsync(seq, R->seq, k * sizeof(int64_t), hipMemcpyDeviceToHost, M.stream));
   if (lo || hi) {
     double* dlo = dalloc<double>(M, k * n);
     double* dhi = dalloc<double>(M, k * n);
@@ -1869,13 +2082,12 @@ ibb_status ibb_result_boxes(const ibb_result* res, double* lo, double* hi, doubl
     hipLaunchKernelGGL(k_rows_out, dim3((unsigned)std::min<int64_t>(k, 65535)), dim3(256), 0, M.stream, R->dP, k, R->ref,
                        R->r, dlo, dhi);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(M.stream));
-    if (lo) HIPCHK(hipMemcpy(lo, dlo, k * n * sizeof(double), hipMemcpyDeviceToHost));
-    if (hi) HIPCHK(hipMemcpy(hi, dhi, k * n * sizeof(double), hipMemcpyDeviceToHost));
+    if (lo) HIPCHK(hipMemcpyAsync(lo, dlo, k * n * sizeof(double), hipMemcpyDeviceToHost, M.stream));
+    if (hi) HIPCHK(hipMemcpyAsync(hi, dhi, k * n * sizeof(double), hipMemcpyDeviceToHost, M.stream));
     M.put(dlo);
     M.put(dhi);
-    HIPCHK(hipStreamSynchronize(M.stream));
   }
+  HIPCHK(hipStreamSynchronize(M.stream));
   return IBB_OK;
 }
 
@@ -1895,6 +2107,7 @@ ibb_status ibb_result_trace(const ibb_result* res, double* gub, int64_t* n_inser
 
 void ibb_result_free(ibb_result* res) {
   if (!res) return;
+  std::lock_guard<std::mutex> lk(g_capture_mu);
   (void)hipStreamSynchronize(res->mem.stream);
   res->mem.release_all();
   (void)hipStreamSynchronize(res->mem.stream);
