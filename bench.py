@@ -91,16 +91,17 @@ def main() -> int:
     res, dt = timed(args.steps, args.warmup)
     boxes = sum(r.boxes_evaluated for r in res)
     r0 = res[-1]
-    # dominant kernel: the selection kernel, which also bounds the children
-    ib_ops = incremental_ops_per_sweep(p.n, min(p.n, 10)) * r0.sweeps
-    t_sel = r0.t_select_ms * 1e-3
-    ach = ib_ops / t_sel / 1e12 if t_sel > 0 else 0.0
+    # dominant kernel: the persistent sweep kernel (selection and the children's bounds in
+    # one workgroup, up to 64 sweeps per launch); one unit of work is one sweep
+    ib_ops_sweep = incremental_ops_per_sweep(p.n, min(p.n, 10))
+    n_sw = max(1, r0.n_select_launches)
+    t_sweep = r0.t_select_ms * 1e-3 / n_sw
+    ach = ib_ops_sweep / t_sweep / 1e12 if t_sweep > 0 else 0.0
     roofline = {
-        "bound": "alu", "kernel": "k_select_ib<SEP_COS> (one workgroup per sweep)", "achieved": round(ach, 6),
-        "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 8), "traffic": None,
-        "avg_launch_us": round(r0.t_select_ms * 1e3 / max(1, r0.n_select_launches), 3),
-        "launches_per_solve": r0.n_select_launches,
-        "flops_per_launch": round(ib_ops / max(1, r0.n_select_launches)),
+        "bound": "alu", "kernel": "k_sweeps_ib<SEP_COS> (persistent, one workgroup)", "per": "sweep",
+        "achieved": round(ach, 6), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 8),
+        "traffic": measured_traffic(), "avg_sweep_us": round(t_sweep * 1e6, 3), "sweeps_per_solve": r0.sweeps,
+        "flops_per_sweep": round(ib_ops_sweep),
     }
 
     # the same workload with full bounds (every child over all n terms): k_bound's roofline
@@ -172,6 +173,24 @@ def main() -> int:
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def measured_traffic():
+    """HBM bytes per sweep of the persistent sweep kernel, from the committed rocprofv3 FETCH_SIZE and
+    WRITE_SIZE counts (scaled by a plain copy's), when the kernel sources are the ones measured; else None."""
+    import glob
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_bytes_sep_cos_n100.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(\{.*?\})\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    src = sorted(glob.glob(os.path.join(ROOT, "paper_2507_01770_amd", "csrc", "*")))
+    h = hashlib.sha256(b"".join(open(f, "rb").read() for f in src)).hexdigest()[:16]
+    return rec["bytes_per_sweep"] if rec.get("source_hash") == h else None
 
 
 def copy_probe(mib: int) -> int:

@@ -27,7 +27,7 @@ constexpr int kSelThreads = 256;
 constexpr int kSelSingleThreads = 1024;   // the one-workgroup selection
 constexpr int kSweepThreads = 512;        // persistent sweeps (room for 256 registers per lane)
 constexpr int kMaxSelBlocks = 1024;
-constexpr int64_t kPersistentMaxKeys = (int64_t)1 << 15;   // lists one workgroup scans faster than a grid
+constexpr int64_t kPersistentMaxKeys = (int64_t)1 << 18;   // lists one workgroup scans about as fast as a grid
 constexpr int kPersistentChunk = 64;                        // sweeps per persistent launch (the list grows meanwhile)
 
 enum StopCode { RUNNING = 0, STOP_CONVERGED = 1, STOP_SWEEPS = 2, STOP_LIVE = 3, STOP_EMPTY = 4, STOP_HOST = 5 };
