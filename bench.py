@@ -59,6 +59,7 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=128, help="requests in the serving trace (0 = skip)")
     ap.add_argument("--fp32-steps", type=int, default=5, help="solves of the same workload with the FP32 filter (0 = skip)")
     ap.add_argument("--full-steps", type=int, default=5, help="solves of the same workload with full bounds (0 = skip)")
+    ap.add_argument("--workloads", type=int, default=1, help="1: also solve the n = 2, 1000 and 10000 workloads once")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM traffic counters) and exit")
     args = ap.parse_args()
@@ -143,6 +144,24 @@ def main() -> int:
                 "bound_avg_launch_us": round(q.t_bound_ms * 1e3 / max(1, q.n_bound_launches), 3),
                 "enclosure": [q.f_lo, q.f_hi]}
 
+    # the other workloads, solved completely once each (incremental bounds)
+    workloads = None
+    if args.workloads:
+        workloads = {}
+        for cfg in (0, 2, 3):
+            q = PR.config(cfg)
+            if cfg != 3:
+                ibb.minimize(q, fetch_boxes=False)
+            torch.cuda.synchronize()
+            tq = time.perf_counter()
+            rq = ibb.minimize(q, fetch_boxes=False)
+            torch.cuda.synchronize()
+            dq = time.perf_counter() - tq
+            assert rq.status == ibb.OK and rq.f_lo <= 0.0 <= rq.f_hi and rq.f_hi - rq.f_lo <= 1e-6, (cfg, rq.f_lo, rq.f_hi)
+            workloads[f"{PR.FAMILY_NAMES[q.family]}_n{q.n}"] = {
+                "time_to_enclosure_ms": round(dq * 1e3, 3), "sweeps": rq.sweeps, "boxes": rq.boxes_evaluated,
+                "boxes_per_s": round(rq.boxes_evaluated / dq, 1), "enclosure": [rq.f_lo, rq.f_hi]}
+
     serving = serve_bench(args.serve_requests) if args.serve_requests > 0 else None
 
     line = {
@@ -166,6 +185,7 @@ def main() -> int:
             "enclosure": [r0.f_lo, r0.f_hi], "bounds": "incremental",
             "full_bounds": full,
             "fp32_bulk_full_bounds": fp32,
+            "other_workloads": workloads,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
