@@ -354,12 +354,12 @@ __device__ __forceinline__ bool select_finish(const Params& P, State* S, const S
     dn[i] = x.n;
     dh[i] = x.h;
   }
-  const int cyc = r >= 0 ? (int)(((int64_t)pcyc + P.m) % n) : pcyc;
+  const int cyc = r >= 0 ? add_mod(pcyc, P.m, n) : pcyc;   // m <= n
   if (threadIdx.x < (unsigned)kWave) {
     const int j = threadIdx.x;
     bool ok = false;
     if (j < P.m) {
-      const int d = (int)(((int64_t)cyc + j) % n);
+      const int d = add_mod(cyc, j, n);
       const I x = src.get(d);                 // same values as the row just written
       const double md = midpoint(x);
       ok = neg(x.n) < md && md < x.h;
@@ -405,6 +405,37 @@ __device__ __forceinline__ void scan_keys(const Params& P, double gub, int64_t i
   for (; i < i1; i += stride) scan_key(P, gub, need_w, i, P.key_flo[i], a);
 }
 
+// The whole list by one workgroup: pairs of keys in 16-byte loads, eight pairs
+// in flight per thread (a single workgroup's scan is bound by load latency).
+template <int NT>
+__device__ __forceinline__ void scan_keys_wg(const Params& P, double gub, int64_t nk, SelAcc& a) {
+  if ((reinterpret_cast<uintptr_t>(P.key_flo) & 15u) != 0u) {   // caller's allocator gave 8-byte alignment
+    scan_keys(P, gub, threadIdx.x, nk, NT, a);
+    return;
+  }
+  const bool need_w = P.tol_x > 0.0;
+  const double2* f2 = reinterpret_cast<const double2*>(P.key_flo);
+  const int64_t np = nk >> 1;
+  constexpr int U = 8;
+  int64_t p = threadIdx.x;
+  for (; p + (U - 1) * NT < np; p += U * NT) {
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = f2[p + u * NT];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      scan_key(P, gub, need_w, 2 * (p + u * NT), v[u].x, a);
+      scan_key(P, gub, need_w, 2 * (p + u * NT) + 1, v[u].y, a);
+    }
+  }
+  for (; p < np; p += NT) {
+    const double2 v = f2[p];
+    scan_key(P, gub, need_w, 2 * p, v.x, a);
+    scan_key(P, gub, need_w, 2 * p + 1, v.y, a);
+  }
+  if ((nk & 1) && threadIdx.x == 0) scan_key(P, gub, need_w, nk - 1, P.key_flo[nk - 1], a);
+}
+
 // Large lists: every workgroup scans a stretch of the keys and writes a partial.
 __global__ __launch_bounds__(kSelThreads) void k_select_part(const Params* __restrict__ PP, State* __restrict__ S) {
   if (S->stop) return;
@@ -432,7 +463,7 @@ __device__ __forceinline__ bool select_body(const Params& P, State* S, int npart
   const double gub = okey_inv(S->gub_key);
   SelAcc a = sel_empty();
   if (nparts == 0) {
-    scan_keys(P, gub, threadIdx.x, S->n_keys, NT, a);
+    scan_keys_wg<NT>(P, gub, S->n_keys, a);
   } else {
     for (int k = threadIdx.x; k < nparts; k += NT) {
       const SelAcc o{Cand{P.part_flo[k], P.part_seq[k], P.part_idx[k]}, P.part_wmax[k], P.part_cnt[k]};
@@ -475,6 +506,9 @@ constexpr int kIbChunkTerms = 2048;  // base terms evaluated by the workgroup be
 constexpr int kIbMaxTerms = kMaxSplit + 1;
 constexpr int kIbCacheChildren = 1024;   // children whose bounds are kept in LDS between the two passes
 constexpr int kIbMaxGrad = kMaxSplit + 2;
+constexpr int kIbGroup = 6;              // table rows a child reads together (their LDS reads overlap)
+constexpr int kIbSlots = 18;             // rows of each table: a multiple of kIbGroup, >= both maxima above
+static_assert(kIbSlots % kIbGroup == 0 && kIbSlots >= kIbMaxTerms && kIbSlots >= kIbMaxGrad, "table rows");
 
 template <int NT>
 struct IbLds {
@@ -484,14 +518,14 @@ struct IbLds {
   int cnt[NT / kWave], ins[NT / kWave];
   double base_n, base_h, base_u, wbase, gub;
   int naff, ngc, tot;
-  int aff[kIbMaxTerms];                 // affected terms, increasing
-  int aj[kIbMaxTerms][2];               // split index of the term's coordinates (-1: not split)
-  double t_n[kIbMaxTerms][4], t_h[kIbMaxTerms][4], t_u[kIbMaxTerms][4];
+  int aff[kIbSlots];                 // affected terms, increasing
+  int aj[kIbSlots][2];                  // split index of the term's coordinates (-1: not split)
+  double t_n[kIbSlots][4], t_h[kIbSlots][4], t_u[kIbSlots][4];
   double c_flo[kIbCacheChildren], c_wm[kIbCacheChildren];   // the children's bounds (nch <= kIbCacheChildren)
   int8_t c_keep[kIbCacheChildren];      // 1: first-order test passed
-  int gc[kIbMaxGrad];                  // CHAIN: affected derivative coordinates, increasing
-  int gj[kIbMaxGrad][3];                // CHAIN: split index of g - 1, g, g + 1 (-1: not split / absent)
-  int gmono[kIbMaxGrad][8];             // first-order test failed, per combination of halves
+  int gc[kIbSlots];                  // CHAIN: affected derivative coordinates, increasing
+  int gj[kIbSlots][3];                   // CHAIN: split index of g - 1, g, g + 1 (-1: not split / absent)
+  int gmono[kIbSlots][8];                // first-order test failed, per combination of halves
   double w[kMaxSplit][2];               // width of each half of each split coordinate
 };
 
@@ -525,9 +559,9 @@ __device__ __forceinline__ void ib_prepare(const Params& P, State* S, IbLds<NT>&
     const int start = (n - cyc < m) ? n - cyc : 0;   // first j whose coordinate wrapped to the front
     int na = 0, ng = 0, last_a = -1, last_g = -1;
     for (int k = 0; k < m; ++k) {
-      const int j = (start + k) % m;
+      const int j = add_mod(start, k, m);
       if (!((mask >> j) & 1u)) continue;
-      const int d = (int)(((int64_t)cyc + j) % n);
+      const int d = add_mod(cyc, j, n);
       const int a0 = FAM == FAM_CHAIN ? d - 1 : d;
       for (int a = a0; a <= d; ++a)
         if (a >= 0 && a < T && a > last_a) {
@@ -608,7 +642,7 @@ __device__ __forceinline__ void ib_prepare(const Params& P, State* S, IbLds<NT>&
   if ((int)threadIdx.x < 2 * m) {              // widths of the halves
     const int j = threadIdx.x >> 1, b = threadIdx.x & 1;
     if ((mask >> j) & 1u) {
-      const I x = ib_half(rn, rh, mid, (int)(((int64_t)cyc + j) % n), j, b);
+      const I x = ib_half(rn, rh, mid, add_mod(cyc, j, n), j, b);
       L.w[j][b] = x.n + x.h;
     }
   }
@@ -642,8 +676,11 @@ __device__ __forceinline__ void ib_prepare(const Params& P, State* S, IbLds<NT>&
       L.tu[r * NT + threadIdx.x] = u;
     }
     __syncthreads();
-    if (wid == 0)   // slot = lane: terms c0 + q*64 + lane in increasing order
-      for (int q = 0; q < CH * NT / kWave; ++q) {
+    // slot = lane: terms c0 + q*64 + lane in increasing order (rows past n hold
+    // only zeros, and a zero added to a slot sum started at +0 changes no bit)
+    const int qn = min(CH * NT / kWave, (n - c0 + kWave - 1) / kWave);
+    if (wid == 0)
+      for (int q = 0; q < qn; ++q) {
         acc = add(acc, I{L.tfn[q * kWave + lane], L.tfh[q * kWave + lane]});
         uacc = uacc + L.tu[q * kWave + lane];
       }
@@ -665,8 +702,12 @@ __device__ __forceinline__ void ib_prepare(const Params& P, State* S, IbLds<NT>&
   __syncthreads();
 }
 
+// bit j of child c; 0 for j < 0 (the coordinate is not split)
+__device__ __forceinline__ int child_bit(uint32_t c, int j) { return j >= 0 ? (int)((c >> (j & 31)) & 1u) : 0; }
+
 // bounds of child c from the tables: lower bound, first-order test failed,
-// widest side, midpoint upper bound
+// widest side, midpoint upper bound.  Rows are read kIbGroup at a time (a row
+// past the table's length is read but not used), then added in increasing order.
 template <int NT, int FAM>
 __device__ __forceinline__ void ib_child(const Params& P, const IbLds<NT>& L, uint32_t mask, int m, uint32_t c,
                                          double& flo, bool& mo, double& wm, double& u) {
@@ -675,20 +716,40 @@ __device__ __forceinline__ void ib_child(const Params& P, const IbLds<NT>& L, ui
   wm = L.wbase;
   mo = false;
   const int na = L.naff;
-  for (int k = 0; k < na; ++k) {
-    const int ja = L.aj[k][0], jb = L.aj[k][1];
-    const int cb = (ja >= 0 ? (int)((c >> ja) & 1u) : 0) | (jb >= 0 ? (int)((c >> jb) & 1u) << 1 : 0);
-    F = add(F, I{L.t_n[k][cb], L.t_h[k][cb]});
-    u = u + L.t_u[k][cb];
-    if (FAM != FAM_CHAIN) mo = mo || L.gmono[k][cb];
+  for (int k0 = 0; k0 < na; k0 += kIbGroup) {
+    int cb[kIbGroup];
+#pragma unroll
+    for (int g = 0; g < kIbGroup; ++g) cb[g] = child_bit(c, L.aj[k0 + g][0]) | (child_bit(c, L.aj[k0 + g][1]) << 1);
+    double tn[kIbGroup], th[kIbGroup], tu[kIbGroup];
+    int gm[kIbGroup];
+#pragma unroll
+    for (int g = 0; g < kIbGroup; ++g) {
+      tn[g] = L.t_n[k0 + g][cb[g]];
+      th[g] = L.t_h[k0 + g][cb[g]];
+      tu[g] = L.t_u[k0 + g][cb[g]];
+      gm[g] = FAM != FAM_CHAIN ? L.gmono[k0 + g][cb[g]] : 0;
+    }
+#pragma unroll
+    for (int g = 0; g < kIbGroup; ++g)
+      if (k0 + g < na) {
+        F = add(F, I{tn[g], th[g]});
+        u = u + tu[g];
+        mo = mo || gm[g];
+      }
   }
   if (FAM == FAM_CHAIN) {
     const int ng = L.ngc;
-    for (int k = 0; k < ng; ++k) {
-      const int j0 = L.gj[k][0], j1 = L.gj[k][1], j2 = L.gj[k][2];
-      const int cb = (j0 >= 0 ? (int)((c >> j0) & 1u) : 0) | (j1 >= 0 ? (int)((c >> j1) & 1u) << 1 : 0) |
-                     (j2 >= 0 ? (int)((c >> j2) & 1u) << 2 : 0);
-      mo = mo || L.gmono[k][cb];
+    for (int k0 = 0; k0 < ng; k0 += kIbGroup) {
+      int gm[kIbGroup];
+#pragma unroll
+      for (int g = 0; g < kIbGroup; ++g) {
+        const int cb = child_bit(c, L.gj[k0 + g][0]) | (child_bit(c, L.gj[k0 + g][1]) << 1) |
+                       (child_bit(c, L.gj[k0 + g][2]) << 2);
+        gm[g] = L.gmono[k0 + g][cb];
+      }
+#pragma unroll
+      for (int g = 0; g < kIbGroup; ++g)
+        if (k0 + g < ng) mo = mo || gm[g];
     }
   }
   for (int j = 0; j < m; ++j)

@@ -113,6 +113,12 @@ struct PlainRow {
   __device__ __forceinline__ I get(int i) const { return I{neg(lo[i]), hi[i]}; }
 };
 
+// (a + b) mod n for a, b in [0, n): one compare instead of an integer division.
+__device__ __forceinline__ int add_mod(int a, int b, int n) {
+  const int s = a + b;
+  return s >= n ? s - n : s;
+}
+
 // child r of a stored row: coordinate (cyc + j) mod n takes the upper half
 // [mid_j, hi] when bit j of r is set and the lower half [lo, mid_j] otherwise
 struct ChildRow {
