@@ -329,6 +329,7 @@ __device__ __forceinline__ bool select_finish(const Params& P, State* S, const S
     else if (gub - b.f <= P.tol_f && (P.tol_x <= 0.0 || tot.wm < P.tol_x)) stop = STOP_CONVERGED;
     else if (t >= P.max_sweeps) stop = STOP_SWEEPS;
     else if (P.max_live > 0 && tot.cnt > P.max_live) stop = STOP_LIVE;
+    else if (t + 1 >= P.hist_cap || S->n_keys + P.nch > P.key_cap) stop = STOP_CAPACITY;
     if (stop) S->stop = stop;
     go = stop == RUNNING;
     if (go) {
@@ -502,6 +503,32 @@ __device__ __forceinline__ bool select_body(const Params& P, State* S, int npart
 // coordinate g of the chained family, the halves of g - 1, g, g + 1 index 8
 // test results.  A coordinate that is not split has a single "half", the
 // parent's interval, so its bit is taken as 0.
+// The counters of a problem that its sweep workgroup keeps current itself while
+// it runs (every thread holds the same copy).  The workgroup still writes each
+// of them to the problem's State as before; the copy only spares it reading back
+// from device memory what it has just written.
+struct Hot {
+  uint64_t gub_key;
+  int64_t n_keys, next_seq, sweeps, n_live, evaluated, ub_evaluated;
+};
+// a value every lane holds alike, moved to scalar registers
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ int64_t uni64(int64_t v) { return (int64_t)uni64((uint64_t)v); }
+__device__ __forceinline__ Hot hot_load(const State* S) {
+  return Hot{uni64(S->gub_key), uni64(S->n_keys), uni64(S->next_seq), uni64(S->sweeps),
+             uni64(S->n_live), uni64(S->evaluated), uni64(S->ub_evaluated)};
+}
+// the selected box: its row, cycling index, split mask and insertion number
+struct Sel {
+  int64_t row, seq;
+  int32_t cyc;
+  uint32_t mask;
+};
+
 constexpr int kIbChunkTerms = 2048;  // base terms evaluated by the workgroup between two barriers
 constexpr int kIbMaxTerms = kMaxSplit + 1;
 constexpr int kIbCacheChildren = 1024;   // children whose bounds are kept in LDS between the two passes
@@ -527,6 +554,8 @@ struct IbLds {
   int gj[kIbSlots][3];                   // CHAIN: split index of g - 1, g, g + 1 (-1: not split / absent)
   int gmono[kIbSlots][8];                // first-order test failed, per combination of halves
   double w[kMaxSplit][2];               // width of each half of each split coordinate
+  double w4[kMaxSplit / 4][16];         // widest split half over coordinates 4g..4g+3 for each 4 bits of c
+  uint64_t gub_key;                     // GUB after the children's midpoint bounds
 };
 
 // the interval of coordinate i of the selected row for half b of split index j
@@ -537,12 +566,13 @@ __device__ __forceinline__ I ib_half(const double* rn, const double* rh, const d
 }
 
 template <int NT, int FAM>
-__device__ __forceinline__ void ib_prepare(const Params& P, State* S, IbLds<NT>& L) {
+__device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const Sel& sel) {
   static_assert(NT % kWave == 0, "whole wavefronts");
-  __syncthreads();   // the selected row, its split points and mask were written by other threads
+  __syncthreads();   // the selected row and its split points were written by other threads
   const int n = P.n, m = P.m, lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
-  const int row = S->sel_row, cyc = S->sel_cyc;
-  const uint32_t mask = S->sel_mask;
+  const int64_t row = sel.row;
+  const int cyc = sel.cyc;
+  const uint32_t mask = sel.mask;
   const double* rn = P.hist_n + (int64_t)row * n;
   const double* rh = P.hist_h + (int64_t)row * n;
   const double* mid = P.hist_mid + (int64_t)row * kMaxSplit;
@@ -554,36 +584,59 @@ __device__ __forceinline__ void ib_prepare(const Params& P, State* S, IbLds<NT>&
   };
   const int T = FAM == FAM_CHAIN ? n - 1 : n;
 
-  // 1. lists of affected terms and derivative coordinates, in increasing index
-  if (threadIdx.x == 0) {
-    const int start = (n - cyc < m) ? n - cyc : 0;   // first j whose coordinate wrapped to the front
-    int na = 0, ng = 0, last_a = -1, last_g = -1;
-    for (int k = 0; k < m; ++k) {
-      const int j = add_mod(start, k, m);
-      if (!((mask >> j) & 1u)) continue;
-      const int d = add_mod(cyc, j, n);
-      const int a0 = FAM == FAM_CHAIN ? d - 1 : d;
-      for (int a = a0; a <= d; ++a)
-        if (a >= 0 && a < T && a > last_a) {
-          L.aff[na] = a;
-          L.aj[na][0] = split_of(a);
-          L.aj[na][1] = FAM == FAM_CHAIN ? split_of(a + 1) : -1;
-          ++na;
-          last_a = a;
-        }
-      if (FAM == FAM_CHAIN)
-        for (int g = d - 1; g <= d + 1; ++g)
-          if (g >= 0 && g < n && g > last_g) {
-            L.gc[ng] = g;
-            L.gj[ng][0] = split_of(g - 1);
-            L.gj[ng][1] = split_of(g);
-            L.gj[ng][2] = split_of(g + 1);
-            ++ng;
-            last_g = g;
-          }
+  // 1. lists of affected terms and derivative coordinates, in increasing index.
+  //    Lane k of wavefront 0 takes the k-th smallest coordinate d of the split
+  //    window; if d is split it adds the entries its predecessor in that order
+  //    has not added (chained family: term d - 1 unless the predecessor is d - 1,
+  //    term d unless d is the last coordinate; derivative coordinates up to d + 1
+  //    beyond the predecessor's d' + 1).  An exclusive scan places them.
+  if (wid == 0) {
+    const int start = (n - cyc < m) ? n - cyc : 0;   // position 0: first j whose coordinate wrapped to the front
+    const int k = lane;
+    const int j = k < m ? add_mod(start, k, m) : 0;
+    const bool sp = k < m && ((mask >> j) & 1u);
+    const int d = sp ? add_mod(cyc, j, n) : 0;
+    const unsigned long long below = __ballot(sp) & ((1ull << k) - 1ull);
+    const int prev = below != 0ull ? add_mod(cyc, add_mod(start, 63 - __clzll(below), m), n) : -2;
+    int nt = 0, ngr = 0, a0 = 0, g0 = 0;
+    if (sp) {
+      if (FAM == FAM_CHAIN) {
+        const bool lo_new = d >= 1 && prev != d - 1;
+        a0 = lo_new ? d - 1 : d;
+        nt = (lo_new ? 1 : 0) + (d < T ? 1 : 0);
+        const int last_g = prev >= 0 ? prev + 1 : -1;
+        g0 = max(max(d - 1, last_g + 1), 0);
+        const int g1 = min(d + 1, n - 1);
+        ngr = g1 >= g0 ? g1 - g0 + 1 : 0;
+      } else {
+        a0 = d;
+        nt = 1;
+      }
     }
-    L.naff = na;
-    L.ngc = ng;
+    int it = nt, ig = ngr;
+    for (int h = 1; h < kWave; h <<= 1) {
+      const int ot = __shfl_up(it, h, kWave), og = __shfl_up(ig, h, kWave);
+      if (lane >= h) { it += ot; ig += og; }
+    }
+    const int pt = it - nt, pg = ig - ngr;   // at most kIbMaxTerms terms, kIbMaxGrad coordinates in all
+    for (int e = 0; e < nt; ++e) {
+      const int a = a0 + e;
+      L.aff[pt + e] = a;
+      L.aj[pt + e][0] = split_of(a);
+      L.aj[pt + e][1] = FAM == FAM_CHAIN ? split_of(a + 1) : -1;
+    }
+    if (FAM == FAM_CHAIN)
+      for (int e = 0; e < ngr; ++e) {
+        const int g = g0 + e;
+        L.gc[pg + e] = g;
+        L.gj[pg + e][0] = split_of(g - 1);
+        L.gj[pg + e][1] = split_of(g);
+        L.gj[pg + e][2] = split_of(g + 1);
+      }
+    if (lane == kWave - 1) {
+      L.naff = it;
+      L.ngc = ig;
+    }
   }
   __syncthreads();
 
@@ -699,6 +752,15 @@ __device__ __forceinline__ void ib_prepare(const Params& P, State* S, IbLds<NT>&
     for (int k = 0; k < NT / kWave; ++k) w = dmax(w, L.red[k]);
     L.wbase = w;
   }
+  if (wid == 1) {   // L.w was written before the barriers above
+    const int g = lane >> 4, nib = lane & 15;
+    double w = 0.0;
+    for (int b = 0; b < 4; ++b) {
+      const int j = 4 * g + b;
+      if (j < m && ((mask >> j) & 1u)) w = dmax(w, L.w[j][(nib >> b) & 1]);
+    }
+    L.w4[g][nib] = w;
+  }
   __syncthreads();
 }
 
@@ -752,16 +814,15 @@ __device__ __forceinline__ void ib_child(const Params& P, const IbLds<NT>& L, ui
         if (k0 + g < ng) mo = mo || gm[g];
     }
   }
-  for (int j = 0; j < m; ++j)
-    if ((mask >> j) & 1u) wm = dmax(wm, L.w[j][(c >> j) & 1u]);
+  static_assert(kMaxSplit == 16, "four nibbles of the child index");
+  wm = dmax(wm, dmax(dmax(L.w4[0][c & 15u], L.w4[1][(c >> 4) & 15u]), dmax(L.w4[2][(c >> 8) & 15u], L.w4[3][(c >> 12) & 15u])));
   flo = neg(F.n);
 }
 
 // GUB = min(GUB, the children's midpoint bounds); returns the new GUB to every thread
 template <int NT, int FAM>
-__device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L) {
+__device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L, uint32_t mask, Hot& h) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
-  const uint32_t mask = S->sel_mask;
   double umin = __builtin_inf();
   int cnt = 0;
   const bool cache = P.nch <= kIbCacheChildren;
@@ -789,17 +850,19 @@ __device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L
     int tot = L.cnt[0];
     for (int k = 1; k < NT / kWave; ++k) { mn = dmin(mn, L.red[k]); tot += L.cnt[k]; }
     const uint64_t key = okey(mn);
-    uint64_t g = S->gub_key;
+    uint64_t g = h.gub_key;
     if (tot > 0 && key < g) {
       g = key;
       S->gub_key = key;
     }
-    S->ub_evaluated += tot;
-    L.gub = okey_inv(g);
+    S->ub_evaluated = h.ub_evaluated + tot;
+    L.gub_key = g;
     L.tot = tot;
   }
   __syncthreads();
-  return L.gub;
+  h.gub_key = uni64(L.gub_key);
+  h.ub_evaluated = uni64(h.ub_evaluated + L.tot);
+  return okey_inv(h.gub_key);
 }
 
 // The survivors (first-order test passed, lower bound <= the new GUB) are
@@ -807,13 +870,13 @@ __device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L
 // insert them from child records (the full-bound path): no records round-trip
 // through device memory
 template <int NT, int FAM>
-__device__ __forceinline__ void ib_children_insert(const Params& P, State* S, IbLds<NT>& L) {
-  ib_prepare<NT, FAM>(P, S, L);
-  const double gub = ib_gub<NT, FAM>(P, S, L);
+__device__ __forceinline__ void ib_children_insert(const Params& P, State* S, IbLds<NT>& L, const Sel& sel, Hot& h) {
+  ib_prepare<NT, FAM>(P, L, sel);
+  const double gub = ib_gub<NT, FAM>(P, S, L, sel.mask, h);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
-  const uint32_t mask = S->sel_mask;
-  const int64_t base = S->n_keys, seq0 = S->next_seq;
-  const int row = S->sel_row;
+  const uint32_t mask = sel.mask;
+  const int64_t base = h.n_keys, seq0 = h.next_seq;
+  const int row = (int)sel.row;
   int64_t done = 0;
   for (int c0 = 0; c0 < P.nch; c0 += NT) {
     const int c = c0 + (int)threadIdx.x;
@@ -854,19 +917,23 @@ __device__ __forceinline__ void ib_children_insert(const Params& P, State* S, Ib
     done += total;
     __syncthreads();   // L.ins is rewritten by the next round
   }
+  const int64_t t = h.sweeps;
   if (threadIdx.x == 0) {
-    const int64_t t = S->sweeps;
     if (t < P.trace_cap) {
       P.tr_gub[t] = gub;
       P.tr_nsurv[t] = done;
-      P.tr_sel[t] = S->sel_seq;
+      P.tr_sel[t] = sel.seq;
     }
     S->n_keys = base + done;
     S->next_seq = seq0 + done;
-    S->evaluated += L.tot;
+    S->evaluated = h.evaluated + L.tot;
     S->sweeps = t + 1;
     S->pending = 0;
   }
+  h.n_keys = uni64(base + done);
+  h.next_seq = uni64(seq0 + done);
+  h.evaluated = uni64(h.evaluated + L.tot);
+  h.sweeps = t + 1;
 }
 
 // Up to `iters` whole sweeps with incremental bounds in one workgroup: the
@@ -879,10 +946,10 @@ __device__ __forceinline__ void ib_children_insert(const Params& P, State* S, Ib
 // keys is read completely before any of it is written, and a key only moves to
 // a lower index, so no key is overwritten before it has been read.
 template <int NT>
-__device__ __forceinline__ void compact_in_place(const Params& P, State* S, IbLds<NT>& L) {
+__device__ __forceinline__ void compact_in_place(const Params& P, State* S, IbLds<NT>& L, Hot& h) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
-  const double gub = okey_inv(S->gub_key);
-  const int64_t nk = S->n_keys;
+  const double gub = okey_inv(h.gub_key);
+  const int64_t nk = h.n_keys;
   int64_t kept = 0;
   for (int64_t c0 = 0; c0 < nk; c0 += NT) {
     const int64_t i = c0 + threadIdx.x;
@@ -913,18 +980,110 @@ __device__ __forceinline__ void compact_in_place(const Params& P, State* S, IbLd
     __syncthreads();
   }
   if (threadIdx.x == 0) S->n_keys = kept;
+  h.n_keys = uni64(kept);
   __syncthreads();
+}
+
+// The selection of the persistent loop: the steps of select_body and
+// select_finish for a list with no pending children, with the counters taken
+// from the workgroup's own copy.  Every wavefront forms the split mask itself
+// (the same ballot over the same values), so no thread waits to read it back.
+template <int NT>
+__device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel& sel) {
+  const double gub = okey_inv(h.gub_key);
+  SelAcc a = sel_empty();
+  scan_keys_wg<NT>(P, gub, h.n_keys, a);
+  const SelAcc tot = sel_block_reduce<NT>(a);
+  __shared__ int32_t go;
+  const int64_t t = h.sweeps, row = t + 1;
+  if (threadIdx.x == 0) {
+    const Cand b = tot.best;
+    if (t > 0 && t - 1 < P.trace_cap) P.tr_nlive[t - 1] = tot.cnt;
+    S->n_live = tot.cnt;
+    S->glb = b.f;
+    S->wmax = tot.wm;
+    int32_t stop = RUNNING;
+    if (tot.cnt == 0) stop = STOP_EMPTY;
+    else if (gub - b.f <= P.tol_f && (P.tol_x <= 0.0 || tot.wm < P.tol_x)) stop = STOP_CONVERGED;
+    else if (t >= P.max_sweeps) stop = STOP_SWEEPS;
+    else if (P.max_live > 0 && tot.cnt > P.max_live) stop = STOP_LIVE;
+    else if (row >= P.hist_cap || h.n_keys + P.nch > P.key_cap) stop = STOP_CAPACITY;
+    if (stop) S->stop = stop;
+    go = stop == RUNNING;
+    if (go) {
+      P.key_flo[b.idx] = __builtin_inf();     // removed from the list
+      S->sel_seq = b.s;
+      S->gub_start = gub;
+      S->pending = 1;
+    }
+  }
+  __syncthreads();
+  h.n_live = uni64(tot.cnt);
+  if (!go) return false;
+  const int32_t ref = P.key_ref[tot.best.idx];
+  const int32_t r = P.key_r[tot.best.idx];
+  const int n = P.n;
+  const int pcyc = P.hist_cyc[ref];
+  const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
+                     n, P.m, pcyc, r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
+  double* dn = P.hist_n + row * n;
+  double* dh = P.hist_h + row * n;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const I x = src.get(i);
+    dn[i] = x.n;
+    dh[i] = x.h;
+  }
+  const int cyc = r >= 0 ? add_mod(pcyc, P.m, n) : pcyc;   // m <= n
+  const int lane = threadIdx.x & (kWave - 1);
+  bool ok = false;
+  double md = 0.0;
+  if (lane < P.m) {
+    const I x = src.get(add_mod(cyc, lane, n));
+    md = midpoint(x);
+    ok = neg(x.n) < md && md < x.h;
+  }
+  const uint32_t mask = (uint32_t)__ballot(ok) & ((1u << P.m) - 1u);   // m <= 16
+  if (threadIdx.x < (unsigned)kWave) {
+    if (lane < P.m) {
+      P.hist_mid[row * kMaxSplit + lane] = md;
+      S->sel_mid[lane] = md;
+    }
+    if (lane == 0) {
+      P.hist_mask[row] = mask;
+      P.hist_cyc[row] = cyc;
+      S->sel_mask = mask;
+      S->sel_cyc = cyc;
+      S->sel_row = (int32_t)row;
+    }
+  }
+  sel.row = row;
+  sel.seq = tot.best.s;
+  sel.cyc = cyc;
+  sel.mask = mask;
+  return true;
+}
+
+// load the selection select_body left in the State (after a barrier)
+__device__ __forceinline__ Sel sel_load(const State* S) {
+  Sel sel;
+  sel.row = (int64_t)__builtin_amdgcn_readfirstlane(S->sel_row);
+  sel.seq = uni64(S->sel_seq);
+  sel.cyc = __builtin_amdgcn_readfirstlane(S->sel_cyc);
+  sel.mask = __builtin_amdgcn_readfirstlane(S->sel_mask);
+  return sel;
 }
 
 template <int NT, int FAM>
 __device__ __forceinline__ void sweeps_ib(const Params& P, State* S, IbLds<NT>& lds, int iters) {
   if (S->stop) return;
+  Hot h = hot_load(S);   // no children are pending here: the incremental sweep inserts its own
   for (int it = 0; it < iters; ++it) {
     // dead keys dominate the list: drop them before the scan
-    if (S->n_keys > 4 * (S->n_live + P.nch) && S->n_keys > 4096) compact_in_place<NT>(P, S, lds);
-    if (!select_body<NT>(P, S, 0, 0)) return;   // stopped (the flag is set)
-    ib_children_insert<NT, FAM>(P, S, lds);
-    __syncthreads();   // keys and counters are read by the next selection
+    if (h.n_keys > 4 * (h.n_live + P.nch) && h.n_keys > 4096) compact_in_place<NT>(P, S, lds, h);
+    Sel sel;
+    if (!select_ib<NT>(P, S, h, sel)) return;   // stopped (the flag is set)
+    ib_children_insert<NT, FAM>(P, S, lds, sel, h);
+    __syncthreads();   // keys written by other threads are read by the next selection
   }
 }
 
@@ -942,7 +1101,11 @@ __global__ __launch_bounds__(NT) void k_select_ib(const Params* __restrict__ PP,
   if (S->stop) return;
   const Params P = *PP;
   __shared__ IbLds<NT> lds;
-  if (select_body<NT>(P, S, nparts, host_stop)) ib_children_insert<NT, FAM>(P, S, lds);
+  if (select_body<NT>(P, S, nparts, host_stop)) {
+    __syncthreads();   // the selection was written to the State by wavefront 0
+    Hot h = hot_load(S);
+    ib_children_insert<NT, FAM>(P, S, lds, sel_load(S), h);
+  }
 }
 
 template <int NT>
@@ -1765,8 +1928,10 @@ ibb_status run_finish(Run& U) {
   R->info.fp64_confirmed = hs.evaluated - hs.fp32_pruned;
   R->info.fp32_sweeps = (int32_t)std::min<int64_t>(hs.fp32_sweeps, INT32_MAX);
   R->info.ub_evaluated = hs.ub_evaluated;
-  R->info.status = hs.stop == STOP_CONVERGED ? IBB_OK : (hs.stop == STOP_EMPTY ? IBB_E_INTERNAL : IBB_NOT_CONVERGED);
+  R->info.status = hs.stop == STOP_CONVERGED ? IBB_OK
+                   : (hs.stop == STOP_EMPTY || hs.stop == STOP_CAPACITY) ? IBB_E_INTERNAL : IBB_NOT_CONVERGED;
   R->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - U.t0).count();
+  if (hs.stop == STOP_CAPACITY) return fail(IBB_E_INTERNAL, "a sweep would pass the sized row or key capacity");
   if (R->info.status == IBB_E_INTERNAL) return fail(IBB_E_INTERNAL, "the live list became empty");
   return IBB_OK;
 }
@@ -2093,7 +2258,8 @@ ibb_status ibb_sweep(ibb_result* R, int64_t n_sweeps, void* hip_stream) {
     Params& P = R->P;
     HIPCHK(hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream));
     HIPCHK(hipStreamSynchronize(M.stream));
-    if (n_sweeps == 0 || U.hs.stop == STOP_CONVERGED || U.hs.stop == STOP_EMPTY) return (ibb_status)R->info.status;
+    if (n_sweeps == 0 || U.hs.stop == STOP_CONVERGED || U.hs.stop == STOP_EMPTY || U.hs.stop == STOP_CAPACITY)
+      return (ibb_status)R->info.status;
     const double before = R->info.seconds;
     U.t0 = std::chrono::steady_clock::now();
     U.n_keys = U.hs.n_keys;

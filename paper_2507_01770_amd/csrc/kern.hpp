@@ -30,7 +30,10 @@ constexpr int kMaxSelBlocks = 1024;
 constexpr int64_t kPersistentMaxKeys = (int64_t)1 << 18;   // lists one workgroup scans about as fast as a grid
 constexpr int kPersistentChunk = 64;                        // sweeps per persistent launch (the list grows meanwhile)
 
-enum StopCode { RUNNING = 0, STOP_CONVERGED = 1, STOP_SWEEPS = 2, STOP_LIVE = 3, STOP_EMPTY = 4, STOP_HOST = 5 };
+// STOP_CAPACITY: the next sweep would pass the row or key capacity the host sized
+// the arrays for (the host grows them before every chunk, so this only guards)
+enum StopCode { RUNNING = 0, STOP_CONVERGED = 1, STOP_SWEEPS = 2, STOP_LIVE = 3, STOP_EMPTY = 4, STOP_HOST = 5,
+                STOP_CAPACITY = 6 };
 
 struct Params {
   int32_t family, n, m, nch;              // nch = 2^m children per selected box
