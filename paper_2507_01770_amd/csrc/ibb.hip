@@ -162,13 +162,16 @@ __global__ __launch_bounds__(kWave) void k_root(const Params* __restrict__ PP, S
   }
 }
 
-// candidate order of the selection: smaller lower bound, then smaller insertion number
+// candidate order of the selection: smaller lower bound, then smaller insertion
+// number.  Keys are appended in insertion order and every compaction keeps their
+// order, so a key's index in the list orders keys as its insertion number does:
+// the scan compares indices and never loads the numbers.
 struct Cand {
   double f;
-  int64_t s, idx;
+  int64_t idx;
 };
 __device__ __forceinline__ bool better(const Cand& a, const Cand& b) {  // a before b
-  return a.f < b.f || (a.f == b.f && a.s < b.s);
+  return a.f < b.f || (a.f == b.f && a.idx < b.idx);
 }
 // running reduction of the selection scan: best key, widest box, live count
 struct SelAcc {
@@ -182,7 +185,7 @@ __device__ __forceinline__ SelAcc sel_merge(SelAcc a, const SelAcc& b) {
   a.cnt += b.cnt;
   return a;
 }
-__device__ __forceinline__ SelAcc sel_empty() { return SelAcc{Cand{__builtin_inf(), INT64_MAX, -1}, 0.0, 0}; }
+__device__ __forceinline__ SelAcc sel_empty() { return SelAcc{Cand{__builtin_inf(), INT64_MAX}, 0.0, 0}; }
 
 // reduce over a workgroup of NT threads; the result is returned to every thread
 template <int NT>
@@ -190,7 +193,6 @@ __device__ __forceinline__ SelAcc sel_block_reduce(SelAcc v) {
   for (int h = 32; h >= 1; h >>= 1) {
     SelAcc o;
     o.best.f = __shfl_xor(v.best.f, h, kWave);
-    o.best.s = (int64_t)__shfl_xor((long long)v.best.s, h, kWave);
     o.best.idx = (int64_t)__shfl_xor((long long)v.best.idx, h, kWave);
     o.wm = __shfl_xor(v.wm, h, kWave);
     o.cnt = (int64_t)__shfl_xor((long long)v.cnt, h, kWave);
@@ -272,7 +274,7 @@ __device__ __forceinline__ void insert_children(const Params& P, State* S, doubl
       P.key_wmax[o] = P.ch_wmax[k];
       a.cnt++;
       a.wm = dmax(a.wm, P.ch_wmax[k]);
-      const Cand cd{f, sq, o};
+      const Cand cd{f, o};
       if (better(cd, a.best)) a.best = cd;
       ++o;
     }
@@ -334,7 +336,7 @@ __device__ __forceinline__ bool select_finish(const Params& P, State* S, const S
     go = stop == RUNNING;
     if (go) {
       P.key_flo[b.idx] = __builtin_inf();     // removed from the list
-      S->sel_seq = b.s;
+      S->sel_seq = P.key_seq[b.idx];
       S->gub_start = gub;
       S->pending = 1;                         // the bound kernel will produce children
     }
@@ -386,10 +388,8 @@ __device__ __forceinline__ void scan_key(const Params& P, double gub, bool need_
   if (!(f <= gub)) return;   // removed (+inf) or above GUB
   a.cnt++;
   if (need_w) a.wm = dmax(a.wm, P.key_wmax[i]);
-  if (f <= a.best.f) {       // only a candidate needs its insertion number
-    const Cand c{f, P.key_seq[i], i};
-    if (better(c, a.best)) a.best = c;
-  }
+  const Cand c{f, i};
+  if (better(c, a.best)) a.best = c;
 }
 __device__ __forceinline__ void scan_keys(const Params& P, double gub, int64_t i0, int64_t i1, int64_t stride,
                                           SelAcc& a) {
@@ -447,7 +447,6 @@ __global__ __launch_bounds__(kSelThreads) void k_select_part(const Params* __res
   a = sel_block_reduce<kSelThreads>(a);
   if (threadIdx.x == 0) {
     P.part_flo[blockIdx.x] = a.best.f;
-    P.part_seq[blockIdx.x] = a.best.s;
     P.part_idx[blockIdx.x] = a.best.idx;
     P.part_wmax[blockIdx.x] = a.wm;
     P.part_cnt[blockIdx.x] = a.cnt;
@@ -467,7 +466,7 @@ __device__ __forceinline__ bool select_body(const Params& P, State* S, int npart
     scan_keys_wg<NT>(P, gub, S->n_keys, a);
   } else {
     for (int k = threadIdx.x; k < nparts; k += NT) {
-      const SelAcc o{Cand{P.part_flo[k], P.part_seq[k], P.part_idx[k]}, P.part_wmax[k], P.part_cnt[k]};
+      const SelAcc o{Cand{P.part_flo[k], P.part_idx[k]}, P.part_wmax[k], P.part_cnt[k]};
       a = sel_merge(a, o);
     }
   }
@@ -1012,7 +1011,6 @@ __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel
     go = stop == RUNNING;
     if (go) {
       P.key_flo[b.idx] = __builtin_inf();     // removed from the list
-      S->sel_seq = b.s;
       S->gub_start = gub;
       S->pending = 1;
     }
@@ -1022,6 +1020,7 @@ __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel
   if (!go) return false;
   const int32_t ref = P.key_ref[tot.best.idx];
   const int32_t r = P.key_r[tot.best.idx];
+  const int64_t seq = P.key_seq[tot.best.idx];
   const int n = P.n;
   const int pcyc = P.hist_cyc[ref];
   const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
@@ -1054,10 +1053,11 @@ __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel
       S->sel_mask = mask;
       S->sel_cyc = cyc;
       S->sel_row = (int32_t)row;
+      S->sel_seq = seq;
     }
   }
   sel.row = row;
-  sel.seq = tot.best.s;
+  sel.seq = seq;
   sel.cyc = cyc;
   sel.mask = mask;
   return true;
@@ -1798,7 +1798,6 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   P.ch_flag = dalloc<uint8_t>(M, P.nch);
   P.ch_wmax = dalloc<double>(M, P.nch);
   P.part_flo = dalloc<double>(M, kMaxSelBlocks);
-  P.part_seq = dalloc<int64_t>(M, kMaxSelBlocks);
   P.part_idx = dalloc<int64_t>(M, kMaxSelBlocks);
   P.part_wmax = dalloc<double>(M, kMaxSelBlocks);
   P.part_cnt = dalloc<int64_t>(M, kMaxSelBlocks);
@@ -1807,7 +1806,7 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   P.tr_nlive = dalloc<int64_t>(M, P.trace_cap);
   P.tr_sel = dalloc<int64_t>(M, P.trace_cap);
   if (!P.key_flo || !P.key_seq || !P.key_ref || !P.key_r || !P.key_wmax || !P.hist_n || !P.hist_h || !P.hist_cyc ||
-      !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.part_flo || !P.part_seq ||
+      !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.part_flo ||
       !P.part_idx || !P.part_wmax || !P.part_cnt || !P.tr_gub || !P.tr_nsurv || !P.tr_nlive || !P.tr_sel)
     return fail(IBB_E_NOMEM, "device allocation failed");
   // root row: (-l, u)

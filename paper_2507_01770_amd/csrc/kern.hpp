@@ -69,7 +69,6 @@ struct Params {
   double* ch_wmax;
   // select partials
   double* part_flo;
-  int64_t* part_seq;
   int64_t* part_idx;
   double* part_wmax;
   int64_t* part_cnt;
