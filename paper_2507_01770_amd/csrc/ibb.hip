@@ -406,35 +406,81 @@ __device__ __forceinline__ void scan_keys(const Params& P, double gub, int64_t i
   for (; i < i1; i += stride) scan_key(P, gub, need_w, i, P.key_flo[i], a);
 }
 
-// The whole list by one workgroup: pairs of keys in 16-byte loads, eight pairs
-// in flight per thread (a single workgroup's scan is bound by load latency).
+// The whole list by one workgroup, reduced over the workgroup (the result is
+// returned to every thread).  Each thread visits its keys in increasing index,
+// so keeping the first key with the smallest lower bound (strict <) keeps the
+// smallest index among equal bounds; indices and counts are 32-bit here.  Pairs
+// of keys come in 16-byte loads, eight pairs in flight per thread (one
+// workgroup's scan is bound by load latency and per-key instructions).
 template <int NT>
-__device__ __forceinline__ void scan_keys_wg(const Params& P, double gub, int64_t nk, SelAcc& a) {
-  if ((reinterpret_cast<uintptr_t>(P.key_flo) & 15u) != 0u) {   // caller's allocator gave 8-byte alignment
+__device__ __forceinline__ SelAcc scan_select_wg(const Params& P, double gub, int64_t nk) {
+  if (nk >= (int64_t)INT32_MAX || (reinterpret_cast<uintptr_t>(P.key_flo) & 15u) != 0u) {
+    SelAcc a = sel_empty();   // general form (lists past 2^31 keys, or 8-byte aligned keys)
     scan_keys(P, gub, threadIdx.x, nk, NT, a);
-    return;
+    return sel_block_reduce<NT>(a);
   }
   const bool need_w = P.tol_x > 0.0;
+  double bf = __builtin_inf(), wm = 0.0;
+  int32_t bi = INT32_MAX, cnt = 0;
+  auto visit = [&](int32_t i, double f) {
+    const bool live = f <= gub;
+    cnt += live ? 1 : 0;
+    if (live && f < bf) {
+      bf = f;
+      bi = i;
+    }
+    if (need_w && live) wm = dmax(wm, P.key_wmax[i]);
+  };
   const double2* f2 = reinterpret_cast<const double2*>(P.key_flo);
-  const int64_t np = nk >> 1;
+  const int32_t np = (int32_t)(nk >> 1);
   constexpr int U = 8;
-  int64_t p = threadIdx.x;
+  int32_t p = threadIdx.x;
   for (; p + (U - 1) * NT < np; p += U * NT) {
     double2 v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) v[u] = f2[p + u * NT];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      scan_key(P, gub, need_w, 2 * (p + u * NT), v[u].x, a);
-      scan_key(P, gub, need_w, 2 * (p + u * NT) + 1, v[u].y, a);
+      visit(2 * (p + u * NT), v[u].x);
+      visit(2 * (p + u * NT) + 1, v[u].y);
     }
   }
   for (; p < np; p += NT) {
     const double2 v = f2[p];
-    scan_key(P, gub, need_w, 2 * p, v.x, a);
-    scan_key(P, gub, need_w, 2 * p + 1, v.y, a);
+    visit(2 * p, v.x);
+    visit(2 * p + 1, v.y);
   }
-  if ((nk & 1) && threadIdx.x == 0) scan_key(P, gub, need_w, nk - 1, P.key_flo[nk - 1], a);
+  if ((nk & 1) && threadIdx.x == 0) visit((int32_t)(nk - 1), P.key_flo[nk - 1]);
+  for (int h = 32; h >= 1; h >>= 1) {
+    const double of = __shfl_xor(bf, h, kWave);
+    const int32_t oi = __shfl_xor(bi, h, kWave);
+    if (of < bf || (of == bf && oi < bi)) {
+      bf = of;
+      bi = oi;
+    }
+    cnt += __shfl_xor(cnt, h, kWave);
+    if (need_w) wm = dmax(wm, __shfl_xor(wm, h, kWave));
+  }
+  constexpr int NW = NT / kWave;
+  __shared__ double s_f[NW], s_w[NW];
+  __shared__ int32_t s_i[NW], s_c[NW];
+  const int w = threadIdx.x >> 6;
+  __syncthreads();   // a previous call may still read these
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    s_f[w] = bf;
+    s_i[w] = bi;
+    s_c[w] = cnt;
+    s_w[w] = wm;
+  }
+  __syncthreads();
+  SelAcc r = sel_empty();
+  for (int k = 0; k < NW; ++k) {
+    const Cand c{s_f[k], s_i[k] == INT32_MAX ? INT64_MAX : (int64_t)s_i[k]};
+    if (better(c, r.best)) r.best = c;
+    r.cnt += s_c[k];
+    r.wm = dmax(r.wm, s_w[k]);
+  }
+  return r;
 }
 
 // Large lists: every workgroup scans a stretch of the keys and writes a partial.
@@ -463,14 +509,14 @@ __device__ __forceinline__ bool select_body(const Params& P, State* S, int npart
   const double gub = okey_inv(S->gub_key);
   SelAcc a = sel_empty();
   if (nparts == 0) {
-    scan_keys_wg<NT>(P, gub, S->n_keys, a);
+    a = scan_select_wg<NT>(P, gub, S->n_keys);
   } else {
     for (int k = threadIdx.x; k < nparts; k += NT) {
       const SelAcc o{Cand{P.part_flo[k], P.part_idx[k]}, P.part_wmax[k], P.part_cnt[k]};
       a = sel_merge(a, o);
     }
+    a = sel_block_reduce<NT>(a);
   }
-  a = sel_block_reduce<NT>(a);
   if (S->pending) insert_children<NT>(P, S, gub, a);
   if (host_stop) {   // the host ends the run here (time limit): keep the inserted list
     if (threadIdx.x == 0) {
@@ -990,9 +1036,7 @@ __device__ __forceinline__ void compact_in_place(const Params& P, State* S, IbLd
 template <int NT>
 __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel& sel) {
   const double gub = okey_inv(h.gub_key);
-  SelAcc a = sel_empty();
-  scan_keys_wg<NT>(P, gub, h.n_keys, a);
-  const SelAcc tot = sel_block_reduce<NT>(a);
+  const SelAcc tot = scan_select_wg<NT>(P, gub, h.n_keys);
   __shared__ int32_t go;
   const int64_t t = h.sweeps, row = t + 1;
   if (threadIdx.x == 0) {
