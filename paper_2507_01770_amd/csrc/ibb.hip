@@ -580,6 +580,7 @@ constexpr int kIbCacheChildren = 1024;   // children whose bounds are kept in LD
 constexpr int kIbMaxGrad = kMaxSplit + 2;
 constexpr int kIbGroup = 6;              // table rows a child reads together (their LDS reads overlap)
 constexpr int kIbSlots = 18;             // rows of each table: a multiple of kIbGroup, >= both maxima above
+constexpr int kIbPreBits = 6;            // split positions folded into the prefix table (2^6 entries)
 static_assert(kIbSlots % kIbGroup == 0 && kIbSlots >= kIbMaxTerms && kIbSlots >= kIbMaxGrad, "table rows");
 
 template <int NT>
@@ -601,6 +602,13 @@ struct IbLds {
   double w[kMaxSplit][2];               // width of each half of each split coordinate
   double w4[kMaxSplit / 4][16];         // widest split half over coordinates 4g..4g+3 for each 4 bits of c
   uint64_t gub_key;                     // GUB after the children's midpoint bounds
+  // prefix table: for each choice x of halves at the first kIbPreBits sorted
+  // positions of the split window, F and the midpoint bound after the leading
+  // terms that involve only those positions, and the first-order tests of the
+  // leading derivative coordinates that do
+  double pre_n[1 << kIbPreBits], pre_h[1 << kIbPreBits], pre_u[1 << kIbPreBits];
+  int pre_mo[1 << kIbPreBits];
+  int pre_terms, pre_grads, start;      // leading entries in the table; sorted position 0 is split index start
 };
 
 // the interval of coordinate i of the selected row for half b of split index j
@@ -686,14 +694,18 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
   __syncthreads();
 
   // 2. the tables (threads from the top down, so that they overlap the base sums
-  //    of the first chunk when n is small) and the widths of the halves
-  static_assert(NT >= 4 * kIbMaxTerms + 8 * kIbMaxGrad, "one thread per table entry");
+  //    of the first chunk when n is small; each kind of entry in wavefronts of
+  //    its own, so that no wavefront runs two kinds one after the other) and the
+  //    widths of the halves
+  static_assert(NT >= 128 + 8 * kIbMaxGrad && 2 * kIbMaxTerms <= kWave && 4 * kIbMaxTerms <= 128,
+                "one thread per table entry");
   {
     const int q = NT - 1 - (int)threadIdx.x;
     const int na = L.naff, ng = L.ngc;
     if (FAM != FAM_CHAIN) {                     // separable: F, midpoint bound, first-order test of each half
-      if (q < 6 * na) {
-        const int part = q / (2 * na), r = q % (2 * na), k = r >> 1, b = r & 1;
+      const int part = q >> 6, r = q & (kWave - 1);
+      if (part < 3 && r < 2 * na) {
+        const int k = r >> 1, b = r & 1;
         const int a = L.aff[k];
         const I x = ib_half(rn, rh, mid, a, L.aj[k][0], b);
         if (part == 0) {
@@ -721,8 +733,8 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
         L.t_h[k][cb] = t.h;
         L.t_u[k][cb] = chain_term(P.chain[a], point(midpoint(xa)), point(midpoint(xb)), R, E).h;
       }
-    } else if (q < 4 * na + 8 * ng) {           // chained: test per combination of halves of g - 1, g, g + 1
-      const int k = (q - 4 * na) >> 3, cb = (q - 4 * na) & 7;
+    } else if (q >= 128 && q < 128 + 8 * ng) {  // chained: test per combination of halves of g - 1, g, g + 1
+      const int k = (q - 128) >> 3, cb = (q - 128) & 7;
       const int g = L.gc[k];
       const int j0 = L.gj[k][0], j1 = L.gj[k][1], j2 = L.gj[k][2];
       int mo = 0;
@@ -784,12 +796,25 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
       }
     __syncthreads();
   }
-  wb = wave_max(wb);
-  if (lane == 0) L.red[wid] = wb;
-  if (wid == 0) {
-    const I F = fold_slots(acc, lane);
-    const double U = fold_slots_hi(uacc, lane);
-    if (lane == 0) { L.base_n = F.n; L.base_h = F.h; L.base_u = U; }
+  if (wid == 0) {   // the slot folds of F and of the midpoint bound (slot s absorbs s + h) and the widest side
+    for (int h = 32; h >= 1; h >>= 1) {
+      const double on = __shfl_down(acc.n, h, kWave), oh = __shfl_down(acc.h, h, kWave);
+      const double ou = __shfl_down(uacc, h, kWave), ow = __shfl_xor(wb, h, kWave);
+      if (lane < h) {
+        acc = add(acc, I{on, oh});
+        uacc = uacc + ou;
+      }
+      wb = dmax(wb, ow);
+    }
+    if (lane == 0) {
+      L.base_n = acc.n;
+      L.base_h = acc.h;
+      L.base_u = uacc;
+      L.red[0] = wb;
+    }
+  } else {
+    wb = wave_max(wb);
+    if (lane == 0) L.red[wid] = wb;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -806,6 +831,43 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
     }
     L.w4[g][nib] = w;
   }
+  if (wid == 2) {   // the prefix table: lane x, bit p of x = half at sorted position p
+    const int start = (n - cyc < m) ? n - cyc : 0;
+    const int K = min(m, kIbPreBits);
+    auto pos = [&](int j) { return j < 0 ? -1 : (j >= start ? j - start : j - start + m); };
+    const int x = lane;
+    I F{L.base_n, L.base_h};
+    double u = L.base_u;
+    int mo = 0;
+    const int na = L.naff, ng = L.ngc;
+    int e = 0;
+    for (; e < na; ++e) {
+      const int pa = pos(L.aj[e][0]), pb = pos(L.aj[e][1]);
+      if (max(pa, pb) >= K) break;
+      const int cb = (pa >= 0 ? (x >> pa) & 1 : 0) | (pb >= 0 ? ((x >> pb) & 1) << 1 : 0);
+      F = add(F, I{L.t_n[e][cb], L.t_h[e][cb]});
+      u = u + L.t_u[e][cb];
+      if (FAM != FAM_CHAIN) mo |= L.gmono[e][cb];
+    }
+    int g = 0;
+    if (FAM == FAM_CHAIN)
+      for (; g < ng; ++g) {
+        const int p0 = pos(L.gj[g][0]), p1 = pos(L.gj[g][1]), p2 = pos(L.gj[g][2]);
+        if (max(max(p0, p1), p2) >= K) break;
+        const int cb = (p0 >= 0 ? (x >> p0) & 1 : 0) | (p1 >= 0 ? ((x >> p1) & 1) << 1 : 0) |
+                       (p2 >= 0 ? ((x >> p2) & 1) << 2 : 0);
+        mo |= L.gmono[g][cb];
+      }
+    L.pre_n[x] = F.n;
+    L.pre_h[x] = F.h;
+    L.pre_u[x] = u;
+    L.pre_mo[x] = mo;
+    if (x == 0) {
+      L.pre_terms = e;
+      L.pre_grads = g;
+      L.start = start;
+    }
+  }
   __syncthreads();
 }
 
@@ -818,23 +880,31 @@ __device__ __forceinline__ int child_bit(uint32_t c, int j) { return j >= 0 ? (i
 template <int NT, int FAM>
 __device__ __forceinline__ void ib_child(const Params& P, const IbLds<NT>& L, uint32_t mask, int m, uint32_t c,
                                          double& flo, bool& mo, double& wm, double& u) {
-  I F{L.base_n, L.base_h};
-  u = L.base_u;
+  // the table entry for c's halves at the first sorted positions (c rotated so
+  // that bit p is sorted position p), then the remaining entries in order
+  const int st = L.start;
+  const uint32_t cr = ((c >> st) | (c << ((m - st) & 31))) & ((1u << m) - 1u);   // m <= 16; st = 0: c
+  const uint32_t x = cr & ((1u << kIbPreBits) - 1u);
+  I F{L.pre_n[x], L.pre_h[x]};
+  u = L.pre_u[x];
   wm = L.wbase;
-  mo = false;
+  mo = L.pre_mo[x] != 0;
   const int na = L.naff;
-  for (int k0 = 0; k0 < na; k0 += kIbGroup) {
-    int cb[kIbGroup];
+  for (int k0 = L.pre_terms; k0 < na; k0 += kIbGroup) {
+    int cb[kIbGroup], kr[kIbGroup];
 #pragma unroll
-    for (int g = 0; g < kIbGroup; ++g) cb[g] = child_bit(c, L.aj[k0 + g][0]) | (child_bit(c, L.aj[k0 + g][1]) << 1);
+    for (int g = 0; g < kIbGroup; ++g) {
+      kr[g] = min(k0 + g, kIbSlots - 1);   // rows past na are read but not used
+      cb[g] = child_bit(c, L.aj[kr[g]][0]) | (child_bit(c, L.aj[kr[g]][1]) << 1);
+    }
     double tn[kIbGroup], th[kIbGroup], tu[kIbGroup];
     int gm[kIbGroup];
 #pragma unroll
     for (int g = 0; g < kIbGroup; ++g) {
-      tn[g] = L.t_n[k0 + g][cb[g]];
-      th[g] = L.t_h[k0 + g][cb[g]];
-      tu[g] = L.t_u[k0 + g][cb[g]];
-      gm[g] = FAM != FAM_CHAIN ? L.gmono[k0 + g][cb[g]] : 0;
+      tn[g] = L.t_n[kr[g]][cb[g]];
+      th[g] = L.t_h[kr[g]][cb[g]];
+      tu[g] = L.t_u[kr[g]][cb[g]];
+      gm[g] = FAM != FAM_CHAIN ? L.gmono[kr[g]][cb[g]] : 0;
     }
 #pragma unroll
     for (int g = 0; g < kIbGroup; ++g)
@@ -846,13 +916,13 @@ __device__ __forceinline__ void ib_child(const Params& P, const IbLds<NT>& L, ui
   }
   if (FAM == FAM_CHAIN) {
     const int ng = L.ngc;
-    for (int k0 = 0; k0 < ng; k0 += kIbGroup) {
+    for (int k0 = L.pre_grads; k0 < ng; k0 += kIbGroup) {
       int gm[kIbGroup];
 #pragma unroll
       for (int g = 0; g < kIbGroup; ++g) {
-        const int cb = child_bit(c, L.gj[k0 + g][0]) | (child_bit(c, L.gj[k0 + g][1]) << 1) |
-                       (child_bit(c, L.gj[k0 + g][2]) << 2);
-        gm[g] = L.gmono[k0 + g][cb];
+        const int kr = min(k0 + g, kIbSlots - 1);
+        const int cb = child_bit(c, L.gj[kr][0]) | (child_bit(c, L.gj[kr][1]) << 1) | (child_bit(c, L.gj[kr][2]) << 2);
+        gm[g] = L.gmono[kr][cb];
       }
 #pragma unroll
       for (int g = 0; g < kIbGroup; ++g)
