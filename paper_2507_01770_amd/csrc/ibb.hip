@@ -412,13 +412,16 @@ __device__ __forceinline__ void scan_keys(const Params& P, double gub, int64_t i
 // smallest index among equal bounds; indices and counts are 32-bit here.  Pairs
 // of keys come in 16-byte loads, eight pairs in flight per thread (one
 // workgroup's scan is bound by load latency and per-key instructions).
+struct OwnSel {   // one thread's part of the selection scan
+  double bf, wm;
+  int32_t bi, cnt;   // bi = INT32_MAX: no candidate
+};
 template <int NT>
-__device__ __forceinline__ SelAcc scan_select_wg(const Params& P, double gub, int64_t nk) {
-  if (nk >= (int64_t)INT32_MAX || (reinterpret_cast<uintptr_t>(P.key_flo) & 15u) != 0u) {
-    SelAcc a = sel_empty();   // general form (lists past 2^31 keys, or 8-byte aligned keys)
-    scan_keys(P, gub, threadIdx.x, nk, NT, a);
-    return sel_block_reduce<NT>(a);
-  }
+__device__ __forceinline__ bool scan_own_ok(const Params& P, int64_t nk) {
+  return nk < (int64_t)INT32_MAX && (reinterpret_cast<uintptr_t>(P.key_flo) & 15u) == 0u;
+}
+template <int NT>
+__device__ __forceinline__ OwnSel scan_own(const Params& P, double gub, int64_t nk) {
   const bool need_w = P.tol_x > 0.0;
   double bf = __builtin_inf(), wm = 0.0;
   int32_t bi = INT32_MAX, cnt = 0;
@@ -451,6 +454,13 @@ __device__ __forceinline__ SelAcc scan_select_wg(const Params& P, double gub, in
     visit(2 * p + 1, v.y);
   }
   if ((nk & 1) && threadIdx.x == 0) visit((int32_t)(nk - 1), P.key_flo[nk - 1]);
+  return OwnSel{bf, wm, bi, cnt};
+}
+template <int NT>
+__device__ __forceinline__ SelAcc reduce_own(const Params& P, OwnSel o) {
+  const bool need_w = P.tol_x > 0.0;
+  double bf = o.bf, wm = o.wm;
+  int32_t bi = o.bi, cnt = o.cnt;
   for (int h = 32; h >= 1; h >>= 1) {
     const double of = __shfl_xor(bf, h, kWave);
     const int32_t oi = __shfl_xor(bi, h, kWave);
@@ -481,6 +491,15 @@ __device__ __forceinline__ SelAcc scan_select_wg(const Params& P, double gub, in
     r.wm = dmax(r.wm, s_w[k]);
   }
   return r;
+}
+template <int NT>
+__device__ __forceinline__ SelAcc scan_select_wg(const Params& P, double gub, int64_t nk) {
+  if (!scan_own_ok<NT>(P, nk)) {
+    SelAcc a = sel_empty();   // general form (lists past 2^31 keys, or 8-byte aligned keys)
+    scan_keys(P, gub, threadIdx.x, nk, NT, a);
+    return sel_block_reduce<NT>(a);
+  }
+  return reduce_own<NT>(P, scan_own<NT>(P, gub, nk));
 }
 
 // Large lists: every workgroup scans a stretch of the keys and writes a partial.
@@ -589,7 +608,8 @@ struct IbLds {
   double tfn[kIbChunkTerms], tfh[kIbChunkTerms], tu[kIbChunkTerms];
   double red[NT / kWave];
   int cnt[NT / kWave], ins[NT / kWave];
-  double base_n, base_h, base_u, wbase, gub;
+  double base_n, base_h, base_u, gub;
+  double wred[NT / kWave];              // widest unsplit side per wavefront
   int naff, ngc, tot;
   int aff[kIbSlots];                 // affected terms, increasing
   int aj[kIbSlots][2];                  // split index of the term's coordinates (-1: not split)
@@ -796,7 +816,8 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
       }
     __syncthreads();
   }
-  if (wid == 0) {   // the slot folds of F and of the midpoint bound (slot s absorbs s + h) and the widest side
+  if (wid == 0) {
+    // the slot folds of F and of the midpoint bound (slot s absorbs s + h) and the widest side
     for (int h = 32; h >= 1; h >>= 1) {
       const double on = __shfl_down(acc.n, h, kWave), oh = __shfl_down(acc.h, h, kWave);
       const double ou = __shfl_down(uacc, h, kWave), ow = __shfl_xor(wb, h, kWave);
@@ -806,66 +827,65 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
       }
       wb = dmax(wb, ow);
     }
+    const I base{__shfl(acc.n, 0, kWave), __shfl(acc.h, 0, kWave)};
+    const double base_u = __shfl(uacc, 0, kWave);
     if (lane == 0) {
-      L.base_n = acc.n;
-      L.base_h = acc.h;
-      L.base_u = uacc;
-      L.red[0] = wb;
+      L.base_n = base.n;
+      L.base_h = base.h;
+      L.base_u = base_u;
+      L.wred[0] = wb;
     }
-  } else {
-    wb = wave_max(wb);
-    if (lane == 0) L.red[wid] = wb;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double w = 0.0;
-    for (int k = 0; k < NT / kWave; ++k) w = dmax(w, L.red[k]);
-    L.wbase = w;
-  }
-  if (wid == 1) {   // L.w was written before the barriers above
-    const int g = lane >> 4, nib = lane & 15;
-    double w = 0.0;
-    for (int b = 0; b < 4; ++b) {
-      const int j = 4 * g + b;
-      if (j < m && ((mask >> j) & 1u)) w = dmax(w, L.w[j][(nib >> b) & 1]);
-    }
-    L.w4[g][nib] = w;
-  }
-  if (wid == 2) {   // the prefix table: lane x, bit p of x = half at sorted position p
+    // the prefix table, lane x: bit p of x is the half at sorted position p; the
+    // leading entries whose split coordinates all lie at positions below K
     const int start = (n - cyc < m) ? n - cyc : 0;
     const int K = min(m, kIbPreBits);
     auto pos = [&](int j) { return j < 0 ? -1 : (j >= start ? j - start : j - start + m); };
-    const int x = lane;
-    I F{L.base_n, L.base_h};
-    double u = L.base_u;
-    int mo = 0;
     const int na = L.naff, ng = L.ngc;
-    int e = 0;
-    for (; e < na; ++e) {
+    const int le = min(lane, kIbSlots - 1);
+    const bool tin = lane < na && max(pos(L.aj[le][0]), pos(L.aj[le][1])) < K;
+    const int pre_t = __builtin_ctzll(~__ballot(tin));
+    int pre_g = 0;
+    if (FAM == FAM_CHAIN) {
+      const bool gin = lane < ng && max(max(pos(L.gj[le][0]), pos(L.gj[le][1])), pos(L.gj[le][2])) < K;
+      pre_g = __builtin_ctzll(~__ballot(gin));
+    }
+    const int x = lane;
+    I F = base;
+    double u = base_u;
+    int mo = 0;
+    for (int e = 0; e < pre_t; ++e) {
       const int pa = pos(L.aj[e][0]), pb = pos(L.aj[e][1]);
-      if (max(pa, pb) >= K) break;
       const int cb = (pa >= 0 ? (x >> pa) & 1 : 0) | (pb >= 0 ? ((x >> pb) & 1) << 1 : 0);
       F = add(F, I{L.t_n[e][cb], L.t_h[e][cb]});
       u = u + L.t_u[e][cb];
       if (FAM != FAM_CHAIN) mo |= L.gmono[e][cb];
     }
-    int g = 0;
-    if (FAM == FAM_CHAIN)
-      for (; g < ng; ++g) {
-        const int p0 = pos(L.gj[g][0]), p1 = pos(L.gj[g][1]), p2 = pos(L.gj[g][2]);
-        if (max(max(p0, p1), p2) >= K) break;
-        const int cb = (p0 >= 0 ? (x >> p0) & 1 : 0) | (p1 >= 0 ? ((x >> p1) & 1) << 1 : 0) |
-                       (p2 >= 0 ? ((x >> p2) & 1) << 2 : 0);
-        mo |= L.gmono[g][cb];
-      }
+    for (int g = 0; g < pre_g; ++g) {
+      const int p0 = pos(L.gj[g][0]), p1 = pos(L.gj[g][1]), p2 = pos(L.gj[g][2]);
+      const int cb = (p0 >= 0 ? (x >> p0) & 1 : 0) | (p1 >= 0 ? ((x >> p1) & 1) << 1 : 0) |
+                     (p2 >= 0 ? ((x >> p2) & 1) << 2 : 0);
+      mo |= L.gmono[g][cb];
+    }
     L.pre_n[x] = F.n;
     L.pre_h[x] = F.h;
     L.pre_u[x] = u;
     L.pre_mo[x] = mo;
     if (x == 0) {
-      L.pre_terms = e;
-      L.pre_grads = g;
+      L.pre_terms = pre_t;
+      L.pre_grads = pre_g;
       L.start = start;
+    }
+  } else {
+    wb = wave_max(wb);
+    if (lane == 0) L.wred[wid] = wb;
+    if (wid == 1) {   // L.w was written before the barriers above
+      const int g = lane >> 4, nib = lane & 15;
+      double w = 0.0;
+      for (int b = 0; b < 4; ++b) {
+        const int j = 4 * g + b;
+        if (j < m && ((mask >> j) & 1u)) w = dmax(w, L.w[j][(nib >> b) & 1]);
+      }
+      L.w4[g][nib] = w;
     }
   }
   __syncthreads();
@@ -879,7 +899,7 @@ __device__ __forceinline__ int child_bit(uint32_t c, int j) { return j >= 0 ? (i
 // past the table's length is read but not used), then added in increasing order.
 template <int NT, int FAM>
 __device__ __forceinline__ void ib_child(const Params& P, const IbLds<NT>& L, uint32_t mask, int m, uint32_t c,
-                                         double& flo, bool& mo, double& wm, double& u) {
+                                         double wbase, double& flo, bool& mo, double& wm, double& u) {
   // the table entry for c's halves at the first sorted positions (c rotated so
   // that bit p is sorted position p), then the remaining entries in order
   const int st = L.start;
@@ -887,7 +907,7 @@ __device__ __forceinline__ void ib_child(const Params& P, const IbLds<NT>& L, ui
   const uint32_t x = cr & ((1u << kIbPreBits) - 1u);
   I F{L.pre_n[x], L.pre_h[x]};
   u = L.pre_u[x];
-  wm = L.wbase;
+  wm = wbase;
   mo = L.pre_mo[x] != 0;
   const int na = L.naff;
   for (int k0 = L.pre_terms; k0 < na; k0 += kIbGroup) {
@@ -938,6 +958,8 @@ __device__ __forceinline__ void ib_child(const Params& P, const IbLds<NT>& L, ui
 template <int NT, int FAM>
 __device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L, uint32_t mask, Hot& h) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  double wbase = 0.0;   // widest unsplit side
+  for (int k = 0; k < NT / kWave; ++k) wbase = dmax(wbase, L.wred[k]);
   double umin = __builtin_inf();
   int cnt = 0;
   const bool cache = P.nch <= kIbCacheChildren;
@@ -945,7 +967,7 @@ __device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L
     if (((uint32_t)c & ~mask) != 0u) continue;
     double flo, wm, u;
     bool mo;
-    ib_child<NT, FAM>(P, L, mask, P.m, (uint32_t)c, flo, mo, wm, u);
+    ib_child<NT, FAM>(P, L, mask, P.m, (uint32_t)c, wbase, flo, mo, wm, u);
     if (cache) {
       L.c_flo[c] = flo;
       L.c_wm[c] = wm;
@@ -993,19 +1015,53 @@ __device__ __forceinline__ void ib_children_insert(const Params& P, State* S, Ib
   const int64_t base = h.n_keys, seq0 = h.next_seq;
   const int row = (int)sel.row;
   int64_t done = 0;
-  for (int c0 = 0; c0 < P.nch; c0 += NT) {
+  if (P.nch <= kIbCacheChildren) {
+    // bounds cached in LDS: each thread takes cpt consecutive children, one scan
+    // places them (children stay in child order)
+    const int cpt = (P.nch + NT - 1) / NT;
+    const int c0 = (int)threadIdx.x * cpt;
+    int mine = 0;
+    for (int k = 0; k < cpt; ++k) {
+      const int c = c0 + k;
+      mine += (c < P.nch && (((uint32_t)c & ~mask) == 0u) && L.c_keep[c] != 0 && !(L.c_flo[c] > gub)) ? 1 : 0;
+    }
+    int incl = mine;
+    for (int h = 1; h < kWave; h <<= 1) {
+      const int o = __shfl_up(incl, h, kWave);
+      if (lane >= h) incl += o;
+    }
+    if (lane == kWave - 1) L.ins[wid] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < NT / kWave; ++k) {
+      const int v = L.ins[k];
+      before += k < wid ? v : 0;
+      total += v;
+    }
+    int64_t o = before + incl - mine;
+    for (int k = 0; k < cpt; ++k) {
+      const int c = c0 + k;
+      if (c < P.nch && (((uint32_t)c & ~mask) == 0u) && L.c_keep[c] != 0 && !(L.c_flo[c] > gub)) {
+        P.key_flo[base + o] = L.c_flo[c];
+        P.key_seq[base + o] = seq0 + o;
+        P.key_ref[base + o] = row;
+        P.key_r[base + o] = c;
+        P.key_wmax[base + o] = L.c_wm[c];
+        ++o;
+      }
+    }
+    done = total;
+    __syncthreads();   // L.ins is rewritten by the next use
+  }
+  for (int c0 = 0; c0 < P.nch && P.nch > kIbCacheChildren; c0 += NT) {
     const int c = c0 + (int)threadIdx.x;
     double flo = 0.0, wm = 0.0, u;
     bool mo = true;
     const bool formed = c < P.nch && (((uint32_t)c & ~mask) == 0u);
-    if (formed) {
-      if (P.nch <= kIbCacheChildren) {
-        flo = L.c_flo[c];
-        wm = L.c_wm[c];
-        mo = L.c_keep[c] == 0;
-      } else {
-        ib_child<NT, FAM>(P, L, mask, P.m, (uint32_t)c, flo, mo, wm, u);
-      }
+    if (formed) {   // bounds not cached: formed again from the tables
+      double wbase = 0.0;
+      for (int k = 0; k < NT / kWave; ++k) wbase = dmax(wbase, L.wred[k]);
+      ib_child<NT, FAM>(P, L, mask, P.m, (uint32_t)c, wbase, flo, mo, wm, u);
     }
     const int keep = formed && !mo && !(flo > gub);
     int incl = keep;
@@ -1106,8 +1162,31 @@ __device__ __forceinline__ void compact_in_place(const Params& P, State* S, IbLd
 template <int NT>
 __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel& sel) {
   const double gub = okey_inv(h.gub_key);
-  const SelAcc tot = scan_select_wg<NT>(P, gub, h.n_keys);
-  __shared__ int32_t go;
+  // each thread fetches the row reference of its own candidate while the
+  // workgroup reduces; the winner's thread passes it on through LDS
+  __shared__ int32_t go, w_ref, w_r;
+  __shared__ int64_t w_seq;
+  SelAcc tot;
+  bool pre = false;
+  if (scan_own_ok<NT>(P, h.n_keys)) {
+    const OwnSel own = scan_own<NT>(P, gub, h.n_keys);
+    int32_t o_ref = 0, o_r = 0;
+    int64_t o_seq = 0;
+    if (own.bi != INT32_MAX) {
+      o_ref = P.key_ref[own.bi];
+      o_r = P.key_r[own.bi];
+      o_seq = P.key_seq[own.bi];
+    }
+    tot = reduce_own<NT>(P, own);
+    if (own.bi != INT32_MAX && (int64_t)own.bi == tot.best.idx) {   // one thread: each key has one scanner
+      w_ref = o_ref;
+      w_r = o_r;
+      w_seq = o_seq;
+    }
+    pre = true;
+  } else {
+    tot = scan_select_wg<NT>(P, gub, h.n_keys);
+  }
   const int64_t t = h.sweeps, row = t + 1;
   if (threadIdx.x == 0) {
     const Cand b = tot.best;
@@ -1132,9 +1211,9 @@ __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel
   __syncthreads();
   h.n_live = uni64(tot.cnt);
   if (!go) return false;
-  const int32_t ref = P.key_ref[tot.best.idx];
-  const int32_t r = P.key_r[tot.best.idx];
-  const int64_t seq = P.key_seq[tot.best.idx];
+  const int32_t ref = pre ? w_ref : P.key_ref[tot.best.idx];
+  const int32_t r = pre ? w_r : P.key_r[tot.best.idx];
+  const int64_t seq = pre ? w_seq : P.key_seq[tot.best.idx];
   const int n = P.n;
   const int pcyc = P.hist_cyc[ref];
   const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
