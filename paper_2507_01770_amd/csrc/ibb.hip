@@ -1718,30 +1718,48 @@ ibb_status fail(ibb_status s, const std::string& msg) {
   } while (0)
 
 // device memory through the caller's allocator, or stream-ordered hipMallocAsync
+// Device memory of one result or engine.  Small requests are carved from slabs
+// (one allocator call per slab, 256-byte aligned pieces); a carved piece is
+// given back with its slab when everything is released.
 struct Mem {
+  static constexpr size_t kSlabBytes = (size_t)1 << 20, kCarveMax = (size_t)1 << 18;
   ibb_allocator alloc{};
   bool have_alloc = false;
   hipStream_t stream = nullptr;
   struct Blk {
     void* p;
     size_t bytes;
+    bool slab;
   };
   std::vector<Blk> blocks;
+  char* slab = nullptr;
+  size_t slab_used = 0;
 
-  void* get(size_t bytes) {
-    bytes = std::max<size_t>(bytes, 256);
+  void* raw(size_t bytes, bool is_slab) {
     void* p = nullptr;
     if (have_alloc) {
       p = alloc.alloc(alloc.ctx, bytes, stream);
     } else if (hipMallocAsync(&p, bytes, stream) != hipSuccess) {
       p = nullptr;
     }
-    if (p) blocks.push_back({p, bytes});
+    if (p) blocks.push_back({p, bytes, is_slab});
     return p;
   }
-  void put(void* p) {
+  void* get(size_t bytes) {
+    bytes = (std::max<size_t>(bytes, 256) + 255) & ~(size_t)255;
+    if (bytes > kCarveMax) return raw(bytes, false);
+    if (!slab || slab_used + bytes > kSlabBytes) {
+      slab = static_cast<char*>(raw(kSlabBytes, true));
+      slab_used = 0;
+      if (!slab) return nullptr;
+    }
+    void* p = slab + slab_used;
+    slab_used += bytes;
+    return p;
+  }
+  void put(void* p) {   // pieces of a slab stay until release_all
     for (size_t i = 0; i < blocks.size(); ++i)
-      if (blocks[i].p == p) {
+      if (blocks[i].p == p && !blocks[i].slab) {
         if (have_alloc) alloc.free(alloc.ctx, p, blocks[i].bytes, stream);
         else (void)hipFreeAsync(p, stream);
         blocks.erase(blocks.begin() + i);
@@ -1754,6 +1772,8 @@ struct Mem {
       else (void)hipFreeAsync(b.p, stream);
     }
     blocks.clear();
+    slab = nullptr;
+    slab_used = 0;
   }
 };
 
@@ -1787,6 +1807,16 @@ ibb_status validate(const ibb_problem* p) {
 template <typename T>
 T* dalloc(Mem& M, int64_t count) {
   return static_cast<T*>(M.get((size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+}
+
+// the per-sweep trace: four rows of `cap` 8-byte entries in one block
+constexpr int64_t kTraceStart = 4096, kTraceMax = (int64_t)1 << 17;
+void set_trace(Params& P, double* block, int64_t cap) {
+  P.tr_gub = block;
+  P.tr_nsurv = reinterpret_cast<int64_t*>(block + cap);
+  P.tr_nlive = reinterpret_cast<int64_t*>(block + 2 * cap);
+  P.tr_sel = reinterpret_cast<int64_t*>(block + 3 * cap);
+  P.trace_cap = cap;
 }
 
 // Whether single-precision evaluation cannot overflow: every intermediate of the
@@ -1974,7 +2004,7 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   P.tol_x = prob->tol_x;
   P.max_sweeps = U.opts.max_sweeps;
   P.max_live = U.opts.max_live_boxes;
-  P.trace_cap = std::min<int64_t>(U.opts.max_sweeps + 1, (int64_t)1 << 17);
+  P.trace_cap = std::min<int64_t>(std::min<int64_t>(U.opts.max_sweeps + 1, kTraceMax), kTraceStart);
   P.key_cap = std::max<int64_t>(4096, 4 * (int64_t)P.nch);
   P.hist_cap = 64;
   P.key_flo = dalloc<double>(M, P.key_cap);
@@ -1994,10 +2024,7 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   P.part_idx = dalloc<int64_t>(M, kMaxSelBlocks);
   P.part_wmax = dalloc<double>(M, kMaxSelBlocks);
   P.part_cnt = dalloc<int64_t>(M, kMaxSelBlocks);
-  P.tr_gub = dalloc<double>(M, P.trace_cap);
-  P.tr_nsurv = dalloc<int64_t>(M, P.trace_cap);
-  P.tr_nlive = dalloc<int64_t>(M, P.trace_cap);
-  P.tr_sel = dalloc<int64_t>(M, P.trace_cap);
+  set_trace(P, dalloc<double>(M, 4 * P.trace_cap), P.trace_cap);
   if (!P.key_flo || !P.key_seq || !P.key_ref || !P.key_r || !P.key_wmax || !P.hist_n || !P.hist_h || !P.hist_cyc ||
       !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.part_flo ||
       !P.part_idx || !P.part_wmax || !P.part_cnt || !P.tr_gub || !P.tr_nsurv || !P.tr_nlive || !P.tr_sel)
@@ -2050,15 +2077,16 @@ ibb_status run_capacity(Run& U, int chunk) {
     P.key_cap = nc;
     changed = true;
   }
-  const int64_t need_tr = std::min<int64_t>(U.sweeps + chunk + 1, (int64_t)1 << 17);
-  if (need_tr > P.trace_cap) {   // a run continued by ibb_sweep past its first budget
-    const int64_t nc = std::min<int64_t>(std::max<int64_t>(2 * P.trace_cap, need_tr), (int64_t)1 << 17);
+  const int64_t need_tr = std::min<int64_t>(U.sweeps + chunk + 1, kTraceMax);
+  if (need_tr > P.trace_cap) {
+    const int64_t nc = std::min<int64_t>(std::max<int64_t>(2 * P.trace_cap, need_tr), kTraceMax);
     const int64_t keep = std::min<int64_t>(U.sweeps, P.trace_cap);
-    ibb_status st = IBB_OK;
-    if ((st = grow(M, P.tr_gub, keep, nc)) != IBB_OK || (st = grow(M, P.tr_nsurv, keep, nc)) != IBB_OK ||
-        (st = grow(M, P.tr_nlive, keep, nc)) != IBB_OK || (st = grow(M, P.tr_sel, keep, nc)) != IBB_OK)
-      return st;
-    P.trace_cap = nc;
+    double* t = dalloc<double>(M, 4 * nc);
+    if (!t) return fail(IBB_E_NOMEM, "device allocation failed");
+    if (keep > 0)   // the four rows of the old block into the new one
+      HIPCHK(hipMemcpy2DAsync(t, nc * 8, P.tr_gub, P.trace_cap * 8, keep * 8, 4, hipMemcpyDeviceToDevice, M.stream));
+    M.put(P.tr_gub);
+    set_trace(P, t, nc);
     changed = true;
   }
   if (changed) return push_params(M, P, U.dP);
@@ -2104,11 +2132,14 @@ ibb_status run_finish(Run& U) {
   for (double v : hflo) glb = std::min(glb, v);
   const int64_t tn = std::min<int64_t>(hs.sweeps, P.trace_cap);
   R->tr_gub.resize(tn); R->tr_nsurv.resize(tn); R->tr_nlive.resize(tn); R->tr_sel.resize(tn);
-  if (tn > 0) {
-    HIPCHK(hipMemcpy(R->tr_gub.data(), P.tr_gub, tn * 8, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(R->tr_nsurv.data(), P.tr_nsurv, tn * 8, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(R->tr_nlive.data(), P.tr_nlive, tn * 8, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(R->tr_sel.data(), P.tr_sel, tn * 8, hipMemcpyDeviceToHost));
+  if (tn > 0) {   // the four trace rows in one copy
+    std::vector<uint64_t> h(4 * tn);
+    HIPCHK(hipMemcpy2DAsync(h.data(), tn * 8, P.tr_gub, P.trace_cap * 8, tn * 8, 4, hipMemcpyDeviceToHost, M.stream));
+    HIPCHK(hipStreamSynchronize(M.stream));
+    std::memcpy(R->tr_gub.data(), h.data(), tn * 8);
+    std::memcpy(R->tr_nsurv.data(), h.data() + tn, tn * 8);
+    std::memcpy(R->tr_nlive.data(), h.data() + 2 * tn, tn * 8);
+    std::memcpy(R->tr_sel.data(), h.data() + 3 * tn, tn * 8);
     if (hs.sweeps <= P.trace_cap) R->tr_nlive[tn - 1] = kept;
   }
   R->info.f_lo = glb;
@@ -2252,26 +2283,28 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
     ~Events() { for (auto e : v) (void)hipEventDestroy(e); }
   } evs;
   auto& ev = evs.v;
-  int chunk = 4;
+  int grow_chunk = 4;   // sweeps per host round trip on the per-sweep path (and under a time limit): 4, 8, ..., 256
   for (;;) {
+    // incremental bounds on a list one workgroup scans quickly: a whole chunk of
+    // sweeps in one launch, as many as keep the list's growth within a bound
+    const bool persist = P.incremental && U.n_keys <= kPersistentMaxKeys;
+    int chunk = persist ? (int)std::min<int64_t>(std::max<int64_t>(kPersistentGrowth / P.nch, 16), 256) : grow_chunk;
+    if (U.opts.time_limit_s > 0.0) chunk = std::min(chunk, grow_chunk);   // the limit is checked between launches
     if ((st = run_capacity(U, chunk)) != IBB_OK) return st;
     const int sb = sel_blocks_for(U.n_keys + (int64_t)(chunk + 1) * P.nch);
     const bool prof = U.opts.profile != 0;
-    if (prof && (int)ev.size() < 4 * chunk) {
+    const int nev = persist ? 4 : 4 * chunk;
+    if (prof && (int)ev.size() < nev) {
       const size_t old_n = ev.size();
-      ev.resize(4 * chunk);
+      ev.resize(nev);
       for (size_t e = old_n; e < ev.size(); ++e)
         if (hipEventCreate(&ev[e]) != hipSuccess) return (fail(IBB_E_DEVICE, "hipEventCreate failed"));
     }
-    // incremental bounds on a list one workgroup scans quickly: the whole chunk of
-    // sweeps in one launch
-    const bool persist = P.incremental && U.n_keys <= kPersistentMaxKeys;
     dispatch_family(P.family, [&](auto fam) {
       constexpr int FAM = decltype(fam)::value;
       if (persist) {
         hipExtLaunchKernelGGL((k_sweeps_ib<kSweepThreads, FAM>), dim3(1), dim3(kSweepThreads), 0, M.stream,
-                              prof ? ev[0] : nullptr, prof ? ev[3] : nullptr, 0, U.dP, U.dS,
-                              std::min(chunk, kPersistentChunk));
+                              prof ? ev[0] : nullptr, prof ? ev[3] : nullptr, 0, U.dP, U.dS, chunk);
         return;
       }
       for (int s = 0; s < chunk; ++s) {
@@ -2332,7 +2365,7 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
       break;
     }
     if ((st = run_after_chunk(U)) != IBB_OK) return st;
-    chunk = std::min(chunk * 2, 256);
+    grow_chunk = std::min(grow_chunk * 2, 256);
   }
   return IBB_OK;
 }

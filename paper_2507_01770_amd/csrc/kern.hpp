@@ -28,7 +28,7 @@ constexpr int kSelSingleThreads = 1024;   // the one-workgroup selection
 constexpr int kSweepThreads = 512;        // persistent sweeps (room for 256 registers per lane)
 constexpr int kMaxSelBlocks = 1024;
 constexpr int64_t kPersistentMaxKeys = (int64_t)1 << 18;   // lists one workgroup scans about as fast as a grid
-constexpr int kPersistentChunk = 64;                        // sweeps per persistent launch (the list grows meanwhile)
+constexpr int64_t kPersistentGrowth = (int64_t)1 << 17;      // keys a persistent launch may add (sets its sweeps)
 
 // STOP_CAPACITY: the next sweep would pass the row or key capacity the host sized
 // the arrays for (the host grows them before every chunk, so this only guards)

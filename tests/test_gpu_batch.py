@@ -92,8 +92,9 @@ def test_server_mix_equals_alone(alone):
 
 def test_server_respects_memory_budget():
     ps = [PR.sep_cos(100, 11 + i) for i in range(6)]
-    # about 0.35 MB each at the start: a 1 MB budget admits at most three at once
-    with ibb.Server(mem_budget_bytes=1 << 20, max_slots=8) as srv:
+    # about 1.4 MB each at the start (a 1 MiB slab and the arrays larger than its
+    # pieces): a 4 MiB budget admits at most three at once
+    with ibb.Server(mem_budget_bytes=4 << 20, max_slots=8) as srv:
         pending = {srv.submit(p, max_sweeps=300) for p in ps}
         t0 = time.time()
         while pending and time.time() - t0 < 120:
