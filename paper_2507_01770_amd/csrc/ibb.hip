@@ -432,7 +432,7 @@ __device__ __forceinline__ OwnSel scan_own(const Params& P, double gub, int64_t 
       bf = f;
       bi = i;
     }
-    if (need_w && live) wm = dmax(wm, P.key_wmax[i]);
+    if (need_w && live) wm = dmax(wm, G(P.key_wmax)[i]);
   };
   const double2* f2 = reinterpret_cast<const double2*>(P.key_flo);
   const int32_t np = (int32_t)(nk >> 1);
@@ -441,7 +441,7 @@ __device__ __forceinline__ OwnSel scan_own(const Params& P, double gub, int64_t 
   for (; p + (U - 1) * NT < np; p += U * NT) {
     double2 v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = f2[p + u * NT];
+    for (int u = 0; u < U; ++u) v[u] = gload(f2 + p + u * NT);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       visit(2 * (p + u * NT), v[u].x);
@@ -449,11 +449,11 @@ __device__ __forceinline__ OwnSel scan_own(const Params& P, double gub, int64_t 
     }
   }
   for (; p < np; p += NT) {
-    const double2 v = f2[p];
+    const double2 v = gload(f2 + p);
     visit(2 * p, v.x);
     visit(2 * p + 1, v.y);
   }
-  if ((nk & 1) && threadIdx.x == 0) visit((int32_t)(nk - 1), P.key_flo[nk - 1]);
+  if ((nk & 1) && threadIdx.x == 0) visit((int32_t)(nk - 1), G(P.key_flo)[nk - 1]);
   return OwnSel{bf, wm, bi, cnt};
 }
 template <int NT>
@@ -583,8 +583,9 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
 }
 __device__ __forceinline__ int64_t uni64(int64_t v) { return (int64_t)uni64((uint64_t)v); }
 __device__ __forceinline__ Hot hot_load(const State* S) {
-  return Hot{uni64(S->gub_key), uni64(S->n_keys), uni64(S->next_seq), uni64(S->sweeps),
-             uni64(S->n_live), uni64(S->evaluated), uni64(S->ub_evaluated)};
+  const auto Sg = G(S);
+  return Hot{uni64(Sg->gub_key), uni64(Sg->n_keys), uni64(Sg->next_seq), uni64(Sg->sweeps),
+             uni64(Sg->n_live), uni64(Sg->evaluated), uni64(Sg->ub_evaluated)};
 }
 // the selected box: its row, cycling index, split mask and insertion number
 struct Sel {
@@ -633,9 +634,9 @@ struct IbLds {
 
 // the interval of coordinate i of the selected row for half b of split index j
 __device__ __forceinline__ I ib_half(const double* rn, const double* rh, const double* mid, int i, int j, int b) {
-  if (j < 0) return I{rn[i], rh[i]};
-  const double md = mid[j];
-  return b ? I{neg(md), rh[i]} : I{rn[i], md};
+  if (j < 0) return I{G(rn)[i], G(rh)[i]};
+  const double md = G(mid)[j];
+  return b ? I{neg(md), G(rh)[i]} : I{G(rn)[i], md};
 }
 
 template <int NT, int FAM>
@@ -729,15 +730,15 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
         const int a = L.aff[k];
         const I x = ib_half(rn, rh, mid, a, L.aj[k][0], b);
         if (part == 0) {
-          const I t = sep_term<FAM>(P.sep[a], x);
+          const I t = sep_term<FAM>(gload(P.sep + a), x);
           L.t_n[k][b] = t.n;
           L.t_h[k][b] = t.h;
         } else if (part == 1) {
-          L.t_u[k][b] = sep_point_hi<FAM>(P.sep[a], midpoint(x));
+          L.t_u[k][b] = sep_point_hi<FAM>(gload(P.sep + a), midpoint(x));
         } else {
-          I t, G;
-          sep_box<FAM>(P.sep[a], x, t, G);
-          L.gmono[k][b] = (G.n < 0.0 && x.n != P.nl[a]) || (G.h < 0.0 && x.h != P.u[a]);
+          I t, Gr;
+          sep_box<FAM>(gload(P.sep + a), x, t, Gr);
+          L.gmono[k][b] = (Gr.n < 0.0 && x.n != G(P.nl)[a]) || (Gr.h < 0.0 && x.h != G(P.u)[a]);
         }
       }
     } else if (q < 4 * na) {                    // chained: affected term, combination of halves
@@ -748,10 +749,11 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
         const I xa = ib_half(rn, rh, mid, a, ja, cb & 1);
         const I xb = ib_half(rn, rh, mid, a + 1, jb, (cb >> 1) & 1);
         I R, E;
-        const I t = chain_term(P.chain[a], xa, xb, R, E);
+        const CoefChain ca = gload(P.chain + a);
+        const I t = chain_term(ca, xa, xb, R, E);
         L.t_n[k][cb] = t.n;
         L.t_h[k][cb] = t.h;
-        L.t_u[k][cb] = chain_term(P.chain[a], point(midpoint(xa)), point(midpoint(xb)), R, E).h;
+        L.t_u[k][cb] = chain_term(ca, point(midpoint(xa)), point(midpoint(xb)), R, E).h;
       }
     } else if (q >= 128 && q < 128 + 8 * ng) {  // chained: test per combination of halves of g - 1, g, g + 1
       const int k = (q - 128) >> 3, cb = (q - 128) & 7;
@@ -763,8 +765,8 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
         const I xg = ib_half(rn, rh, mid, g, j1, (cb >> 1) & 1);
         const I xp = has_prev ? ib_half(rn, rh, mid, g - 1, j0, cb & 1) : xg;
         const I xq = has_next ? ib_half(rn, rh, mid, g + 1, j2, (cb >> 2) & 1) : xg;
-        const I G = chain_grad(P.chain[has_prev ? g - 1 : g], P.chain[g], xp, xg, xq, has_prev, has_next);
-        mo = (G.n < 0.0 && xg.n != P.nl[g]) || (G.h < 0.0 && xg.h != P.u[g]);
+        const I Gr = chain_grad(gload(P.chain + (has_prev ? g - 1 : g)), gload(P.chain + g), xp, xg, xq, has_prev, has_next);
+        mo = (Gr.n < 0.0 && xg.n != G(P.nl)[g]) || (Gr.h < 0.0 && xg.h != G(P.u)[g]);
       }
       L.gmono[k][cb] = mo;
     }
@@ -787,17 +789,19 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
       I t{0.0, 0.0};
       double u = 0.0;
       if (i < n && split_of(i) < 0) {
-        const I x{rn[i], rh[i]};
+        const I x{G(rn)[i], G(rh)[i]};
         wb = dmax(wb, x.n + x.h);
         if (i < T && !(FAM == FAM_CHAIN && split_of(i + 1) >= 0)) {
           if (FAM != FAM_CHAIN) {
-            t = sep_term<FAM>(P.sep[i], x);
-            u = sep_point_hi<FAM>(P.sep[i], midpoint(x));
+            const CoefSep ci = gload(P.sep + i);
+            t = sep_term<FAM>(ci, x);
+            u = sep_point_hi<FAM>(ci, midpoint(x));
           } else {
-            const I xn{rn[i + 1], rh[i + 1]};
+            const I xn{G(rn)[i + 1], G(rh)[i + 1]};
             I R, E;
-            t = chain_term(P.chain[i], x, xn, R, E);
-            u = chain_term(P.chain[i], point(midpoint(x)), point(midpoint(xn)), R, E).h;
+            const CoefChain ci = gload(P.chain + i);
+            t = chain_term(ci, x, xn, R, E);
+            u = chain_term(ci, point(midpoint(x)), point(midpoint(xn)), R, E).h;
           }
         }
       }
@@ -990,9 +994,9 @@ __device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L
     uint64_t g = h.gub_key;
     if (tot > 0 && key < g) {
       g = key;
-      S->gub_key = key;
+      G(S)->gub_key = key;
     }
-    S->ub_evaluated = h.ub_evaluated + tot;
+    G(S)->ub_evaluated = h.ub_evaluated + tot;
     L.gub_key = g;
     L.tot = tot;
   }
@@ -1042,11 +1046,11 @@ __device__ __forceinline__ void ib_children_insert(const Params& P, State* S, Ib
     for (int k = 0; k < cpt; ++k) {
       const int c = c0 + k;
       if (c < P.nch && (((uint32_t)c & ~mask) == 0u) && L.c_keep[c] != 0 && !(L.c_flo[c] > gub)) {
-        P.key_flo[base + o] = L.c_flo[c];
-        P.key_seq[base + o] = seq0 + o;
-        P.key_ref[base + o] = row;
-        P.key_r[base + o] = c;
-        P.key_wmax[base + o] = L.c_wm[c];
+        G(P.key_flo)[base + o] = L.c_flo[c];
+        G(P.key_seq)[base + o] = seq0 + o;
+        G(P.key_ref)[base + o] = row;
+        G(P.key_r)[base + o] = c;
+        G(P.key_wmax)[base + o] = L.c_wm[c];
         ++o;
       }
     }
@@ -1079,11 +1083,11 @@ __device__ __forceinline__ void ib_children_insert(const Params& P, State* S, Ib
     }
     if (keep) {
       const int64_t o = done + before + incl - 1;
-      P.key_flo[base + o] = flo;
-      P.key_seq[base + o] = seq0 + o;
-      P.key_ref[base + o] = row;
-      P.key_r[base + o] = c;
-      P.key_wmax[base + o] = wm;
+      G(P.key_flo)[base + o] = flo;
+      G(P.key_seq)[base + o] = seq0 + o;
+      G(P.key_ref)[base + o] = row;
+      G(P.key_r)[base + o] = c;
+      G(P.key_wmax)[base + o] = wm;
     }
     done += total;
     __syncthreads();   // L.ins is rewritten by the next round
@@ -1091,15 +1095,16 @@ __device__ __forceinline__ void ib_children_insert(const Params& P, State* S, Ib
   const int64_t t = h.sweeps;
   if (threadIdx.x == 0) {
     if (t < P.trace_cap) {
-      P.tr_gub[t] = gub;
-      P.tr_nsurv[t] = done;
-      P.tr_sel[t] = sel.seq;
+      G(P.tr_gub)[t] = gub;
+      G(P.tr_nsurv)[t] = done;
+      G(P.tr_sel)[t] = sel.seq;
     }
-    S->n_keys = base + done;
-    S->next_seq = seq0 + done;
-    S->evaluated = h.evaluated + L.tot;
-    S->sweeps = t + 1;
-    S->pending = 0;
+    const auto Sg = G(S);
+    Sg->n_keys = base + done;
+    Sg->next_seq = seq0 + done;
+    Sg->evaluated = h.evaluated + L.tot;
+    Sg->sweeps = t + 1;
+    Sg->pending = 0;
   }
   h.n_keys = uni64(base + done);
   h.next_seq = uni64(seq0 + done);
@@ -1128,7 +1133,7 @@ __device__ __forceinline__ void compact_in_place(const Params& P, State* S, IbLd
     int64_t sq = 0;
     int32_t rf = 0, rr = 0;
     const bool in = i < nk;
-    if (in) { f = P.key_flo[i]; sq = P.key_seq[i]; rf = P.key_ref[i]; rr = P.key_r[i]; w = P.key_wmax[i]; }
+    if (in) { f = G(P.key_flo)[i]; sq = G(P.key_seq)[i]; rf = G(P.key_ref)[i]; rr = G(P.key_r)[i]; w = G(P.key_wmax)[i]; }
     const int keep = in && f <= gub;
     int incl = keep;
     for (int h = 1; h < kWave; h <<= 1) {
@@ -1145,12 +1150,12 @@ __device__ __forceinline__ void compact_in_place(const Params& P, State* S, IbLd
     }
     if (keep) {
       const int64_t o = kept + before + incl - 1;
-      P.key_flo[o] = f; P.key_seq[o] = sq; P.key_ref[o] = rf; P.key_r[o] = rr; P.key_wmax[o] = w;
+      G(P.key_flo)[o] = f; G(P.key_seq)[o] = sq; G(P.key_ref)[o] = rf; G(P.key_r)[o] = rr; G(P.key_wmax)[o] = w;
     }
     kept += total;
     __syncthreads();
   }
-  if (threadIdx.x == 0) S->n_keys = kept;
+  if (threadIdx.x == 0) G(S)->n_keys = kept;
   h.n_keys = uni64(kept);
   __syncthreads();
 }
@@ -1173,9 +1178,9 @@ __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel
     int32_t o_ref = 0, o_r = 0;
     int64_t o_seq = 0;
     if (own.bi != INT32_MAX) {
-      o_ref = P.key_ref[own.bi];
-      o_r = P.key_r[own.bi];
-      o_seq = P.key_seq[own.bi];
+      o_ref = G(P.key_ref)[own.bi];
+      o_r = G(P.key_r)[own.bi];
+      o_seq = G(P.key_seq)[own.bi];
     }
     tot = reduce_own<NT>(P, own);
     if (own.bi != INT32_MAX && (int64_t)own.bi == tot.best.idx) {   // one thread: each key has one scanner
@@ -1188,38 +1193,39 @@ __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel
     tot = scan_select_wg<NT>(P, gub, h.n_keys);
   }
   const int64_t t = h.sweeps, row = t + 1;
+  const auto Sg = G(S);
   if (threadIdx.x == 0) {
     const Cand b = tot.best;
-    if (t > 0 && t - 1 < P.trace_cap) P.tr_nlive[t - 1] = tot.cnt;
-    S->n_live = tot.cnt;
-    S->glb = b.f;
-    S->wmax = tot.wm;
+    if (t > 0 && t - 1 < P.trace_cap) G(P.tr_nlive)[t - 1] = tot.cnt;
+    Sg->n_live = tot.cnt;
+    Sg->glb = b.f;
+    Sg->wmax = tot.wm;
     int32_t stop = RUNNING;
     if (tot.cnt == 0) stop = STOP_EMPTY;
     else if (gub - b.f <= P.tol_f && (P.tol_x <= 0.0 || tot.wm < P.tol_x)) stop = STOP_CONVERGED;
     else if (t >= P.max_sweeps) stop = STOP_SWEEPS;
     else if (P.max_live > 0 && tot.cnt > P.max_live) stop = STOP_LIVE;
     else if (row >= P.hist_cap || h.n_keys + P.nch > P.key_cap) stop = STOP_CAPACITY;
-    if (stop) S->stop = stop;
+    if (stop) Sg->stop = stop;
     go = stop == RUNNING;
     if (go) {
-      P.key_flo[b.idx] = __builtin_inf();     // removed from the list
-      S->gub_start = gub;
-      S->pending = 1;
+      G(P.key_flo)[b.idx] = __builtin_inf();     // removed from the list
+      Sg->gub_start = gub;
+      Sg->pending = 1;
     }
   }
   __syncthreads();
   h.n_live = uni64(tot.cnt);
   if (!go) return false;
-  const int32_t ref = pre ? w_ref : P.key_ref[tot.best.idx];
-  const int32_t r = pre ? w_r : P.key_r[tot.best.idx];
-  const int64_t seq = pre ? w_seq : P.key_seq[tot.best.idx];
+  const int32_t ref = pre ? w_ref : G(P.key_ref)[tot.best.idx];
+  const int32_t r = pre ? w_r : G(P.key_r)[tot.best.idx];
+  const int64_t seq = pre ? w_seq : G(P.key_seq)[tot.best.idx];
   const int n = P.n;
-  const int pcyc = P.hist_cyc[ref];
+  const int pcyc = G(P.hist_cyc)[ref];
   const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
-                     n, P.m, pcyc, r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
-  double* dn = P.hist_n + row * n;
-  double* dh = P.hist_h + row * n;
+                     n, P.m, pcyc, r >= 0 ? G(P.hist_mask)[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
+  const gptr<double> dn = G(P.hist_n + row * n);
+  const gptr<double> dh = G(P.hist_h + row * n);
   for (int i = threadIdx.x; i < n; i += NT) {
     const I x = src.get(i);
     dn[i] = x.n;
@@ -1237,16 +1243,16 @@ __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel
   const uint32_t mask = (uint32_t)__ballot(ok) & ((1u << P.m) - 1u);   // m <= 16
   if (threadIdx.x < (unsigned)kWave) {
     if (lane < P.m) {
-      P.hist_mid[row * kMaxSplit + lane] = md;
-      S->sel_mid[lane] = md;
+      G(P.hist_mid)[row * kMaxSplit + lane] = md;
+      Sg->sel_mid[lane] = md;
     }
     if (lane == 0) {
-      P.hist_mask[row] = mask;
-      P.hist_cyc[row] = cyc;
-      S->sel_mask = mask;
-      S->sel_cyc = cyc;
-      S->sel_row = (int32_t)row;
-      S->sel_seq = seq;
+      G(P.hist_mask)[row] = mask;
+      G(P.hist_cyc)[row] = cyc;
+      Sg->sel_mask = mask;
+      Sg->sel_cyc = cyc;
+      Sg->sel_row = (int32_t)row;
+      Sg->sel_seq = seq;
     }
   }
   sel.row = row;
@@ -1268,7 +1274,7 @@ __device__ __forceinline__ Sel sel_load(const State* S) {
 
 template <int NT, int FAM>
 __device__ __forceinline__ void sweeps_ib(const Params& P, State* S, IbLds<NT>& lds, int iters) {
-  if (S->stop) return;
+  if (G(S)->stop) return;
   Hot h = hot_load(S);   // no children are pending here: the incremental sweep inserts its own
   for (int it = 0; it < iters; ++it) {
     // dead keys dominate the list: drop them before the scan

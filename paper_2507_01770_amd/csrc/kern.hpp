@@ -21,6 +21,27 @@
 namespace ibb {
 
 constexpr int kWave = 64;
+
+// Everything a Params or State pointer reaches is device (global) memory.
+// Accesses through G(p) compile to global loads and stores: LDS waits do not
+// wait for them (accesses through generic pointers count against both).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> G(T* p) {
+  return (gptr<T>)p;
+}
+// a record (a multiple of 8 bytes) read from device memory with global loads
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  static_assert(sizeof(T) % 8 == 0, "whole 8-byte words");
+  T v;
+  const gptr<const uint64_t> src = G(reinterpret_cast<const uint64_t*>(p));
+  uint64_t* dst = reinterpret_cast<uint64_t*>(&v);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 8); ++k) dst[k] = src[k];
+  return v;
+}
 constexpr int kBoundWaves = 4;            // waves per workgroup in the bound kernels
 constexpr int kMaxSplit = 16;             // M <= 16
 constexpr int kSelThreads = 256;
@@ -130,11 +151,11 @@ struct ChildRow {
   int n, m, cyc;
   uint32_t mask, r;
   __device__ __forceinline__ I get(int i) const {
-    I x{pn[i], ph[i]};
+    I x{G(pn)[i], G(ph)[i]};
     int j = i - cyc;
     if (j < 0) j += n;
     if (j < m && ((mask >> j) & 1u)) {
-      const double md = mid[j];
+      const double md = G(mid)[j];
       if ((r >> j) & 1u) x.n = neg(md); else x.h = md;
     }
     return x;
