@@ -475,7 +475,8 @@ __device__ __forceinline__ SelAcc reduce_own(const Params& P, OwnSel o) {
   __shared__ double s_f[NW], s_w[NW];
   __shared__ int32_t s_i[NW], s_c[NW];
   const int w = threadIdx.x >> 6;
-  __syncthreads();   // a previous call may still read these
+  // (callers run at most one reduction per sweep, with barriers in between: no
+  // thread still reads these when they are written again)
   if ((threadIdx.x & (kWave - 1)) == 0) {
     s_f[w] = bf;
     s_i[w] = bi;
@@ -847,28 +848,50 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
     const int na = L.naff, ng = L.ngc;
     const int le = min(lane, kIbSlots - 1);
     const bool tin = lane < na && max(pos(L.aj[le][0]), pos(L.aj[le][1])) < K;
-    const int pre_t = __builtin_ctzll(~__ballot(tin));
+    const int pre_t = min(__builtin_ctzll(~__ballot(tin)), kIbPreBits + 1);
     int pre_g = 0;
     if (FAM == FAM_CHAIN) {
       const bool gin = lane < ng && max(max(pos(L.gj[le][0]), pos(L.gj[le][1])), pos(L.gj[le][2])) < K;
-      pre_g = __builtin_ctzll(~__ballot(gin));
+      pre_g = min(__builtin_ctzll(~__ballot(gin)), kIbPreBits + 2);
     }
     const int x = lane;
     I F = base;
     double u = base_u;
     int mo = 0;
-    for (int e = 0; e < pre_t; ++e) {
-      const int pa = pos(L.aj[e][0]), pb = pos(L.aj[e][1]);
-      const int cb = (pa >= 0 ? (x >> pa) & 1 : 0) | (pb >= 0 ? ((x >> pb) & 1) << 1 : 0);
-      F = add(F, I{L.t_n[e][cb], L.t_h[e][cb]});
-      u = u + L.t_u[e][cb];
-      if (FAM != FAM_CHAIN) mo |= L.gmono[e][cb];
+    // at most K + 1 terms and K + 2 derivative coordinates involve only positions
+    // below K: their rows are read together, then added in order
+    constexpr int kPreT = kIbPreBits + 1, kPreG = kIbPreBits + 2;
+    {
+      double tn[kPreT], th[kPreT], tu[kPreT];
+      int gm[kPreT];
+#pragma unroll
+      for (int e = 0; e < kPreT; ++e) {
+        const int er = min(e, kIbSlots - 1);
+        const int pa = pos(L.aj[er][0]), pb = pos(L.aj[er][1]);
+        const int cb = (pa >= 0 ? (x >> pa) & 1 : 0) | (pb >= 0 ? ((x >> pb) & 1) << 1 : 0);
+        tn[e] = L.t_n[er][cb];
+        th[e] = L.t_h[er][cb];
+        tu[e] = L.t_u[er][cb];
+        gm[e] = FAM != FAM_CHAIN ? L.gmono[er][cb] : 0;
+      }
+#pragma unroll
+      for (int e = 0; e < kPreT; ++e)
+        if (e < pre_t) {
+          F = add(F, I{tn[e], th[e]});
+          u = u + tu[e];
+          mo |= gm[e];
+        }
     }
-    for (int g = 0; g < pre_g; ++g) {
-      const int p0 = pos(L.gj[g][0]), p1 = pos(L.gj[g][1]), p2 = pos(L.gj[g][2]);
-      const int cb = (p0 >= 0 ? (x >> p0) & 1 : 0) | (p1 >= 0 ? ((x >> p1) & 1) << 1 : 0) |
-                     (p2 >= 0 ? ((x >> p2) & 1) << 2 : 0);
-      mo |= L.gmono[g][cb];
+    if (FAM == FAM_CHAIN) {
+#pragma unroll
+      for (int g = 0; g < kPreG; ++g) {
+        const int gr = min(g, kIbSlots - 1);
+        const int p0 = pos(L.gj[gr][0]), p1 = pos(L.gj[gr][1]), p2 = pos(L.gj[gr][2]);
+        const int cb = (p0 >= 0 ? (x >> p0) & 1 : 0) | (p1 >= 0 ? ((x >> p1) & 1) << 1 : 0) |
+                       (p2 >= 0 ? ((x >> p2) & 1) << 2 : 0);
+        const int v = L.gmono[gr][cb];
+        if (g < pre_g) mo |= v;
+      }
     }
     L.pre_n[x] = F.n;
     L.pre_h[x] = F.h;
