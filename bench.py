@@ -93,6 +93,7 @@ def main() -> int:
         return rs + [rp], dt
 
     # headline: incremental child bounds (the default)
+    phase("headline: incremental bounds")
     res, dt = timed(args.steps, args.warmup)
     boxes = sum(r.boxes_evaluated for r in res[:-1])
     r0 = res[-1]
@@ -112,6 +113,7 @@ def main() -> int:
     # the same workload with full bounds (every child over all n terms): k_bound's roofline
     full = None
     if args.full_steps > 0:
+        phase("full bounds")
         rf, df = timed(args.full_steps, 1, incremental=False)
         q = rf[-1]
         formed = q.boxes_evaluated - 1          # children (the root is bounded by another kernel)
@@ -129,6 +131,7 @@ def main() -> int:
 
     cpu = None
     if args.cpu_sweeps > 0:
+        phase("cpu baseline (oracle)")
         from oracle import oracle as O
         tc = time.perf_counter()
         o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=args.cpu_sweeps, incremental=True)
@@ -139,6 +142,7 @@ def main() -> int:
 
     fp32 = None
     if args.fp32_steps > 0:
+        phase("fp32 filter")
         r32, d32 = timed(args.fp32_steps, 1, precision="fp32_bulk")
         q = r32[-1]
         fp32 = {"boxes_per_s": round(sum(r.boxes_evaluated for r in r32[:-1]) / d32, 1),
@@ -151,8 +155,10 @@ def main() -> int:
     # the other workloads, solved completely once each (incremental bounds)
     workloads = None
     if args.workloads:
+        phase("other workloads")
         workloads = {}
         for cfg in (0, 2, 3):
+            phase(f"workload {cfg}")
             q = PR.config(cfg)
             if cfg != 3:
                 ibb.minimize(q, fetch_boxes=False)
@@ -166,6 +172,8 @@ def main() -> int:
                 "time_to_enclosure_ms": round(dq * 1e3, 3), "sweeps": rq.sweeps, "boxes": rq.boxes_evaluated,
                 "boxes_per_s": round(rq.boxes_evaluated / dq, 1), "enclosure": [rq.f_lo, rq.f_hi]}
 
+    if args.serve_requests > 0:
+        phase("serving")
     serving = serve_bench(args.serve_requests) if args.serve_requests > 0 else None
 
     line = {
@@ -197,6 +205,11 @@ def main() -> int:
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def phase(name: str) -> None:
+    """A progress line on stderr (the JSON result line goes to stdout)."""
+    print(f"bench: {name}", file=sys.stderr, flush=True)
 
 
 def measured_traffic():
