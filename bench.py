@@ -129,17 +129,6 @@ def main() -> int:
                              "flops_per_launch": round(ops / max(1, q.n_bound_launches))},
                 "select_avg_launch_us": round(q.t_select_ms * 1e3 / max(1, q.n_select_launches), 3)}
 
-    cpu = None
-    if args.cpu_sweeps > 0:
-        phase("cpu baseline (oracle)")
-        from oracle import oracle as O
-        tc = time.perf_counter()
-        o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=args.cpu_sweeps, incremental=True)
-        tcpu = time.perf_counter() - tc
-        cpu = {"value": round(o.boxes_evaluated / tcpu, 2), "unit": "boxes/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {o.sweeps} sweeps of the same workload with incremental child bounds "
-                         f"({o.boxes_evaluated} boxes, {tcpu:.1f} s, single thread, fesetround per endpoint operation)"}
-
     fp32 = None
     if args.fp32_steps > 0:
         phase("fp32 filter")
@@ -175,6 +164,18 @@ def main() -> int:
     if args.serve_requests > 0:
         phase("serving")
     serving = serve_bench(args.serve_requests) if args.serve_requests > 0 else None
+
+    # the CPU oracle last, after all GPU work
+    cpu = None
+    if args.cpu_sweeps > 0:
+        phase("cpu baseline (oracle)")
+        from oracle import oracle as O
+        tc = time.perf_counter()
+        o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=args.cpu_sweeps, incremental=True)
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": round(o.boxes_evaluated / tcpu, 2), "unit": "boxes/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {o.sweeps} sweeps of the same workload with incremental child bounds "
+                         f"({o.boxes_evaluated} boxes, {tcpu:.1f} s, single thread, fesetround per endpoint operation)"}
 
     line = {
         "metric": "boxes/sec and time-to-enclosure (width 1e-6); served problems/sec + p50/p99",
