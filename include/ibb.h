@@ -41,7 +41,8 @@ typedef enum {
   IBB_E_NOMEM = -2,      /* device or host allocation failed */
   IBB_E_DEVICE = -3,     /* a HIP call failed */
   IBB_E_CAPACITY = -4,   /* a size exceeds what the library supports */
-  IBB_E_INTERNAL = -5
+  IBB_E_INTERNAL = -5    /* the live list became empty, or a sweep would have passed the row or key
+                            capacity sized for it (a guard: the library grows both before every chunk) */
 } ibb_status;
 
 /* Objective families (closed forms with per-coordinate coefficients).
