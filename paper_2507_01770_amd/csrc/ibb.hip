@@ -610,9 +610,8 @@ struct IbLds {
   double tfn[kIbChunkTerms], tfh[kIbChunkTerms], tu[kIbChunkTerms];
   double red[NT / kWave];
   int cnt[NT / kWave], ins[NT / kWave];
-  double base_n, base_h, base_u, gub;
   double wred[NT / kWave];              // widest unsplit side per wavefront
-  int naff, ngc, tot;
+  int naff, ngc;
   int aff[kIbSlots];                 // affected terms, increasing
   int aj[kIbSlots][2];                  // split index of the term's coordinates (-1: not split)
   double t_n[kIbSlots][4], t_h[kIbSlots][4], t_u[kIbSlots][4];
@@ -623,7 +622,6 @@ struct IbLds {
   int gmono[kIbSlots][8];                // first-order test failed, per combination of halves
   double w[kMaxSplit][2];               // width of each half of each split coordinate
   double w4[kMaxSplit / 4][16];         // widest split half over coordinates 4g..4g+3 for each 4 bits of c
-  uint64_t gub_key;                     // GUB after the children's midpoint bounds
   // prefix table: for each choice x of halves at the first kIbPreBits sorted
   // positions of the split window, F and the midpoint bound after the leading
   // terms that involve only those positions, and the first-order tests of the
@@ -834,12 +832,7 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
     }
     const I base{__shfl(acc.n, 0, kWave), __shfl(acc.h, 0, kWave)};
     const double base_u = __shfl(uacc, 0, kWave);
-    if (lane == 0) {
-      L.base_n = base.n;
-      L.base_h = base.h;
-      L.base_u = base_u;
-      L.wred[0] = wb;
-    }
+    if (lane == 0) L.wred[0] = wb;
     // the prefix table, lane x: bit p of x is the half at sorted position p; the
     // leading entries whose split coordinates all lie at positions below K
     const int start = (n - cyc < m) ? n - cyc : 0;
@@ -981,9 +974,12 @@ __device__ __forceinline__ void ib_child(const Params& P, const IbLds<NT>& L, ui
   flo = neg(F.n);
 }
 
-// GUB = min(GUB, the children's midpoint bounds); returns the new GUB to every thread
+// GUB = min(GUB, the children's midpoint bounds); returns the new GUB and the
+// number of children formed to every thread (each thread reduces the
+// wavefronts' partials itself: the same values in the same order)
 template <int NT, int FAM>
-__device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L, uint32_t mask, Hot& h) {
+__device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L, uint32_t mask, Hot& h,
+                                         int& formed) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
   double wbase = 0.0;   // widest unsplit side
   for (int k = 0; k < NT / kWave; ++k) wbase = dmax(wbase, L.wred[k]);
@@ -1008,24 +1004,19 @@ __device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L
     cnt += __shfl_xor(cnt, h, kWave);
   }
   if (lane == 0) { L.red[wid] = umin; L.cnt[wid] = cnt; }
-  __syncthreads();
+  __syncthreads();   // L.red and L.cnt are written again only in the next sweep, after more barriers
+  double mn = L.red[0];
+  int tot = L.cnt[0];
+  for (int k = 1; k < NT / kWave; ++k) { mn = dmin(mn, L.red[k]); tot += L.cnt[k]; }
+  const uint64_t key = okey(mn);
+  const bool lower = tot > 0 && key < h.gub_key;
   if (threadIdx.x == 0) {
-    double mn = L.red[0];
-    int tot = L.cnt[0];
-    for (int k = 1; k < NT / kWave; ++k) { mn = dmin(mn, L.red[k]); tot += L.cnt[k]; }
-    const uint64_t key = okey(mn);
-    uint64_t g = h.gub_key;
-    if (tot > 0 && key < g) {
-      g = key;
-      G(S)->gub_key = key;
-    }
+    if (lower) G(S)->gub_key = key;
     G(S)->ub_evaluated = h.ub_evaluated + tot;
-    L.gub_key = g;
-    L.tot = tot;
   }
-  __syncthreads();
-  h.gub_key = uni64(L.gub_key);
-  h.ub_evaluated = uni64(h.ub_evaluated + L.tot);
+  if (lower) h.gub_key = uni64(key);
+  h.ub_evaluated = uni64(h.ub_evaluated + tot);
+  formed = tot;
   return okey_inv(h.gub_key);
 }
 
@@ -1036,7 +1027,8 @@ __device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L
 template <int NT, int FAM>
 __device__ __forceinline__ void ib_children_insert(const Params& P, State* S, IbLds<NT>& L, const Sel& sel, Hot& h) {
   ib_prepare<NT, FAM>(P, L, sel);
-  const double gub = ib_gub<NT, FAM>(P, S, L, sel.mask, h);
+  int formed = 0;
+  const double gub = ib_gub<NT, FAM>(P, S, L, sel.mask, h, formed);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
   const uint32_t mask = sel.mask;
   const int64_t base = h.n_keys, seq0 = h.next_seq;
@@ -1125,13 +1117,13 @@ __device__ __forceinline__ void ib_children_insert(const Params& P, State* S, Ib
     const auto Sg = G(S);
     Sg->n_keys = base + done;
     Sg->next_seq = seq0 + done;
-    Sg->evaluated = h.evaluated + L.tot;
+    Sg->evaluated = h.evaluated + formed;
     Sg->sweeps = t + 1;
     Sg->pending = 0;
   }
   h.n_keys = uni64(base + done);
   h.next_seq = uni64(seq0 + done);
-  h.evaluated = uni64(h.evaluated + L.tot);
+  h.evaluated = uni64(h.evaluated + formed);
   h.sweeps = t + 1;
 }
 
