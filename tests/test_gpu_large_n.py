@@ -27,7 +27,7 @@ def same(a, b):
     assert np.array_equal(a.flo, b.flo) and np.array_equal(a.seq, b.seq)
 
 
-@pytest.mark.parametrize("n,budget", [(1024, 5), (1100, 6), (2500, 3)])
+@pytest.mark.parametrize("n,budget", [(1024, 5), (2500, 3)])
 def test_chain_large_n_identical_to_oracle(n, budget):
     p = PR.chain(n, 505, hi=2.3)
     print(f"case chain n={n} budget={budget}", flush=True)
