@@ -1,8 +1,15 @@
-"""Variable cycling (Sec. 3.2) in the oracle's iteration, read off its output
-boxes: a box whose lineage has been split k times has had the coordinates
-s mod n, s = 0 .. k*m - 1, bisected once each (split windows of m consecutive
-coordinates in index order, wrapping to the first coordinate after the last).
-The worked example of Sec. 3.2 is the fixture tests/golden/variable_cycling.txt."""
+"""The partition of a selected box, read off the oracle's output boxes.
+
+Child indexing (Sec. 3.1, Eqs. 8-11, with two pieces per coordinate instead of
+four): digit j of the child index r (base 2, least significant first) picks
+the half of the j-th coordinate of the split window, and the children enter the
+list in increasing r.
+
+Variable cycling (Sec. 3.2): a box whose lineage has been split k times has had
+the coordinates s mod n, s = 0 .. k*m - 1, bisected once each (split windows of
+m consecutive coordinates in index order, wrapping to the first coordinate
+after the last).  The worked example of Sec. 3.2 is the fixture
+tests/golden/variable_cycling.txt."""
 import os
 
 import numpy as np
@@ -89,3 +96,43 @@ def test_wrap_to_the_first_window(n, sweeps, min_k):
     f = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, split_dims=m, max_sweeps=sweeps, incremental=False)
     assert check_pattern(p, f, m) >= min_k
 
+
+
+def children_of(parent_lo, parent_hi, lo, hi, window):
+    """child index of each box (rows of lo/hi) cut from the parent box, from the
+    halves it takes in the window's coordinates (Eqs. 8-11 with two pieces)"""
+    rs = np.zeros(lo.shape[0], dtype=np.int64)
+    outside = np.setdiff1d(np.arange(lo.shape[1]), window)
+    assert np.array_equal(lo[:, outside], np.broadcast_to(parent_lo[outside], lo[:, outside].shape))
+    assert np.array_equal(hi[:, outside], np.broadcast_to(parent_hi[outside], hi[:, outside].shape))
+    for j, c in enumerate(window):
+        upper = lo[:, c] != parent_lo[c]
+        # lower half [lo, mid], upper half [mid, hi], one split point for all children
+        mids = np.concatenate([hi[~upper, c], lo[upper, c]])
+        assert np.all(mids == mids[0])
+        mid = mids[0]
+        assert parent_lo[c] < mid < parent_hi[c]
+        assert abs(mid - 0.5 * (parent_lo[c] + parent_hi[c])) <= 2.0 ** -50 * (parent_hi[c] - parent_lo[c])
+        assert np.all(hi[upper, c] == parent_hi[c]) and np.all(lo[~upper, c] == parent_lo[c])
+        rs |= upper.astype(np.int64) << j
+    return rs
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_children_follow_eqs_8_to_11(seed):
+    n, m = 12, 10
+    p = PR.sep_cos(n, seed)
+    o1 = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, split_dims=m, max_sweeps=1, incremental=True)
+    o2 = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, split_dims=m, max_sweeps=2, incremental=True)
+    # sweep 1: the root (cycling index 1) is cut along x1..x10
+    order = np.argsort(o1.seq)
+    r1 = children_of(p.lower, p.upper, o1.lo[order], o1.hi[order], np.arange(m))
+    assert np.all(np.diff(r1) > 0) and o1.lo.shape[0] > 1
+    # sweep 2: the box selected then (index 11) is cut along x11, x12, x1..x8
+    par = np.nonzero(o1.seq == o2.trace_sel[1])[0]
+    assert par.size == 1
+    new = o2.seq > o1.seq.max()
+    order = np.argsort(o2.seq[new])
+    window = (np.arange(m) + m) % n
+    r2 = children_of(o1.lo[par[0]], o1.hi[par[0]], o2.lo[new][order], o2.hi[new][order], window)
+    assert np.all(np.diff(r2) > 0) and r2.size > 1
