@@ -120,3 +120,25 @@ def test_box_width_criterion():
     assert r.status == O.ST_OK
     assert np.all(r.hi - r.lo < 1e-4)
     assert inside_some_box(p.x_star, r.lo, r.hi)
+
+
+@pytest.mark.parametrize("make,incremental", [(lambda: PR.sep_cos(8, 34), False), (lambda: PR.chain(6, 35, hi=2.3), True),
+                                              (lambda: PR.sep_abs_sin2(5, 36), True)])
+def test_selection_takes_the_smallest_lower_bound(make, incremental):
+    # Sec. 3.1: each iteration takes the listed box with the smallest lower bound
+    # (ties: the earlier insertion).  The list after t sweeps is the output of a
+    # run stopped there; the box the next sweep selects must be its minimum, and
+    # the reported GLB is that minimum's lower bound.
+    p = make()
+    runs = [O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-9, max_sweeps=t, incremental=incremental)
+            for t in range(1, 16)]
+    checked = 0
+    for a, b in zip(runs, runs[1:]):
+        if a.status != O.ST_NOT_CONVERGED or b.sweeps <= a.sweeps:
+            break
+        assert np.array_equal(b.trace_sel[: a.sweeps], a.trace_sel)   # the same iteration up to there
+        best = min(range(a.flo.size), key=lambda i: (a.flo[i], a.seq[i]))
+        assert b.trace_sel[a.sweeps] == a.seq[best]
+        assert a.f_lo == a.flo[best] and a.f_lo <= a.f_hi
+        checked += 1
+    assert checked >= 10
