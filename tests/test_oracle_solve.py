@@ -140,5 +140,7 @@ def test_selection_takes_the_smallest_lower_bound(make, incremental):
         best = min(range(a.flo.size), key=lambda i: (a.flo[i], a.seq[i]))
         assert b.trace_sel[a.sweeps] == a.seq[best]
         assert a.f_lo == a.flo[best] and a.f_lo <= a.f_hi
+        # cutoff: no listed box has a lower bound above GUB, which never increases
+        assert np.all(a.flo <= a.f_hi) and b.f_hi <= a.f_hi and a.f_hi == a.trace_gub[-1]
         checked += 1
     assert checked >= 10
