@@ -144,3 +144,15 @@ def test_selection_takes_the_smallest_lower_bound(make, incremental):
         assert np.all(a.flo <= a.f_hi) and b.f_hi <= a.f_hi and a.f_hi == a.trace_gub[-1]
         checked += 1
     assert checked >= 10
+
+
+@pytest.mark.parametrize("make", [lambda: PR.sep_cos(6, 37), lambda: PR.chain(5, 38, hi=2.3)])
+def test_stops_at_the_first_sweep_that_meets_the_tolerance(make):
+    # stop as soon as GUB - GLB <= tol_f: one sweep fewer does not meet it
+    p = make()
+    full = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=100000)
+    assert full.status == O.ST_OK and full.f_hi - full.f_lo <= 1e-6 and full.sweeps > 1
+    short = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=full.sweeps - 1)
+    assert short.status == O.ST_NOT_CONVERGED and short.sweeps == full.sweeps - 1
+    assert short.f_hi - short.f_lo > 1e-6
+    assert short.f_lo <= full.f_lo and full.f_hi <= short.f_hi   # the enclosure only tightens
