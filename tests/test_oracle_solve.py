@@ -156,3 +156,25 @@ def test_stops_at_the_first_sweep_that_meets_the_tolerance(make):
     assert short.status == O.ST_NOT_CONVERGED and short.sweeps == full.sweeps - 1
     assert short.f_hi - short.f_lo > 1e-6
     assert short.f_lo <= full.f_lo and full.f_hi <= short.f_hi   # the enclosure only tightens
+
+
+@pytest.mark.parametrize("make", [lambda: PR.sep_cos(8, 34), lambda: PR.chain(7, 39, hi=2.3)])
+def test_trace_bookkeeping(make):
+    # per sweep t: nsurv children enter the list, the selected box leaves it, and a
+    # lower GUB may cut listed boxes; with GUB unchanged nothing else leaves.  The
+    # live count after sweep t is the size of the output of a run stopped there.
+    p = make()
+    r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-9, max_sweeps=40)
+    nl, ns, g = r.trace_nlive, r.trace_nsurv, r.trace_gub
+    assert nl.size == ns.size == g.size == r.sweeps >= 12
+    assert nl[0] == ns[0]
+    same_gub = 0
+    for t in range(1, r.sweeps):
+        assert nl[t] <= nl[t - 1] - 1 + ns[t]
+        if g[t] == g[t - 1]:
+            assert nl[t] == nl[t - 1] - 1 + ns[t]
+            same_gub += 1
+    assert same_gub >= 1
+    for k in (1, 4, 9):
+        s = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-9, max_sweeps=k)
+        assert s.flo.size == nl[k - 1] and np.array_equal(s.trace_nlive, nl[:k])
