@@ -56,9 +56,8 @@ def test_separable_large_n_matches_oracle(fam, n, seed, budget):
 
 
 @pytest.mark.skip(reason="faulted the GPU once (with a per-row term cache that has since been "
-                         "taken out, cause not shown); the batched and served engines have not run "
-                         "incremental problems of more than 1024 terms since, so this stays off the "
-                         "GPU until a cause is shown on the CPU")
+                         "taken out, cause not shown); stays off the GPU until a cause is shown on "
+                         "the CPU")
 def test_large_n_alone_batch_and_server():
     big = [PR.chain(1100, 505, hi=2.3), PR.sep_abs_sin2(1500, 7)]
     budget = dict(max_sweeps=60)
