@@ -178,3 +178,18 @@ def test_trace_bookkeeping(make):
     for k in (1, 4, 9):
         s = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-9, max_sweeps=k)
         assert s.flo.size == nl[k - 1] and np.array_equal(s.trace_nlive, nl[:k])
+
+
+def test_live_box_limit_stops_the_run():
+    # the run stops (not converged, enclosure still rigorous) at the first sweep
+    # that leaves more live boxes than the limit
+    p = PR.sep_cos(8, 34)
+    free = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-9, max_sweeps=40)
+    nl = free.trace_nlive
+    limit = 900
+    first = int(np.nonzero(nl > limit)[0][0])
+    assert first >= 1
+    r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-9, max_sweeps=40, max_live_boxes=limit)
+    assert r.status == O.ST_NOT_CONVERGED and r.sweeps == first + 1
+    assert r.flo.size == nl[first] and np.array_equal(r.trace_nlive, nl[: first + 1])
+    assert r.f_lo <= 0.0 <= r.f_hi
