@@ -99,6 +99,25 @@ def test_budget_and_width_criterion(incremental):
 
 
 @pytest.mark.parametrize("incremental", MODES)
+def test_live_box_limit_identical_to_oracle(incremental):
+    # the run stops at the first sweep that leaves more live boxes than the limit
+    # (here the sixth), inside the persistent loop, exactly where the oracle stops
+    p = PR.chain(12, 505, hi=2.3)
+    free = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=p.tol_x, max_sweeps=3000,
+                   incremental=incremental)
+    limit = int(free.trace_nlive[:5].max())
+    print(f"case {p.name} live limit {limit} incremental={incremental}", flush=True)
+    r = ibb.minimize(p, max_sweeps=3000, max_live_boxes=limit, incremental=incremental)
+    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=p.tol_x, max_sweeps=3000,
+                max_live_boxes=limit, incremental=incremental)
+    assert o.status == O.ST_NOT_CONVERGED and o.sweeps == 6
+    assert r.status == ibb.NOT_CONVERGED and r.sweeps == o.sweeps
+    assert np.array_equal(r.trace_nlive, o.trace_nlive) and np.array_equal(r.trace_gub, o.trace_gub)
+    assert r.f_lo == o.f_lo and r.f_hi == o.f_hi
+    assert np.array_equal(r.seq, o.seq) and np.array_equal(r.flo, o.flo)
+    assert np.array_equal(r.lo, o.lo) and np.array_equal(r.hi, o.hi)
+
+@pytest.mark.parametrize("incremental", MODES)
 def test_workload0_full_parity(incremental):
     p = PR.config(0)
     r, o = run_both(p, incremental)
