@@ -118,6 +118,21 @@ def test_live_box_limit_identical_to_oracle(incremental):
     assert np.array_equal(r.lo, o.lo) and np.array_equal(r.hi, o.hi)
 
 @pytest.mark.parametrize("incremental", MODES)
+def test_width_criterion_identical_to_oracle(incremental):
+    # with a box-width tolerance the run goes on until every listed box is narrower
+    # as well (3 and 9 sweeps past the GUB - GLB criterion here), sweep for sweep as
+    # in the oracle
+    p = PR.chain(5, 505, hi=2.3)
+    for tol_x in (1e-3, 1e-4):
+        p.tol_x = tol_x
+        r, o = run_both(p, incremental, max_sweeps=100000)
+        assert o.status == O.ST_OK and r.status == ibb.OK and r.sweeps == o.sweeps
+        assert np.array_equal(r.trace_gub, o.trace_gub) and np.array_equal(r.trace_nlive, o.trace_nlive)
+        assert r.f_lo == o.f_lo and r.f_hi == o.f_hi
+        assert np.array_equal(r.lo, o.lo) and np.array_equal(r.hi, o.hi)
+        assert np.all(r.hi - r.lo < tol_x)
+
+@pytest.mark.parametrize("incremental", MODES)
 def test_workload0_full_parity(incremental):
     p = PR.config(0)
     r, o = run_both(p, incremental)

@@ -193,3 +193,16 @@ def test_live_box_limit_stops_the_run():
     assert r.status == O.ST_NOT_CONVERGED and r.sweeps == first + 1
     assert r.flo.size == nl[first] and np.array_equal(r.trace_nlive, nl[: first + 1])
     assert r.f_lo <= 0.0 <= r.f_hi
+
+
+def test_width_criterion_stops_at_the_first_sweep_that_meets_both():
+    # with tol_x > 0 the run stops when GUB - GLB <= tol_f and every listed box is
+    # narrower than tol_x; one sweep fewer meets only the first or neither
+    p = PR.chain(5, 505, hi=2.3)
+    base = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, max_sweeps=100000)
+    full = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=1e-4, max_sweeps=100000)
+    assert full.status == O.ST_OK and full.sweeps > base.sweeps
+    assert np.all(full.hi - full.lo < 1e-4) and full.f_hi - full.f_lo <= p.tol_f
+    short = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=1e-4, max_sweeps=full.sweeps - 1)
+    assert short.status == O.ST_NOT_CONVERGED
+    assert np.any(short.hi - short.lo >= 1e-4) or short.f_hi - short.f_lo > p.tol_f
