@@ -133,6 +133,30 @@ def test_width_criterion_identical_to_oracle(incremental):
         assert np.all(r.hi - r.lo < tol_x)
 
 @pytest.mark.parametrize("incremental", MODES)
+def test_one_ulp_coordinates_identical_to_oracle(incremental):
+    # coordinates one ulp wide are never split (their split point is an endpoint)
+    # and the children that would take their upper halves are not formed
+    p = PR.chain(6, 505, hi=2.3)
+    p.lower[2], p.upper[2] = 1.0, np.nextafter(1.0, 2.0)
+    p.lower[4], p.upper[4] = 0.5, np.nextafter(0.5, 1.0)
+    for m in (3, 6):
+        print(f"case {p.name} one-ulp coordinates m={m} incremental={incremental}", flush=True)
+        r = ibb.minimize(p, split_dims=m, max_sweeps=3000, incremental=incremental)
+        o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, split_dims=m, max_sweeps=3000,
+                    incremental=incremental)
+        assert o.status == O.ST_OK and r.status == ibb.OK and r.sweeps == o.sweeps
+        assert r.boxes_evaluated == o.boxes_evaluated
+        assert np.array_equal(r.trace_gub, o.trace_gub) and np.array_equal(r.trace_nsurv, o.trace_nsurv)
+        assert r.f_lo == o.f_lo and r.f_hi == o.f_hi
+        assert np.array_equal(r.lo, o.lo) and np.array_equal(r.hi, o.hi)
+    q = PR.sep_cos(5, 7)
+    q.lower[1], q.upper[1] = 0.25, np.nextafter(0.25, 1.0)
+    r, o = run_both(q, incremental, max_sweeps=3000)
+    assert o.status == O.ST_OK and r.status == ibb.OK
+    assert r.f_lo <= o.f_hi and o.f_lo <= r.f_hi
+    assert np.all(r.lo[:, 1] == q.lower[1]) and np.all(r.hi[:, 1] == q.upper[1])
+
+@pytest.mark.parametrize("incremental", MODES)
 def test_workload0_full_parity(incremental):
     p = PR.config(0)
     r, o = run_both(p, incremental)

@@ -136,3 +136,18 @@ def test_children_follow_eqs_8_to_11(seed):
     window = (np.arange(m) + m) % n
     r2 = children_of(o1.lo[par[0]], o1.hi[par[0]], o2.lo[new][order], o2.hi[new][order], window)
     assert np.all(np.diff(r2) > 0) and r2.size > 1
+
+
+def test_one_ulp_coordinates_are_never_split():
+    # a coordinate one ulp wide has its split point on an endpoint: it is not
+    # split, and the children that would take its upper half are not formed
+    p = PR.chain(6, 505, hi=2.3)
+    p.lower[2], p.upper[2] = 1.0, np.nextafter(1.0, 2.0)
+    p.lower[4], p.upper[4] = 0.5, np.nextafter(0.5, 1.0)
+    one = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, split_dims=6, max_sweeps=1)
+    assert one.boxes_evaluated == 1 + 2 ** 4
+    for incremental in (False, True):
+        r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, max_sweeps=3000, incremental=incremental)
+        assert r.status == O.ST_OK and r.f_hi - r.f_lo <= p.tol_f
+        for c in (2, 4):
+            assert np.all(r.lo[:, c] == p.lower[c]) and np.all(r.hi[:, c] == p.upper[c])
