@@ -156,6 +156,19 @@ def test_one_ulp_coordinates_identical_to_oracle(incremental):
     assert r.f_lo <= o.f_hi and o.f_lo <= r.f_hi
     assert np.all(r.lo[:, 1] == q.lower[1]) and np.all(r.hi[:, 1] == q.upper[1])
 
+@pytest.mark.parametrize("lo,hi,n", [(1.0, 2.3, 6), (-3.0, 1.0, 9)])
+@pytest.mark.parametrize("incremental", MODES)
+def test_minimiser_on_the_boundary_identical_to_oracle(lo, hi, n, incremental):
+    # x* = (1, ..., 1) on a face of the domain: the boxes on that face survive the
+    # first-order test, sweep for sweep as in the oracle
+    p = PR.chain(n, 505, lo=lo, hi=hi)
+    r, o = run_both(p, incremental, max_sweeps=3000)
+    assert o.status == O.ST_OK and r.status == ibb.OK and r.sweeps == o.sweeps
+    assert np.array_equal(r.trace_gub, o.trace_gub) and np.array_equal(r.trace_nlive, o.trace_nlive)
+    assert r.f_lo == o.f_lo and r.f_hi == o.f_hi and r.f_lo <= 0.0 <= r.f_hi
+    assert np.array_equal(r.lo, o.lo) and np.array_equal(r.hi, o.hi)
+    assert inside_some_box(np.ones(n), r.lo, r.hi)
+
 @pytest.mark.parametrize("incremental", MODES)
 def test_workload0_full_parity(incremental):
     p = PR.config(0)

@@ -206,3 +206,16 @@ def test_width_criterion_stops_at_the_first_sweep_that_meets_both():
     short = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=1e-4, max_sweeps=full.sweeps - 1)
     assert short.status == O.ST_NOT_CONVERGED
     assert np.any(short.hi - short.lo >= 1e-4) or short.f_hi - short.f_lo > p.tol_f
+
+
+@pytest.mark.parametrize("lo,hi,n", [(1.0, 2.3, 6), (-3.0, 1.0, 9)])
+def test_minimiser_on_the_domain_boundary_is_kept(lo, hi, n):
+    # chained family, x* = (1, ..., 1) on the lower (upper) face of the domain: the
+    # gradient does not vanish there, and the first-order test must not drop the
+    # boxes on that face (Sec. 3.1: a sign of the derivative rules a box out only
+    # when the box does not touch the bound on the descending side)
+    p = PR.chain(n, 505, lo=lo, hi=hi)
+    for incremental in (False, True):
+        r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, max_sweeps=3000, incremental=incremental)
+        assert r.status == O.ST_OK and r.f_lo <= 0.0 <= r.f_hi
+        assert inside_some_box(np.ones(n), r.lo, r.hi)
