@@ -63,3 +63,37 @@ def _solve_rc(**kw):
 def test_validation_rejects_before_touching_the_device(kw, msg):
     rc, err = _solve_rc(**kw)
     assert rc == -1 and msg in err, (rc, err)
+
+
+def _problem_struct():
+    p = PR.sep_cos(3, 1)
+    return ibb._ProblemKeep(p.family, p.coef, p.lower, p.upper, 1e-6, 0.0)
+
+
+def test_empty_inputs_are_accepted_without_device_work():
+    # count 0 / nb 0 returns before any device call, with NULL arrays
+    L = ibb.lib()
+    k = _problem_struct()
+    assert L.ibb_eval_boxes(C.byref(k.s), 0, 0, None, None, None, None, None, None, None) == 0
+    assert L.ibb_interval_op(0, 0, None, None, None, None) == 0
+    assert L.ibb_point_trig(0, 0, None, None, None) == 0
+    assert L.ibb_interval_op32(0, 0, None, None, None, None) == 0
+    assert L.ibb_point_trig32(1, 0, None, None, None) == 0
+
+
+@pytest.mark.parametrize("call,msg", [
+    (lambda L, k: L.ibb_eval_boxes(C.byref(k.s), 0, -1, None, None, None, None, None, None, None), "nb < 0"),
+    (lambda L, k: L.ibb_eval_boxes(C.byref(k.s), 0, 4, None, None, None, None, None, None, None), "NULL"),
+    (lambda L, k: L.ibb_eval_boxes(C.byref(k.s), 5, 4, None, None, None, None, None, None, None), "precision"),
+    (lambda L, k: L.ibb_interval_op(11, 4, None, None, None, None), "unknown op"),
+    (lambda L, k: L.ibb_interval_op(0, -1, None, None, None, None), "count < 0"),
+    (lambda L, k: L.ibb_interval_op(0, 4, None, None, None, None), "NULL"),
+    (lambda L, k: L.ibb_point_trig(2, 4, None, None, None), "fn must be"),
+    (lambda L, k: L.ibb_point_trig(0, -3, None, None, None), "count < 0"),
+    (lambda L, k: L.ibb_interval_op32(3, 4, None, None, None, None), "single precision"),
+    (lambda L, k: L.ibb_point_trig32(0, 4, None, None, None), "NULL"),
+])
+def test_bad_kernel_arguments_rejected_before_the_device(call, msg):
+    L = ibb.lib()
+    rc = call(L, _problem_struct())
+    assert rc == -1 and msg in L.ibb_last_error().decode()
