@@ -78,3 +78,14 @@ def test_workload_sizes_sampled(cfg):
     else:
         assert _contains(gF, F) and np.all(gub >= ub) and not np.any(gmono & ~mono)
         assert np.all(np.abs(gF - F) <= 1e-12 * p.n * (np.abs(F) + 1.0))
+
+
+@pytest.mark.parametrize("precision", [ibb.FP64, ibb.FP32_BULK])
+def test_empty_box_batch(precision):
+    # no boxes: empty results, no launch
+    p = PR.sep_cos(5, 3)
+    print(f"case empty batch precision={precision}", flush=True)
+    e = torch.empty((0, 5), dtype=torch.float64, device="cuda")
+    F, ub, mono, G = ibb.eval_boxes(p, e, e.clone(), want_grad=True, precision=precision)
+    torch.cuda.synchronize()
+    assert F.shape == (0, 2) and ub.shape == (0,) and mono.shape == (0,) and G.shape == (0, 5, 2)
