@@ -170,6 +170,20 @@ def test_minimiser_on_the_boundary_identical_to_oracle(lo, hi, n, incremental):
     assert inside_some_box(np.ones(n), r.lo, r.hi)
 
 @pytest.mark.parametrize("incremental", MODES)
+def test_zero_sweeps_identical_to_oracle(incremental):
+    # a tolerance the root already meets, and a budget of no sweeps: the output is
+    # the root box with its own bounds and empty traces
+    p = PR.chain(4, 505, hi=2.3)
+    for tol_f, budget, status in ((1e6, 100, ibb.OK), (1e-6, 0, ibb.NOT_CONVERGED)):
+        p.tol_f = tol_f
+        print(f"case {p.name} tol_f={tol_f} max_sweeps={budget} incremental={incremental}", flush=True)
+        r, o = run_both(p, incremental, max_sweeps=budget)
+        assert r.status == status and o.status == status and r.sweeps == o.sweeps == 0
+        assert r.f_lo == o.f_lo and r.f_hi == o.f_hi and r.boxes_evaluated == 1
+        assert r.n_boxes == 1 and np.array_equal(r.lo, o.lo) and np.array_equal(r.hi, o.hi)
+        assert r.trace_gub.size == 0 and r.trace_nlive.size == 0
+
+@pytest.mark.parametrize("incremental", MODES)
 def test_workload0_full_parity(incremental):
     p = PR.config(0)
     r, o = run_both(p, incremental)
