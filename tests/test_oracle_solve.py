@@ -219,3 +219,16 @@ def test_minimiser_on_the_domain_boundary_is_kept(lo, hi, n):
         r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, max_sweeps=3000, incremental=incremental)
         assert r.status == O.ST_OK and r.f_lo <= 0.0 <= r.f_hi
         assert inside_some_box(np.ones(n), r.lo, r.hi)
+
+
+def test_stop_test_comes_before_the_first_selection():
+    # Sec. 3.1: the list starts as the whole domain; when the root already meets
+    # the tolerance (or no sweep is allowed) the output is the domain itself, with
+    # GLB its lower bound and GUB its midpoint bound
+    p = PR.chain(4, 505, hi=2.3)
+    F, ub, _ = O.eval_boxes(p.family, p.coef, p.lower, p.upper, p.lower[None], p.upper[None])
+    for tol_f, budget, status in ((1e6, 100, O.ST_OK), (1e-6, 0, O.ST_NOT_CONVERGED)):
+        r = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=tol_f, max_sweeps=budget)
+        assert r.status == status and r.sweeps == 0 and r.boxes_evaluated == 1
+        assert np.array_equal(r.lo, p.lower[None]) and np.array_equal(r.hi, p.upper[None])
+        assert r.f_lo == F[0, 0] and r.f_hi == ub[0] and r.trace_gub.size == 0
