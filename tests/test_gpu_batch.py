@@ -185,3 +185,27 @@ def test_server_results_freed_while_it_runs():
         assert (a.status, a.f_lo, a.f_hi, a.sweeps, a.boxes_evaluated) == (b.status, b.f_lo, b.f_hi, b.sweeps,
                                                                              b.boxes_evaluated)
         assert np.array_equal(a.trace_gub, b.trace_gub) and np.array_equal(a.flo, b.flo)
+
+
+def degenerate_mix():
+    root_done = PR.chain(4, 505, hi=2.3)
+    root_done.tol_f = 1e6                      # the root meets the tolerance: no sweep
+    ulp = PR.chain(6, 505, hi=2.3)             # two coordinates one ulp wide: never split
+    ulp.lower[2], ulp.upper[2] = 1.0, np.nextafter(1.0, 2.0)
+    ulp.lower[4], ulp.upper[4] = 0.5, np.nextafter(0.5, 1.0)
+    face = PR.chain(6, 505, lo=1.0, hi=2.3)    # minimiser on a face of the domain
+    return [root_done, ulp, face, PR.sep_cos(9, 2)]
+
+
+@pytest.mark.parametrize("incremental", [False, True])
+def test_batch_with_degenerate_members_equals_alone(incremental):
+    ps = degenerate_mix()
+    alone = []
+    for p in ps:
+        print(f"case alone {p.name} incremental={incremental}", flush=True)
+        alone.append(ibb.minimize(p, max_boxes_fetched=500, incremental=incremental, **BUDGET))
+    assert alone[0].sweeps == 0 and alone[0].n_boxes == 1
+    print(f"case batch of degenerate members incremental={incremental}", flush=True)
+    got = ibb.solve_batch(ps, max_boxes_fetched=500, incremental=incremental, **BUDGET)
+    for a, b in zip(alone, got):
+        same(a, b)
