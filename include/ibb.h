@@ -227,7 +227,8 @@ ibb_status ibb_point_trig32(int32_t fn, int64_t count, const float* d_y, float* 
 /* Solve count problems together.  outs[i] receives problem i's result (NULL if
  * it failed; free each with ibb_result_free) and statuses[i] its status
  * (IBB_OK, IBB_NOT_CONVERGED or an error).  The call returns IBB_OK unless the
- * batch itself could not run.  The work runs on a stream of its own, ordered
+ * batch itself could not run; after such an error outs[i] still holds the
+ * results of the problems that finished before it, which the caller frees.  The work runs on a stream of its own, ordered
  * after the work enqueued on hip_stream; the call returns when it is done and the
  * results are bound to hip_stream. */
 ibb_status ibb_solve_batch(const ibb_problem* probs, int32_t count, const ibb_options* opts,

@@ -385,7 +385,12 @@ def solve_batch(problems, *, fetch_boxes=True, max_boxes_fetched=100_000, stream
     o = _options(**opts)
     outs = (C.c_void_p * len(keeps))()
     sts = (C.c_int32 * len(keeps))()
-    _check(L.ibb_solve_batch(arr, len(keeps), C.byref(o), None, _stream_ptr(stream), outs, sts))
+    rc = L.ibb_solve_batch(arr, len(keeps), C.byref(o), None, _stream_ptr(stream), outs, sts)
+    if rc != OK:   # results of problems that finished before the error are still ours to free
+        for i in range(len(keeps)):
+            if outs[i]:
+                L.ibb_result_free(C.c_void_p(outs[i]))
+        _check(rc)
     res = []
     for i, k in enumerate(keeps):
         if sts[i] in (OK, NOT_CONVERGED) and outs[i]:

@@ -85,3 +85,48 @@ def test_refused_allocation_gives_nomem_and_returns_everything(incremental):
     again = ibb.minimize(p, max_sweeps=300, incremental=incremental, fetch_boxes=False)
     assert (again.status, again.sweeps, again.f_lo, again.f_hi) == (ref.status, ref.sweeps, ref.f_lo, ref.f_hi)
     assert np.array_equal(again.trace_gub, ref.trace_gub)
+
+
+@pytest.mark.parametrize("incremental", [False, True])
+def test_refused_allocation_in_a_batch(incremental):
+    # a refusal while problems are admitted fails those problems; one while the
+    # batch runs (its row or key arrays growing) fails the call, and the results
+    # of problems that finished before it are still handed over.  Either way,
+    # once the caller frees the results every block has come back.
+    ps = [PR.chain(13, 505), PR.sep_cos(9, 2), PR.chain(5, 505, hi=2.3)]
+    L = ibb.lib()
+    keeps = [ibb._prob_args(p) for p in ps]
+    arr = (ibb._Problem * len(keeps))(*[k.s for k in keeps])
+    o = ibb._options(max_sweeps=300, incremental=incremental)
+
+    def run(alloc):
+        outs = (C.c_void_p * len(ps))()
+        sts = (C.c_int32 * len(ps))()
+        rc = L.ibb_solve_batch(arr, len(ps), C.byref(o), C.byref(alloc.struct), ibb._stream_ptr(), outs, sts)
+        torch.cuda.synchronize()
+        got = [(sts[i], bool(outs[i])) for i in range(len(ps))]
+        for i in range(len(ps)):
+            if outs[i]:
+                L.ibb_result_free(C.c_void_p(outs[i]))
+        return rc, got
+
+    counts = []
+    for _ in range(2):
+        a = CountingAllocator()
+        rc, got = run(a)
+        assert rc == ibb.OK and all(st in (ibb.OK, ibb.NOT_CONVERGED) and have for st, have in got)
+        assert not a.live and a.bad_frees == 0
+        counts.append(a.calls)
+    total = counts[-1]
+    outcomes = set()
+    for fail_at in sorted({1, 2, max(1, total // 3), max(1, total // 2), total}):
+        print(f"case batch refuse request {fail_at} of {total} incremental={incremental}", flush=True)
+        a = CountingAllocator(fail_at)
+        rc, got = run(a)
+        assert rc in (ibb.OK, NOMEM), rc
+        for st, have in got:
+            assert have == (st in (ibb.OK, ibb.NOT_CONVERGED))
+            assert st in (ibb.OK, ibb.NOT_CONVERGED, NOMEM, ibb.PENDING)
+        assert not a.live and a.bad_frees == 0, (fail_at, a.live)
+        outcomes.add(rc)
+    assert NOMEM in outcomes
