@@ -141,8 +141,8 @@ __global__ __launch_bounds__(kWave) void k_root(const Params* __restrict__ PP, S
   bound_box<FAM>(P, X, lane, F, mo, wm, nullptr);
   const double u = point_ub<FAM>(P, X, lane);
   if (lane == 0) {
-    S->gub_key = okey(u + 0.0);
-    P.key_flo[0] = neg(F.n);
+    S->gub_key = okey(hi_or_inf(u));
+    P.key_flo[0] = lo_or_ninf(neg(F.n));
     P.key_seq[0] = 0;
     P.key_ref[0] = 0;
     P.key_r[0] = -1;
@@ -328,6 +328,7 @@ __device__ __forceinline__ bool select_finish(const Params& P, State* S, const S
     S->wmax = tot.wm;
     int32_t stop = RUNNING;
     if (tot.cnt == 0) stop = STOP_EMPTY;
+    else if (b.idx < 0 || b.idx >= S->n_keys) stop = STOP_INTERNAL;
     else if (gub - b.f <= P.tol_f && (P.tol_x <= 0.0 || tot.wm < P.tol_x)) stop = STOP_CONVERGED;
     else if (t >= P.max_sweeps) stop = STOP_SWEEPS;
     else if (P.max_live > 0 && tot.cnt > P.max_live) stop = STOP_LIVE;
@@ -971,7 +972,7 @@ __device__ __forceinline__ void ib_child(const Params& P, const IbLds<NT>& L, ui
   }
   static_assert(kMaxSplit == 16, "four nibbles of the child index");
   wm = dmax(wm, dmax(dmax(L.w4[0][c & 15u], L.w4[1][(c >> 4) & 15u]), dmax(L.w4[2][(c >> 8) & 15u], L.w4[3][(c >> 12) & 15u])));
-  flo = neg(F.n);
+  flo = lo_or_ninf(neg(F.n));
 }
 
 // GUB = min(GUB, the children's midpoint bounds); returns the new GUB and the
@@ -996,7 +997,7 @@ __device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L
       L.c_wm[c] = wm;
       L.c_keep[c] = mo ? 0 : 1;
     }
-    umin = dmin(umin, u + 0.0);
+    umin = dmin(umin, hi_or_inf(u));
     ++cnt;
   }
   for (int h = 32; h >= 1; h >>= 1) {
@@ -1217,6 +1218,7 @@ __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel
     Sg->wmax = tot.wm;
     int32_t stop = RUNNING;
     if (tot.cnt == 0) stop = STOP_EMPTY;
+    else if (b.idx < 0 || b.idx >= h.n_keys) stop = STOP_INTERNAL;
     else if (gub - b.f <= P.tol_f && (P.tol_x <= 0.0 || tot.wm < P.tol_x)) stop = STOP_CONVERGED;
     else if (t >= P.max_sweeps) stop = STOP_SWEEPS;
     else if (P.max_live > 0 && tot.cnt > P.max_live) stop = STOP_LIVE;
@@ -1471,7 +1473,7 @@ __device__ void bound_body(const Params& P, State* S, int cbase) {
   bool cmo = any_mo;
   if (!mid_role && w == 0) {
     const I F = fold_slots(acc, lane);
-    flo = neg(F.n);
+    flo = lo_or_ninf(neg(F.n));
     for (int k = 1; k < W; ++k) { cmo = cmo || s_flag[first + k]; cwm = dmax(cwm, s_wm[first + k]); }
   }
 
@@ -1516,7 +1518,7 @@ __device__ void bound_body(const Params& P, State* S, int cbase) {
       if (lane == 0 && c < P.nch) {
         if (formed) {
           if (do_ub) {
-            atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(u + 0.0));
+            atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(hi_or_inf(u)));
             atomicAdd((unsigned long long*)&S->ub_evaluated, 1ull);
           }
           if (r32) {
@@ -1535,7 +1537,7 @@ __device__ void bound_body(const Params& P, State* S, int cbase) {
     if (mid_role) {
       const double u = fold_slots_hi(hacc, lane);
       if (lane == 0 && formed) {
-        atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(u + 0.0));
+        atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(hi_or_inf(u)));
         atomicAdd((unsigned long long*)&S->ub_evaluated, 1ull);
       }
     } else if (lane == 0 && c < P.nch) {
@@ -1937,20 +1939,12 @@ struct ibb_result {
   double* wmax = nullptr;
   std::vector<double> tr_gub;
   std::vector<int64_t> tr_nsurv, tr_nlive, tr_sel;
+  // set when an ibb_sweep call failed after it had started to change the run:
+  // the device state and the boxes are then no longer a consistent result
+  bool broken = false;
 };
 
 namespace {
-
-// grow an array on the device, keeping the first `keep` elements
-template <typename T>
-ibb_status grow(Mem& M, T*& ptr, int64_t keep, int64_t new_count) {
-  T* np = dalloc<T>(M, new_count);
-  if (!np) return fail(IBB_E_NOMEM, "device allocation failed while growing the box list");
-  if (keep > 0) HIPCHK(hipMemcpyAsync(np, ptr, keep * sizeof(T), hipMemcpyDeviceToDevice, M.stream));
-  M.put(ptr);
-  ptr = np;
-  return IBB_OK;
-}
 
 ibb_status push_params(Mem& M, const Params& P, Params* dP) {
   HIPCHK(hipMemcpyAsync(dP, &P, sizeof(Params), hipMemcpyHostToDevice, M.stream));
@@ -2056,6 +2050,8 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   HIPCHK(hipMemcpyAsync(P.hist_n, nl.data(), n * sizeof(double), hipMemcpyHostToDevice, M.stream));
   HIPCHK(hipMemcpyAsync(P.hist_h, prob->upper, n * sizeof(double), hipMemcpyHostToDevice, M.stream));
   HIPCHK(hipMemsetAsync(U.dS, 0, sizeof(State), M.stream));
+  // child records start as "not formed": nothing reads a record no bound kernel wrote
+  HIPCHK(hipMemsetAsync(P.ch_flag, 0, P.nch, M.stream));
   st = push_params(M, P, U.dP);
   if (st != IBB_OK) return st;
   HIPCHK(hipStreamSynchronize(M.stream));   // nl must outlive its copy
@@ -2069,49 +2065,89 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   return IBB_OK;
 }
 
-// room for `chunk` more sweeps: one row and at most nch keys per sweep
+// room for `chunk` more sweeps: one row and at most nch keys per sweep.
+// Every array that has to grow is allocated before anything is copied or given
+// back: if the allocator refuses a request, the blocks taken so far are returned
+// and the arrays, the capacities and the device copy of the parameters stay as
+// they were (the run can go on with what it has, or be released).  Only when
+// every request succeeded are the contents copied, the old blocks returned, the
+// new layout taken and the parameters pushed.
 ibb_status run_capacity(Run& U, int chunk) {
   Mem& M = U.R->mem;
   Params& P = U.R->P;
   const int n = P.n;
-  bool changed = false;
   const int64_t need_rows = U.sweeps + chunk + 2;
-  if (need_rows > P.hist_cap) {
-    const int64_t nc = std::max<int64_t>(2 * P.hist_cap, need_rows);
-    const int64_t keep = U.sweeps + 2;
-    ibb_status st = IBB_OK;
-    if ((st = grow(M, P.hist_n, keep * n, nc * n)) != IBB_OK || (st = grow(M, P.hist_h, keep * n, nc * n)) != IBB_OK ||
-        (st = grow(M, P.hist_cyc, keep, nc)) != IBB_OK || (st = grow(M, P.hist_mask, keep, nc)) != IBB_OK ||
-        (st = grow(M, P.hist_mid, keep * kMaxSplit, nc * kMaxSplit)) != IBB_OK)
-      return st;
-    P.hist_cap = nc;
-    changed = true;
-  }
   const int64_t need_keys = U.n_keys + (int64_t)(chunk + 1) * P.nch;   // +1: children pending from the last chunk
-  if (need_keys > P.key_cap) {
-    const int64_t nc = std::max<int64_t>(2 * P.key_cap, need_keys);
-    ibb_status st = IBB_OK;
-    if ((st = grow(M, P.key_flo, U.n_keys, nc)) != IBB_OK || (st = grow(M, P.key_seq, U.n_keys, nc)) != IBB_OK ||
-        (st = grow(M, P.key_ref, U.n_keys, nc)) != IBB_OK || (st = grow(M, P.key_r, U.n_keys, nc)) != IBB_OK ||
-        (st = grow(M, P.key_wmax, U.n_keys, nc)) != IBB_OK)
-      return st;
-    P.key_cap = nc;
-    changed = true;
-  }
   const int64_t need_tr = std::min<int64_t>(U.sweeps + chunk + 1, kTraceMax);
-  if (need_tr > P.trace_cap) {
-    const int64_t nc = std::min<int64_t>(std::max<int64_t>(2 * P.trace_cap, need_tr), kTraceMax);
-    const int64_t keep = std::min<int64_t>(U.sweeps, P.trace_cap);
-    double* t = dalloc<double>(M, 4 * nc);
-    if (!t) return fail(IBB_E_NOMEM, "device allocation failed");
-    if (keep > 0)   // the four rows of the old block into the new one
-      HIPCHK(hipMemcpy2DAsync(t, nc * 8, P.tr_gub, P.trace_cap * 8, keep * 8, 4, hipMemcpyDeviceToDevice, M.stream));
-    M.put(P.tr_gub);
-    set_trace(P, t, nc);
-    changed = true;
+  const bool g_rows = need_rows > P.hist_cap, g_keys = need_keys > P.key_cap, g_tr = need_tr > P.trace_cap;
+  if (!g_rows && !g_keys && !g_tr) return IBB_OK;
+  Params Q = P;   // the grown layout
+  std::vector<void*> fresh;
+  bool ok = true;
+  auto take = [&](auto*& dst, int64_t count) {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(dst)>>;
+    dst = ok ? dalloc<std::remove_const_t<T>>(M, count) : nullptr;
+    if (dst) fresh.push_back((void*)dst);
+    else ok = false;
+  };
+  if (g_rows) {
+    Q.hist_cap = std::max<int64_t>(2 * P.hist_cap, need_rows);
+    take(Q.hist_n, Q.hist_cap * n);
+    take(Q.hist_h, Q.hist_cap * n);
+    take(Q.hist_cyc, Q.hist_cap);
+    take(Q.hist_mask, Q.hist_cap);
+    take(Q.hist_mid, Q.hist_cap * kMaxSplit);
   }
-  if (changed) return push_params(M, P, U.dP);
-  return IBB_OK;
+  if (g_keys) {
+    Q.key_cap = std::max<int64_t>(2 * P.key_cap, need_keys);
+    take(Q.key_flo, Q.key_cap);
+    take(Q.key_seq, Q.key_cap);
+    take(Q.key_ref, Q.key_cap);
+    take(Q.key_r, Q.key_cap);
+    take(Q.key_wmax, Q.key_cap);
+  }
+  double* tr = nullptr;
+  int64_t tr_cap = P.trace_cap;
+  if (g_tr) {
+    tr_cap = std::min<int64_t>(std::max<int64_t>(2 * P.trace_cap, need_tr), kTraceMax);
+    take(tr, 4 * tr_cap);
+  }
+  if (!ok) {
+    for (void* q : fresh) M.put(q);
+    return fail(IBB_E_NOMEM, "device allocation failed while growing the box list");
+  }
+  auto copy = [&](void* dst, const void* src, size_t bytes) {
+    return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, M.stream) == hipSuccess;
+  };
+  bool copied = true;
+  if (g_rows) {
+    const int64_t keep = U.sweeps + 2;   // rows 0 .. sweeps + 1 are in use (the last one may be pending)
+    copied = copied && copy(Q.hist_n, P.hist_n, keep * n * sizeof(double)) &&
+             copy(Q.hist_h, P.hist_h, keep * n * sizeof(double)) && copy(Q.hist_cyc, P.hist_cyc, keep * sizeof(int32_t)) &&
+             copy(Q.hist_mask, P.hist_mask, keep * sizeof(uint32_t)) &&
+             copy(Q.hist_mid, P.hist_mid, keep * kMaxSplit * sizeof(double));
+  }
+  if (g_keys) {
+    const int64_t keep = U.n_keys;
+    copied = copied && copy(Q.key_flo, P.key_flo, keep * sizeof(double)) && copy(Q.key_seq, P.key_seq, keep * sizeof(int64_t)) &&
+             copy(Q.key_ref, P.key_ref, keep * sizeof(int32_t)) && copy(Q.key_r, P.key_r, keep * sizeof(int32_t)) &&
+             copy(Q.key_wmax, P.key_wmax, keep * sizeof(double));
+  }
+  if (g_tr) {
+    const int64_t keep = std::min<int64_t>(U.sweeps, P.trace_cap);
+    if (keep > 0)   // the four rows of the old block into the new one
+      copied = copied && hipMemcpy2DAsync(tr, tr_cap * 8, P.tr_gub, P.trace_cap * 8, keep * 8, 4,
+                                          hipMemcpyDeviceToDevice, M.stream) == hipSuccess;
+    set_trace(Q, tr, tr_cap);
+  }
+  if (!copied) {   // the old arrays are untouched; the new blocks go back with the rest at release
+    return fail(IBB_E_DEVICE, "copy failed while growing the box list");
+  }
+  if (g_rows) { M.put(P.hist_n); M.put(P.hist_h); M.put(P.hist_cyc); M.put(P.hist_mask); M.put(P.hist_mid); }
+  if (g_keys) { M.put(P.key_flo); M.put(P.key_seq); M.put(P.key_ref); M.put(P.key_r); M.put(P.key_wmax); }
+  if (g_tr) M.put(P.tr_gub);
+  P = Q;
+  return push_params(M, P, U.dP);
 }
 
 // after a chunk: take the device counters, drop removed keys when they dominate
@@ -2173,9 +2209,11 @@ ibb_status run_finish(Run& U) {
   R->info.fp32_sweeps = (int32_t)std::min<int64_t>(hs.fp32_sweeps, INT32_MAX);
   R->info.ub_evaluated = hs.ub_evaluated;
   R->info.status = hs.stop == STOP_CONVERGED ? IBB_OK
-                   : (hs.stop == STOP_EMPTY || hs.stop == STOP_CAPACITY) ? IBB_E_INTERNAL : IBB_NOT_CONVERGED;
+                   : (hs.stop == STOP_EMPTY || hs.stop == STOP_CAPACITY || hs.stop == STOP_INTERNAL) ? IBB_E_INTERNAL
+                                                                                                 : IBB_NOT_CONVERGED;
   R->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - U.t0).count();
   if (hs.stop == STOP_CAPACITY) return fail(IBB_E_INTERNAL, "a sweep would pass the sized row or key capacity");
+  if (hs.stop == STOP_INTERNAL) return fail(IBB_E_INTERNAL, "the selection counted live boxes but found none");
   if (R->info.status == IBB_E_INTERNAL) return fail(IBB_E_INTERNAL, "the live list became empty");
   return IBB_OK;
 }
@@ -2494,6 +2532,7 @@ ibb_status ibb_sweep(ibb_result* R, int64_t n_sweeps, void* hip_stream) {
     if (!R) return fail(IBB_E_INVALID, "result is NULL");
     if (n_sweeps < 0) return fail(IBB_E_INVALID, "n_sweeps < 0");
     if (!R->dS || !R->dP) return fail(IBB_E_INVALID, "result holds no device state");
+    if (R->broken) return fail(IBB_E_INVALID, "an earlier ibb_sweep on this result failed; free it");
     Run U;
     U.R = R;
     U.dP = R->dP;
@@ -2504,7 +2543,8 @@ ibb_status ibb_sweep(ibb_result* R, int64_t n_sweeps, void* hip_stream) {
     Params& P = R->P;
     HIPCHK(hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream));
     HIPCHK(hipStreamSynchronize(M.stream));
-    if (n_sweeps == 0 || U.hs.stop == STOP_CONVERGED || U.hs.stop == STOP_EMPTY || U.hs.stop == STOP_CAPACITY)
+    if (n_sweeps == 0 || U.hs.stop == STOP_CONVERGED || U.hs.stop == STOP_EMPTY || U.hs.stop == STOP_CAPACITY ||
+        U.hs.stop == STOP_INTERNAL)
       return (ibb_status)R->info.status;
     const double before = R->info.seconds;
     U.t0 = std::chrono::steady_clock::now();
@@ -2517,10 +2557,20 @@ ibb_status ibb_sweep(ibb_result* R, int64_t n_sweeps, void* hip_stream) {
     const int32_t running = RUNNING;
     HIPCHK(hipMemcpyAsync(&U.dS->stop, &running, sizeof(int32_t), hipMemcpyHostToDevice, M.stream));
     HIPCHK(hipStreamSynchronize(M.stream));
-    if ((st = run_sweeps(U, R->info.bound_shape)) != IBB_OK) return st;
+    // from here on a failure leaves the run half-way: the result is marked unusable
+    // (its info is kept, its boxes are dropped) and only ibb_result_info and
+    // ibb_result_free accept it afterwards
+    auto broken = [&](ibb_status e) {
+      R->broken = true;
+      R->n_boxes = 0;
+      R->info.n_boxes = 0;
+      R->info.status = e;
+      return e;
+    };
+    if ((st = run_sweeps(U, R->info.bound_shape)) != IBB_OK) return broken(st);
     M.put(R->flo); M.put(R->seq); M.put(R->ref); M.put(R->r); M.put(R->wmax);
     R->flo = nullptr; R->seq = nullptr; R->ref = nullptr; R->r = nullptr; R->wmax = nullptr;
-    if ((st = run_finish(U)) != IBB_OK) return st;
+    if ((st = run_finish(U)) != IBB_OK) return broken(st);
     R->info.seconds += before;
     return (ibb_status)R->info.status;
   } catch (...) {
@@ -2537,6 +2587,7 @@ ibb_status ibb_result_info(const ibb_result* res, ibb_info* info) {
 ibb_status ibb_result_boxes(const ibb_result* res, double* lo, double* hi, double* f_lo_per_box, int64_t* seq,
                             int64_t capacity, int64_t* written) {
   if (!res || capacity < 0) return fail(IBB_E_INVALID, "bad argument");
+  if (res->broken) return fail(IBB_E_INVALID, "an ibb_sweep on this result failed; its boxes are gone");
   ibb_result* R = const_cast<ibb_result*>(res);
   const int64_t k = std::min(capacity, R->n_boxes);
   if (written) *written = k;

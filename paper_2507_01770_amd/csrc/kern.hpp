@@ -53,8 +53,16 @@ constexpr int64_t kPersistentGrowth = (int64_t)1 << 17;      // keys a persisten
 
 // STOP_CAPACITY: the next sweep would pass the row or key capacity the host sized
 // the arrays for (the host grows them before every chunk, so this only guards)
+// STOP_INTERNAL: the selection counted live keys but found none to take (a guard)
 enum StopCode { RUNNING = 0, STOP_CONVERGED = 1, STOP_SWEEPS = 2, STOP_LIVE = 3, STOP_EMPTY = 4, STOP_HOST = 5,
-                STOP_CAPACITY = 6 };
+                STOP_CAPACITY = 6, STOP_INTERNAL = 7 };
+
+// A bound that came out NaN says nothing about f: as a lower bound it counts as
+// -inf (the box is kept and can never be cut off), as an upper bound as +inf (it
+// never lowers GUB).  Validated inputs do not produce NaN; this keeps rigour and
+// keeps every index the selection derives from the keys in range if one did.
+__device__ __forceinline__ double lo_or_ninf(double v) { return v == v ? v : -__builtin_inf(); }
+__device__ __forceinline__ double hi_or_inf(double v) { return v == v ? v + 0.0 : __builtin_inf(); }
 
 struct Params {
   int32_t family, n, m, nch;              // nch = 2^m children per selected box
