@@ -6,7 +6,7 @@ import time
 import numpy as np
 import pytest
 
-from oracle import oracle as O
+import oracle_runs as ORC
 from paper_2507_01770_amd import problems as PR
 
 pytestmark = pytest.mark.gpu
@@ -27,12 +27,20 @@ def same(a, b):
     assert np.array_equal(a.flo, b.flo) and np.array_equal(a.seq, b.seq)
 
 
-@pytest.mark.parametrize("n,budget", [(1024, 5), (2500, 3)])
+CHAIN_LARGE = [(1024, 5), (2500, 3)]
+SEP_LARGE = [(PR.SEP_ABS_SIN2, 2000, 4, 4), (PR.SEP_COS, 1500, 9, 4)]
+for _n, _budget in CHAIN_LARGE:
+    ORC.prefetch(PR.chain(_n, 505, hi=2.3), max_sweeps=_budget, incremental=True)
+for _fam, _n, _seed, _budget in SEP_LARGE:
+    ORC.prefetch(PR.make(_fam, _n, _seed), max_sweeps=_budget, incremental=True)
+
+
+@pytest.mark.parametrize("n,budget", CHAIN_LARGE)
 def test_chain_large_n_identical_to_oracle(n, budget):
     p = PR.chain(n, 505, hi=2.3)
     print(f"case chain n={n} budget={budget}", flush=True)
     r = ibb.minimize(p, max_sweeps=budget, max_boxes_fetched=200_000)
-    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=p.tol_x, max_sweeps=budget, incremental=True)
+    o = ORC.solve(p, max_sweeps=budget, incremental=True)
     assert r.status == o.status and r.sweeps == o.sweeps
     assert np.array_equal(r.trace_gub, o.trace_gub)
     assert np.array_equal(r.trace_nsurv, o.trace_nsurv)
@@ -43,12 +51,12 @@ def test_chain_large_n_identical_to_oracle(n, budget):
     assert np.array_equal(r.lo, o.lo) and np.array_equal(r.hi, o.hi)
 
 
-@pytest.mark.parametrize("fam,n,seed,budget", [(PR.SEP_ABS_SIN2, 2000, 4, 4), (PR.SEP_COS, 1500, 9, 4)])
+@pytest.mark.parametrize("fam,n,seed,budget", SEP_LARGE)
 def test_separable_large_n_matches_oracle(fam, n, seed, budget):
     p = PR.make(fam, n, seed)
     print(f"case {p.name} budget={budget}", flush=True)
     r = ibb.minimize(p, max_sweeps=budget, fetch_boxes=False)
-    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=p.tol_x, max_sweeps=budget, incremental=True)
+    o = ORC.solve(p, max_sweeps=budget, incremental=True)
     assert r.sweeps == o.sweeps == budget
     assert np.allclose(r.trace_gub, o.trace_gub, rtol=1e-12, atol=1e-12)
     assert np.array_equal(r.trace_sel, o.trace_sel)

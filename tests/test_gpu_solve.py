@@ -11,6 +11,7 @@ are compared with a prefix of the oracle's iteration.
 import numpy as np
 import pytest
 
+import oracle_runs as ORC
 from oracle import oracle as O
 from paper_2507_01770_amd import problems as PR
 
@@ -31,8 +32,7 @@ def run_both(p, incremental, **kw):
     """The same iteration on the GPU and in the oracle, with full or incremental child bounds."""
     print(f"case {p.name} incremental={incremental} {kw}", flush=True)
     r = ibb.minimize(p, incremental=incremental, **kw)
-    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=p.tol_x,
-                max_sweeps=kw.get("max_sweeps", 100000), incremental=incremental)
+    o = ORC.solve(p, max_sweeps=kw.get("max_sweeps", 100000), incremental=incremental)
     return r, o
 
 
@@ -43,9 +43,19 @@ MODES = [False, True]
 # n = 13 on [-2, 2] does not converge quickly and stops on the sweep budget.
 # n = 70 and 100 use two wavefronts per child, n = 200 four.
 # n = 13 runs 300 sweeps: the row arrays grow past 256 rows on the way.
-@pytest.mark.parametrize("n,hi,budget", [(2, 2.0, 3000), (3, 2.3, 3000), (5, 2.3, 3000), (8, 2.3, 3000),
-                                         (12, 2.3, 3000), (13, 2.0, 300), (70, 2.0, 3000), (100, 2.3, 30),
-                                         (200, 2.3, 20)])
+CHAIN_CASES = [(2, 2.0, 3000), (3, 2.3, 3000), (5, 2.3, 3000), (8, 2.3, 3000), (12, 2.3, 3000), (13, 2.0, 300),
+               (70, 2.0, 3000), (100, 2.3, 30), (200, 2.3, 20)]
+WORKLOAD_PREFIX = [(1, 6), (2, 12)]
+# the slow oracle runs start on host threads as soon as this module is imported
+for _inc in MODES:
+    for _cfg, _prefix in WORKLOAD_PREFIX:
+        ORC.prefetch(PR.config(_cfg), max_sweeps=_prefix, incremental=_inc)
+    for _n, _hi, _budget in CHAIN_CASES:
+        if _n >= 12:
+            ORC.prefetch(PR.chain(_n, 505, hi=_hi), max_sweeps=_budget, incremental=_inc)
+
+
+@pytest.mark.parametrize("n,hi,budget", CHAIN_CASES)
 @pytest.mark.parametrize("incremental", MODES)
 def test_chain_identical_iteration(n, hi, budget, incremental):
     p = PR.chain(n, 505, hi=hi)
@@ -191,7 +201,7 @@ def test_workload0_full_parity(incremental):
     assert r.sweeps == o.sweeps
 
 
-@pytest.mark.parametrize("cfg,prefix", [(1, 6), (2, 12)])
+@pytest.mark.parametrize("cfg,prefix", WORKLOAD_PREFIX)
 @pytest.mark.parametrize("incremental", MODES)
 def test_workload_full_run_and_prefix(cfg, prefix, incremental):
     p = PR.config(cfg)
@@ -201,7 +211,7 @@ def test_workload_full_run_and_prefix(cfg, prefix, incremental):
     assert r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6
     assert inside_some_box(p.x_star, r.lo, r.hi) or r.n_boxes > 2000
     print(f"case workload {cfg} oracle prefix {prefix}", flush=True)
-    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=prefix, incremental=incremental)
+    o = ORC.solve(p, max_sweeps=prefix, incremental=incremental)
     if p.family == PR.CHAIN:
         assert np.array_equal(r.trace_gub[:prefix], o.trace_gub)
         assert np.array_equal(r.trace_nsurv[:prefix], o.trace_nsurv)

@@ -11,6 +11,7 @@ to last-bit differences of the trig enclosures.
 import numpy as np
 import pytest
 
+import oracle_runs as ORC
 from oracle import oracle as O
 from paper_2507_01770_amd import problems as PR
 
@@ -25,15 +26,22 @@ import paper_2507_01770_amd as ibb  # noqa: E402
 MODES = [False, True]
 
 
-@pytest.mark.parametrize("n,m,budget", [(20, 1, 400), (20, 3, 300), (13, 5, 200), (30, 7, 100), (14, 11, 30),
-                                        (12, 12, 16), (24, 16, 2)])
+CHAIN_WIDTHS = [(20, 1, 400), (20, 3, 300), (13, 5, 200), (30, 7, 100), (14, 11, 30), (12, 12, 16), (24, 16, 2)]
+SEP_WIDTHS = [(40, 3, 300), (14, 12, 40)]
+for _inc in MODES:
+    for _n, _m, _budget in CHAIN_WIDTHS:
+        ORC.prefetch(PR.chain(_n, 505, hi=2.3), split_dims=_m, max_sweeps=_budget, incremental=_inc)
+    for _n, _m, _budget in SEP_WIDTHS:
+        ORC.prefetch(PR.sep_cos(_n, 7), split_dims=_m, max_sweeps=_budget, incremental=_inc)
+
+
+@pytest.mark.parametrize("n,m,budget", CHAIN_WIDTHS)
 @pytest.mark.parametrize("incremental", MODES)
 def test_chain_split_width_identical_iteration(n, m, budget, incremental):
     p = PR.chain(n, 505, hi=2.3)
     print(f"case chain n={n} m={m} budget={budget} incremental={incremental}", flush=True)
     r = ibb.minimize(p, split_dims=m, max_sweeps=budget, incremental=incremental, max_boxes_fetched=200_000)
-    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=p.tol_x, split_dims=m, max_sweeps=budget,
-                incremental=incremental)
+    o = ORC.solve(p, split_dims=m, max_sweeps=budget, incremental=incremental)
     assert r.status == o.status and r.sweeps == o.sweeps and r.boxes_evaluated == o.boxes_evaluated
     assert np.array_equal(r.trace_gub, o.trace_gub)
     assert np.array_equal(r.trace_nsurv, o.trace_nsurv)
@@ -45,14 +53,13 @@ def test_chain_split_width_identical_iteration(n, m, budget, incremental):
     assert np.array_equal(r.lo, o.lo) and np.array_equal(r.hi, o.hi)
 
 
-@pytest.mark.parametrize("n,m,budget", [(40, 3, 300), (14, 12, 40)])
+@pytest.mark.parametrize("n,m,budget", SEP_WIDTHS)
 @pytest.mark.parametrize("incremental", MODES)
 def test_separable_split_width_matches_oracle(n, m, budget, incremental):
     p = PR.sep_cos(n, 7)
     print(f"case sep_cos n={n} m={m} budget={budget} incremental={incremental}", flush=True)
     r = ibb.minimize(p, split_dims=m, max_sweeps=budget, incremental=incremental, fetch_boxes=False)
-    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=p.tol_x, split_dims=m, max_sweeps=budget,
-                incremental=incremental)
+    o = ORC.solve(p, split_dims=m, max_sweeps=budget, incremental=incremental)
     assert r.status == ibb.OK and o.status == O.ST_OK
     assert r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6
     assert abs(r.sweeps - o.sweeps) <= max(2, o.sweeps // 20)
