@@ -9,9 +9,12 @@ oracle's, and the excess must stay tiny.  Sizes span several 64-wide tiles with
 a ragged tail; the workload sizes (n = 100, 1000, 10000) are checked on a
 sample of boxes.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
+import test_oracle_sum_order as SUM
 from oracle import oracle as O
 from paper_2507_01770_amd import problems as PR
 
@@ -89,3 +92,19 @@ def test_empty_box_batch(precision):
     F, ub, mono, G = ibb.eval_boxes(p, e, e.clone(), want_grad=True, precision=precision)
     torch.cuda.synchronize()
     assert F.shape == (0, 2) and ub.shape == (0,) and mono.shape == (0,) and G.shape == (0, 5, 2)
+
+
+@pytest.mark.parametrize("n,seed", SUM.CASES)
+def test_sum_order_bit_exact(n, seed):
+    # point boxes whose terms are exactly t_i (the oracle pin of the canonical
+    # order): the GPU's slot sums and wavefront fold must give the bits that the
+    # exact-rational evaluation of that order gives, in both directions
+    ts = SUM.designed_terms(n, seed)
+    coef, lower, upper = SUM.point_problem(ts)
+    p = dataclasses.replace(PR.sep_abs_sin2(n, 1), coef=coef, lower=lower, upper=upper, x_star=None)
+    x = torch.from_numpy(ts.reshape(1, -1)).cuda()
+    print(f"case sum order n={n} seed={seed}", flush=True)
+    F, ub, mono = (t.cpu().numpy() for t in ibb.eval_boxes(p, x, x))
+    tl = [float(t) for t in ts]
+    assert F[0, 0] == SUM.canonical(tl, False) and F[0, 1] == SUM.canonical(tl, True)
+    assert ub[0] == SUM.canonical(tl, True)
