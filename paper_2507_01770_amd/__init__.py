@@ -337,9 +337,10 @@ class Run:
         self._k = _prob_args(problem)
         self._stream = stream
         o = _options(**opts)
+        self._alloc = _TorchAllocator()   # outlives the result: its blocks go back through it
         self._h = C.c_void_p()
-        _check(lib().ibb_solve(C.byref(self._k.s), C.byref(o), None, _stream_ptr(stream), C.byref(self._h)),
-               ok=(OK, NOT_CONVERGED))
+        _check(lib().ibb_solve(C.byref(self._k.s), C.byref(o), C.byref(self._alloc.struct), _stream_ptr(stream),
+                               C.byref(self._h)), ok=(OK, NOT_CONVERGED))
 
     def sweep(self, n_sweeps: int) -> int:
         return _check(lib().ibb_sweep(self._h, int(n_sweeps), _stream_ptr(self._stream)), ok=(OK, NOT_CONVERGED))
@@ -385,7 +386,8 @@ def solve_batch(problems, *, fetch_boxes=True, max_boxes_fetched=100_000, stream
     o = _options(**opts)
     outs = (C.c_void_p * len(keeps))()
     sts = (C.c_int32 * len(keeps))()
-    rc = L.ibb_solve_batch(arr, len(keeps), C.byref(o), None, _stream_ptr(stream), outs, sts)
+    alloc = _TorchAllocator()   # kept until every result below has been freed
+    rc = L.ibb_solve_batch(arr, len(keeps), C.byref(o), C.byref(alloc.struct), _stream_ptr(stream), outs, sts)
     if rc != OK:   # results of problems that finished before the error are still ours to free
         for i in range(len(keeps)):
             if outs[i]:
@@ -407,8 +409,12 @@ class Server:
     def __init__(self, mem_budget_bytes=8 << 30, max_slots=64, stream=None):
         torch = _torch()
         self._stream = stream if stream is not None else torch.cuda.Stream()
+        # device memory through torch's caching allocator; the callbacks run on the
+        # server's own thread (ctypes takes the GIL for them), and the allocator
+        # outlives the server and every result it hands over
+        self._alloc = _TorchAllocator()
         self._h = C.c_void_p()
-        _check(lib().ibb_server_create(int(mem_budget_bytes), int(max_slots), None,
+        _check(lib().ibb_server_create(int(mem_budget_bytes), int(max_slots), C.byref(self._alloc.struct),
                                        C.c_void_p(self._stream.cuda_stream), C.byref(self._h)))
         self._n = {}
 

@@ -216,8 +216,11 @@ __device__ __forceinline__ void insert_children(const Params& P, State* S, doubl
   constexpr int NW = NT / kWave;
   __shared__ int w_ins[NW], w_form[NW], w_n32[NW];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
-  const int per = (P.nch + NT - 1) / NT;
-  const int c0 = threadIdx.x * per, c1 = min(P.nch, c0 + per);
+  // K > 1: the records of the K parents, parent-major (record p nch + c)
+  const bool multi = P.select_k > 1;
+  const int nrec = multi ? S->sel_count * P.nch : P.nch;
+  const int per = (nrec + NT - 1) / NT;
+  const int c0 = threadIdx.x * per, c1 = min(nrec, c0 + per);
   int mine = 0, nformed = 0, n32 = 0;
   for (int k = c0; k < c1; ++k) {
     const uint8_t fl = P.ch_flag[k];
@@ -269,8 +272,8 @@ __device__ __forceinline__ void insert_children(const Params& P, State* S, doubl
       const int64_t sq = seq0 + (o - base);
       P.key_flo[o] = f;
       P.key_seq[o] = sq;
-      P.key_ref[o] = row;
-      P.key_r[o] = k;
+      P.key_ref[o] = multi ? P.sel_tab[k >> P.m].row : row;
+      P.key_r[o] = multi ? (k & (P.nch - 1)) : k;
       P.key_wmax[o] = P.ch_wmax[k];
       a.cnt++;
       a.wm = dmax(a.wm, P.ch_wmax[k]);
@@ -1324,6 +1327,58 @@ __global__ __launch_bounds__(NT) void k_select_ib(const Params* __restrict__ PP,
   }
 }
 
+// K > 1 with incremental bounds: workgroup p bounds the children of the box of
+// rank p of the sweep's selection (its own base sums and tables, exactly as the
+// K = 1 sweep forms them), writes their records p nch + c for the insertion in
+// the next selection, and lowers GUB to the minimum of their midpoint bounds.
+template <int NT, int FAM>
+__global__ __launch_bounds__(NT) void k_ib_parents(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  if (S->stop) return;
+  const int pr = blockIdx.x;
+  if (pr >= S->sel_count) return;
+  const Params& P = *PP;
+  __shared__ IbLds<NT> lds;
+  const SelRec rec = P.sel_tab[pr];
+  const Sel sel{rec.row, rec.seq, rec.cyc, rec.mask};
+  ib_prepare<NT, FAM>(P, lds, sel);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  double wbase = 0.0;
+  for (int k = 0; k < NT / kWave; ++k) wbase = dmax(wbase, lds.wred[k]);
+  double umin = __builtin_inf();
+  int cnt = 0;
+  const int64_t g0 = (int64_t)pr * P.nch;
+  for (int c = threadIdx.x; c < P.nch; c += NT) {
+    if (((uint32_t)c & ~sel.mask) != 0u) {
+      P.ch_flag[g0 + c] = 0;   // takes the upper half of a coordinate that cannot be split
+      continue;
+    }
+    double flo, wm, u;
+    bool mo;
+    ib_child<NT, FAM>(P, lds, sel.mask, P.m, (uint32_t)c, wbase, flo, mo, wm, u);
+    P.ch_flo[g0 + c] = flo;
+    P.ch_wmax[g0 + c] = wm;
+    P.ch_flag[g0 + c] = mo ? 1 : 2;
+    umin = dmin(umin, hi_or_inf(u));
+    ++cnt;
+  }
+  for (int h = 32; h >= 1; h >>= 1) {
+    umin = dmin(umin, __shfl_xor(umin, h, kWave));
+    cnt += __shfl_xor(cnt, h, kWave);
+  }
+  if (lane == 0) { lds.red[wid] = umin; lds.cnt[wid] = cnt; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mn = lds.red[0];
+    int tot = lds.cnt[0];
+    for (int k = 1; k < NT / kWave; ++k) { mn = dmin(mn, lds.red[k]); tot += lds.cnt[k]; }
+    if (tot > 0) {
+      atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(mn));
+      atomicAdd((unsigned long long*)&S->ub_evaluated, (unsigned long long)tot);
+    }
+  }
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_select(const Params* __restrict__ PP, State* __restrict__ S, int nparts,
                                                int host_stop) {
@@ -1331,6 +1386,247 @@ __global__ __launch_bounds__(NT) void k_select(const Params* __restrict__ PP, St
   if (S->stop) return;
   const Params P = *PP;
   select_body<NT>(P, S, nparts, host_stop);
+}
+
+// ---------------------------------------------------------------------------
+// K > 1 boxes per sweep: Sec. 3.1 selects the region with the smallest lower
+// bound; a sweep here may take the K smallest (lower bound, insertion number)
+// at once (K a fixed option: it changes the iteration, so it is never tuned).
+// One workgroup inserts the previous sweep's survivors (records of K parents,
+// parent-major), counts the live list and tests the stopping criteria as for
+// K = 1, then finds the K-th smallest lower bound by a radix selection over the
+// ordered 64-bit keys of the live boxes (8 bits per pass from the top; a pass
+// whose boundary bin is taken whole ends it), takes every box below that bound
+// and, among boxes equal to it, the first ones in list order (list order is
+// insertion order), ranks the at most K candidates by (lower bound, list
+// index), and writes one row per selected box: box p of sweep t gets row
+// 1 + t K + p, its cycling index, split points and split mask, and an entry in
+// the selection table.
+template <int NT>
+struct KSelLds {
+  int hist[256];
+  int wtot[NT / kWave];
+  int bin, below, ncand;
+  double cf[kMaxSelectK];      // candidates, unordered
+  int32_t ci[kMaxSelectK];
+  int32_t si[kMaxSelectK];     // list index by rank
+  int32_t sref[kMaxSelectK], sr[kMaxSelectK];   // parent row and child index by rank
+};
+
+template <int NT>
+__device__ __forceinline__ int ksel_count_prefix(int v, KSelLds<NT>& L, int& total) {
+  // exclusive prefix over the workgroup of one int per thread (thread order)
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  int incl = v;
+  for (int h = 1; h < kWave; h <<= 1) {
+    const int o = __shfl_up(incl, h, kWave);
+    if (lane >= h) incl += o;
+  }
+  if (lane == kWave - 1) L.wtot[wid] = incl;
+  __syncthreads();
+  int before = 0;
+  total = 0;
+  for (int k = 0; k < NT / kWave; ++k) {
+    const int t = L.wtot[k];
+    before += k < wid ? t : 0;
+    total += t;
+  }
+  __syncthreads();   // L.wtot is written again by the next call
+  return before + incl - v;
+}
+
+template <int NT>
+__device__ bool select_k_body(const Params& P, State* S, int host_stop, KSelLds<NT>& L) {
+  const double gub = okey_inv(S->gub_key);
+  SelAcc ins = sel_empty();
+  if (S->pending) insert_children<NT>(P, S, gub, ins);   // ends with a barrier
+  const int64_t nk = S->n_keys;
+  const int K = P.select_k;
+  const bool need_w = P.tol_x > 0.0;
+  // live count, GLB and widest box over the whole list
+  SelAcc a = sel_empty();
+  for (int64_t i = threadIdx.x; i < nk; i += NT) {
+    const double f = P.key_flo[i];
+    if (!(f <= gub)) continue;
+    a.cnt++;
+    if (need_w) a.wm = dmax(a.wm, P.key_wmax[i]);
+    if (f < a.best.f) a.best = Cand{f, i};
+  }
+  a = sel_block_reduce<NT>(a);
+  __shared__ int32_t go;
+  const int64_t t = S->sweeps;
+  if (threadIdx.x == 0) {
+    if (t > 0 && t - 1 < P.trace_cap) P.tr_nlive[t - 1] = a.cnt;
+    S->n_live = a.cnt;
+    S->glb = a.best.f;
+    S->wmax = a.wm;
+    int32_t stop = RUNNING;
+    if (host_stop) stop = STOP_HOST;
+    else if (a.cnt == 0) stop = STOP_EMPTY;
+    else if (gub - a.best.f <= P.tol_f && (P.tol_x <= 0.0 || a.wm < P.tol_x)) stop = STOP_CONVERGED;
+    else if (t >= P.max_sweeps) stop = STOP_SWEEPS;
+    else if (P.max_live > 0 && a.cnt > P.max_live) stop = STOP_LIVE;
+    else if ((t + 1) * K >= P.hist_cap || nk + (int64_t)K * P.nch > P.key_cap) stop = STOP_CAPACITY;
+    if (stop) S->stop = stop;
+    go = stop == RUNNING;
+    L.ncand = 0;
+  }
+  __syncthreads();
+  if (!go) return false;
+
+  // radix selection of the K-th smallest ordered key among the live boxes
+  uint64_t prefix = 0;
+  int need = K, shift = 64;
+  bool whole = a.cnt <= K;   // every live box is taken
+  if (!whole) {
+    for (shift = 56; shift >= 0; shift -= 8) {
+      for (int b = threadIdx.x; b < 256; b += NT) L.hist[b] = 0;
+      if (threadIdx.x == 0) { L.bin = 0; L.below = 0; }
+      __syncthreads();
+      const uint64_t hmask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+      for (int64_t i = threadIdx.x; i < nk; i += NT) {
+        const double f = P.key_flo[i];
+        if (!(f <= gub)) continue;
+        const uint64_t u = okey(f);
+        if ((u & hmask) == (prefix & hmask)) atomicAdd(&L.hist[(int)((u >> shift) & 255u)], 1);
+      }
+      __syncthreads();
+      if (threadIdx.x < (unsigned)kWave) {   // the bin where the count below reaches `need`
+        const int lane = threadIdx.x;
+        const int h0 = L.hist[4 * lane], h1 = L.hist[4 * lane + 1], h2 = L.hist[4 * lane + 2], h3 = L.hist[4 * lane + 3];
+        const int sum = h0 + h1 + h2 + h3;
+        int incl = sum;
+        for (int h = 1; h < kWave; h <<= 1) {
+          const int o = __shfl_up(incl, h, kWave);
+          if (lane >= h) incl += o;
+        }
+        const int excl = incl - sum;
+        if (excl < need && need <= incl) {
+          int below = excl, b = 4 * lane;
+          const int hs[4] = {h0, h1, h2, h3};
+          for (int q = 0; q < 4; ++q) {
+            if (below + hs[q] >= need) { b = 4 * lane + q; break; }
+            below += hs[q];
+          }
+          L.bin = b;
+          L.below = below;
+        }
+      }
+      __syncthreads();
+      const int b = L.bin & 255, inbin = L.hist[b];
+      prefix |= (uint64_t)b << shift;
+      need -= L.below;
+      __syncthreads();   // every thread has read the bin before the histogram is cleared
+      if (inbin == need) { whole = true; break; }
+    }
+    if (!whole) shift = 0;   // all 64 bits fixed: prefix is the K-th smallest key itself
+  }
+  // take, in list order: every live key below the bound and, when the bound is a
+  // single key value, the first `need` keys equal to it
+  const uint64_t top = shift >= 64 ? 0ull : (prefix >> shift);
+  int eqbase = 0;   // keys equal to the bound in earlier chunks (every thread keeps the same count)
+  for (int64_t c0 = 0; c0 < nk; c0 += NT) {
+    const int64_t i = c0 + threadIdx.x;
+    bool take = false, eq = false;
+    double f = 0.0;
+    if (i < nk) {
+      f = P.key_flo[i];
+      if (f <= gub) {
+        const uint64_t u = okey(f);
+        if (whole) take = shift >= 64 || (u >> shift) <= top;
+        else {
+          take = u < prefix;
+          eq = u == prefix;
+        }
+      }
+    }
+    if (!whole) {
+      int tot = 0;
+      const int rank = ksel_count_prefix<NT>(eq ? 1 : 0, L, tot);
+      if (eq && eqbase + rank < need) take = true;
+      eqbase += tot;
+    }
+    if (take) {
+      const int slot = atomicAdd(&L.ncand, 1);
+      if (slot < kMaxSelectK) {
+        L.cf[slot] = f;
+        L.ci[slot] = (int32_t)i;
+      }
+    }
+  }
+  __syncthreads();
+  const int nc = min(L.ncand, K);
+  // rank the candidates by (lower bound, list index)
+  for (int q = threadIdx.x; q < nc; q += NT) {
+    const double fq = L.cf[q];
+    const int32_t iq = L.ci[q];
+    int rank = 0;
+    for (int j = 0; j < nc; ++j) {
+      const double fj = L.cf[j];
+      rank += (fj < fq || (fj == fq && L.ci[j] < iq)) ? 1 : 0;
+    }
+    L.si[rank] = iq;
+  }
+  __syncthreads();
+  // per selected box (one wavefront each): remove its key, its cycling index,
+  // split points and mask, its table entry
+  const int n = P.n, lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  for (int pr = wid; pr < nc; pr += NT / kWave) {
+    const int32_t idx = L.si[pr];
+    const int32_t ref = P.key_ref[idx];
+    const int32_t r = P.key_r[idx];
+    const int64_t seq = P.key_seq[idx];
+    const int pcyc = P.hist_cyc[ref];
+    const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
+                       n, P.m, pcyc, r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
+    const int cyc = r >= 0 ? add_mod(pcyc, P.m, n) : pcyc;
+    const int64_t row = 1 + t * K + pr;
+    bool ok = false;
+    if (lane < P.m) {
+      const I x = src.get(add_mod(cyc, lane, n));
+      const double md = midpoint(x);
+      ok = neg(x.n) < md && md < x.h;
+      P.hist_mid[row * kMaxSplit + lane] = md;
+    }
+    const uint32_t mask = (uint32_t)__ballot(ok) & ((1u << P.m) - 1u);   // m <= 16
+    if (lane == 0) {
+      P.hist_mask[row] = mask;
+      P.hist_cyc[row] = cyc;
+      P.sel_tab[pr] = SelRec{seq, (int32_t)row, cyc, mask, 0u};
+      P.key_flo[idx] = __builtin_inf();   // removed from the list
+      L.sref[pr] = ref;
+      L.sr[pr] = r;
+      if (pr == 0) S->sel_seq = seq;
+    }
+  }
+  __syncthreads();
+  // the selected boxes' real endpoints, row by row
+  for (int pr = 0; pr < nc; ++pr) {
+    const int32_t ref = L.sref[pr], r = L.sr[pr];
+    const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
+                       n, P.m, P.hist_cyc[ref], r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
+    const int64_t row = 1 + t * K + pr;
+    for (int i = threadIdx.x; i < n; i += NT) {
+      const I x = src.get(i);
+      P.hist_n[row * n + i] = x.n;
+      P.hist_h[row * n + i] = x.h;
+    }
+  }
+  if (threadIdx.x == 0) {
+    S->sel_count = nc;
+    S->gub_start = gub;
+    S->pending = 1;
+  }
+  return true;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_select_k(const Params* __restrict__ PP, State* __restrict__ S, int host_stop) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params P = *PP;
+  __shared__ KSelLds<NT> lds;
+  select_k_body<NT>(P, S, host_stop, lds);
 }
 
 // Bound the children of the selected box.
@@ -1354,12 +1650,30 @@ __device__ void bound_body(const Params& P, State* S, int cbase) {
   const bool mid_role = CONC && role_w >= W;
   const int w = role_w % W;
   const int first = local * WPC + (mid_role ? W : 0);   // wave slot of this role's wave 0
-  const int c = cbase + local;
-  const int row = S->sel_row;
-  const uint32_t mask = S->sel_mask;
-  const bool formed = c < P.nch && (((uint32_t)c & ~mask) == 0u);
+  // record g: child c of the selected box (K > 1: child c = g mod nch of the box
+  // of rank g / nch, taken from the sweep's selection table)
+  const int g = cbase + local;
+  int row, cyc, c;
+  uint32_t mask;
+  bool in;   // a record of this sweep
+  if (P.select_k > 1) {
+    const int pr = g >> P.m;
+    in = g < P.select_k * P.nch && pr < S->sel_count;
+    const SelRec sr = P.sel_tab[in ? pr : 0];
+    row = sr.row;
+    cyc = sr.cyc;
+    mask = sr.mask;
+    c = g & (P.nch - 1);
+  } else {
+    in = g < P.nch;
+    row = S->sel_row;
+    cyc = S->sel_cyc;
+    mask = S->sel_mask;
+    c = g;
+  }
+  const bool formed = in && (((uint32_t)c & ~mask) == 0u);
   const ChildRow X{P.hist_n + (int64_t)row * P.n, P.hist_h + (int64_t)row * P.n, P.hist_mid + (int64_t)row * kMaxSplit,
-                   P.n, P.m, S->sel_cyc, mask, (uint32_t)(c < P.nch ? c : 0)};
+                   P.n, P.m, cyc, mask, (uint32_t)(in ? c : 0)};
   const int n = P.n;
   const int rounds = ((n + kWave - 1) / kWave + W - 1) / W;
   __shared__ double ln[kBoundWaves][kWave], lh[kBoundWaves][kWave];
@@ -1515,21 +1829,21 @@ __device__ void bound_body(const Params& P, State* S, int cbase) {
     }
     if (w == 0) {
       const double u = fold_slots_hi(hacc, lane);
-      if (lane == 0 && c < P.nch) {
+      if (lane == 0 && in) {
         if (formed) {
           if (do_ub) {
             atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(hi_or_inf(u)));
             atomicAdd((unsigned long long*)&S->ub_evaluated, 1ull);
           }
           if (r32) {
-            P.ch_flag[c] = 3;
+            P.ch_flag[g] = 3;
           } else {
-            P.ch_flo[c] = flo;
-            P.ch_flag[c] = cmo ? 1 : 2;
-            P.ch_wmax[c] = cwm;
+            P.ch_flo[g] = flo;
+            P.ch_flag[g] = cmo ? 1 : 2;
+            P.ch_wmax[g] = cwm;
           }
         } else {
-          P.ch_flag[c] = 0;   // takes the upper half of a coordinate that cannot be split
+          P.ch_flag[g] = 0;   // takes the upper half of a coordinate that cannot be split
         }
       }
     }
@@ -1540,13 +1854,13 @@ __device__ void bound_body(const Params& P, State* S, int cbase) {
         atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(hi_or_inf(u)));
         atomicAdd((unsigned long long*)&S->ub_evaluated, 1ull);
       }
-    } else if (lane == 0 && c < P.nch) {
+    } else if (lane == 0 && in) {
       if (formed) {
-        P.ch_flo[c] = flo;
-        P.ch_flag[c] = cmo ? 1 : 2;
-        P.ch_wmax[c] = cwm;
+        P.ch_flo[g] = flo;
+        P.ch_flag[g] = cmo ? 1 : 2;
+        P.ch_wmax[g] = cwm;
       } else {
-        P.ch_flag[c] = 0;
+        P.ch_flag[g] = 0;
       }
     }
   }
@@ -2020,8 +2334,10 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   P.max_sweeps = U.opts.max_sweeps;
   P.max_live = U.opts.max_live_boxes;
   P.trace_cap = std::min<int64_t>(std::min<int64_t>(U.opts.max_sweeps + 1, kTraceMax), kTraceStart);
-  P.key_cap = std::max<int64_t>(4096, 4 * (int64_t)P.nch);
-  P.hist_cap = 64;
+  P.select_k = U.opts.select_k;
+  const int64_t nrec = (int64_t)P.select_k * P.nch;   // child records per sweep
+  P.key_cap = std::max<int64_t>(4096, 4 * nrec);
+  P.hist_cap = std::max<int64_t>(64, 2 * (int64_t)P.select_k + 2);
   P.key_flo = dalloc<double>(M, P.key_cap);
   P.key_seq = dalloc<int64_t>(M, P.key_cap);
   P.key_ref = dalloc<int32_t>(M, P.key_cap);
@@ -2032,16 +2348,17 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   P.hist_cyc = dalloc<int32_t>(M, P.hist_cap);
   P.hist_mask = dalloc<uint32_t>(M, P.hist_cap);
   P.hist_mid = dalloc<double>(M, P.hist_cap * kMaxSplit);
-  P.ch_flo = dalloc<double>(M, P.nch);
-  P.ch_flag = dalloc<uint8_t>(M, P.nch);
-  P.ch_wmax = dalloc<double>(M, P.nch);
+  P.ch_flo = dalloc<double>(M, nrec);
+  P.ch_flag = dalloc<uint8_t>(M, nrec);
+  P.ch_wmax = dalloc<double>(M, nrec);
+  P.sel_tab = dalloc<SelRec>(M, P.select_k);
   P.part_flo = dalloc<double>(M, kMaxSelBlocks);
   P.part_idx = dalloc<int64_t>(M, kMaxSelBlocks);
   P.part_wmax = dalloc<double>(M, kMaxSelBlocks);
   P.part_cnt = dalloc<int64_t>(M, kMaxSelBlocks);
   set_trace(P, dalloc<double>(M, 4 * P.trace_cap), P.trace_cap);
   if (!P.key_flo || !P.key_seq || !P.key_ref || !P.key_r || !P.key_wmax || !P.hist_n || !P.hist_h || !P.hist_cyc ||
-      !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.part_flo ||
+      !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.sel_tab || !P.part_flo ||
       !P.part_idx || !P.part_wmax || !P.part_cnt || !P.tr_gub || !P.tr_nsurv || !P.tr_nlive || !P.tr_sel)
     return fail(IBB_E_NOMEM, "device allocation failed");
   // root row: (-l, u)
@@ -2051,7 +2368,7 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   HIPCHK(hipMemcpyAsync(P.hist_h, prob->upper, n * sizeof(double), hipMemcpyHostToDevice, M.stream));
   HIPCHK(hipMemsetAsync(U.dS, 0, sizeof(State), M.stream));
   // child records start as "not formed": nothing reads a record no bound kernel wrote
-  HIPCHK(hipMemsetAsync(P.ch_flag, 0, P.nch, M.stream));
+  HIPCHK(hipMemsetAsync(P.ch_flag, 0, nrec, M.stream));
   st = push_params(M, P, U.dP);
   if (st != IBB_OK) return st;
   HIPCHK(hipStreamSynchronize(M.stream));   // nl must outlive its copy
@@ -2076,8 +2393,10 @@ ibb_status run_capacity(Run& U, int chunk) {
   Mem& M = U.R->mem;
   Params& P = U.R->P;
   const int n = P.n;
-  const int64_t need_rows = U.sweeps + chunk + 2;
-  const int64_t need_keys = U.n_keys + (int64_t)(chunk + 1) * P.nch;   // +1: children pending from the last chunk
+  const int64_t K = P.select_k;
+  // rows 0 .. (sweeps + 1) K are in use (the last K may belong to a pending selection)
+  const int64_t need_rows = (U.sweeps + chunk + 1) * K + 1;
+  const int64_t need_keys = U.n_keys + (int64_t)(chunk + 1) * K * P.nch;   // +1: children pending from the last chunk
   const int64_t need_tr = std::min<int64_t>(U.sweeps + chunk + 1, kTraceMax);
   const bool g_rows = need_rows > P.hist_cap, g_keys = need_keys > P.key_cap, g_tr = need_tr > P.trace_cap;
   if (!g_rows && !g_keys && !g_tr) return IBB_OK;
@@ -2121,7 +2440,7 @@ ibb_status run_capacity(Run& U, int chunk) {
   };
   bool copied = true;
   if (g_rows) {
-    const int64_t keep = U.sweeps + 2;   // rows 0 .. sweeps + 1 are in use (the last one may be pending)
+    const int64_t keep = (U.sweeps + 1) * K + 1;
     copied = copied && copy(Q.hist_n, P.hist_n, keep * n * sizeof(double)) &&
              copy(Q.hist_h, P.hist_h, keep * n * sizeof(double)) && copy(Q.hist_cyc, P.hist_cyc, keep * sizeof(int32_t)) &&
              copy(Q.hist_mask, P.hist_mask, keep * sizeof(uint32_t)) &&
@@ -2220,7 +2539,9 @@ ibb_status run_finish(Run& U) {
 
 ibb_status check_options(const ibb_options& o) {
   if (o.split_dims < 1 || o.split_dims > kMaxSplit) return fail(IBB_E_INVALID, "split_dims must be in 1..16");
-  if (o.select_k != 1) return fail(IBB_E_INVALID, "this build selects one box per sweep (select_k = 1)");
+  if (o.select_k < 1 || o.select_k > kMaxSelectK) return fail(IBB_E_INVALID, "select_k must be in 1..1024");
+  if (((int64_t)o.select_k << o.split_dims) > ((int64_t)1 << 24))
+    return fail(IBB_E_INVALID, "select_k * 2^split_dims must not exceed 2^24 children per sweep");
   if (o.precision != IBB_FP64 && o.precision != IBB_FP32_BULK) return fail(IBB_E_INVALID, "unknown precision");
   if (o.incremental != 0 && o.incremental != 1) return fail(IBB_E_INVALID, "incremental must be 0 or 1");
   if (o.incremental && o.precision == IBB_FP32_BULK)
@@ -2283,7 +2604,10 @@ ibb_status autotune_bound(Run& U, int n_tiles, int& best) {
   Mem& M = R->mem;
   Params& P = R->P;
   best = P.prec32 ? (n_tiles <= 1 ? 2 : (n_tiles <= 4 ? 3 : 4)) : (n_tiles <= 1 ? 0 : (n_tiles <= 4 ? 1 : 4));
-  hipLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS, 0, 0);
+  if (P.select_k > 1)
+    hipLaunchKernelGGL(k_select_k<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS, 0);
+  else
+    hipLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS, 0, 0);
   HIPCHK(hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream));
   HIPCHK(hipStreamSynchronize(M.stream));
   U.sweeps = U.hs.sweeps;
@@ -2301,7 +2625,7 @@ ibb_status autotune_bound(Run& U, int n_tiles, int& best) {
     for (int v = 0; v < kNumBoundShapes && st == IBB_OK; ++v) {
       if (P.prec32 && kBoundShapes[v].conc) continue;
       if (kBoundShapes[v].w > 1 && kBoundShapes[v].w > n_tiles) continue;   // idle waves
-      launch_bound<FAM>(v, P.nch, M.stream, nullptr, nullptr, U.dP, U.dS);
+      launch_bound<FAM>(v, P.select_k * P.nch, M.stream, nullptr, nullptr, U.dP, U.dS);
       if (first) {
         if (hipMemcpyAsync(&after, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
             hipStreamSynchronize(M.stream) != hipSuccess) { st = fail(IBB_E_DEVICE, "autotune copy failed"); break; }
@@ -2310,7 +2634,7 @@ ibb_status autotune_bound(Run& U, int n_tiles, int& best) {
       float tot = 0.0f;
       for (int r = 0; r < 3; ++r) {
         float ms = 0.0f;
-        launch_bound<FAM>(v, P.nch, M.stream, ev[0], ev[1], U.dP, U.dS);
+        launch_bound<FAM>(v, P.select_k * P.nch, M.stream, ev[0], ev[1], U.dP, U.dS);
         if (hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess) {
           st = fail(IBB_E_DEVICE, "autotune timing failed");
           break;
@@ -2346,7 +2670,8 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
   for (;;) {
     // incremental bounds on a list one workgroup scans quickly: a whole chunk of
     // sweeps in one launch, as many as keep the list's growth within a bound
-    const bool persist = P.incremental && U.n_keys <= kPersistentMaxKeys;
+    const bool multi = P.select_k > 1;   // K boxes per sweep: a selection kernel and a bound kernel per sweep
+    const bool persist = !multi && P.incremental && U.n_keys <= kPersistentMaxKeys;
     int chunk = persist ? (int)std::min<int64_t>(std::max<int64_t>(kPersistentGrowth / P.nch, 16), 256) : grow_chunk;
     if (U.opts.time_limit_s > 0.0) chunk = std::min(chunk, grow_chunk);   // the limit is checked between launches
     if ((st = run_capacity(U, chunk)) != IBB_OK) return st;
@@ -2366,7 +2691,17 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
                               prof ? ev[0] : nullptr, prof ? ev[3] : nullptr, 0, U.dP, U.dS, chunk);
         return;
       }
-      for (int s = 0; s < chunk; ++s) {
+      for (int s = 0; s < chunk && multi; ++s) {
+        hipExtLaunchKernelGGL(k_select_k<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
+                              prof ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP, U.dS, 0);
+        if (P.incremental)
+          hipExtLaunchKernelGGL((k_ib_parents<kSweepThreads, FAM>), dim3(P.select_k), dim3(kSweepThreads), 0, M.stream,
+                                prof ? ev[4 * s + 1] : nullptr, prof ? ev[4 * s + 2] : nullptr, 0, U.dP, U.dS);
+        else
+          launch_bound<FAM>(bound_shape, P.select_k * P.nch, M.stream, prof ? ev[4 * s + 1] : nullptr,
+                            prof ? ev[4 * s + 2] : nullptr, U.dP, U.dS);
+      }
+      for (int s = 0; s < chunk && !multi; ++s) {
         if (sb > 1)
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
                                 nullptr, 0, U.dP, U.dS);
@@ -2402,7 +2737,7 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
           if (hipEventElapsedTime(&ms, ev[4 * s + 0], ev[4 * s + 3]) == hipSuccess) R->info.t_select_ms += ms;
           R->info.n_select_launches++;
         }
-        if (s < ran && !P.incremental) {
+        if (s < ran && (!P.incremental || multi)) {
           if (hipEventElapsedTime(&ms, ev[4 * s + 1], ev[4 * s + 2]) == hipSuccess) R->info.t_bound_ms += ms;
           R->info.n_bound_launches++;
         }
@@ -2412,10 +2747,14 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
     const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - U.t0).count();
     if (U.opts.time_limit_s > 0.0 && el > U.opts.time_limit_s) {
       // insert the last sweep's children, then stop
-      const int sbf = sel_blocks_for(U.hs.n_keys);
-      if (sbf > 1) hipLaunchKernelGGL(k_select_part, dim3(sbf), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
-      hipLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS,
-                         sbf > 1 ? sbf : 0, 1);
+      if (multi) {
+        hipLaunchKernelGGL(k_select_k<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS, 1);
+      } else {
+        const int sbf = sel_blocks_for(U.hs.n_keys);
+        if (sbf > 1) hipLaunchKernelGGL(k_select_part, dim3(sbf), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+        hipLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS,
+                           sbf > 1 ? sbf : 0, 1);
+      }
       if (hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
           hipStreamSynchronize(M.stream) != hipSuccess)
         return (fail(IBB_E_DEVICE, "final insert failed"));
@@ -2502,8 +2841,8 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
       return bail(fail(IBB_E_INVALID, "forced bound shape not available for this precision"));
   }
   const int n_tiles = (n + kWave - 1) / kWave;
-  const uint64_t tune_key = ((uint64_t)P.family << 40) | ((uint64_t)std::min(n_tiles, 1 << 20) << 8) |
-                            ((uint64_t)P.m << 1) | (uint64_t)(P.prec32 != 0);
+  const uint64_t tune_key = ((uint64_t)P.family << 52) | ((uint64_t)std::min(P.select_k, 1 << 11) << 40) |
+                            ((uint64_t)std::min(n_tiles, 1 << 20) << 8) | ((uint64_t)P.m << 1) | (uint64_t)(P.prec32 != 0);
   if (P.incremental) bound_variant = -1;
   else if (bound_variant < 0) bound_variant = tuned_shape(tune_key);
   if (!P.incremental && bound_variant < 0) {

@@ -64,6 +64,15 @@ enum StopCode { RUNNING = 0, STOP_CONVERGED = 1, STOP_SWEEPS = 2, STOP_LIVE = 3,
 __device__ __forceinline__ double lo_or_ninf(double v) { return v == v ? v : -__builtin_inf(); }
 __device__ __forceinline__ double hi_or_inf(double v) { return v == v ? v + 0.0 : __builtin_inf(); }
 
+// one box selected in a sweep that takes K > 1 boxes: its insertion number, the
+// row its real endpoints were written to, its cycling index and split mask
+struct SelRec {
+  int64_t seq;
+  int32_t row, cyc;
+  uint32_t mask, pad;
+};
+constexpr int kMaxSelectK = 1024;         // K <= 1024 boxes per sweep
+
 struct Params {
   int32_t family, n, m, nch;              // nch = 2^m children per selected box
   double tol_f, tol_x;
@@ -107,6 +116,10 @@ struct Params {
   int64_t* tr_nlive;
   int64_t* tr_sel;
   int64_t trace_cap;
+  // K boxes per sweep (K > 1: the selected boxes are listed in sel_tab by rank,
+  // box p of sweep t has row 1 + t K + p, its children are records p nch + c)
+  int32_t select_k, pad_k;
+  SelRec* sel_tab;                        // [select_k]
 };
 
 struct State {
@@ -126,6 +139,7 @@ struct State {
   double gub_start;
   int32_t use32, p32_fails;
   int64_t p32_resume, fp32_pruned, fp32_sweeps;
+  int32_t sel_count, pad_sel;             // K > 1: boxes selected by the last selection
 };
 
 // bisection point: 0.5 lo + 0.5 hi rounded up, kept inside [lo, hi]

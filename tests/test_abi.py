@@ -59,6 +59,9 @@ def _solve_rc(**kw):
     (dict(tol_f=0.0), "tol_f"),
     (dict(coef=np.concatenate([np.ones(3), np.ones(3), [1.5, 1, 1], np.zeros(3)])), "positive integer"),
     (dict(split_dims=17), "split_dims"),
+    (dict(select_k=0), "select_k"),
+    (dict(select_k=1025), "select_k"),
+    (dict(select_k=1024, split_dims=15), "2^24"),
 ])
 def test_validation_rejects_before_touching_the_device(kw, msg):
     rc, err = _solve_rc(**kw)
@@ -97,3 +100,17 @@ def test_bad_kernel_arguments_rejected_before_the_device(call, msg):
     L = ibb.lib()
     rc = call(L, _problem_struct())
     assert rc == -1 and msg in L.ibb_last_error().decode()
+
+
+def test_batch_and_server_take_one_box_per_sweep():
+    # K > 1 boxes per sweep runs in ibb_solve / ibb_sweep; the batched engine and
+    # the server refuse it before any device work
+    k = _problem_struct()
+    o = ibb._Options()
+    L = ibb.lib()
+    L.ibb_options_default(C.byref(o))
+    o.select_k = 4
+    outs = (C.c_void_p * 1)()
+    sts = (C.c_int32 * 1)()
+    rc = L.ibb_solve_batch(C.byref(k.s), 1, C.byref(o), None, None, outs, sts)
+    assert rc == -1 and "select_k" in L.ibb_last_error().decode()
