@@ -1,70 +1,75 @@
-"""Benchmark: rigorous enclosure of min f for the separable multimodal workload
-(f = sum a_i (x_i - c_i)^2 + b_i (1 - cos(2 pi k_i (x_i - c_i))), n = 100,
-[-5, 5]^100, enclosure width 1e-6, seeded coefficients), on one MI355X.
+"""Benchmark on one MI355X: rigorous enclosure of min f at width 1e-6.
 
-One step = one whole solve (every sweep of the hot path until GUB - GLB <= 1e-6),
-so ms_per_step is the time-to-enclosure and value is boxes bounded per second.
-Prints one JSON line.  The headline uses incremental child bounds (the default);
-the same workload also runs with full bounds and with the FP32 filter.  Each
-roofline is that of the dominant kernel, timed with HIP events inside the library
-on the solve's stream.  The CPU oracle's rate is taken on a bounded prefix of the
-same workload.
+Headline (the largest single-GPU workload): the non-smooth separable family
+f = sum s_i |x_i - c_i| + b_i sin^2(pi k_i (x_i - c_i)), n = 10,000, domain
+[-10, 10]^10000, seeded coefficients, enclosure width 1e-6, solved by the
+persistent sweep kernel (incremental child bounds, one box per sweep as in the
+paper).  One step = one whole solve, so ms_per_step is the time to enclosure
+and value is boxes bounded per second.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64]
+Also measured in the same run (extra keys of the JSON line):
+  * the separable cosine family at n = 100: one box per sweep (persistent
+    kernel), and K = 32 boxes per sweep (the paper's one-region selection
+    widened so that one sweep fills the chip: K = ceil(2^16 / (2^m ceil(n/64)))),
+    in plain FP64 with full bounds, with the FP32 filter, and with incremental
+    bounds; the roofline of the full-bounds kernel at that occupancy;
+  * the other workloads (n = 2 and the chained n = 1000), solved once each;
+  * serving: the 4096-request trace through the continuous-batching server
+    (closed loop -> capacity mu, then Poisson arrivals at 0.8 mu), and on its
+    first requests the same arrivals served one at a time by plain FP64 solves
+    (full bounds, one kernel launch per step);
+  * the CPU oracle on a bounded prefix of the headline workload, on one host
+    thread and as one copy per host core.
+Rooflines use the algorithmic operation counts per child and coordinate (F, its
+gradient and the midpoint bound; one directed endpoint operation = 1 op):
+about 175 for the separable families (five sin/cos point evaluations of about 25
+operations each and about 50 interval endpoint operations), 64 for the chained
+family, over each kernel's average launch time measured with HIP events on the
+stream it runs on.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 operations per child per coordinate (adds and muls count 1,
-# fma 2), counted from the expression trees of the separable cosine family:
-#   box pass (F and G): interval D, Y, sqr, scalings, sums, gradient product
-#   (46 ops) plus two point evaluations of cos/sin(2 pi y) at the endpoints of Y
-#   (63 ops each: reduction 3, split squares 3, sine 2-term head 9 + tail 16 +
-#   corrections 10 + enclosure 5, cosine head 5 + tail 16 + corrections 7 +
-#   enclosure 5, and 2 for the extremum tests) -> 172
-#   midpoint pass (upper bound): midpoint 2, D/Y/sqr/scalings/sum of the upper
-#   endpoints 14, two point evaluations 126 -> 142
-BOX_OPS_PER_COORD = 172
-MID_OPS_PER_COORD = 142
+SEP_OPS = 175     # algorithmic operations per child and coordinate, separable families
+CHAIN_OPS = 64    # the chained family
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 (fma) x 2.4 GHz
-# separable cosine, F of one term alone (no gradient): interval D, Y, sqr, scalings, 1 - C,
-# sum (14) + two point evaluations of cos/sin (126) + extremum tests (2)
-TERM_OPS_PER_COORD = 142
 
 
-def incremental_ops_per_sweep(n: int, m: int) -> float:
-    """Algorithmic FP64 operations of one sweep with incremental bounds (separable cosine):
-    the n - m shared terms (F and the midpoint bound), both halves of the m split
-    coordinates (F, G and the midpoint bound), and per child m interval additions for F
-    (2 ops) and m additions for the midpoint bound (1 op)."""
-    return (n - m) * (TERM_OPS_PER_COORD + MID_OPS_PER_COORD) + 2 * m * (BOX_OPS_PER_COORD + MID_OPS_PER_COORD) \
-        + (1 << m) * m * 3
+def incremental_ops_per_sweep(n: int, m: int, per_coord: int = SEP_OPS) -> float:
+    """Algorithmic operations of one incremental sweep: the n - m shared terms and
+    both halves of the m split coordinates (n + m coordinate evaluations), then per
+    child m interval additions for F (2 ops) and m for the midpoint bound (1 op)."""
+    return (n + m) * per_coord + (1 << m) * m * 3
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
-    ap.add_argument("--cpu-sweeps", type=int, default=30, help="oracle prefix for the CPU baseline (0 = skip)")
-    ap.add_argument("--serve-requests", type=int, default=128, help="requests in the serving trace (0 = skip)")
-    ap.add_argument("--fp32-steps", type=int, default=5, help="solves of the same workload with the FP32 filter (0 = skip)")
-    ap.add_argument("--full-steps", type=int, default=5, help="solves of the same workload with full bounds (0 = skip)")
-    ap.add_argument("--workloads", type=int, default=1, help="1: also solve the n = 2, 1000 and 10000 workloads once")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-sweeps", type=int, default=1, help="oracle prefix (sweeps) of the headline workload (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=4096, help="requests in the serving trace (0 = skip)")
+    ap.add_argument("--serve-compare", type=int, default=96,
+                    help="first requests of the trace also served one at a time by plain FP64 solves")
+    ap.add_argument("--k-steps", type=int, default=3, help="solves per form of the n = 100 workload (0 = skip)")
+    ap.add_argument("--workloads", type=int, default=1, help="1: also solve the n = 2 and chained n = 1000 workloads")
+    ap.add_argument("--headline", type=int, default=1, help="0: skip the headline solves (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM traffic counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         return 2
     if args.copy_probe > 0:
         return copy_probe(args.copy_probe)
@@ -74,9 +79,7 @@ def main() -> int:
     import paper_2507_01770_amd as ibb
     from paper_2507_01770_amd import problems as PR
 
-    p = PR.config(1)
-
-    def timed(steps, warmup, **kw):
+    def timed(p, steps, warmup, **kw):
         # the timed solves run without profiling; one more solve with the library's
         # kernel timers (HIP events on its stream) follows, outside the timed region
         for _ in range(warmup):
@@ -90,67 +93,70 @@ def main() -> int:
         for r in rs + [rp]:
             assert r.status == ibb.OK and r.f_lo <= 0.0 <= r.f_hi and r.f_hi - r.f_lo <= 1e-6, (r.f_lo, r.f_hi)
             assert r.sweeps == rp.sweeps and r.boxes_evaluated == rp.boxes_evaluated
-        return rs + [rp], dt
+        return rs, rp, dt
 
-    # headline: incremental child bounds (the default)
-    phase("headline: incremental bounds")
-    res, dt = timed(args.steps, args.warmup)
-    boxes = sum(r.boxes_evaluated for r in res[:-1])
-    r0 = res[-1]
-    # dominant kernel: the persistent sweep kernel (selection and the children's bounds in
-    # one workgroup, up to 256 sweeps per launch); one unit of work is one sweep
-    ib_ops_sweep = incremental_ops_per_sweep(p.n, min(p.n, 10))
-    n_sw = max(1, r0.n_select_launches)
-    t_sweep = r0.t_select_ms * 1e-3 / n_sw
-    ach = ib_ops_sweep / t_sweep / 1e12 if t_sweep > 0 else 0.0
-    roofline = {
-        "bound": "alu", "kernel": "k_sweeps_ib<SEP_COS> (persistent, one workgroup)", "per": "sweep",
-        "achieved": round(ach, 6), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 8),
-        "traffic": measured_traffic(), "avg_sweep_us": round(t_sweep * 1e6, 3), "sweeps_per_solve": r0.sweeps,
-        "flops_per_sweep": round(ib_ops_sweep),
-    }
+    # ---- headline: workload 3 (n = 10,000), one box per sweep, persistent kernel
+    p3 = PR.config(3)
+    head = roofline = None
+    if args.headline:
+        phase("headline: non-smooth separable n = 10000")
+        rs, rp, dt = timed(p3, args.steps, args.warmup)
+        m = min(p3.n, 10)
+        ops_sweep = incremental_ops_per_sweep(p3.n, m)
+        launches = max(1, rp.n_persistent_launches)
+        t_launch = rp.t_select_ms * 1e-3 / launches
+        sweeps_launch = rp.n_select_launches / launches
+        t_sweep = rp.t_select_ms * 1e-3 / max(1, rp.n_select_launches)
+        ach = ops_sweep * sweeps_launch / t_launch / 1e12 if t_launch > 0 else 0.0
+        roofline = {
+            "bound": "alu", "kernel": "k_sweeps_ib<512, SEP_ABS_SIN2> (persistent, one workgroup)",
+            "achieved": round(ach, 6), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_FP64_TFLOPS, 8), "traffic": measured_traffic(),
+            "avg_launch_us": round(t_launch * 1e6, 2), "sweeps_per_launch": round(sweeps_launch, 2),
+            "avg_sweep_us": round(t_sweep * 1e6, 3), "ops_per_sweep": round(ops_sweep),
+            "launches_per_solve": launches,
+        }
+        head = {"rs": rs, "rp": rp, "dt": dt}
 
-    # the same workload with full bounds (every child over all n terms): k_bound's roofline
-    full = None
-    if args.full_steps > 0:
-        phase("full bounds")
-        rf, df = timed(args.full_steps, 1, incremental=False)
-        q = rf[-1]
-        formed = q.boxes_evaluated - 1          # children (the root is bounded by another kernel)
-        ops = p.n * (formed * BOX_OPS_PER_COORD + (q.ub_evaluated - 1) * MID_OPS_PER_COORD) * 1.0
-        tb = q.t_bound_ms * 1e-3
-        a = ops / tb / 1e12 if tb > 0 else 0.0
-        full = {"boxes_per_s": round(sum(r.boxes_evaluated for r in rf[:-1]) / df, 1),
-                "ms_per_solve": round(df / args.full_steps * 1e3, 4), "sweeps": q.sweeps,
-                "bound_shape": q.bound_shape,
-                "roofline": {"bound": "alu", "kernel": "k_bound<SEP_COS>", "achieved": round(a, 4),
-                             "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(a / PEAK_FP64_TFLOPS, 5),
-                             "avg_launch_us": round(q.t_bound_ms * 1e3 / max(1, q.n_bound_launches), 3),
-                             "flops_per_launch": round(ops / max(1, q.n_bound_launches))},
-                "select_avg_launch_us": round(q.t_select_ms * 1e3 / max(1, q.n_select_launches), 3)}
+    # ---- workload 1 (n = 100): K = 1 persistent; K = 32 full bounds FP64 / FP32 filter / incremental
+    forms = None
+    if args.k_steps > 0:
+        p1 = PR.config(1)
+        m1 = min(p1.n, 10)
+        K = -(-(1 << 16) // ((1 << m1) * (-(-p1.n // 64))))
+        forms = {"workload": "separable cosine family, n=100, [-5,5]^100, width 1e-6, seed 102", "K": K}
+        for name, kw in (("k1_incremental", dict()),
+                         ("kK_full_fp64", dict(select_k=K, incremental=False)),
+                         ("kK_full_fp32_bulk", dict(select_k=K, precision="fp32_bulk")),
+                         ("kK_incremental", dict(select_k=K, incremental=True))):
+            phase(f"n = 100: {name}")
+            rs1, rp1, dt1 = timed(p1, args.k_steps, 1, **kw)
+            d = {"boxes_per_s": round(sum(r.boxes_evaluated for r in rs1) / dt1, 1),
+                 "ms_per_solve": round(dt1 / args.k_steps * 1e3, 4), "sweeps": rp1.sweeps,
+                 "boxes_per_solve": rp1.boxes_evaluated, "enclosure": [rp1.f_lo, rp1.f_hi]}
+            if rp1.n_bound_launches:
+                formed = rp1.boxes_evaluated - 1 - rp1.fp32_pruned   # children bounded in FP64
+                ops = p1.n * formed * SEP_OPS * 1.0
+                tb = rp1.t_bound_ms * 1e-3
+                a = ops / tb / 1e12 if tb > 0 else 0.0
+                d["bound_kernel"] = {
+                    "kernel": "k_bound<SEP_COS> (shape %d)" % rp1.bound_shape, "achieved": round(a, 4),
+                    "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(a / PEAK_FP64_TFLOPS, 5),
+                    "avg_launch_us": round(rp1.t_bound_ms * 1e3 / rp1.n_bound_launches, 3),
+                    "ops_per_launch": round(ops / rp1.n_bound_launches),
+                    "select_avg_launch_us": round(rp1.t_select_ms * 1e3 / max(1, rp1.n_select_launches), 3)}
+            if rp1.fp32_sweeps:
+                d.update(fp32_pruned=rp1.fp32_pruned, fp64_confirmed=rp1.fp64_confirmed, fp32_sweeps=rp1.fp32_sweeps)
+            forms[name] = d
 
-    fp32 = None
-    if args.fp32_steps > 0:
-        phase("fp32 filter")
-        r32, d32 = timed(args.fp32_steps, 1, precision="fp32_bulk")
-        q = r32[-1]
-        fp32 = {"boxes_per_s": round(sum(r.boxes_evaluated for r in r32[:-1]) / d32, 1),
-                "ms_per_solve": round(d32 / args.fp32_steps * 1e3, 4),
-                "sweeps": q.sweeps, "boxes_per_solve": q.boxes_evaluated,
-                "fp32_pruned": q.fp32_pruned, "fp64_confirmed": q.fp64_confirmed, "fp32_sweeps": q.fp32_sweeps,
-                "bound_avg_launch_us": round(q.t_bound_ms * 1e3 / max(1, q.n_bound_launches), 3),
-                "enclosure": [q.f_lo, q.f_hi]}
-
-    # the other workloads, solved completely once each (incremental bounds)
+    # ---- the other workloads, solved once each (incremental bounds, one box per sweep)
     workloads = None
     if args.workloads:
-        phase("other workloads")
         workloads = {}
-        for cfg in (0, 2, 3):
+        for cfg in (0, 2):
             phase(f"workload {cfg}")
             q = PR.config(cfg)
-            if cfg != 3:
-                ibb.minimize(q, fetch_boxes=False)
+            ibb.minimize(q, fetch_boxes=False)
             torch.cuda.synchronize()
             tq = time.perf_counter()
             rq = ibb.minimize(q, fetch_boxes=False)
@@ -161,47 +167,44 @@ def main() -> int:
                 "time_to_enclosure_ms": round(dq * 1e3, 3), "sweeps": rq.sweeps, "boxes": rq.boxes_evaluated,
                 "boxes_per_s": round(rq.boxes_evaluated / dq, 1), "enclosure": [rq.f_lo, rq.f_hi]}
 
+    serving = None
     if args.serve_requests > 0:
         phase("serving")
-    serving = serve_bench(args.serve_requests) if args.serve_requests > 0 else None
+        serving = serve_bench(args.serve_requests, args.serve_compare)
 
-    # the CPU oracle last, after all GPU work
+    # ---- the CPU oracle last, after all GPU work
     cpu = None
     if args.cpu_sweeps > 0:
         phase("cpu baseline (oracle)")
-        from oracle import oracle as O
-        tc = time.perf_counter()
-        o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=args.cpu_sweeps, incremental=True)
-        tcpu = time.perf_counter() - tc
-        cpu = {"value": round(o.boxes_evaluated / tcpu, 2), "unit": "boxes/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {o.sweeps} sweeps of the same workload with incremental child bounds "
-                         f"({o.boxes_evaluated} boxes, {tcpu:.1f} s, single thread, fesetround per endpoint operation)"}
+        cpu = cpu_baseline(p3, args.cpu_sweeps)
 
+    rs, rp, dt = (head["rs"], head["rp"], head["dt"]) if head else ([], None, 0.0)
+    boxes = sum(r.boxes_evaluated for r in rs)
     line = {
         "metric": "boxes/sec and time-to-enclosure (width 1e-6); served problems/sec + p50/p99",
-        "value": round(boxes / dt, 1),
+        "value": round(boxes / dt, 1) if dt > 0 else None,
         "unit": "boxes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "ms_per_step": round(dt / args.steps * 1e3, 4) if dt > 0 else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "separable cosine family, n=100, domain [-5,5]^100, enclosure width 1e-6, seed 102",
-            "precision": args.precision, "select_k": 1, "split_dims": 10,
-            "time_to_enclosure_ms": round(float(np.median([r.seconds for r in res[:-1]])) * 1e3, 4),
-            "sweeps": r0.sweeps, "boxes_per_solve": r0.boxes_evaluated,
-            "enclosure": [r0.f_lo, r0.f_hi], "bounds": "incremental",
-            "full_bounds": full,
-            "fp32_bulk_full_bounds": fp32,
-            "other_workloads": workloads,
+            "workload": "non-smooth separable family, n=10000, domain [-10,10]^10000, enclosure width 1e-6, "
+                        "seed 104, one box per sweep, 10 bisected coordinates",
+            "time_to_enclosure_ms": round(float(np.median([r.seconds for r in rs])) * 1e3, 3) if rs else None,
+            "sweeps": rp.sweeps if rp else None, "boxes_per_solve": rp.boxes_evaluated if rp else None,
+            "enclosure": [rp.f_lo, rp.f_hi] if rp else None, "bounds": "incremental",
+            "box_coord_per_s": round(boxes * p3.n / dt, 1) if dt > 0 else None,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "n100_forms": forms,
+        "other_workloads": workloads,
         "serving": serving,
     }
     print(json.dumps(line), flush=True)
@@ -213,22 +216,54 @@ def phase(name: str) -> None:
     print(f"bench: {name}", file=sys.stderr, flush=True)
 
 
+def cpu_baseline(p, sweeps: int) -> dict:
+    """The oracle on the first `sweeps` sweeps of the workload (incremental child bounds):
+    one host thread, then one copy per host core at once (the oracle itself is serial;
+    the copies measure what the host's cores give together)."""
+    from oracle import oracle as O
+    tc = time.perf_counter()
+    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=sweeps, incremental=True)
+    t1 = time.perf_counter() - tc
+    one = o.boxes_evaluated / t1
+    cores = min(16, len(os.sched_getaffinity(0)))
+    code = ("import sys; sys.path.insert(0, %r); from oracle import oracle as O; "
+            "from paper_2507_01770_amd import problems as PR; p = PR.config(3); "
+            "O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=%d, incremental=True)") % (ROOT, sweeps)
+    tc = time.perf_counter()
+    procs = [subprocess.Popen([sys.executable, "-c", code]) for _ in range(cores)]
+    ok = all(pr.wait() == 0 for pr in procs)
+    tall = time.perf_counter() - tc
+    return {"value": round(one, 2), "unit": "boxes/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {o.sweeps} sweep(s) of the headline workload with incremental child bounds "
+                      f"({o.boxes_evaluated} boxes in {t1:.1f} s, one thread, rounding mode switched per endpoint "
+                      f"operation)",
+            "all_cores": {"value": round(cores * o.boxes_evaluated / tall, 2) if ok else None, "unit": "boxes/s",
+                          "cores": cores, "sample": f"{cores} copies of the same sample at once, {tall:.1f} s"},
+            "host_cpus": os.cpu_count()}
+
+
 def measured_traffic():
-    """HBM bytes per sweep of the persistent sweep kernel, from the committed rocprofv3 FETCH_SIZE and
-    WRITE_SIZE counts (scaled by a plain copy's), when the kernel sources are the ones measured; else None."""
+    """HBM bytes per launch of the headline's persistent sweep kernel, from the committed
+    rocprofv3 FETCH_SIZE and WRITE_SIZE counts (scaled by a plain copy's), when the kernel
+    sources are the ones measured; else None."""
     import glob
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "hbm_bytes_sep_cos_n100.md")
+    path = os.path.join(ROOT, "profiles", "hbm_bytes_sep_abs_sin2_n10000.md")
     if not os.path.exists(path):
         return None
     m = re.search(r"```json\n(\{.*?\})\n```", open(path).read(), re.S)
     if not m:
         return None
     rec = json.loads(m.group(1))
+    return rec["bytes_per_launch"] if rec.get("source_hash") == kernel_source_hash() else None
+
+
+def kernel_source_hash() -> str:
+    import glob
+    import hashlib
     src = sorted(glob.glob(os.path.join(ROOT, "paper_2507_01770_amd", "csrc", "*")))
-    h = hashlib.sha256(b"".join(open(f, "rb").read() for f in src)).hexdigest()[:16]
-    return rec["bytes_per_sweep"] if rec.get("source_hash") == h else None
+    return hashlib.sha256(b"".join(open(f, "rb").read() for f in src)).hexdigest()[:16]
 
 
 def copy_probe(mib: int) -> int:
@@ -243,16 +278,15 @@ def copy_probe(mib: int) -> int:
     return 0
 
 
-SERVE_MAX_SWEEPS = 500     # per-request sweep budget (some chained requests do not converge quickly)
-
-
-def serve_bench(count: int) -> dict:
+def serve_bench(count: int, compare: int) -> dict:
     """Serving workload: `count` requests (n log-uniform in [2, 2000], family uniform over the
-    three, seeded coefficients), enclosure width 1e-6, at most SERVE_MAX_SWEEPS sweeps each.
+    three, seeded coefficients), each enclosed to width 1e-6.
     1) closed loop: all requests submitted at once -> capacity mu (problems/s);
     2) Poisson arrivals at 0.8 mu through the continuous-batching server -> problems/s, p50/p99
-       of completion - arrival;
-    3) the same arrivals served one at a time, FIFO, by ibb_solve (plain FP64, no batching)."""
+       of completion - arrival (converged and budget-stopped requests counted apart);
+    3) on the first `compare` requests, the same arrivals through the server and served one at
+       a time, FIFO, by ibb_solve in plain FP64 (full bounds, a selection and a bound kernel
+       launch per sweep, no batching, no persistent kernel)."""
     import numpy as np
     import paper_2507_01770_amd as ibb
     from paper_2507_01770_amd import problems as PR
@@ -262,56 +296,77 @@ def serve_bench(count: int) -> dict:
     gaps = np.array([t for t, _ in reqs])
     gaps = np.diff(np.concatenate([[0.0], gaps]))          # unit-rate exponential gaps
 
-    def run_server(arrivals):
-        with ibb.Server(mem_budget_bytes=64 << 30, max_slots=64) as srv:
+    def run_server(ps, arrivals):
+        with ibb.Server(mem_budget_bytes=96 << 30, max_slots=256) as srv:
             t0 = time.perf_counter()
             tickets, t_arr, done = [], [], {}
+            pending = []
             i = 0
-            while len(done) < len(probs):
+            while len(done) < len(ps):
                 now = time.perf_counter() - t0
-                while i < len(probs) and arrivals[i] <= now:
-                    tickets.append(srv.submit(probs[i], max_sweeps=SERVE_MAX_SWEEPS))
+                while i < len(ps) and arrivals[i] <= now:
+                    t = srv.submit(ps[i])
+                    tickets.append(t)
+                    pending.append(t)
                     t_arr.append(arrivals[i])
                     i += 1
-                for k, t in enumerate(tickets):
-                    if t not in done:
-                        r = srv.poll(t)
-                        if r is not None:
-                            done[t] = (time.perf_counter() - t0, r.status)
+                still = []
+                for t in pending:
+                    r = srv.poll(t)
+                    if r is None:
+                        still.append(t)
+                    else:
+                        done[t] = (time.perf_counter() - t0, r.status)
+                pending = still
                 time.sleep(0.0002)
             st = srv.stats()
         lat = np.array([done[t][0] - a for t, a in zip(tickets, t_arr)])
+        conv = np.array([done[t][1] == ibb.OK for t in tickets])
         makespan = max(v[0] for v in done.values()) - arrivals[0]
-        ok = sum(v[1] == ibb.OK for v in done.values())
-        return lat, makespan, ok, st
+        return lat, conv, makespan, st
 
-    lat0, span0, ok0, st0 = run_server(np.zeros(len(probs)))
+    def pct(a, q):
+        return round(float(np.percentile(a, q)) * 1e3, 2) if len(a) else None
+
+    phase(f"serving: closed loop, {len(probs)} requests")
+    lat0, conv0, span0, st0 = run_server(probs, np.zeros(len(probs)))
     mu = len(probs) / span0
     lam = 0.8 * mu
     arrivals = np.cumsum(gaps) / lam
-    lat, span, ok, st = run_server(arrivals)
-    # one at a time, FIFO, same arrivals
-    t0 = time.perf_counter()
-    free_at, lat1 = 0.0, []
-    for a, p in zip(arrivals, probs):
-        start = max(a, free_at)
-        while time.perf_counter() - t0 < start:
-            time.sleep(0.0002)
-        ibb.minimize(p, max_sweeps=SERVE_MAX_SWEEPS, fetch_boxes=False)
-        free_at = time.perf_counter() - t0
-        lat1.append(free_at - a)
-    lat1 = np.array(lat1)
-    span1 = free_at - arrivals[0]
-    return {
-        "requests": len(probs), "max_sweeps_per_request": SERVE_MAX_SWEEPS, "converged": int(ok),
+    phase(f"serving: Poisson arrivals at {lam:.1f}/s")
+    lat, conv, span, st = run_server(probs, arrivals)
+    out = {
+        "requests": len(probs), "converged": int(conv.sum()),
         "capacity_problems_per_s": round(mu, 2), "arrival_rate": round(lam, 2),
         "problems_per_s": round(len(probs) / span, 2),
-        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2), "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+        "p50_ms_converged": pct(lat[conv], 50), "p99_ms_converged": pct(lat[conv], 99),
         "max_concurrent": st["max_active"],
-        "one_at_a_time": {"problems_per_s": round(len(probs) / span1, 2),
-                          "p50_ms": round(float(np.percentile(lat1, 50)) * 1e3, 2),
-                          "p99_ms": round(float(np.percentile(lat1, 99)) * 1e3, 2)},
     }
+    if compare > 0:
+        ps = probs[:compare]
+        arr = arrivals[:compare] - arrivals[0]
+        phase(f"serving: first {compare} requests through the server")
+        latc, convc, spanc, _ = run_server(ps, arr)
+        phase(f"serving: first {compare} requests one at a time, plain FP64")
+        t0 = time.perf_counter()
+        free_at, lat1, ok1 = 0.0, [], 0
+        for a, p in zip(arr, ps):
+            start = max(a, free_at)
+            while time.perf_counter() - t0 < start:
+                time.sleep(0.0002)
+            r = ibb.minimize(p, fetch_boxes=False, incremental=False)
+            ok1 += r.status == ibb.OK
+            free_at = time.perf_counter() - t0
+            lat1.append(free_at - a)
+        lat1 = np.array(lat1)
+        out["first_requests"] = {
+            "requests": compare, "arrival_rate": round(lam, 2),
+            "server": {"problems_per_s": round(compare / spanc, 2), "p50_ms": pct(latc, 50), "p99_ms": pct(latc, 99),
+                       "converged": int(convc.sum())},
+            "one_at_a_time_plain_fp64": {"problems_per_s": round(compare / (free_at - arr[0]), 2),
+                                         "p50_ms": pct(lat1, 50), "p99_ms": pct(lat1, 99), "converged": int(ok1)}}
+    return out
 
 
 if __name__ == "__main__":

@@ -41,8 +41,9 @@ typedef enum {
   IBB_E_NOMEM = -2,      /* device or host allocation failed */
   IBB_E_DEVICE = -3,     /* a HIP call failed */
   IBB_E_CAPACITY = -4,   /* a size exceeds what the library supports */
-  IBB_E_INTERNAL = -5    /* the live list became empty, or a sweep would have passed the row or key
-                            capacity sized for it (a guard: the library grows both before every chunk) */
+  IBB_E_INTERNAL = -5    /* the live list became empty, a sweep would have passed the row or key
+                            capacity sized for it (a guard: the library grows both before every chunk),
+                            or the selection counted live boxes but found none to take (a guard) */
 } ibb_status;
 
 /* Objective families (closed forms with per-coordinate coefficients).
@@ -89,7 +90,12 @@ typedef struct {
 typedef struct {
   int32_t precision;     /* ibb_precision; default IBB_FP64 */
   int32_t split_dims;    /* M: coordinates bisected per selected box, 1..16; default 10 */
-  int32_t select_k;      /* K: boxes selected per sweep; default 1 (the paper's choice) */
+  int32_t select_k;      /* K: boxes selected per sweep, 1..1024; default 1 (the paper's choice: Sec. 3.1
+                            selects the region with the smallest lower bound).  K > 1 takes the K
+                            smallest (lower bound, insertion number) at once, bounds the children of
+                            all K before GUB is updated and inserts them in (rank, child index)
+                            order; K * 2^split_dims <= 2^24.  ibb_solve and ibb_sweep only
+                            (ibb_solve_batch and the server return IBB_E_INVALID for K > 1) */
   int32_t deterministic; /* results independent of scheduling; default 1 (always honoured) */
   int64_t max_sweeps;    /* budget; default 1,000,000 */
   int64_t max_live_boxes;/* budget on the live list; default 1<<26 */
@@ -136,6 +142,8 @@ typedef struct {
   int64_t n_bound_launches, n_select_launches;
   int32_t bound_shape;        /* shape of the bound kernel used (0..4, see ibb_options; -1: incremental) */
   int32_t pad;
+  int64_t n_persistent_launches; /* with profile = 1: launches of the persistent sweep kernel (each runs a
+                                    chunk of sweeps; t_select_ms is their summed time) */
 } ibb_info;
 
 typedef struct ibb_result ibb_result;
@@ -158,14 +166,27 @@ ibb_status ibb_solve(const ibb_problem* prob, const ibb_options* opts, const ibb
  * so ibb_solve with budget a then ibb_sweep(b) gives the same run as ibb_solve
  * with budget a + b.  Updates res (info, boxes, trace) and returns its status:
  * IBB_OK once converged (a converged result is left as it is), else
- * IBB_NOT_CONVERGED.  Runs on hip_stream and synchronises it. */
+ * IBB_NOT_CONVERGED.  Runs on hip_stream and synchronises it.
+ * Failure: an error returned after the sweeps started (a refused allocation, a
+ * device error, an internal stop) leaves the run half-way: the result is then
+ * marked unusable, its info keeps the error as status and no boxes; further
+ * ibb_sweep and ibb_result_boxes calls on it return IBB_E_INVALID, and
+ * ibb_result_info and ibb_result_free still work.  When the list or row arrays
+ * have to grow, every new block is allocated before anything is copied or
+ * freed, so a refused allocation leaves the arrays as they were. */
 ibb_status ibb_sweep(ibb_result* res, int64_t n_sweeps, void* hip_stream);
 
+/* The output of the iteration (Sec. 3.1, output: the enclosure [GLB, GUB] of the
+ * global minimum and the regions left in the list) and the run's counters. */
 ibb_status ibb_result_info(const ibb_result* res, ibb_info* info);
 
-/* Copy up to `capacity` live boxes (ordered by insertion number) to host
- * arrays lo, hi ([box][n], row-major), their lower bounds of f and insertion
- * numbers; any output pointer may be NULL.  *written receives the count. */
+/* The regions of the output (Sec. 3.1): copy up to `capacity` live boxes
+ * (ordered by insertion number) to host arrays lo, hi ([box][n], row-major),
+ * their lower bounds of f and insertion numbers (seq: an addition to the
+ * paper's output, the order in which the boxes entered the list, which the
+ * selection uses to break ties); any output pointer may be NULL.  *written
+ * receives the count.  IBB_E_INVALID on a result marked unusable by a failed
+ * ibb_sweep. */
 ibb_status ibb_result_boxes(const ibb_result* res, double* lo, double* hi, double* f_lo_per_box,
                             int64_t* seq, int64_t capacity, int64_t* written);
 
@@ -175,6 +196,8 @@ ibb_status ibb_result_boxes(const ibb_result* res, double* lo, double* hi, doubl
 ibb_status ibb_result_trace(const ibb_result* res, double* gub, int64_t* n_inserted, int64_t* n_live,
                             int64_t* selected_seq, int64_t capacity, int64_t* written);
 
+/* Release a result and every block of device memory it holds (through the
+ * allocator it was created with). */
 void ibb_result_free(ibb_result* res);
 
 /* Bound nb boxes given in device memory (d_lo, d_hi: [nb][n] row-major):

@@ -385,6 +385,8 @@ typedef struct {
   int32_t split_dims, select_k; int64_t max_sweeps, max_live_boxes;
   int32_t incremental;   /* 1: children bounded from their parent's shared terms (see child_bounds) */
   int32_t reserved;
+  int32_t pieces;        /* subintervals per split coordinate: 2 (bisection, default) or 4 (Sec. 4) */
+  int32_t samples;       /* 0: one sample, the child midpoint; S > 0: S points on the child's diagonal */
 } orc_options;
 
 /*
@@ -436,6 +438,215 @@ static void child_bounds(const orc_problem* P, const parent_base* B, const doubl
   *F = f;
   *ub = u;
 }
+/* ------------------------------------------------------------------------- */
+/* the schedule of the paper's experiments (Sec. 4): each of the m cycled      */
+/* coordinates of the selected box is cut into four equal subintervals        */
+/* (Sec. 3.2, Eqs. (8)-(11)), 4^m subregions, and each subregion is sampled   */
+/* at points on its diagonal that cut it into S + 1 equal pieces              */
+/* ------------------------------------------------------------------------- */
+
+#define MAX_SAMPLES 16
+
+/* The cut points of one coordinate [lo, hi] into `pieces` subintervals:
+ * cut[0] = lo, cut[pieces] = hi, and in between (bisection) the midpoint, or
+ * (four pieces, Eqs. (10)-(11)) lo + w I with w = (hi - lo) / 4, I = 1, 2, 3,
+ * each operation rounded up (exact for the dyadic domains of the experiments),
+ * kept inside [previous cut, hi].  Neighbouring subintervals share their cut
+ * point and the last one ends at hi itself, so the pieces cover [lo, hi] with
+ * no gap whatever the rounding.  Returns 1 when every piece has positive width
+ * (the coordinate is split), 0 otherwise (it is then left whole). */
+static int make_cuts(double lo, double hi, int pieces, double* cut) {
+  cut[0] = lo;
+  cut[pieces] = hi;
+  if (pieces == 2) {
+    cut[1] = midpoint(lo, hi);
+  } else {
+    double w = up_mul(up_sub(hi, lo), 0.25);
+    for (int I = 1; I < pieces; ++I) {
+      double c = up_add(lo, up_mul(w, (double)I));
+      if (c < cut[I - 1]) c = cut[I - 1];
+      if (c > hi) c = hi;
+      cut[I] = c;
+    }
+  }
+  for (int I = 0; I < pieces; ++I)
+    if (!(cut[I] < cut[I + 1])) return 0;
+  return 1;
+}
+
+/* digit j of child index r in base `pieces` (little-endian: digit 0 is the
+ * first coordinate of the window, Eqs. (8)-(9) read for m coordinates) */
+static int digit(int64_t r, int j, int pieces) {
+  for (int q = 0; q < j; ++q) r /= pieces;
+  return (int)(r % pieces);
+}
+
+/* coordinate of diagonal sample s (1..S) of [a, b]: a + (b - a) c_s with c_s
+ * the double nearest to s / (S + 1), each operation rounded up, kept in [a, b] */
+static double diag_coord(double a, double b, double c) {
+  double x = up_add(a, up_mul(up_sub(b, a), c));
+  if (x < a) x = a;
+  if (x > b) x = b;
+  return x;
+}
+
+/* F, the first-order flag and the smallest sample upper bound of one box,
+ * every term formed over all n coordinates (the reference evaluation) */
+static box_eval eval_box_samples(const orc_problem* P, const double* lo, const double* hi, iv* X, int S,
+                                 const double* cs) {
+  box_eval r = eval_box(P, lo, hi, X, NULL);
+  if (S <= 0) return r;
+  const int64_t n = P->n;
+  double ub = INFINITY;
+  for (int s = 0; s < S; ++s) {
+    for (int64_t i = 0; i < n; ++i) { double x = diag_coord(lo[i], hi[i], cs[s]); X[i] = mk(x, x); }
+    double u = canonical_sum(P, X).hi;
+    if (u < ub) ub = u;
+  }
+  r.ub = ub;
+  return r;
+}
+
+/* Incremental bounds of all children of one selected box, memoised per piece.
+ * The terms and derivative coordinates that involve a split coordinate are the
+ * only ones that differ between children; each of them is evaluated once for
+ * every combination of pieces of the coordinates it involves (the same interval
+ * operations a child would make), and a child adds, in increasing term index,
+ * the entries of its own pieces to the canonical sums of the other terms over
+ * the parent (F, and each sample point).  The first-order test is taken over
+ * the affected derivative coordinates only: every other coordinate has the
+ * parent's interval and derivative, and the parent passed the test there (the
+ * root, whose sides lie on the domain's bounds, passes it everywhere). */
+typedef struct {
+  int n_aff;
+  int64_t aff[48];
+  int aj[48][2];                   /* window index of the term's coordinates (-1: not split) */
+  iv tF[48][16];                   /* term over the pieces (digit of first + pieces * digit of second) */
+  double tS[48][16][MAX_SAMPLES];  /* term's upper bound at each sample point */
+  int n_g;
+  int64_t gc[48];
+  int gj[48][3];                   /* window index of g - 1, g, g + 1 (-1: not split or absent) */
+  unsigned char gm[48][64];        /* first-order test fails, per combination of pieces */
+  iv base_F;
+  double base_S[MAX_SAMPLES];
+  double wbase;                    /* widest side among the coordinates not split */
+} piece_tab;
+
+static int win_of(const int* dim, const int* split, int m, int64_t i) {
+  for (int j = 0; j < m; ++j)
+    if (split[j] && dim[j] == i) return j;
+  return -1;
+}
+
+static iv piece_iv(const double* plo, const double* phi, const double (*cut)[5], int j, int64_t i, int d) {
+  return j < 0 ? mk(plo[i], phi[i]) : mk(cut[j][d], cut[j][d + 1]);
+}
+
+static void piece_tab_form(const orc_problem* P, const double* plo, const double* phi, const int* dim,
+                           const int* split, const double (*cut)[5], int m, int pieces, int S, const double* cs,
+                           iv* X, unsigned char* affected, piece_tab* B) {
+  const int64_t n = P->n, T = n_terms(P);
+  const int chain = P->family == FAM_CHAIN;
+  for (int64_t i = 0; i < T; ++i) affected[i] = 0;
+  for (int j = 0; j < m; ++j) {
+    if (!split[j]) continue;
+    const int64_t d = dim[j];
+    if (d < T) affected[d] = 1;
+    if (chain && d >= 1) affected[d - 1] = 1;
+  }
+  B->n_aff = 0;
+  for (int64_t i = 0; i < T; ++i)
+    if (affected[i]) {
+      int a = B->n_aff++;
+      B->aff[a] = i;
+      B->aj[a][0] = win_of(dim, split, m, i);
+      B->aj[a][1] = chain ? win_of(dim, split, m, i + 1) : -1;
+      const int nb = (chain && B->aj[a][1] >= 0) ? pieces : 1, na = B->aj[a][0] >= 0 ? pieces : 1;
+      for (int db = 0; db < nb; ++db)
+        for (int da = 0; da < na; ++da) {
+          const int cb = da + pieces * db;
+          X[i] = piece_iv(plo, phi, cut, B->aj[a][0], i, da);
+          if (chain) X[i + 1] = piece_iv(plo, phi, cut, B->aj[a][1], i + 1, db);
+          B->tF[a][cb] = term(P, X, i);
+          iv xa = X[i], xb = chain ? X[i + 1] : X[i];
+          for (int s = 0; s < S; ++s) {
+            double pa = diag_coord(xa.lo, xa.hi, cs[s]);
+            X[i] = mk(pa, pa);
+            if (chain) { double pb = diag_coord(xb.lo, xb.hi, cs[s]); X[i + 1] = mk(pb, pb); }
+            B->tS[a][cb][s] = term(P, X, i).hi;
+          }
+        }
+    }
+  /* derivative coordinates whose interval derivative involves a split coordinate */
+  B->n_g = 0;
+  for (int64_t g = 0; g < n; ++g) {
+    int jm = g >= 1 ? win_of(dim, split, m, g - 1) : -1, j0 = win_of(dim, split, m, g),
+        jp = g + 1 < n ? win_of(dim, split, m, g + 1) : -1;
+    if (!chain) jm = jp = -1;
+    if (jm < 0 && j0 < 0 && jp < 0) continue;
+    int k = B->n_g++;
+    B->gc[k] = g;
+    B->gj[k][0] = jm; B->gj[k][1] = j0; B->gj[k][2] = jp;
+    for (int c = 0; c < pieces * pieces * pieces; ++c) {
+      const int d0 = c % pieces, d1 = (c / pieces) % pieces, d2 = c / (pieces * pieces);
+      if ((jm < 0 && d0) || (j0 < 0 && d1) || (jp < 0 && d2)) { B->gm[k][c] = 0; continue; }
+      if (g >= 1) X[g - 1] = piece_iv(plo, phi, cut, jm, g - 1, d0);
+      X[g] = piece_iv(plo, phi, cut, j0, g, d1);
+      if (g + 1 < n) X[g + 1] = piece_iv(plo, phi, cut, jp, g + 1, d2);
+      iv G = grad(P, X, g);
+      B->gm[k][c] = (G.lo > 0.0 && X[g].lo != P->lower[g]) || (G.hi < 0.0 && X[g].hi != P->upper[g]);
+    }
+  }
+  /* canonical sums of the unaffected terms over the parent and at its sample points */
+  for (int64_t i = 0; i < n; ++i) X[i] = mk(plo[i], phi[i]);
+  B->base_F = canonical_sum_except(P, X, affected);
+  for (int s = 0; s < S; ++s) {
+    for (int64_t i = 0; i < n; ++i) { double x = diag_coord(plo[i], phi[i], cs[s]); X[i] = mk(x, x); }
+    B->base_S[s] = canonical_sum_except(P, X, affected).hi;
+  }
+  B->wbase = 0.0;
+  for (int64_t i = 0; i < n; ++i)
+    if (win_of(dim, split, m, i) < 0) B->wbase = dmax(B->wbase, up_sub(phi[i], plo[i]));
+}
+
+/* one child from the tables: F (the base plus the affected terms in increasing
+ * index; lower endpoints summed rounding down, upper ones rounding up), the
+ * first-order flag, the smallest sample upper bound and the widest side */
+static box_eval piece_child(const piece_tab* B, const int* dig, const double (*cut)[5], const int* split, int m,
+                            int pieces, int S, double* wmax) {
+  box_eval r;
+  int cb[48];
+  for (int a = 0; a < B->n_aff; ++a) {
+    const int ja = B->aj[a][0], jb = B->aj[a][1];
+    cb[a] = (ja >= 0 ? dig[ja] : 0) + pieces * (jb >= 0 ? dig[jb] : 0);
+  }
+  volatile double lo = B->base_F.lo, hi = B->base_F.hi;
+  fesetround(FE_DOWNWARD);
+  for (int a = 0; a < B->n_aff; ++a) lo = lo + B->tF[a][cb[a]].lo;
+  fesetround(FE_UPWARD);
+  for (int a = 0; a < B->n_aff; ++a) hi = hi + B->tF[a][cb[a]].hi;
+  double ub = INFINITY;
+  for (int s = 0; s < S; ++s) {
+    volatile double u = B->base_S[s];
+    for (int a = 0; a < B->n_aff; ++a) u = u + B->tS[a][cb[a]][s];
+    if (u < ub) ub = u;
+  }
+  fesetround(FE_TONEAREST);
+  r.F = fix(mk(lo, hi));
+  r.ub = isnan(ub) ? INFINITY : ub;
+  r.mono = 0;
+  for (int k = 0; k < B->n_g && !r.mono; ++k) {
+    const int c = (B->gj[k][0] >= 0 ? dig[B->gj[k][0]] : 0) + pieces * (B->gj[k][1] >= 0 ? dig[B->gj[k][1]] : 0) +
+                  pieces * pieces * (B->gj[k][2] >= 0 ? dig[B->gj[k][2]] : 0);
+    r.mono = B->gm[k][c];
+  }
+  double w = B->wbase;
+  for (int j = 0; j < m; ++j)
+    if (split[j]) w = dmax(w, up_sub(cut[j][dig[j] + 1], cut[j][dig[j]]));
+  *wmax = w;
+  return r;
+}
+
 typedef struct { double f_lo, f_hi; int64_t n_boxes, sweeps, boxes_evaluated; int32_t status; } orc_info;
 
 enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_INVALID = -1, ST_NOMEM = -2, ST_INTERNAL = -5 };
@@ -504,6 +715,12 @@ void* orc_solve(const orc_problem* P, const orc_options* O, int64_t trace_cap) {
   }
   const int m = n < O->split_dims ? n : O->split_dims;
   const int K = O->select_k > 0 ? O->select_k : 1;
+  const int PC = O->pieces == 4 ? 4 : 2;                            /* subintervals per split coordinate */
+  const int NS = O->samples > 0 ? (O->samples < MAX_SAMPLES ? O->samples : MAX_SAMPLES) : 0;
+  const int general = PC != 2 || NS > 0;                           /* the schedule of Sec. 4 (or part of it) */
+  double cs[MAX_SAMPLES];
+  for (int q = 0; q < NS; ++q) cs[q] = (double)(q + 1) / (double)(NS + 1);   /* nearest double to q+1 / (S+1) */
+  piece_tab* tab = general ? (piece_tab*)malloc(sizeof(piece_tab)) : NULL;
   iv* X = (iv*)malloc((size_t)n * sizeof(iv));
   box* par = (box*)malloc((size_t)K * sizeof(box));
   double* clo = (double*)malloc((size_t)n * sizeof(double));
@@ -546,40 +763,58 @@ void* orc_solve(const orc_problem* P, const orc_options* O, int64_t trace_cap) {
       S->live[best] = S->live[--S->n_live];
     }
 
-    /* Partition each parent on m cycled coordinates d_j = (cyc + j) mod n,
-     * child r takes the upper half of d_j when bit j of r is set (Sec. 3.2).
-     * A coordinate whose midpoint equals an endpoint is not split; children
-     * that would take its upper half are not formed. */
-    int64_t nch = (int64_t)1 << m;
+    /* Partition each parent on m cycled coordinates d_j = (cyc + j) mod n
+     * (Sec. 3.2): cut into `pieces` subintervals each (bisection, or the four
+     * equal pieces of Eqs. (10)-(11)); child r takes piece digit_j(r) of d_j.
+     * A coordinate whose pieces would not all have positive width is not
+     * split; children that would take another piece of it are not formed. */
+    int64_t nch = 1;
+    for (int j = 0; j < m; ++j) nch *= PC;
     int64_t cap_ch = (int64_t)kk * nch;
     double* ch_flo = (double*)malloc((size_t)cap_ch * sizeof(double));
     double* ch_ub = (double*)malloc((size_t)cap_ch * sizeof(double));
     unsigned char* ch_ok = (unsigned char*)malloc((size_t)cap_ch);
     double gub_new = S->gub;
     for (int p = 0; p < kk; ++p) {
-      int dim[64]; double mid[64]; int split[64];
+      int dim[64], split[64], dig[64];
+      double cut[64][5];
       int split_dim[64], n_split = 0;
       for (int j = 0; j < m; ++j) {
         dim[j] = (int)(((int64_t)par[p].cyc + j) % n);
-        mid[j] = midpoint(par[p].lo[dim[j]], par[p].hi[dim[j]]);
-        split[j] = par[p].lo[dim[j]] < mid[j] && mid[j] < par[p].hi[dim[j]];
+        split[j] = make_cuts(par[p].lo[dim[j]], par[p].hi[dim[j]], PC, cut[j]);
         if (split[j]) split_dim[n_split++] = dim[j];
       }
-      if (O->incremental) parent_base_form(P, par[p].lo, par[p].hi, split_dim, n_split, X, &pb);
+      if (general && O->incremental)
+        piece_tab_form(P, par[p].lo, par[p].hi, dim, split, (const double(*)[5])cut, m, PC, NS, cs, X, pb.affected,
+                       tab);
+      else if (O->incremental)
+        parent_base_form(P, par[p].lo, par[p].hi, split_dim, n_split, X, &pb);
       for (int64_t r = 0; r < nch; ++r) {
         int64_t c = (int64_t)p * nch + r;
         ch_ok[c] = 0;
         int isvoid = 0;
-        for (int j = 0; j < m; ++j) if (((r >> j) & 1) && !split[j]) isvoid = 1;
-        if (isvoid) continue;
-        memcpy(clo, par[p].lo, (size_t)n * sizeof(double));
-        memcpy(chi, par[p].hi, (size_t)n * sizeof(double));
-        for (int j = 0; j < m; ++j) {
-          if (!split[j]) continue;
-          if ((r >> j) & 1) clo[dim[j]] = mid[j]; else chi[dim[j]] = mid[j];
+        int64_t rr = r;
+        for (int j = 0; j < m; ++j) {   /* the digits of r, as digit() gives them */
+          dig[j] = (int)(rr % PC);
+          rr /= PC;
+          if (dig[j] && !split[j]) isvoid = 1;
         }
-        box_eval e = eval_box(P, clo, chi, X, NULL);
-        if (O->incremental) child_bounds(P, &pb, clo, chi, X, &e.F, &e.ub);
+        if (isvoid) continue;
+        box_eval e;
+        if (general && O->incremental) {
+          double w;
+          e = piece_child(tab, dig, (const double(*)[5])cut, split, m, PC, NS, &w);
+        } else {
+          memcpy(clo, par[p].lo, (size_t)n * sizeof(double));
+          memcpy(chi, par[p].hi, (size_t)n * sizeof(double));
+          for (int j = 0; j < m; ++j) {
+            if (!split[j]) continue;
+            clo[dim[j]] = cut[j][dig[j]];
+            chi[dim[j]] = cut[j][dig[j] + 1];
+          }
+          e = general ? eval_box_samples(P, clo, chi, X, NS, cs) : eval_box(P, clo, chi, X, NULL);
+          if (!general && O->incremental) child_bounds(P, &pb, clo, chi, X, &e.F, &e.ub);
+        }
         S->info.boxes_evaluated++;
         ch_flo[c] = e.F.lo;
         ch_ub[c] = e.ub;
@@ -593,11 +828,11 @@ void* orc_solve(const orc_problem* P, const orc_options* O, int64_t trace_cap) {
     /* Insert survivors: lower bound <= GUB and passing the first-order test */
     int64_t nsurv = 0;
     for (int p = 0; p < kk; ++p) {
-      int dim[64]; double mid[64]; int split[64];
+      int dim[64], split[64];
+      double cut[64][5];
       for (int j = 0; j < m; ++j) {
         dim[j] = (int)(((int64_t)par[p].cyc + j) % n);
-        mid[j] = midpoint(par[p].lo[dim[j]], par[p].hi[dim[j]]);
-        split[j] = par[p].lo[dim[j]] < mid[j] && mid[j] < par[p].hi[dim[j]];
+        split[j] = make_cuts(par[p].lo[dim[j]], par[p].hi[dim[j]], PC, cut[j]);
       }
       for (int64_t r = 0; r < nch; ++r) {
         int64_t c = (int64_t)p * nch + r;
@@ -609,7 +844,9 @@ void* orc_solve(const orc_problem* P, const orc_options* O, int64_t trace_cap) {
         memcpy(b.hi, par[p].hi, (size_t)n * sizeof(double));
         for (int j = 0; j < m; ++j) {
           if (!split[j]) continue;
-          if ((r >> j) & 1) b.lo[dim[j]] = mid[j]; else b.hi[dim[j]] = mid[j];
+          const int d = digit(r, j, PC);
+          b.lo[dim[j]] = cut[j][d];
+          b.hi[dim[j]] = cut[j][d + 1];
         }
         b.flo = ch_flo[c];
         b.seq = next_seq++;
@@ -643,7 +880,7 @@ done:
     S->info.f_lo = glb;
   }
   qsort(S->live, (size_t)S->n_live, sizeof(box), cmp_seq);
-  free(X); free(par); free(clo); free(chi); free(pb.affected);
+  free(X); free(par); free(clo); free(chi); free(pb.affected); free(tab);
   return S;
 }
 

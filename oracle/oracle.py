@@ -49,7 +49,8 @@ class _Problem(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("split_dims", C.c_int32), ("select_k", C.c_int32),
                 ("max_sweeps", C.c_int64), ("max_live_boxes", C.c_int64),
-                ("incremental", C.c_int32), ("reserved", C.c_int32)]
+                ("incremental", C.c_int32), ("reserved", C.c_int32),
+                ("pieces", C.c_int32), ("samples", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -158,14 +159,19 @@ class SolveResult:
 
 
 def solve(family, coef, lower, upper, tol_f=1e-6, tol_x=0.0, split_dims=10, select_k=1,
-          max_sweeps=100000, max_live_boxes=0, trace_cap=None, incremental=False) -> SolveResult:
+          max_sweeps=100000, max_live_boxes=0, trace_cap=None, incremental=False, pieces=2,
+          samples=0) -> SolveResult:
     """The iteration of Sec. 3.1-3.2.  incremental=True bounds each child from its
-    parent's shared terms (same enclosures up to the order of the additions)."""
+    parent's shared terms (same enclosures up to the order of the additions).
+    pieces=4, samples=10 (with tol_x = 1e-4 and a tol_f that never binds) is the
+    schedule of the paper's experiments (Sec. 4): four equal subintervals of each
+    cycled coordinate (Eqs. (8)-(11)) and ten sample points on each subregion's
+    diagonal; with it, incremental=True is the practical mode (4^m children)."""
     k = _Keep(family, coef, lower, upper, tol_f, tol_x)
     n = k.lower.shape[0]
     if trace_cap is None:
         trace_cap = max_sweeps
-    opts = _Options(split_dims, select_k, max_sweeps, max_live_boxes, int(bool(incremental)), 0)
+    opts = _Options(split_dims, select_k, max_sweeps, max_live_boxes, int(bool(incremental)), 0, pieces, samples)
     L = lib()
     h = L.orc_solve(C.byref(k.p), C.byref(opts), trace_cap)
     if not h:

@@ -56,7 +56,7 @@ class _Info(C.Structure):
                 ("seconds", C.c_double), ("status", C.c_int32), ("fp32_sweeps", C.c_int32),
                 ("ub_evaluated", C.c_int64), ("t_bound_ms", C.c_double), ("t_select_ms", C.c_double),
                 ("n_bound_launches", C.c_int64), ("n_select_launches", C.c_int64),
-                ("bound_shape", C.c_int32), ("pad", C.c_int32)]
+                ("bound_shape", C.c_int32), ("pad", C.c_int32), ("n_persistent_launches", C.c_int64)]
 
 
 _lib = None

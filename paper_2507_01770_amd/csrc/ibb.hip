@@ -2728,6 +2728,7 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[0], ev[3]) == hipSuccess) R->info.t_select_ms += ms;
       R->info.n_select_launches += ran + (U.hs.stop ? 1 : 0);
+      R->info.n_persistent_launches++;
     } else if (prof) {
       // bound launches that did work in this chunk; the select of the stopping sweep ran too
       const int64_t ran = (U.hs.sweeps + (U.hs.pending ? 1 : 0)) - (U.sweeps + (U.pending ? 1 : 0));
