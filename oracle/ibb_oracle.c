@@ -736,7 +736,10 @@ void* orc_solve(const orc_problem* P, const orc_options* O, int64_t trace_cap) {
   memcpy(root.hi, P->upper, (size_t)n * sizeof(double));
   box_eval e0 = eval_box(P, root.lo, root.hi, X, NULL);
   root.flo = e0.F.lo; root.seq = 0; root.cyc = 0; root.wmax = box_wmax(n, root.lo, root.hi);
-  S->gub = e0.ub;
+  /* with diagonal samples (the schedule of Sec. 4) nothing is sampled before the
+   * first iteration, which samples the subregions of the whole domain: GUB
+   * starts at +inf; with the midpoint rule the root's midpoint bound starts it */
+  S->gub = NS > 0 ? INFINITY : e0.ub;
   S->info.boxes_evaluated = 1;
   int64_t next_seq = 1;
   push_box(S, root);
