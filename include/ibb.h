@@ -116,6 +116,17 @@ typedef struct {
                             O(n + 2^m m) work per sweep instead of O(2^m n).  0: every child is
                             bounded over all n terms (the FP32 filter and bound_shape apply only here;
                             IBB_E_INVALID for incremental = 1 with IBB_FP32_BULK or a bound_shape) */
+  int32_t pieces;        /* subintervals per split coordinate: 2 (default; 0 means 2): bisection at the
+                            midpoint; 4: the schedule of the paper's experiments (Sec. 4), each of the
+                            split_dims cycled coordinates cut into four equal pieces (Sec. 3.2,
+                            Eqs. (8)-(11): digit j of the child index in base 4 picks the piece of the
+                            j-th coordinate), 4^split_dims children per sweep.  4 needs diag_samples
+                            in 1..16, incremental = 1, select_k = 1, IBB_FP64, split_dims <= 12 */
+  int32_t diag_samples;  /* 0 with pieces = 2 (the child midpoint is the one sample); with pieces = 4,
+                            S sample points per child on its diagonal, cutting it into S + 1 equal
+                            pieces (the paper uses 10); GUB starts at +inf and takes the smallest
+                            sample upper bound.  The paper stops on region width: set tol_x = 1e-4
+                            and a tol_f that never binds (e.g. 1e300) */
   int32_t reserved;      /* 0 */
 } ibb_options;
 

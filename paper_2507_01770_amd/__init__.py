@@ -39,7 +39,8 @@ class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("split_dims", C.c_int32), ("select_k", C.c_int32),
                 ("deterministic", C.c_int32), ("max_sweeps", C.c_int64), ("max_live_boxes", C.c_int64),
                 ("time_limit_s", C.c_double), ("profile", C.c_int32), ("bound_shape", C.c_int32),
-                ("incremental", C.c_int32), ("reserved", C.c_int32)]
+                ("incremental", C.c_int32), ("pieces", C.c_int32), ("diag_samples", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -279,12 +280,12 @@ class Result:
 def minimize(problem=None, *, family=None, coef=None, lower=None, upper=None, tol_f=None, tol_x=None,
              precision=FP64, split_dims=10, select_k=1, max_sweeps=1_000_000, max_live_boxes=1 << 26,
              time_limit_s=0.0, fetch_boxes=True, max_boxes_fetched=100_000, use_torch_allocator=True,
-             profile=False, bound_shape=None, incremental=None, stream=None) -> Result:
+             profile=False, bound_shape=None, incremental=None, pieces=2, diag_samples=0, stream=None) -> Result:
     """Enclose min f over [lower, upper]; returns [f_lo, f_hi] and the surviving boxes."""
     k = _prob_args(problem, family, coef, lower, upper, tol_f, tol_x)
     L = lib()
     opts = _options(precision, split_dims, select_k, max_sweeps, max_live_boxes, time_limit_s, profile, bound_shape,
-                    incremental)
+                    incremental, pieces, diag_samples)
     alloc = _TorchAllocator() if use_torch_allocator else None
     h = C.c_void_p()
     rc = L.ibb_solve(C.byref(k.s), C.byref(opts), C.byref(alloc.struct) if alloc else None, _stream_ptr(stream),
@@ -367,14 +368,15 @@ class Run:
 
 
 def _options(precision=FP64, split_dims=10, select_k=1, max_sweeps=1_000_000, max_live_boxes=1 << 26,
-             time_limit_s=0.0, profile=False, bound_shape=None, incremental=None):
+             time_limit_s=0.0, profile=False, bound_shape=None, incremental=None, pieces=2, diag_samples=0):
     """incremental=None: incremental child bounds unless the FP32 filter or a bound shape
-    (both about full bounds) is asked for."""
+    (both about full bounds) is asked for.  pieces=4, diag_samples=10: the paper's schedule."""
     prec = _prec(precision)
     if incremental is None:
         incremental = prec == FP64 and bound_shape is None
     return _Options(prec, split_dims, select_k, 1, max_sweeps, max_live_boxes, time_limit_s, int(profile),
-                    0 if bound_shape is None else int(bound_shape) + 1, int(bool(incremental)), 0)
+                    0 if bound_shape is None else int(bound_shape) + 1, int(bool(incremental)), int(pieces),
+                    int(diag_samples), 0)
 
 
 def solve_batch(problems, *, fetch_boxes=True, max_boxes_fetched=100_000, stream=None, **opts) -> list:

@@ -141,7 +141,9 @@ __global__ __launch_bounds__(kWave) void k_root(const Params* __restrict__ PP, S
   bound_box<FAM>(P, X, lane, F, mo, wm, nullptr);
   const double u = point_ub<FAM>(P, X, lane);
   if (lane == 0) {
-    S->gub_key = okey(hi_or_inf(u));
+    // with diagonal samples (the paper's schedule) nothing is sampled before the
+    // first sweep, which samples the subregions of the whole domain: GUB = +inf
+    S->gub_key = okey(P.nsamp > 0 ? __builtin_inf() : hi_or_inf(u));
     P.key_flo[0] = lo_or_ninf(neg(F.n));
     P.key_seq[0] = 0;
     P.key_ref[0] = 0;
@@ -319,7 +321,7 @@ __device__ __forceinline__ void insert_children(const Params& P, State* S, doubl
 
 // One workgroup: stop test on [GLB, GUB]; if running, remove the best key from the
 // list and build its row (child r of row ref) and the split points of that row.
-template <int NT>
+template <int NT, int PIECES = 2>
 __device__ __forceinline__ bool select_finish(const Params& P, State* S, const SelAcc& tot, double gub) {
   __shared__ int32_t go;
   if (threadIdx.x == 0) {
@@ -352,8 +354,10 @@ __device__ __forceinline__ bool select_finish(const Params& P, State* S, const S
   const int32_t r = P.key_r[tot.best.idx];
   const int n = P.n;
   const int pcyc = P.hist_cyc[ref];
-  const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
-                     n, P.m, pcyc, r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
+  using Row = typename std::conditional<PIECES == 4, ChildRow4, ChildRow>::type;
+  const Row src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n,
+                PIECES == 4 ? P.hist_cut + (int64_t)ref * (3 * kMaxSplit) : P.hist_mid + (int64_t)ref * kMaxSplit,
+                n, P.m, pcyc, r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
   double* dn = P.hist_n + row * n;
   double* dh = P.hist_h + row * n;
   for (int i = threadIdx.x; i < n; i += NT) {
@@ -368,10 +372,16 @@ __device__ __forceinline__ bool select_finish(const Params& P, State* S, const S
     if (j < P.m) {
       const int d = add_mod(cyc, j, n);
       const I x = src.get(d);                 // same values as the row just written
-      const double md = midpoint(x);
-      ok = neg(x.n) < md && md < x.h;
-      P.hist_mid[row * kMaxSplit + j] = md;
-      S->sel_mid[j] = md;
+      if (PIECES == 4) {                      // the four pieces of Eqs. (10)-(11)
+        double c[3];
+        ok = cuts4(x, c);
+        for (int q = 0; q < 3; ++q) P.hist_cut[row * (3 * kMaxSplit) + 3 * j + q] = c[q];
+      } else {
+        const double md = midpoint(x);
+        ok = neg(x.n) < md && md < x.h;
+        P.hist_mid[row * kMaxSplit + j] = md;
+        S->sel_mid[j] = md;
+      }
     }
     const unsigned long long bal = __ballot(ok);
     if (j == 0) {
@@ -528,7 +538,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_part(const Params* __res
 // test the stopping criteria and select the next box.  Kernel boundaries make
 // the children written by k_bound and the partials visible: no device-scope
 // fences are needed.
-template <int NT>
+template <int NT, int PIECES = 2>
 __device__ __forceinline__ bool select_body(const Params& P, State* S, int nparts, int host_stop) {
   const double gub = okey_inv(S->gub_key);
   SelAcc a = sel_empty();
@@ -551,7 +561,7 @@ __device__ __forceinline__ bool select_body(const Params& P, State* S, int npart
     }
     return false;
   }
-  return select_finish<NT>(P, S, a, gub);
+  return select_finish<NT, PIECES>(P, S, a, gub);
 }
 
 // ---------------------------------------------------------------------------
@@ -1379,6 +1389,322 @@ __global__ __launch_bounds__(NT) void k_ib_parents(const Params* __restrict__ PP
   }
 }
 
+// ---------------------------------------------------------------------------
+// The schedule of the paper's experiments (Sec. 4): the selected box's m cycled
+// coordinates are cut into four equal pieces (Eqs. (8)-(11), digit j of the
+// child index picks the piece of the j-th coordinate), 4^m children, each
+// sampled at nsamp points of its diagonal.  Children are bounded incrementally:
+// k_prep4 (one workgroup) forms, for the selected box, the canonical sums of the
+// terms no split coordinate touches (F over the box and the upper bound at each
+// of its diagonal points), and tables of the other terms and of the first-order
+// test for every combination of pieces of the coordinates they involve;
+// k_children4 (one thread per child, the whole chip) adds a child's table
+// entries in increasing term index, takes the smallest sample bound into GUB
+// and writes the child's record for the next selection to insert.
+
+// offsets in the tables
+constexpr int kTabBase = kTabRows * 16 * kTabEntry;   // doubles: base F (-lo, hi), base samples, wbase, widths
+constexpr int kTiAff = 4, kTiAj = kTiAff + kTabRows, kTiGc = kTiAj + 2 * kTabRows, kTiGj = kTiGc + kTabRows,
+              kTiGm = kTiGj + 3 * kTabRows;
+static_assert(kTiGm + 64 * kTabRows <= kTabInts, "table layout");
+
+template <int NT, int FAM>
+__global__ __launch_bounds__(NT) void k_prep4(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params& P = *PP;
+  const int n = P.n, m = P.m, ns = P.nsamp;
+  const int row = S->sel_row, cyc = S->sel_cyc;
+  const uint32_t mask = S->sel_mask;
+  const double* rn = P.hist_n + (int64_t)row * n;
+  const double* rh = P.hist_h + (int64_t)row * n;
+  const double* cut = P.hist_cut + (int64_t)row * (3 * kMaxSplit);
+  const int T = FAM == FAM_CHAIN ? n - 1 : n;
+  auto split_of = [&](int i) -> int {   // window index j if coordinate i is split, else -1
+    if (i < 0 || i >= n) return -1;
+    int j = i - cyc;
+    if (j < 0) j += n;
+    return (j < m && ((mask >> j) & 1u)) ? j : -1;
+  };
+  auto piece = [&](int i, int j, int d) -> I {   // coordinate i of the child with digit d on window index j
+    if (j < 0) return I{G(rn)[i], G(rh)[i]};
+    return I{d > 0 ? neg(G(cut)[3 * j + d - 1]) : G(rn)[i], d < 3 ? G(cut)[3 * j + d] : G(rh)[i]};
+  };
+  __shared__ int s_aff[kTabRows], s_aj[kTabRows][2], s_gc[kTabRows], s_gj[kTabRows][3];
+  __shared__ int s_naff, s_ngc;
+  if (threadIdx.x == 0) {
+    // affected terms and derivative coordinates in increasing index (few: m <= 12)
+    int ca[3 * kMaxSplit], cg[3 * kMaxSplit];
+    int na = 0, ng = 0;
+    for (int j = 0; j < m; ++j) {
+      if (!((mask >> j) & 1u)) continue;
+      const int d = add_mod(cyc, j, n);
+      if (d < T) ca[na++] = d;
+      if (FAM == FAM_CHAIN && d >= 1) ca[na++] = d - 1;
+      cg[ng++] = d;
+      if (FAM == FAM_CHAIN) {
+        if (d >= 1) cg[ng++] = d - 1;
+        if (d + 1 < n) cg[ng++] = d + 1;
+      }
+    }
+    auto sort_unique = [](int* v, int k) {
+      for (int a = 1; a < k; ++a)
+        for (int b = a; b > 0 && v[b - 1] > v[b]; --b) { const int t = v[b]; v[b] = v[b - 1]; v[b - 1] = t; }
+      int u = 0;
+      for (int a = 0; a < k; ++a)
+        if (u == 0 || v[u - 1] != v[a]) v[u++] = v[a];
+      return u;
+    };
+    na = sort_unique(ca, na);
+    ng = sort_unique(cg, ng);
+    for (int a = 0; a < na; ++a) {
+      s_aff[a] = ca[a];
+      s_aj[a][0] = split_of(ca[a]);
+      s_aj[a][1] = FAM == FAM_CHAIN ? split_of(ca[a] + 1) : -1;
+      P.tabi[kTiAff + a] = ca[a];
+      P.tabi[kTiAj + 2 * a] = s_aj[a][0];
+      P.tabi[kTiAj + 2 * a + 1] = s_aj[a][1];
+    }
+    for (int k = 0; k < ng; ++k) {
+      const int g = cg[k];
+      s_gc[k] = g;
+      s_gj[k][0] = FAM == FAM_CHAIN ? split_of(g - 1) : -1;
+      s_gj[k][1] = split_of(g);
+      s_gj[k][2] = FAM == FAM_CHAIN ? split_of(g + 1) : -1;
+      P.tabi[kTiGc + k] = g;
+      for (int q = 0; q < 3; ++q) P.tabi[kTiGj + 3 * k + q] = s_gj[k][q];
+    }
+    s_naff = na;
+    s_ngc = ng;
+    P.tabi[0] = na;
+    P.tabi[1] = ng;
+  }
+  __syncthreads();
+  const int na = s_naff, ng = s_ngc;
+  // term tables: F over the pieces and the upper bound at each diagonal point
+  for (int e = threadIdx.x; e < na * 16; e += NT) {
+    const int a = e >> 4, cb = e & 15, d0 = cb & 3, d1 = cb >> 2;
+    const int i = s_aff[a], j0 = s_aj[a][0], j1 = s_aj[a][1];
+    if ((j0 < 0 && d0) || (j1 < 0 && d1)) continue;   // a combination no child has
+    double* ent = P.tab + (a * 16 + cb) * kTabEntry;
+    const I xa = piece(i, j0, d0);
+    if (FAM != FAM_CHAIN) {
+      const CoefSep c = gload(P.sep + i);
+      const I t = sep_term<FAM>(c, xa);
+      G(ent)[0] = t.n;
+      G(ent)[1] = t.h;
+      for (int q = 0; q < ns; ++q) G(ent)[2 + q] = sep_point_hi<FAM>(c, diag_coord(xa, P.cs[q]));
+    } else {
+      const I xb = piece(i + 1, j1, d1);
+      const CoefChain c = gload(P.chain + i);
+      I R, E;
+      const I t = chain_term(c, xa, xb, R, E);
+      G(ent)[0] = t.n;
+      G(ent)[1] = t.h;
+      for (int q = 0; q < ns; ++q)
+        G(ent)[2 + q] = chain_term(c, point(diag_coord(xa, P.cs[q])), point(diag_coord(xb, P.cs[q])), R, E).h;
+    }
+  }
+  // first-order test per combination of the pieces of g - 1, g, g + 1
+  for (int e = threadIdx.x; e < ng * 64; e += NT) {
+    const int k = e >> 6, cb = e & 63, d0 = cb & 3, d1 = (cb >> 2) & 3, d2 = cb >> 4;
+    const int g = s_gc[k], j0 = s_gj[k][0], j1 = s_gj[k][1], j2 = s_gj[k][2];
+    int mo = 0;
+    if (!((j0 < 0 && d0) || (j1 < 0 && d1) || (j2 < 0 && d2))) {
+      const I xg = piece(g, j1, d1);
+      I Gr;
+      if (FAM != FAM_CHAIN) {
+        I t;
+        sep_box<FAM>(gload(P.sep + g), xg, t, Gr);
+      } else {
+        const bool has_prev = g > 0, has_next = g + 1 < n;
+        const I xp = has_prev ? piece(g - 1, j0, d0) : xg;
+        const I xq = has_next ? piece(g + 1, j2, d2) : xg;
+        Gr = chain_grad(gload(P.chain + (has_prev ? g - 1 : g)), gload(P.chain + g), xp, xg, xq, has_prev, has_next);
+      }
+      mo = (Gr.n < 0.0 && xg.n != G(P.nl)[g]) || (Gr.h < 0.0 && xg.h != G(P.u)[g]);
+    }
+    P.tabi[kTiGm + 64 * k + cb] = mo;
+  }
+  // canonical sums (slot i mod 64, slots in order, then the folds) of the terms
+  // no split coordinate touches: F over the box and the bound at each diagonal
+  // point of the box; the widest side among the coordinates not split
+  constexpr int NE = 2 + kMaxSamples;
+  __shared__ double sv[NT][NE];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  I acc{0.0, 0.0};
+  double su[kMaxSamples];
+#pragma unroll
+  for (int q = 0; q < kMaxSamples; ++q) su[q] = 0.0;
+  double wb = 0.0;
+  for (int c0 = 0; c0 < n; c0 += NT) {
+    const int i = c0 + (int)threadIdx.x;
+    double v[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) v[q] = 0.0;
+    if (i < n && split_of(i) < 0) {
+      const I x{G(rn)[i], G(rh)[i]};
+      wb = dmax(wb, x.n + x.h);
+      if (i < T && !(FAM == FAM_CHAIN && split_of(i + 1) >= 0)) {
+        if (FAM != FAM_CHAIN) {
+          const CoefSep c = gload(P.sep + i);
+          const I t = sep_term<FAM>(c, x);
+          v[0] = t.n;
+          v[1] = t.h;
+#pragma unroll
+          for (int q = 0; q < kMaxSamples; ++q)
+            if (q < ns) v[2 + q] = sep_point_hi<FAM>(c, diag_coord(x, P.cs[q]));
+        } else {
+          const I xn{G(rn)[i + 1], G(rh)[i + 1]};
+          const CoefChain c = gload(P.chain + i);
+          I R, E;
+          const I t = chain_term(c, x, xn, R, E);
+          v[0] = t.n;
+          v[1] = t.h;
+#pragma unroll
+          for (int q = 0; q < kMaxSamples; ++q)
+            if (q < ns) v[2 + q] = chain_term(c, point(diag_coord(x, P.cs[q])), point(diag_coord(xn, P.cs[q])), R, E).h;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) sv[threadIdx.x][q] = v[q];
+    __syncthreads();
+    if (wid == 0) {   // lane s: terms c0 + r*64 + s in increasing order (zeros past n change no bit)
+      const int rows = min(NT / kWave, (n - c0 + kWave - 1) / kWave);
+      for (int r = 0; r < rows; ++r) {
+        const int t = r * kWave + lane;
+        acc = add(acc, I{sv[t][0], sv[t][1]});
+#pragma unroll
+        for (int q = 0; q < kMaxSamples; ++q)
+          if (q < ns) su[q] = su[q] + sv[t][2 + q];
+      }
+    }
+    __syncthreads();
+  }
+  __shared__ double s_wb[NT / kWave];
+  wb = wave_max(wb);
+  if (lane == 0) s_wb[wid] = wb;
+  __syncthreads();
+  if (wid == 0) {
+    const I F = fold_slots(acc, lane);
+    double* base = P.tab + kTabBase;
+    if (lane == 0) { G(base)[0] = F.n; G(base)[1] = F.h; }
+#pragma unroll
+    for (int q = 0; q < kMaxSamples; ++q)
+      if (q < ns) {   // uniform branch
+        const double u = fold_slots_hi(su[q], lane);
+        if (lane == 0) G(base)[2 + q] = u;
+      }
+    if (lane == 0) {
+      double w = 0.0;
+      for (int k = 0; k < NT / kWave; ++k) w = dmax(w, s_wb[k]);
+      G(base)[2 + kMaxSamples] = w;
+    }
+    if (lane < 4 * m) {   // widths of the pieces of the split coordinates
+      const int j = lane >> 2, d = lane & 3;
+      double w = 0.0;
+      if ((mask >> j) & 1u) {
+        const I x = piece(add_mod(cyc, j, n), j, d);
+        w = x.n + x.h;
+      }
+      G(base)[3 + kMaxSamples + 4 * j + d] = w;
+    }
+  }
+}
+
+// one thread per child of the selected box; the tables in LDS (dynamic: `rows`
+// term rows of 16 combinations of 2 + nsamp doubles, then 3 m test rows of 64)
+template <int FAM>
+__global__ __launch_bounds__(256) void k_children4(const Params* __restrict__ PP, State* __restrict__ S, int rows) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params& P = *PP;
+  extern __shared__ double sm[];
+  const int na = G(P.tabi)[0], ng = G(P.tabi)[1], ns = P.nsamp, m = P.m;
+  const uint32_t mask = S->sel_mask;
+  const int E = 2 + ns;                              // doubles per table entry in LDS
+  double* st = sm;                                   // [rows][16][E]
+  int* sgm = reinterpret_cast<int*>(sm + rows * 16 * E);   // [3 m][64]
+  __shared__ int s_aj[kTabRows][2], s_gj[kTabRows][3];
+  __shared__ double s_base[2 + kMaxSamples + 1 + 4 * kMaxSplit];
+  if (na > rows || ng > 3 * m) {   // more table rows than the launch sized its LDS for (a guard)
+    if (threadIdx.x == 0) S->stop = STOP_INTERNAL;
+    return;
+  }
+  for (int e = threadIdx.x; e < na * 16 * E; e += blockDim.x) st[e] = G(P.tab)[(e / E) * kTabEntry + e % E];
+  for (int e = threadIdx.x; e < ng * 64; e += blockDim.x) sgm[e] = G(P.tabi)[kTiGm + e];
+  for (int e = threadIdx.x; e < 2 * na; e += blockDim.x) s_aj[e >> 1][e & 1] = G(P.tabi)[kTiAj + e];
+  for (int e = threadIdx.x; e < 3 * ng; e += blockDim.x) s_gj[e / 3][e % 3] = G(P.tabi)[kTiGj + e];
+  for (int e = threadIdx.x; e < 3 + kMaxSamples + 4 * kMaxSplit; e += blockDim.x) s_base[e] = G(P.tab)[kTabBase + e];
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t cu = (uint32_t)c;
+  auto dig = [&](int j) { return j >= 0 ? (int)((cu >> (2 * j)) & 3u) : 0; };
+  bool formed = c < P.nch;
+  for (int j = 0; j < m; ++j)
+    if (!((mask >> j) & 1u) && dig(j) != 0) formed = false;
+  double ub = __builtin_inf();
+  if (formed) {
+    I F{s_base[0], s_base[1]};
+    double u[kMaxSamples];
+#pragma unroll
+    for (int q = 0; q < kMaxSamples; ++q) u[q] = s_base[2 + q];
+    for (int a = 0; a < na; ++a) {
+      const int cb = dig(s_aj[a][0]) | (dig(s_aj[a][1]) << 2);
+      const double* e = st + (a * 16 + cb) * E;
+      F = add(F, I{e[0], e[1]});
+#pragma unroll
+      for (int q = 0; q < kMaxSamples; ++q)
+        if (q < ns) u[q] = u[q] + e[2 + q];
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxSamples; ++q)
+      if (q < ns) ub = dmin(ub, u[q]);
+    ub = hi_or_inf(ub);
+    bool mo = false;
+    for (int k = 0; k < ng; ++k) mo = mo || sgm[64 * k + (dig(s_gj[k][0]) | (dig(s_gj[k][1]) << 2) | (dig(s_gj[k][2]) << 4))];
+    double wm = s_base[2 + kMaxSamples];
+    for (int j = 0; j < m; ++j)
+      if ((mask >> j) & 1u) wm = dmax(wm, s_base[3 + kMaxSamples + 4 * j + dig(j)]);
+    G(P.ch_flo)[c] = lo_or_ninf(neg(F.n));
+    G(P.ch_wmax)[c] = wm;
+    G(P.ch_flag)[c] = mo ? 1 : 2;
+  } else if (c < P.nch) {
+    G(P.ch_flag)[c] = 0;   // takes a piece of a coordinate that cannot be cut
+  }
+  // GUB: the block's smallest sample bound
+  __shared__ double s_u[256 / kWave];
+  __shared__ int s_n[256 / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  double um = ub;
+  int cnt = formed ? 1 : 0;
+  for (int h = 32; h >= 1; h >>= 1) {
+    um = dmin(um, __shfl_xor(um, h, kWave));
+    cnt += __shfl_xor(cnt, h, kWave);
+  }
+  if (lane == 0) { s_u[wid] = um; s_n[wid] = cnt; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mn = s_u[0];
+    int tot = s_n[0];
+    for (int k = 1; k < 256 / kWave; ++k) { mn = dmin(mn, s_u[k]); tot += s_n[k]; }
+    if (tot > 0) {
+      atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(mn));
+      atomicAdd((unsigned long long*)&S->ub_evaluated, (unsigned long long)tot);
+    }
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_select4(const Params* __restrict__ PP, State* __restrict__ S, int nparts,
+                                                int host_stop) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params P = *PP;
+  select_body<NT, 4>(P, S, nparts, host_stop);
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_select(const Params* __restrict__ PP, State* __restrict__ S, int nparts,
                                                int host_stop) {
@@ -1951,12 +2277,23 @@ __global__ __launch_bounds__(256) void k_rows_out(const Params* __restrict__ PP,
   const Params P = *PP;
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     const int32_t row = ref[b], r = rr[b];
-    const ChildRow X{P.hist_n + (int64_t)row * P.n, P.hist_h + (int64_t)row * P.n, P.hist_mid + (int64_t)row * kMaxSplit,
-                     P.n, P.m, P.hist_cyc[row], r >= 0 ? P.hist_mask[row] : 0u, r >= 0 ? (uint32_t)r : 0u};
-    for (int i = threadIdx.x; i < P.n; i += 256) {
-      const I x = X.get(i);
-      lo[b * P.n + i] = neg(x.n);
-      hi[b * P.n + i] = x.h;
+    const uint32_t mask = r >= 0 ? P.hist_mask[row] : 0u, rc = r >= 0 ? (uint32_t)r : 0u;
+    if (P.pieces == 4) {
+      const ChildRow4 X{P.hist_n + (int64_t)row * P.n, P.hist_h + (int64_t)row * P.n,
+                        P.hist_cut + (int64_t)row * (3 * kMaxSplit), P.n, P.m, P.hist_cyc[row], mask, rc};
+      for (int i = threadIdx.x; i < P.n; i += 256) {
+        const I x = X.get(i);
+        lo[b * P.n + i] = neg(x.n);
+        hi[b * P.n + i] = x.h;
+      }
+    } else {
+      const ChildRow X{P.hist_n + (int64_t)row * P.n, P.hist_h + (int64_t)row * P.n,
+                       P.hist_mid + (int64_t)row * kMaxSplit, P.n, P.m, P.hist_cyc[row], mask, rc};
+      for (int i = threadIdx.x; i < P.n; i += 256) {
+        const I x = X.get(i);
+        lo[b * P.n + i] = neg(x.n);
+        hi[b * P.n + i] = x.h;
+      }
     }
   }
 }
@@ -2328,7 +2665,11 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   if (st != IBB_OK) return st;
   P.incremental = U.opts.incremental ? 1 : 0;
   P.m = std::min(n, U.opts.split_dims);
-  P.nch = 1 << P.m;
+  P.pieces = U.opts.pieces == 4 ? 4 : 2;
+  P.nch = P.pieces == 4 ? 1 << (2 * P.m) : 1 << P.m;
+  P.nsamp = U.opts.diag_samples;
+  for (int q = 0; q < kMaxSamples; ++q)   // the double nearest (q + 1) / (S + 1)
+    P.cs[q] = q < P.nsamp ? (double)(q + 1) / (double)(P.nsamp + 1) : 0.0;
   P.tol_f = prob->tol_f;
   P.tol_x = prob->tol_x;
   P.max_sweeps = U.opts.max_sweeps;
@@ -2348,6 +2689,10 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   P.hist_cyc = dalloc<int32_t>(M, P.hist_cap);
   P.hist_mask = dalloc<uint32_t>(M, P.hist_cap);
   P.hist_mid = dalloc<double>(M, P.hist_cap * kMaxSplit);
+  const bool four = P.pieces == 4;
+  P.hist_cut = four ? dalloc<double>(M, P.hist_cap * 3 * kMaxSplit) : nullptr;
+  P.tab = four ? dalloc<double>(M, kTabDoubles) : nullptr;
+  P.tabi = four ? dalloc<int32_t>(M, kTabInts) : nullptr;
   P.ch_flo = dalloc<double>(M, nrec);
   P.ch_flag = dalloc<uint8_t>(M, nrec);
   P.ch_wmax = dalloc<double>(M, nrec);
@@ -2358,7 +2703,8 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   P.part_cnt = dalloc<int64_t>(M, kMaxSelBlocks);
   set_trace(P, dalloc<double>(M, 4 * P.trace_cap), P.trace_cap);
   if (!P.key_flo || !P.key_seq || !P.key_ref || !P.key_r || !P.key_wmax || !P.hist_n || !P.hist_h || !P.hist_cyc ||
-      !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.sel_tab || !P.part_flo ||
+      !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.sel_tab ||
+      (four && (!P.hist_cut || !P.tab || !P.tabi)) || !P.part_flo ||
       !P.part_idx || !P.part_wmax || !P.part_cnt || !P.tr_gub || !P.tr_nsurv || !P.tr_nlive || !P.tr_sel)
     return fail(IBB_E_NOMEM, "device allocation failed");
   // root row: (-l, u)
@@ -2416,6 +2762,7 @@ ibb_status run_capacity(Run& U, int chunk) {
     take(Q.hist_cyc, Q.hist_cap);
     take(Q.hist_mask, Q.hist_cap);
     take(Q.hist_mid, Q.hist_cap * kMaxSplit);
+    if (P.pieces == 4) take(Q.hist_cut, Q.hist_cap * 3 * kMaxSplit);
   }
   if (g_keys) {
     Q.key_cap = std::max<int64_t>(2 * P.key_cap, need_keys);
@@ -2444,7 +2791,8 @@ ibb_status run_capacity(Run& U, int chunk) {
     copied = copied && copy(Q.hist_n, P.hist_n, keep * n * sizeof(double)) &&
              copy(Q.hist_h, P.hist_h, keep * n * sizeof(double)) && copy(Q.hist_cyc, P.hist_cyc, keep * sizeof(int32_t)) &&
              copy(Q.hist_mask, P.hist_mask, keep * sizeof(uint32_t)) &&
-             copy(Q.hist_mid, P.hist_mid, keep * kMaxSplit * sizeof(double));
+             copy(Q.hist_mid, P.hist_mid, keep * kMaxSplit * sizeof(double)) &&
+             (P.pieces != 4 || copy(Q.hist_cut, P.hist_cut, keep * 3 * kMaxSplit * sizeof(double)));
   }
   if (g_keys) {
     const int64_t keep = U.n_keys;
@@ -2462,7 +2810,10 @@ ibb_status run_capacity(Run& U, int chunk) {
   if (!copied) {   // the old arrays are untouched; the new blocks go back with the rest at release
     return fail(IBB_E_DEVICE, "copy failed while growing the box list");
   }
-  if (g_rows) { M.put(P.hist_n); M.put(P.hist_h); M.put(P.hist_cyc); M.put(P.hist_mask); M.put(P.hist_mid); }
+  if (g_rows) {
+    M.put(P.hist_n); M.put(P.hist_h); M.put(P.hist_cyc); M.put(P.hist_mask); M.put(P.hist_mid);
+    if (P.pieces == 4) M.put(P.hist_cut);
+  }
   if (g_keys) { M.put(P.key_flo); M.put(P.key_seq); M.put(P.key_ref); M.put(P.key_r); M.put(P.key_wmax); }
   if (g_tr) M.put(P.tr_gub);
   P = Q;
@@ -2549,6 +2900,14 @@ ibb_status check_options(const ibb_options& o) {
   if (o.incremental && o.bound_shape != 0)
     return fail(IBB_E_INVALID, "bound_shape applies to full bounds (incremental = 0)");
   if (o.max_sweeps < 0) return fail(IBB_E_INVALID, "max_sweeps must be >= 0");
+  const int pc = o.pieces == 0 ? 2 : o.pieces;   // 0: the default, bisection
+  if (!((pc == 2 && o.diag_samples == 0) || (pc == 4 && o.diag_samples >= 1 && o.diag_samples <= kMaxSamples)))
+    return fail(IBB_E_INVALID, "pieces and diag_samples: 2 and 0 (bisection, midpoint), or 4 and 1..16 (the paper's schedule)");
+  if (pc == 4) {
+    if (!o.incremental || o.select_k != 1 || o.precision != IBB_FP64 || o.bound_shape != 0)
+      return fail(IBB_E_INVALID, "the four-piece schedule runs with incremental bounds, select_k = 1 and FP64");
+    if (o.split_dims > 12) return fail(IBB_E_INVALID, "the four-piece schedule splits at most 12 coordinates (4^12 children)");
+  }
   return IBB_OK;
 }
 
@@ -2671,8 +3030,11 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
     // incremental bounds on a list one workgroup scans quickly: a whole chunk of
     // sweeps in one launch, as many as keep the list's growth within a bound
     const bool multi = P.select_k > 1;   // K boxes per sweep: a selection kernel and a bound kernel per sweep
-    const bool persist = !multi && P.incremental && U.n_keys <= kPersistentMaxKeys;
+    const bool four = P.pieces == 4;     // the paper's schedule: selection, tables, children kernels per sweep
+    const bool persist = !multi && !four && P.incremental && U.n_keys <= kPersistentMaxKeys;
     int chunk = persist ? (int)std::min<int64_t>(std::max<int64_t>(kPersistentGrowth / P.nch, 16), 256) : grow_chunk;
+    if (!persist)   // the key arrays are sized for every child of the chunk surviving: keep that within 2^23 keys
+      chunk = (int)std::max<int64_t>(1, std::min<int64_t>(chunk, ((int64_t)1 << 23) / ((int64_t)P.select_k * P.nch)));
     if (U.opts.time_limit_s > 0.0) chunk = std::min(chunk, grow_chunk);   // the limit is checked between launches
     if ((st = run_capacity(U, chunk)) != IBB_OK) return st;
     const int sb = sel_blocks_for(U.n_keys + (int64_t)(chunk + 1) * P.nch);
@@ -2684,12 +3046,28 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
       for (size_t e = old_n; e < ev.size(); ++e)
         if (hipEventCreate(&ev[e]) != hipSuccess) return (fail(IBB_E_DEVICE, "hipEventCreate failed"));
     }
+    // LDS of the children kernel of the four-piece schedule: table rows for at most
+    // m affected terms (2 m + 2 for the chained family), 3 m test rows
+    const int rows4 = P.family == IBB_CHAIN ? 2 * P.m + 2 : P.m;
+    const size_t lds4 = (size_t)rows4 * 16 * (2 + P.nsamp) * sizeof(double) + (size_t)3 * P.m * 64 * sizeof(int);
     dispatch_family(P.family, [&](auto fam) {
       constexpr int FAM = decltype(fam)::value;
       if (persist) {
         hipExtLaunchKernelGGL((k_sweeps_ib<kSweepThreads, FAM>), dim3(1), dim3(kSweepThreads), 0, M.stream,
                               prof ? ev[0] : nullptr, prof ? ev[3] : nullptr, 0, U.dP, U.dS, chunk);
         return;
+      }
+      for (int s = 0; s < chunk && four; ++s) {
+        if (sb > 1)
+          hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
+                                nullptr, 0, U.dP, U.dS);
+        hipExtLaunchKernelGGL(k_select4<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
+                              (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
+                              U.dS, sb > 1 ? sb : 0, 0);
+        hipExtLaunchKernelGGL((k_prep4<kSweepThreads, FAM>), dim3(1), dim3(kSweepThreads), 0, M.stream,
+                              prof ? ev[4 * s + 1] : nullptr, nullptr, 0, U.dP, U.dS);
+        hipExtLaunchKernelGGL(k_children4<FAM>, dim3((unsigned)((P.nch + 255) / 256)), dim3(256), lds4, M.stream,
+                              nullptr, prof ? ev[4 * s + 2] : nullptr, 0, U.dP, U.dS, rows4);
       }
       for (int s = 0; s < chunk && multi; ++s) {
         hipExtLaunchKernelGGL(k_select_k<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
@@ -2738,7 +3116,7 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
           if (hipEventElapsedTime(&ms, ev[4 * s + 0], ev[4 * s + 3]) == hipSuccess) R->info.t_select_ms += ms;
           R->info.n_select_launches++;
         }
-        if (s < ran && (!P.incremental || multi)) {
+        if (s < ran && (!P.incremental || multi || four)) {
           if (hipEventElapsedTime(&ms, ev[4 * s + 1], ev[4 * s + 2]) == hipSuccess) R->info.t_bound_ms += ms;
           R->info.n_bound_launches++;
         }
@@ -2750,6 +3128,11 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
       // insert the last sweep's children, then stop
       if (multi) {
         hipLaunchKernelGGL(k_select_k<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS, 1);
+      } else if (four) {
+        const int sbf = sel_blocks_for(U.hs.n_keys);
+        if (sbf > 1) hipLaunchKernelGGL(k_select_part, dim3(sbf), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+        hipLaunchKernelGGL(k_select4<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP, U.dS,
+                           sbf > 1 ? sbf : 0, 1);
       } else {
         const int sbf = sel_blocks_for(U.hs.n_keys);
         if (sbf > 1) hipLaunchKernelGGL(k_select_part, dim3(sbf), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
@@ -2785,6 +3168,8 @@ ibb_status ibb_options_default(ibb_options* o) {
   o->profile = 0;
   o->bound_shape = 0;
   o->incremental = 1;
+  o->pieces = 2;
+  o->diag_samples = 0;
   o->reserved = 0;
   return IBB_OK;
 }

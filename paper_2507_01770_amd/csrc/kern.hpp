@@ -72,6 +72,15 @@ struct SelRec {
   uint32_t mask, pad;
 };
 constexpr int kMaxSelectK = 1024;         // K <= 1024 boxes per sweep
+constexpr int kMaxSamples = 16;           // diagonal samples per child
+// piece tables of one sweep (four pieces per split coordinate): at most
+// kTabRows affected terms (combinations of the pieces of their one or two
+// coordinates) and kTabRows affected derivative coordinates (pieces of up to
+// three coordinates)
+constexpr int kTabRows = 48;
+constexpr int kTabEntry = 2 + kMaxSamples;   // F (-lo, hi), then the sample upper bounds
+constexpr int kTabDoubles = kTabRows * 16 * kTabEntry + 2 + kMaxSamples + 1 + kMaxSplit * 4;
+constexpr int kTabInts = 4 + kTabRows * (1 + 2) + kTabRows * (1 + 3) + kTabRows * 64;
 
 struct Params {
   int32_t family, n, m, nch;              // nch = 2^m children per selected box
@@ -120,6 +129,14 @@ struct Params {
   // box p of sweep t has row 1 + t K + p, its children are records p nch + c)
   int32_t select_k, pad_k;
   SelRec* sel_tab;                        // [select_k]
+  // the schedule of the paper's experiments: pieces = 4 cuts each split
+  // coordinate into four (nch = 4^m children), nsamp > 0 samples every child at
+  // nsamp points of its diagonal (cs[s]: the double nearest (s + 1) / (nsamp + 1))
+  int32_t pieces, nsamp;
+  double cs[kMaxSamples];
+  double* hist_cut;                       // [row][kMaxSplit][3] cut points of 4-piece rows
+  double* tab;                            // the sweep's piece tables (kTabDoubles)
+  int32_t* tabi;                          // their index part (kTabInts)
 };
 
 struct State {
@@ -183,6 +200,52 @@ struct ChildRow {
     return x;
   }
 };
+
+// child r of a stored row cut into four pieces per split coordinate: coordinate
+// (cyc + j) mod n takes piece (r >> 2j) & 3 of [lo, c_1, c_2, c_3, hi]
+struct ChildRow4 {
+  const double* pn;
+  const double* ph;
+  const double* cut;   // [kMaxSplit][3]
+  int n, m, cyc;
+  uint32_t mask, r;
+  __device__ __forceinline__ I get(int i) const {
+    I x{G(pn)[i], G(ph)[i]};
+    int j = i - cyc;
+    if (j < 0) j += n;
+    if (j < m && ((mask >> j) & 1u)) {
+      const int d = (int)((r >> (2 * j)) & 3u);
+      if (d > 0) x.n = neg(G(cut)[3 * j + d - 1]);
+      if (d < 3) x.h = G(cut)[3 * j + d];
+    }
+    return x;
+  }
+};
+
+// the cut points of [lo, hi] = (-x.n, x.h) into four pieces: lo + w I, w =
+// (hi - lo) / 4, I = 1, 2, 3, every operation rounded up (the kernels run in
+// round-up mode), each kept inside [previous cut, hi]; true when every piece has
+// positive width
+__device__ __forceinline__ bool cuts4(I x, double* c) {
+  const double w = (x.h + x.n) * 0.25;
+  double prev = neg(x.n);
+  bool ok = true;
+  for (int q = 0; q < 3; ++q) {
+    double v = w * (double)(q + 1) - x.n;
+    v = dmin(dmax(v, prev), x.h);
+    ok = ok && prev < v;
+    c[q] = v;
+    prev = v;
+  }
+  return ok && prev < x.h;
+}
+
+// coordinate of a diagonal sample of [lo, hi] = (-x.n, x.h): lo + (hi - lo) c,
+// each operation rounded up, kept inside [lo, hi]
+__device__ __forceinline__ double diag_coord(I x, double c) {
+  const double v = (x.h + x.n) * c - x.n;
+  return dmin(dmax(v, neg(x.n)), x.h);
+}
 
 // wave-level helpers ---------------------------------------------------------
 

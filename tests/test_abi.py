@@ -43,7 +43,7 @@ def _solve_rc(**kw):
     k = ibb._ProblemKeep(args["family"], args["coef"], args["lower"], args["upper"], args["tol_f"], args["tol_x"])
     o = ibb._Options()
     ibb.lib().ibb_options_default(C.byref(o))
-    for key in ("split_dims", "select_k", "precision"):
+    for key in ("split_dims", "select_k", "precision", "pieces", "diag_samples", "incremental"):
         if key in kw:
             setattr(o, key, kw[key])
     h = C.c_void_p()
@@ -62,6 +62,13 @@ def _solve_rc(**kw):
     (dict(select_k=0), "select_k"),
     (dict(select_k=1025), "select_k"),
     (dict(select_k=1024, split_dims=15), "2^24"),
+    (dict(pieces=3), "pieces"),
+    (dict(pieces=4, diag_samples=0), "pieces"),
+    (dict(pieces=2, diag_samples=10), "pieces"),
+    (dict(pieces=4, diag_samples=17), "pieces"),
+    (dict(pieces=4, diag_samples=10, select_k=2), "four-piece"),
+    (dict(pieces=4, diag_samples=10, incremental=0), "four-piece"),
+    (dict(pieces=4, diag_samples=10, split_dims=13), "12 coordinates"),
 ])
 def test_validation_rejects_before_touching_the_device(kw, msg):
     rc, err = _solve_rc(**kw)

@@ -1,0 +1,126 @@
+"""The schedule of the paper's experiments on the GPU (ibb_solve through the C
+ABI): m cycled coordinates cut into four equal pieces each (Eqs. (8)-(11)), 4^m
+children per sweep, ten diagonal samples per child, stop when every side of
+every listed box is narrower than 1e-4 (Sec. 4).
+
+Chained family: bit-identical to the oracle sweep by sweep (GUB, children
+inserted, live count, selected box) and in the output boxes, including the
+Rosenbrock function of Eqs. (S22)-(S23) at n = 50 with the paper's 4^10
+children per sweep.  Rastrigin (Eqs. (S14)-(S15), the separable cosine family
+with a = 1, b = 10, k = 1, c = 0 on [-5.5, 6]^n): the iteration counts and
+output-region counts the paper prints in Table S7 (fixture
+tests/golden/paper_schedule_results.txt) at n = 50 and 100, and the oracle's
+run at n = 20 (the same path up to the last bits of the trig enclosures).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle_runs as ORC
+from paper_2507_01770_amd import problems as PR
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2507_01770_amd as ibb  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_schedule_results.txt")
+PAPER = dict(pieces=4, samples=10)
+
+
+def paper_rows():
+    rows = {}
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.strip() and not line.lstrip().startswith("#"):
+                fn, n, it, reg, src = line.split()
+                rows[(fn, int(n))] = (int(it), int(reg))
+    return rows
+
+
+def rastrigin(n):
+    coef = np.concatenate([np.ones(n), 10.0 * np.ones(n), np.ones(n), np.zeros(n)])
+    return PR.Problem(PR.SEP_COS, n, coef, np.full(n, -5.5), np.full(n, 6.0), tol_f=1e300, tol_x=1e-4,
+                      x_star=np.zeros(n))
+
+
+def rosenbrock(n):
+    coef = np.concatenate([100.0 * np.ones(n - 1), np.ones(n - 1)])
+    return PR.Problem(PR.CHAIN, n, coef, np.full(n, -30.0), np.full(n, 30.0), tol_f=1e300, tol_x=1e-4,
+                      x_star=np.ones(n))
+
+
+def chain_width(n, hi, seed=505):
+    p = PR.chain(n, seed, hi=hi)
+    p.tol_f, p.tol_x = 1e300, 1e-4
+    return p
+
+
+# (problem, split width, sweep budget)
+CHAIN_CASES = [("chain_n6", lambda: chain_width(6, 2.3), 3, 100000), ("chain_n12", lambda: chain_width(12, 2.3), 4, 40),
+               ("chain_n7_wrap", lambda: chain_width(7, 2.0), 5, 60), ("rosenbrock_n50", lambda: rosenbrock(50), 10, 100000)]
+for _name, _make, _m, _budget in CHAIN_CASES:
+    ORC.prefetch(_make(), split_dims=_m, max_sweeps=_budget, incremental=True, **PAPER)
+ORC.prefetch(rastrigin(20), split_dims=10, max_sweeps=100000, incremental=True, **PAPER)
+
+
+def gpu(p, m, budget, **kw):
+    return ibb.minimize(p, split_dims=m, max_sweeps=budget, pieces=4, diag_samples=10, max_boxes_fetched=200_000, **kw)
+
+
+@pytest.mark.parametrize("name,make,m,budget", CHAIN_CASES)
+def test_chain_identical_to_oracle(name, make, m, budget):
+    p = make()
+    print(f"case {name} m={m} budget={budget}", flush=True)
+    r = gpu(p, m, budget)
+    o = ORC.solve(p, split_dims=m, max_sweeps=budget, incremental=True, **PAPER)
+    assert r.status == o.status and r.sweeps == o.sweeps and r.boxes_evaluated == o.boxes_evaluated
+    assert np.array_equal(r.trace_gub, o.trace_gub)
+    assert np.array_equal(r.trace_nsurv, o.trace_nsurv)
+    assert np.array_equal(r.trace_nlive, o.trace_nlive)
+    assert np.array_equal(r.trace_sel, o.trace_sel)
+    assert r.f_lo == o.f_lo and r.f_hi == o.f_hi
+    assert r.n_boxes == len(o.flo)
+    assert np.array_equal(r.seq, o.seq) and np.array_equal(r.flo, o.flo)
+    assert np.array_equal(r.lo, o.lo) and np.array_equal(r.hi, o.hi)
+    if r.status == ibb.OK:
+        assert np.all(r.hi - r.lo < 1e-4)
+        assert np.any(np.all((r.lo <= p.x_star) & (p.x_star <= r.hi), axis=1))
+
+
+@pytest.mark.parametrize("n", [50, 100])
+def test_rastrigin_matches_table_s7(n):
+    p = rastrigin(n)
+    print(f"case rastrigin n={n}", flush=True)
+    r = gpu(p, 10, 100000)
+    it, reg = paper_rows()[("rastrigin", n)]
+    assert r.status == ibb.OK and r.sweeps == it and r.n_boxes == reg
+    assert np.all(r.hi - r.lo < 1e-4) and np.all((r.lo <= 0.0) & (0.0 <= r.hi))
+    assert r.f_lo <= 0.0 <= r.f_hi
+    assert r.boxes_evaluated == 1 + it * 4 ** 10
+
+
+def test_rastrigin_n20_follows_the_oracle():
+    p = rastrigin(20)
+    r = gpu(p, 10, 100000)
+    o = ORC.solve(p, split_dims=10, max_sweeps=100000, incremental=True, **PAPER)
+    assert r.status == o.status == ibb.OK and r.sweeps == o.sweeps == 18
+    assert np.array_equal(r.trace_nsurv, o.trace_nsurv) and np.array_equal(r.trace_sel, o.trace_sel)
+    assert np.allclose(r.trace_gub, o.trace_gub, rtol=1e-12, atol=1e-300)
+    assert np.array_equal(r.lo, o.lo) and np.array_equal(r.hi, o.hi)
+
+
+def test_four_pieces_continue_the_same_run():
+    p = chain_width(12, 2.3)
+    whole = gpu(p, 4, 25, fetch_boxes=False)
+    with ibb.Run(p, split_dims=4, max_sweeps=5, pieces=4, diag_samples=10) as run:
+        for _ in range(4):
+            run.sweep(5)
+        got = run.result(fetch_boxes=False)
+    assert (got.status, got.sweeps, got.f_lo, got.f_hi, got.n_boxes) == \
+        (whole.status, whole.sweeps, whole.f_lo, whole.f_hi, whole.n_boxes)
+    assert np.array_equal(got.trace_gub, whole.trace_gub) and np.array_equal(got.flo, whole.flo)
