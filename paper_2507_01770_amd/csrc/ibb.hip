@@ -541,6 +541,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_part(const Params* __res
 template <int NT, int PIECES = 2>
 __device__ __forceinline__ bool select_body(const Params& P, State* S, int nparts, int host_stop) {
   const double gub = okey_inv(S->gub_key);
+  // every thread reads the pending flag before the scan's barriers: thread 0 sets
+  // it again in select_finish with no barrier in between, so a later read could see
+  // the new value in some wavefronts and send them alone into insert_children
+  const int32_t pending = S->pending;
   SelAcc a = sel_empty();
   if (nparts == 0) {
     a = scan_select_wg<NT>(P, gub, S->n_keys);
@@ -551,7 +555,7 @@ __device__ __forceinline__ bool select_body(const Params& P, State* S, int npart
     }
     a = sel_block_reduce<NT>(a);
   }
-  if (S->pending) insert_children<NT>(P, S, gub, a);
+  if (pending) insert_children<NT>(P, S, gub, a);
   if (host_stop) {   // the host ends the run here (time limit): keep the inserted list
     if (threadIdx.x == 0) {
       const int64_t t = S->sweeps;
@@ -3079,7 +3083,7 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
           launch_bound<FAM>(bound_shape, P.select_k * P.nch, M.stream, prof ? ev[4 * s + 1] : nullptr,
                             prof ? ev[4 * s + 2] : nullptr, U.dP, U.dS);
       }
-      for (int s = 0; s < chunk && !multi; ++s) {
+      for (int s = 0; s < chunk && !multi && !four; ++s) {
         if (sb > 1)
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
                                 nullptr, 0, U.dP, U.dS);
