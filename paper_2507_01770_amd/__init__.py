@@ -275,6 +275,7 @@ class Result:
     fp64_confirmed: int = 0        # boxes bounded in FP64
     fp32_sweeps: int = 0           # sweeps in which the FP32 filter ran
     bound_shape: int = -1          # shape of the bound kernel (0..4), picked by the autotuner unless forced
+    n_persistent_launches: int = 0   # launches of the persistent sweep kernel (profile=True)
 
 
 def minimize(problem=None, *, family=None, coef=None, lower=None, upper=None, tol_f=None, tol_x=None,
@@ -326,7 +327,8 @@ def _read_result(h, n, fetch_boxes=True, max_boxes_fetched=100_000) -> Result:
     return Result(info.f_lo, info.f_hi, info.status, info.sweeps, info.boxes_evaluated, nb, info.seconds,
                   lo, hi, flo, seq, tg[:got], tn[:got], tl[:got], tsel[:got], info.ub_evaluated,
                   info.t_bound_ms, info.t_select_ms, info.n_bound_launches, info.n_select_launches,
-                  info.fp32_pruned, info.fp64_confirmed, info.fp32_sweeps, info.bound_shape)
+                  info.fp32_pruned, info.fp64_confirmed, info.fp32_sweeps, info.bound_shape,
+                  info.n_persistent_launches)
 
 
 class Run:

@@ -45,3 +45,15 @@ def test_traffic_reported_only_for_the_measured_sources(tmp_path, monkeypatch):
 def test_traffic_absent_without_a_profile(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic() is None
+
+
+def test_every_result_field_bench_reads_exists():
+    # bench.py reads solve results through these names; each must be a Result field
+    import dataclasses
+    import re
+    import paper_2507_01770_amd as ibb
+    fields = {f.name for f in dataclasses.fields(ibb.Result)}
+    text = open(os.path.join(ROOT, "bench.py")).read()
+    used = set(re.findall(r"\b(?:r|rp|rp1|rq|rs1|res)\.([a-z_][a-z0-9_]*)\b", text))
+    assert used, "no result fields found"
+    assert used <= fields, sorted(used - fields)
