@@ -135,12 +135,20 @@ def main() -> int:
                  "ms_per_solve": round(dt1 / args.k_steps * 1e3, 4), "sweeps": rp1.sweeps,
                  "boxes_per_solve": rp1.boxes_evaluated, "enclosure": [rp1.f_lo, rp1.f_hi]}
             if rp1.n_bound_launches:
-                formed = rp1.boxes_evaluated - 1 - rp1.fp32_pruned   # children bounded in FP64
-                ops = p1.n * formed * SEP_OPS * 1.0
+                if kw.get("incremental"):
+                    # k_ib_parents: one workgroup per selected box; per box the incremental
+                    # sweep's work (its 2^m children, each parent's shared terms once)
+                    parents = (rp1.boxes_evaluated - 1) / (1 << m1)
+                    ops = parents * incremental_ops_per_sweep(p1.n, m1)
+                    kname = "k_ib_parents<512, SEP_COS>"
+                else:
+                    formed = rp1.boxes_evaluated - 1 - rp1.fp32_pruned   # children bounded in FP64
+                    ops = p1.n * formed * SEP_OPS * 1.0
+                    kname = "k_bound<SEP_COS> (shape %d)" % rp1.bound_shape
                 tb = rp1.t_bound_ms * 1e-3
                 a = ops / tb / 1e12 if tb > 0 else 0.0
                 d["bound_kernel"] = {
-                    "kernel": "k_bound<SEP_COS> (shape %d)" % rp1.bound_shape, "achieved": round(a, 4),
+                    "kernel": kname, "achieved": round(a, 4),
                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(a / PEAK_FP64_TFLOPS, 5),
                     "avg_launch_us": round(rp1.t_bound_ms * 1e3 / rp1.n_bound_launches, 3),
                     "ops_per_launch": round(ops / rp1.n_bound_launches),
@@ -225,10 +233,13 @@ def cpu_baseline(p, sweeps: int) -> dict:
     o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=sweeps, incremental=True)
     t1 = time.perf_counter() - tc
     one = o.boxes_evaluated / t1
+    phase(f"cpu baseline: one thread, {o.boxes_evaluated} boxes in {t1:.1f} s")
     cores = min(16, len(os.sched_getaffinity(0)))
-    code = ("import sys; sys.path.insert(0, %r); from oracle import oracle as O; "
-            "from paper_2507_01770_amd import problems as PR; p = PR.config(3); "
-            "O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=%d, incremental=True)") % (ROOT, sweeps)
+    code = ("import sys, time; sys.path.insert(0, %r); from oracle import oracle as O; "
+            "from paper_2507_01770_amd import problems as PR; p = PR.config(3); t = time.perf_counter(); "
+            "O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=%d, incremental=True); "
+            "print('bench: cpu baseline: a copy finished in %%.1f s' %% (time.perf_counter() - t), "
+            "file=sys.stderr, flush=True)") % (ROOT, sweeps)
     tc = time.perf_counter()
     procs = [subprocess.Popen([sys.executable, "-c", code]) for _ in range(cores)]
     ok = all(pr.wait() == 0 for pr in procs)
