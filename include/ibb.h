@@ -227,7 +227,8 @@ ibb_status ibb_eval_boxes(const ibb_problem* prob, int32_t precision, int64_t nb
 /* Elementwise interval operations with outward rounding (Sec. 2.1, Eqs. (3)-(6)),
  * for testing the arithmetic.  d_a, d_b, d_out: device [count][2] (lo, hi).
  * op: 0 add, 1 sub, 2 mul, 3 div (= a * (1/b), Eq. (6)), 4 sqrt, 5 sqr, 6 abs,
- * 7 reciprocal, 8 cos(2 pi a), 9 sin(2 pi a), 10 derivative of |.|.
+ * 7 reciprocal, 8 cos(2 pi a), 9 sin(2 pi a), 10 derivative of |.|, 11 exp,
+ * 12 cos(a), 13 sin(a) (a in radians: cos / sin(2 pi y) of y = a [1 / (2 pi)]).
  * Unary ops ignore d_b (may be NULL).  A divisor that contains 0 gives
  * [-inf, +inf]. */
 ibb_status ibb_interval_op(int32_t op, int64_t count, const double* d_a, const double* d_b, double* d_out,

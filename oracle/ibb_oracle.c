@@ -345,6 +345,337 @@ static iv canonical_sum_except(const orc_problem* P, const iv* X, const unsigned
 
 static iv canonical_sum(const orc_problem* P, const iv* X) { return canonical_sum_except(P, X, NULL); }
 
+/* ------------------------------------------------------------------------- */
+/* generic closed-form f: an expression tape                                 */
+/*                                                                           */
+/* f = g(R_1, ..., R_K): each R_k is a sum or a product over i in a range of */
+/* an element expression e_k(x_i, x_{i+1}, i), and g is a scalar expression  */
+/* of the R_k and constants.  This covers the benchmark functions of the     */
+/* paper's SI Appendix A (Eqs. S1-S21) and Appendix D (Eq. S22), which are    */
+/* sums and products over the coordinates with an outer nonlinearity.        */
+/*                                                                           */
+/* The tape is carried in the problem's coefficient array (doubles):         */
+/*   [1, K, Q, C]                                                            */
+/*   K reductions: [kind (0 sum, 1 product), s_off, s_end, t_off, t_end, L]   */
+/*                 then L ops of 5 doubles [code, a, b, c_lo, c_hi]          */
+/*                 (range: i from s_off + (s_end ? n : 0) to t_off +           */
+/*                  (t_end ? n : 0), exclusive)                               */
+/*   Q scalar ops of 5 doubles; the last one's value is f                    */
+/*   C coefficient columns of n doubles                                      */
+/* Operands a, b index earlier ops of the same program.                      */
+/*                                                                           */
+/* Values are intervals (Sec. 2.1, Eqs. (3)-(6), outward rounding).          */
+/* Derivatives: the element programs carry forward tangents with respect to   */
+/* x_i and x_{i+1}; the scalar program is differentiated in reverse (adjoint  */
+/* intervals); then G_j = sum over k of adj(R_k) dR_k/dx_j, k increasing,     */
+/* where for a sum dR/dx_j = D0 e(j) + D1 e(j-1) and for a product            */
+/* dR/dx_j = D0 e(j) * (prod_{i<j} e(i)) * (prod_{i>j} e(i)), the left        */
+/* product taken left to right and the right one nested from the right.     */
+/* Orders: sums and products run left to right over i; adjoint contributions */
+/* are added in reverse op order.  These orders define the bounds.           */
+/* ------------------------------------------------------------------------- */
+
+enum { FAM_TAPE = 4 };
+enum { T_CONST = 0, T_X = 1, T_XNEXT = 2, T_COEF = 3, T_ADD = 4, T_SUB = 5, T_MUL = 6, T_DIV = 7, T_NEG = 8,
+       T_SQR = 9, T_SQRT = 10, T_EXP = 11, T_COS = 12, T_SIN = 13, T_COS2PI = 14, T_SIN2PI = 15, T_ABS = 16,
+       T_RED = 17, T_INDEX = 18 };
+#define TAPE_MAX_OPS 64
+#define TAPE_MAX_RED 8
+
+typedef struct { int code, a, b; double clo, chi; } tape_op;
+typedef struct { int kind, start, stop, nops; tape_op op[TAPE_MAX_OPS]; } tape_red;
+typedef struct { int K, Q, C; tape_red red[TAPE_MAX_RED]; tape_op sc[TAPE_MAX_OPS]; const double* col; } tape;
+
+/* an op that the stage does not allow, or whose operands are not earlier ops */
+static int tape_op_bad(const tape_op* o, int q, int elem, int lim) {
+  const int c = o->code;
+  if (c < 0 || c > T_INDEX) return 1;
+  if (elem && c == T_RED) return 1;
+  if (!elem && (c == T_X || c == T_XNEXT || c == T_COEF || c == T_INDEX)) return 1;
+  if ((c == T_COEF || c == T_RED) && (o->a < 0 || o->a >= lim)) return 1;
+  if (c >= T_ADD && c <= T_ABS && (o->a < 0 || o->a >= q)) return 1;
+  if (c >= T_ADD && c <= T_DIV && (o->b < 0 || o->b >= q)) return 1;
+  if (c == T_CONST && !(o->clo <= o->chi)) return 1;
+  return 0;
+}
+
+static int tape_parse(const orc_problem* P, tape* T) {
+  const double* c = P->coef;
+  const int64_t n = P->n, len = P->coef_len;
+  if (len < 4 || c[0] != 1.0) return -1;
+  T->K = (int)c[1]; T->Q = (int)c[2]; T->C = (int)c[3];
+  if (T->K < 0 || T->K > TAPE_MAX_RED || T->Q < 1 || T->Q > TAPE_MAX_OPS || T->C < 0) return -1;
+  int64_t at = 4;
+  for (int k = 0; k < T->K; ++k) {
+    if (at + 6 > len) return -1;
+    tape_red* R = &T->red[k];
+    R->kind = (int)c[at];
+    int64_t s = (int64_t)c[at + 1] + (c[at + 2] != 0.0 ? n : 0), t = (int64_t)c[at + 3] + (c[at + 4] != 0.0 ? n : 0);
+    R->nops = (int)c[at + 5];
+    at += 6;
+    if (R->nops < 1 || R->nops > TAPE_MAX_OPS || at + 5 * R->nops > len) return -1;
+    if (s < 0) s = 0;
+    if (t > n) t = n;
+    R->start = (int)s; R->stop = (int)(t > s ? t : s);
+    for (int q = 0; q < R->nops; ++q, at += 5) {
+      R->op[q].code = (int)c[at]; R->op[q].a = (int)c[at + 1]; R->op[q].b = (int)c[at + 2];
+      R->op[q].clo = c[at + 3]; R->op[q].chi = c[at + 4];
+      if (tape_op_bad(&R->op[q], q, 1, T->C)) return -1;
+      if (R->op[q].code == T_XNEXT && (R->kind != 0 || R->stop > n - 1)) return -1;
+    }
+  }
+  if (at + 5 * T->Q > len) return -1;
+  for (int q = 0; q < T->Q; ++q, at += 5) {
+    T->sc[q].code = (int)c[at]; T->sc[q].a = (int)c[at + 1]; T->sc[q].b = (int)c[at + 2];
+    T->sc[q].clo = c[at + 3]; T->sc[q].chi = c[at + 4];
+    if (tape_op_bad(&T->sc[q], q, 0, T->K)) return -1;
+  }
+  if (at + (int64_t)T->C * n != len) return -1;
+  T->col = c + at;
+  return 0;
+}
+
+/* exp enclosure of a double: expl in extended precision +- |v| 2^-58 */
+static void pt_exp(double x, double* lo, double* hi) {
+  if (x == 0.0) { *lo = *hi = 1.0; return; }
+  if (isinf(x)) { *lo = *hi = x > 0 ? INFINITY : 0.0; return; }
+  long double v = expl((long double)x);
+  long double m = v * 0x1p-58L;
+  volatile long double vv = v, mm = m;
+  fesetround(FE_DOWNWARD);
+  volatile long double l = vv - mm;
+  volatile double ld = (double)l;
+  fesetround(FE_UPWARD);
+  volatile long double h = vv + mm;
+  volatile double hd = (double)h;
+  fesetround(FE_TONEAREST);
+  *lo = ld < 0.0 ? 0.0 : ld;
+  *hi = hd;
+}
+static iv iv_exp(iv a) {
+  if (bad(a)) return mk(0.0, INFINITY);
+  double l, h, t;
+  pt_exp(a.lo, &l, &t);
+  pt_exp(a.hi, &t, &h);
+  return mk(l, h);
+}
+/* [1 / (2 pi)]: the two adjacent doubles around it (1 / (2 pi) =
+ * 0.15915494309189533576888..., between 0x3FC45F306DC9C882 = 0.159154943091895317...
+ * and 0x3FC45F306DC9C883 = 0.159154943091895345...) */
+static iv inv_two_pi(void) { return mk(hexd(0x3FC45F306DC9C882ull), hexd(0x3FC45F306DC9C883ull)); }
+/* [2 pi] from the doubles around pi (exact doubling) */
+static iv two_pi(void) { return mk(2.0 * hexd(PI_LO_BITS), 2.0 * hexd(PI_HI_BITS)); }
+static iv iv_cos(iv a) { return iv_cos2pi(iv_mul(a, inv_two_pi())); }
+static iv iv_sin(iv a) { return iv_sin2pi(iv_mul(a, inv_two_pi())); }
+static iv iv_neg(iv a) { return mk(-a.hi, -a.lo); }
+
+/* value with optional tangents (d0: d/dx_i, d1: d/dx_{i+1}); has0/has1 = 0: exactly zero */
+typedef struct { iv v, d0, d1; int has0, has1; } tv;
+
+static iv acc_add(iv s, int* has, iv t) { if (*has) return iv_add(s, t); *has = 1; return t; }
+
+/* the value of one op from its operands' values (shared by both stages) */
+static iv op_value(const tape_op* o, const iv* V, iv x0, iv x1, int64_t i, const tape* T, int64_t n,
+                   const iv* red) {
+  switch (o->code) {
+  case T_CONST: return mk(o->clo, o->chi);
+  case T_X: return x0;
+  case T_XNEXT: return x1;
+  case T_COEF: { double v = T->col[(int64_t)o->a * n + i]; return mk(v, v); }
+  case T_INDEX: return mk((double)(i + 1), (double)(i + 1));
+  case T_RED: return red[o->a];
+  case T_ADD: return iv_add(V[o->a], V[o->b]);
+  case T_SUB: return iv_sub(V[o->a], V[o->b]);
+  case T_MUL: return iv_mul(V[o->a], V[o->b]);
+  case T_DIV: return iv_div(V[o->a], V[o->b]);
+  case T_NEG: return iv_neg(V[o->a]);
+  case T_SQR: return iv_sqr(V[o->a]);
+  case T_SQRT: return iv_sqrt(V[o->a]);
+  case T_EXP: return iv_exp(V[o->a]);
+  case T_COS: return iv_cos(V[o->a]);
+  case T_SIN: return iv_sin(V[o->a]);
+  case T_COS2PI: return iv_cos2pi(V[o->a]);
+  case T_SIN2PI: return iv_sin2pi(V[o->a]);
+  case T_ABS: return iv_abs(V[o->a]);
+  }
+  return entire();
+}
+
+/* the derivative factor of a unary op u = h(a): dh/da over the operand's value a
+ * and the op's own value v */
+static iv unary_factor(int code, iv a, iv v) {
+  switch (code) {
+  case T_NEG: return mk(-1.0, -1.0);
+  case T_SQR: return iv_scale(2.0, a);
+  case T_SQRT: return iv_recip(iv_scale(2.0, v));
+  case T_EXP: return v;
+  case T_COS: return iv_neg(iv_sin(a));
+  case T_SIN: return iv_cos(a);
+  case T_COS2PI: return iv_neg(iv_mul(two_pi(), iv_sin2pi(a)));
+  case T_SIN2PI: return iv_mul(two_pi(), iv_cos2pi(a));
+  case T_ABS: return iv_dabs(a);
+  }
+  return entire();
+}
+
+/* forward pass of one element program at index i; returns the last op's value
+ * and tangents in *out */
+static void elem_eval(const tape* T, const tape_red* R, int64_t n, int64_t i, iv x0, iv x1, int want_d, tv* out) {
+  iv V[TAPE_MAX_OPS];
+  tv W[TAPE_MAX_OPS];
+  for (int q = 0; q < R->nops; ++q) {
+    const tape_op* o = &R->op[q];
+    V[q] = op_value(o, V, x0, x1, i, T, n, NULL);
+    tv w;
+    w.v = V[q]; w.has0 = w.has1 = 0; w.d0 = w.d1 = mk(0.0, 0.0);
+    if (want_d) {
+      const tv* A = o->a >= 0 && o->a < q ? &W[o->a] : NULL;
+      const tv* B = o->b >= 0 && o->b < q ? &W[o->b] : NULL;
+      switch (o->code) {
+      case T_X: w.d0 = mk(1.0, 1.0); w.has0 = 1; break;
+      case T_XNEXT: w.d1 = mk(1.0, 1.0); w.has1 = 1; break;
+      case T_ADD: case T_SUB: {
+        if (A->has0) w.d0 = acc_add(w.d0, &w.has0, A->d0);
+        if (A->has1) w.d1 = acc_add(w.d1, &w.has1, A->d1);
+        if (B->has0) w.d0 = acc_add(w.d0, &w.has0, o->code == T_SUB ? iv_neg(B->d0) : B->d0);
+        if (B->has1) w.d1 = acc_add(w.d1, &w.has1, o->code == T_SUB ? iv_neg(B->d1) : B->d1);
+        break;
+      }
+      case T_MUL: {   /* d(ab) = da b + a db */
+        if (A->has0) w.d0 = acc_add(w.d0, &w.has0, iv_mul(A->d0, B->v));
+        if (A->has1) w.d1 = acc_add(w.d1, &w.has1, iv_mul(A->d1, B->v));
+        if (B->has0) w.d0 = acc_add(w.d0, &w.has0, iv_mul(A->v, B->d0));
+        if (B->has1) w.d1 = acc_add(w.d1, &w.has1, iv_mul(A->v, B->d1));
+        break;
+      }
+      case T_DIV: {   /* d(a/b) = (da - (a/b) db) (1/b) */
+        const iv rb = iv_recip(B->v);
+        for (int s = 0; s < 2; ++s) {
+          const int ha = s ? A->has1 : A->has0, hb = s ? B->has1 : B->has0;
+          if (!ha && !hb) continue;
+          iv num;
+          if (ha && hb) num = iv_sub(s ? A->d1 : A->d0, iv_mul(V[q], s ? B->d1 : B->d0));
+          else if (ha) num = s ? A->d1 : A->d0;
+          else num = iv_neg(iv_mul(V[q], s ? B->d1 : B->d0));
+          if (s) { w.d1 = iv_mul(num, rb); w.has1 = 1; } else { w.d0 = iv_mul(num, rb); w.has0 = 1; }
+        }
+        break;
+      }
+      case T_NEG: case T_SQR: case T_SQRT: case T_EXP: case T_COS: case T_SIN: case T_COS2PI: case T_SIN2PI:
+      case T_ABS: {
+        if (!A->has0 && !A->has1) break;
+        const iv f = unary_factor(o->code, A->v, V[q]);
+        if (A->has0) { w.d0 = iv_mul(f, A->d0); w.has0 = 1; }
+        if (A->has1) { w.d1 = iv_mul(f, A->d1); w.has1 = 1; }
+        break;
+      }
+      default: break;   /* constants, coefficients, the index: no tangent */
+      }
+    }
+    W[q] = w;
+  }
+  *out = W[R->nops - 1];
+}
+
+/* F over the box X (and G when G != NULL) of a tape problem */
+static iv tape_eval(const orc_problem* P, const iv* X, iv* G) {
+  tape T;
+  if (tape_parse(P, &T) != 0) return entire();
+  const int64_t n = P->n;
+  iv red[TAPE_MAX_RED];
+  tv* E[TAPE_MAX_RED];
+  for (int k = 0; k < T.K; ++k) {
+    const tape_red* R = &T.red[k];
+    E[k] = G ? (tv*)malloc((size_t)(n > 0 ? n : 1) * sizeof(tv)) : NULL;
+    int have = 0;
+    iv acc = R->kind ? mk(1.0, 1.0) : mk(0.0, 0.0);
+    for (int64_t i = R->start; i < R->stop; ++i) {
+      tv e;
+      elem_eval(&T, R, n, i, X[i], i + 1 < n ? X[i + 1] : X[i], G != NULL, &e);
+      if (G) E[k][i] = e;
+      acc = have ? (R->kind ? iv_mul(acc, e.v) : iv_add(acc, e.v)) : e.v;
+      have = 1;
+    }
+    red[k] = acc;
+  }
+  /* scalar program: values, then adjoints in reverse */
+  iv V[TAPE_MAX_OPS];
+  for (int q = 0; q < T.Q; ++q) V[q] = op_value(&T.sc[q], V, mk(0.0, 0.0), mk(0.0, 0.0), 0, &T, n, red);
+  iv F = V[T.Q - 1];
+  if (!G) return F;
+  iv A[TAPE_MAX_OPS], AR[TAPE_MAX_RED];
+  int hA[TAPE_MAX_OPS], hR[TAPE_MAX_RED];
+  for (int q = 0; q < T.Q; ++q) { hA[q] = 0; A[q] = mk(0.0, 0.0); }
+  for (int k = 0; k < T.K; ++k) { hR[k] = 0; AR[k] = mk(0.0, 0.0); }
+  A[T.Q - 1] = mk(1.0, 1.0); hA[T.Q - 1] = 1;
+  for (int q = T.Q - 1; q >= 0; --q) {
+    if (!hA[q]) continue;
+    const tape_op* o = &T.sc[q];
+    const iv a = A[q];
+    switch (o->code) {
+    case T_RED: AR[o->a] = acc_add(AR[o->a], &hR[o->a], a); break;
+    case T_ADD: A[o->a] = acc_add(A[o->a], &hA[o->a], a); A[o->b] = acc_add(A[o->b], &hA[o->b], a); break;
+    case T_SUB: A[o->a] = acc_add(A[o->a], &hA[o->a], a); A[o->b] = acc_add(A[o->b], &hA[o->b], iv_neg(a)); break;
+    case T_MUL:
+      A[o->a] = acc_add(A[o->a], &hA[o->a], iv_mul(a, V[o->b]));
+      A[o->b] = acc_add(A[o->b], &hA[o->b], iv_mul(a, V[o->a]));
+      break;
+    case T_DIV: {
+      const iv rb = iv_recip(V[o->b]);
+      A[o->a] = acc_add(A[o->a], &hA[o->a], iv_mul(a, rb));
+      A[o->b] = acc_add(A[o->b], &hA[o->b], iv_neg(iv_mul(a, iv_mul(V[q], rb))));
+      break;
+    }
+    case T_NEG: case T_SQR: case T_SQRT: case T_EXP: case T_COS: case T_SIN: case T_COS2PI: case T_SIN2PI:
+    case T_ABS:
+      A[o->a] = acc_add(A[o->a], &hA[o->a], iv_mul(a, unary_factor(o->code, V[o->a], V[q])));
+      break;
+    default: break;
+    }
+  }
+  /* products: left products pre[j] = e(start) ... e(j-1) (left to right) and
+   * right products suf[j] = e(j+1) (e(j+2) (... e(stop-1))) */
+  iv* PRE[TAPE_MAX_RED];
+  iv* SUF[TAPE_MAX_RED];
+  for (int k = 0; k < T.K; ++k) {
+    PRE[k] = SUF[k] = NULL;
+    const tape_red* R = &T.red[k];
+    if (R->kind != 1 || R->stop <= R->start) continue;
+    PRE[k] = (iv*)malloc((size_t)n * sizeof(iv));
+    SUF[k] = (iv*)malloc((size_t)n * sizeof(iv));
+    PRE[k][R->start] = mk(1.0, 1.0);   /* empty */
+    for (int64_t i = R->start + 1; i < R->stop; ++i)
+      PRE[k][i] = i - 1 == R->start ? E[k][i - 1].v : iv_mul(PRE[k][i - 1], E[k][i - 1].v);
+    SUF[k][R->stop - 1] = mk(1.0, 1.0);   /* empty */
+    for (int64_t i = R->stop - 2; i >= R->start; --i)
+      SUF[k][i] = i + 1 == R->stop - 1 ? E[k][i + 1].v : iv_mul(E[k][i + 1].v, SUF[k][i + 1]);
+  }
+  /* G_j over the reductions, k increasing */
+  for (int64_t j = 0; j < n; ++j) {
+    int hg = 0;
+    iv g = mk(0.0, 0.0);
+    for (int k = 0; k < T.K; ++k) {
+      if (!hR[k]) continue;
+      const tape_red* R = &T.red[k];
+      int hd = 0;
+      iv d = mk(0.0, 0.0);
+      if (R->kind == 0) {
+        if (j >= R->start && j < R->stop && E[k][j].has0) d = acc_add(d, &hd, E[k][j].d0);
+        if (j - 1 >= R->start && j - 1 < R->stop && E[k][j - 1].has1) d = acc_add(d, &hd, E[k][j - 1].d1);
+      } else if (j >= R->start && j < R->stop && E[k][j].has0) {
+        const int hp = j > R->start, hs = j < R->stop - 1;
+        const iv loo = hp && hs ? iv_mul(PRE[k][j], SUF[k][j]) : (hp ? PRE[k][j] : (hs ? SUF[k][j] : mk(1.0, 1.0)));
+        d = iv_mul(E[k][j].d0, loo);
+        hd = 1;
+      }
+      if (hd) g = acc_add(g, &hg, iv_mul(AR[k], d));
+    }
+    G[j] = g;
+  }
+  for (int k = 0; k < T.K; ++k) { free(E[k]); free(PRE[k]); free(SUF[k]); }
+  return F;
+}
+
 /* bisection point of [lo, hi]: 0.5 lo + 0.5 hi rounded up, kept inside */
 static double midpoint(double lo, double hi) {
   double m = up_add(up_mul(0.5, lo), up_mul(0.5, hi));
@@ -354,6 +685,11 @@ static double midpoint(double lo, double hi) {
 }
 
 typedef struct { iv F; double ub; int mono; } box_eval;
+
+/* upper bound of f at a point (X holds point intervals) */
+static double point_hi(const orc_problem* P, const iv* X) {
+  return P->family == FAM_TAPE ? tape_eval(P, X, NULL).hi : canonical_sum(P, X).hi;
+}
 
 /*
  * Bound one box: F over the box, the first-order test (Sec. 3.1: discard when
@@ -365,15 +701,25 @@ static box_eval eval_box(const orc_problem* P, const double* lo, const double* h
   const int64_t n = P->n;
   box_eval r;
   for (int64_t i = 0; i < n; ++i) X[i] = mk(lo[i], hi[i]);
-  r.F = canonical_sum(P, X);
   r.mono = 0;
-  for (int64_t j = 0; j < n; ++j) {
-    iv g = grad(P, X, j);
-    if (G) G[j] = g;
-    if ((g.lo > 0.0 && lo[j] != P->lower[j]) || (g.hi < 0.0 && hi[j] != P->upper[j])) r.mono = 1;
+  if (P->family == FAM_TAPE) {
+    iv* GG = G ? G : (iv*)malloc((size_t)(n > 0 ? n : 1) * sizeof(iv));
+    r.F = tape_eval(P, X, GG);
+    for (int64_t j = 0; j < n; ++j) {
+      const iv g = GG[j];
+      if ((g.lo > 0.0 && lo[j] != P->lower[j]) || (g.hi < 0.0 && hi[j] != P->upper[j])) r.mono = 1;
+    }
+    if (!G) free(GG);
+  } else {
+    r.F = canonical_sum(P, X);
+    for (int64_t j = 0; j < n; ++j) {
+      iv g = grad(P, X, j);
+      if (G) G[j] = g;
+      if ((g.lo > 0.0 && lo[j] != P->lower[j]) || (g.hi < 0.0 && hi[j] != P->upper[j])) r.mono = 1;
+    }
   }
   for (int64_t i = 0; i < n; ++i) { double m = midpoint(lo[i], hi[i]); X[i] = mk(m, m); }
-  r.ub = canonical_sum(P, X).hi;
+  r.ub = point_hi(P, X);
   return r;
 }
 
@@ -500,7 +846,7 @@ static box_eval eval_box_samples(const orc_problem* P, const double* lo, const d
   double ub = INFINITY;
   for (int s = 0; s < S; ++s) {
     for (int64_t i = 0; i < n; ++i) { double x = diag_coord(lo[i], hi[i], cs[s]); X[i] = mk(x, x); }
-    double u = canonical_sum(P, X).hi;
+    double u = point_hi(P, X);
     if (u < ub) ub = u;
   }
   r.ub = ub;
@@ -718,6 +1064,9 @@ void* orc_solve(const orc_problem* P, const orc_options* O, int64_t trace_cap) {
   const int PC = O->pieces == 4 ? 4 : 2;                            /* subintervals per split coordinate */
   const int NS = O->samples > 0 ? (O->samples < MAX_SAMPLES ? O->samples : MAX_SAMPLES) : 0;
   const int general = PC != 2 || NS > 0;                           /* the schedule of Sec. 4 (or part of it) */
+  orc_options O_local = *O;
+  if (P->family == FAM_TAPE) O_local.incremental = 0;               /* tapes: every child bounded in full */
+  O = &O_local;
   double cs[MAX_SAMPLES];
   for (int q = 0; q < NS; ++q) cs[q] = (double)(q + 1) / (double)(NS + 1);   /* nearest double to q+1 / (S+1) */
   piece_tab* tab = general ? (piece_tab*)malloc(sizeof(piece_tab)) : NULL;
@@ -942,7 +1291,7 @@ int orc_eval_boxes(const orc_problem* P, int64_t nb, const double* lo, const dou
 
 /* op codes shared with the test suite (values chosen here) */
 enum { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_DIV = 3, OP_SQRT = 4, OP_SQR = 5, OP_ABS = 6,
-       OP_RECIP = 7, OP_COS2PI = 8, OP_SIN2PI = 9, OP_DABS = 10 };
+       OP_RECIP = 7, OP_COS2PI = 8, OP_SIN2PI = 9, OP_DABS = 10, OP_EXP = 11, OP_COS = 12, OP_SIN = 13 };
 
 /* a, b, out are [cnt][2] (lo, hi) arrays; b is ignored by the unary ops */
 int orc_iv_op(int op, int64_t cnt, const double* a, const double* b, double* out) {
@@ -962,6 +1311,9 @@ int orc_iv_op(int op, int64_t cnt, const double* a, const double* b, double* out
     case OP_COS2PI: r = iv_cos2pi(x); break;
     case OP_SIN2PI: r = iv_sin2pi(x); break;
     case OP_DABS: r = iv_dabs(x); break;
+    case OP_EXP: r = iv_exp(x); break;
+    case OP_COS: r = iv_cos(x); break;
+    case OP_SIN: r = iv_sin(x); break;
     default: return -1;
     }
     out[2 * i] = r.lo; out[2 * i + 1] = r.hi;

@@ -26,7 +26,7 @@ GCC_FLAGS = ["-O2", "-std=gnu11", "-frounding-math", "-fno-fast-math", "-ffp-con
              "-fexcess-precision=standard", "-fPIC", "-shared"]
 
 SEP_COS, CHAIN, SEP_ABS_SIN2 = 1, 2, 3
-OP = dict(add=0, sub=1, mul=2, div=3, sqrt=4, sqr=5, abs=6, recip=7, cos2pi=8, sin2pi=9, dabs=10)
+OP = dict(add=0, sub=1, mul=2, div=3, sqrt=4, sqr=5, abs=6, recip=7, cos2pi=8, sin2pi=9, dabs=10, exp=11, cos=12, sin=13)
 ST_OK, ST_NOT_CONVERGED = 0, 1
 
 

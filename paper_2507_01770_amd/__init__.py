@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(HERE, "libibb.so")
 SEP_COS, CHAIN, SEP_ABS_SIN2 = 1, 2, 3
 FP64, FP32_BULK = 0, 1
 OK, NOT_CONVERGED, PENDING = 0, 1, 2
-OPS = dict(add=0, sub=1, mul=2, div=3, sqrt=4, sqr=5, abs=6, recip=7, cos2pi=8, sin2pi=9, dabs=10)
+OPS = dict(add=0, sub=1, mul=2, div=3, sqrt=4, sqr=5, abs=6, recip=7, cos2pi=8, sin2pi=9, dabs=10, exp=11,
+           cos=12, sin=13)
 
 
 class IbbError(RuntimeError):
@@ -230,6 +231,10 @@ def point_trig32(fn: str, y, stream=None):
 def eval_boxes(problem, lo, hi, want_grad=False, precision=FP64, stream=None):
     """Bound boxes lo, hi ([nb, n] device tensors).  Returns F [nb,2], ub [nb], mono [nb] (bool)
     and, when want_grad, G [nb, n, 2].  precision='fp32_bulk' gives the FP32 filter's F, test and G."""
+    return _eval(lib().ibb_eval_boxes, problem, lo, hi, want_grad, precision, stream)
+
+
+def _eval(fn, problem, lo, hi, want_grad, precision, stream):
     torch = _torch()
     k = _prob_args(problem)
     lo = lo.to(device="cuda", dtype=torch.float64).contiguous()
@@ -240,8 +245,8 @@ def eval_boxes(problem, lo, hi, want_grad=False, precision=FP64, stream=None):
     mono = torch.empty(nb, dtype=torch.uint8, device="cuda")
     G = torch.empty((nb, lo.shape[1], 2), dtype=torch.float64, device="cuda") if want_grad else None
     vp = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
-    _check(lib().ibb_eval_boxes(C.byref(k.s), _prec(precision), nb, vp(lo), vp(hi), vp(F), vp(ub), vp(mono),
-                                None if G is None else vp(G), _stream_ptr(stream)))
+    _check(fn(C.byref(k.s), _prec(precision), nb, vp(lo), vp(hi), vp(F), vp(ub), vp(mono),
+              None if G is None else vp(G), _stream_ptr(stream)))
     return (F, ub, mono.bool(), G) if want_grad else (F, ub, mono.bool())
 
 

@@ -388,6 +388,7 @@ __device__ __forceinline__ bool select_finish(const Params& P, State* S, const S
       const uint32_t mask = (uint32_t)bal & ((P.m >= 32) ? 0xffffffffu : ((1u << P.m) - 1u));
       P.hist_mask[row] = mask;
       P.hist_cyc[row] = cyc;
+      if (P.hist_par) P.hist_par[row] = r >= 0 ? ref : -1;
       S->sel_mask = mask;
       S->sel_cyc = cyc;
       S->sel_row = (int32_t)row;
@@ -614,6 +615,7 @@ struct Sel {
 };
 
 constexpr int kIbChunkTerms = 2048;  // base terms evaluated by the workgroup between two barriers
+constexpr int kTermCacheMinN = 1024;  // the term cache pays for its 24 n bytes per row from this n on
 constexpr int kIbMaxTerms = kMaxSplit + 1;
 constexpr int kIbCacheChildren = 1024;   // children whose bounds are kept in LDS between the two passes
 constexpr int kIbMaxGrad = kMaxSplit + 2;
@@ -796,10 +798,24 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
     }
   }
 
-  // 3. base sums over the terms no split coordinate touches; widest unsplit side
+  // 3. base sums over the terms no split coordinate touches; widest unsplit side.
+  //    With the term cache, a term that the parent row's cut left unchanged is the
+  //    parent's (same intervals, same value), and every base term is kept for this
+  //    row's own children.
   I acc{0.0, 0.0};
   double uacc = 0.0, wb = 0.0;
   constexpr int CH = IbLds<NT>::CH;
+  const int32_t par = P.tcache ? G(P.hist_par)[row] : -1;
+  const int pcyc = par >= 0 ? G(P.hist_cyc)[par] : 0;
+  const uint32_t pmask = par >= 0 ? G(P.hist_mask)[par] : 0u;
+  auto cut_by_parent = [&](int i) -> bool {   // coordinate i differs from the parent row's
+    if (i >= n) return false;
+    int j = i - pcyc;
+    if (j < 0) j += n;
+    return j < m && ((pmask >> j) & 1u);
+  };
+  const double* ptc = par >= 0 ? P.tcache + (int64_t)par * 3 * n : nullptr;
+  double* rtc = P.tcache ? P.tcache + row * 3 * n : nullptr;
   for (int c0 = 0; c0 < n; c0 += CH * NT) {
     for (int r = 0; r < CH; ++r) {
       const int i = c0 + r * NT + (int)threadIdx.x;
@@ -809,7 +825,10 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
         const I x{G(rn)[i], G(rh)[i]};
         wb = dmax(wb, x.n + x.h);
         if (i < T && !(FAM == FAM_CHAIN && split_of(i + 1) >= 0)) {
-          if (FAM != FAM_CHAIN) {
+          if (ptc && !cut_by_parent(i) && !(FAM == FAM_CHAIN && cut_by_parent(i + 1))) {
+            t = I{G(ptc)[i], G(ptc)[n + i]};
+            u = G(ptc)[2 * n + i];
+          } else if (FAM != FAM_CHAIN) {
             const CoefSep ci = gload(P.sep + i);
             t = sep_term<FAM>(ci, x);
             u = sep_point_hi<FAM>(ci, midpoint(x));
@@ -819,6 +838,11 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
             const CoefChain ci = gload(P.chain + i);
             t = chain_term(ci, x, xn, R, E);
             u = chain_term(ci, point(midpoint(x)), point(midpoint(xn)), R, E).h;
+          }
+          if (rtc) {
+            G(rtc)[i] = t.n;
+            G(rtc)[n + i] = t.h;
+            G(rtc)[2 * n + i] = u;
           }
         }
       }
@@ -1283,6 +1307,7 @@ __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel
     if (lane == 0) {
       G(P.hist_mask)[row] = mask;
       G(P.hist_cyc)[row] = cyc;
+      if (P.hist_par) G(P.hist_par)[row] = r >= 0 ? ref : -1;
       Sg->sel_mask = mask;
       Sg->sel_cyc = cyc;
       Sg->sel_row = (int32_t)row;
@@ -1694,7 +1719,9 @@ __global__ __launch_bounds__(256) void k_children4(const Params* __restrict__ PP
     int tot = s_n[0];
     for (int k = 1; k < 256 / kWave; ++k) { mn = dmin(mn, s_u[k]); tot += s_n[k]; }
     if (tot > 0) {
-      atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(mn));
+      const unsigned long long key = okey(mn);
+      if (key < __hip_atomic_load(&S->gub_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMin((unsigned long long*)&S->gub_key, key);
       atomicAdd((unsigned long long*)&S->ub_evaluated, (unsigned long long)tot);
     }
   }
@@ -1765,126 +1792,12 @@ __device__ __forceinline__ int ksel_count_prefix(int v, KSelLds<NT>& L, int& tot
   return before + incl - v;
 }
 
+// The end of a K > 1 selection, in one workgroup: rank the (at most K)
+// candidates in L by (lower bound, list index) and write one row per selected box
+// (rank p of sweep t: row 1 + t K + p), its table entry, and remove its key.
 template <int NT>
-__device__ bool select_k_body(const Params& P, State* S, int host_stop, KSelLds<NT>& L) {
-  const double gub = okey_inv(S->gub_key);
-  SelAcc ins = sel_empty();
-  if (S->pending) insert_children<NT>(P, S, gub, ins);   // ends with a barrier
-  const int64_t nk = S->n_keys;
+__device__ void ksel_finish(const Params& P, State* S, KSelLds<NT>& L, int64_t t, double gub) {
   const int K = P.select_k;
-  const bool need_w = P.tol_x > 0.0;
-  // live count, GLB and widest box over the whole list
-  SelAcc a = sel_empty();
-  for (int64_t i = threadIdx.x; i < nk; i += NT) {
-    const double f = P.key_flo[i];
-    if (!(f <= gub)) continue;
-    a.cnt++;
-    if (need_w) a.wm = dmax(a.wm, P.key_wmax[i]);
-    if (f < a.best.f) a.best = Cand{f, i};
-  }
-  a = sel_block_reduce<NT>(a);
-  __shared__ int32_t go;
-  const int64_t t = S->sweeps;
-  if (threadIdx.x == 0) {
-    if (t > 0 && t - 1 < P.trace_cap) P.tr_nlive[t - 1] = a.cnt;
-    S->n_live = a.cnt;
-    S->glb = a.best.f;
-    S->wmax = a.wm;
-    int32_t stop = RUNNING;
-    if (host_stop) stop = STOP_HOST;
-    else if (a.cnt == 0) stop = STOP_EMPTY;
-    else if (gub - a.best.f <= P.tol_f && (P.tol_x <= 0.0 || a.wm < P.tol_x)) stop = STOP_CONVERGED;
-    else if (t >= P.max_sweeps) stop = STOP_SWEEPS;
-    else if (P.max_live > 0 && a.cnt > P.max_live) stop = STOP_LIVE;
-    else if ((t + 1) * K >= P.hist_cap || nk + (int64_t)K * P.nch > P.key_cap) stop = STOP_CAPACITY;
-    if (stop) S->stop = stop;
-    go = stop == RUNNING;
-    L.ncand = 0;
-  }
-  __syncthreads();
-  if (!go) return false;
-
-  // radix selection of the K-th smallest ordered key among the live boxes
-  uint64_t prefix = 0;
-  int need = K, shift = 64;
-  bool whole = a.cnt <= K;   // every live box is taken
-  if (!whole) {
-    for (shift = 56; shift >= 0; shift -= 8) {
-      for (int b = threadIdx.x; b < 256; b += NT) L.hist[b] = 0;
-      if (threadIdx.x == 0) { L.bin = 0; L.below = 0; }
-      __syncthreads();
-      const uint64_t hmask = shift == 56 ? 0ull : (~0ull << (shift + 8));
-      for (int64_t i = threadIdx.x; i < nk; i += NT) {
-        const double f = P.key_flo[i];
-        if (!(f <= gub)) continue;
-        const uint64_t u = okey(f);
-        if ((u & hmask) == (prefix & hmask)) atomicAdd(&L.hist[(int)((u >> shift) & 255u)], 1);
-      }
-      __syncthreads();
-      if (threadIdx.x < (unsigned)kWave) {   // the bin where the count below reaches `need`
-        const int lane = threadIdx.x;
-        const int h0 = L.hist[4 * lane], h1 = L.hist[4 * lane + 1], h2 = L.hist[4 * lane + 2], h3 = L.hist[4 * lane + 3];
-        const int sum = h0 + h1 + h2 + h3;
-        int incl = sum;
-        for (int h = 1; h < kWave; h <<= 1) {
-          const int o = __shfl_up(incl, h, kWave);
-          if (lane >= h) incl += o;
-        }
-        const int excl = incl - sum;
-        if (excl < need && need <= incl) {
-          int below = excl, b = 4 * lane;
-          const int hs[4] = {h0, h1, h2, h3};
-          for (int q = 0; q < 4; ++q) {
-            if (below + hs[q] >= need) { b = 4 * lane + q; break; }
-            below += hs[q];
-          }
-          L.bin = b;
-          L.below = below;
-        }
-      }
-      __syncthreads();
-      const int b = L.bin & 255, inbin = L.hist[b];
-      prefix |= (uint64_t)b << shift;
-      need -= L.below;
-      __syncthreads();   // every thread has read the bin before the histogram is cleared
-      if (inbin == need) { whole = true; break; }
-    }
-    if (!whole) shift = 0;   // all 64 bits fixed: prefix is the K-th smallest key itself
-  }
-  // take, in list order: every live key below the bound and, when the bound is a
-  // single key value, the first `need` keys equal to it
-  const uint64_t top = shift >= 64 ? 0ull : (prefix >> shift);
-  int eqbase = 0;   // keys equal to the bound in earlier chunks (every thread keeps the same count)
-  for (int64_t c0 = 0; c0 < nk; c0 += NT) {
-    const int64_t i = c0 + threadIdx.x;
-    bool take = false, eq = false;
-    double f = 0.0;
-    if (i < nk) {
-      f = P.key_flo[i];
-      if (f <= gub) {
-        const uint64_t u = okey(f);
-        if (whole) take = shift >= 64 || (u >> shift) <= top;
-        else {
-          take = u < prefix;
-          eq = u == prefix;
-        }
-      }
-    }
-    if (!whole) {
-      int tot = 0;
-      const int rank = ksel_count_prefix<NT>(eq ? 1 : 0, L, tot);
-      if (eq && eqbase + rank < need) take = true;
-      eqbase += tot;
-    }
-    if (take) {
-      const int slot = atomicAdd(&L.ncand, 1);
-      if (slot < kMaxSelectK) {
-        L.cf[slot] = f;
-        L.ci[slot] = (int32_t)i;
-      }
-    }
-  }
-  __syncthreads();
   const int nc = min(L.ncand, K);
   // rank the candidates by (lower bound, list index)
   for (int q = threadIdx.x; q < nc; q += NT) {
@@ -1947,6 +1860,129 @@ __device__ bool select_k_body(const Params& P, State* S, int host_stop, KSelLds<
     S->gub_start = gub;
     S->pending = 1;
   }
+}
+
+template <int NT>
+__device__ bool select_k_body(const Params& P, State* S, int host_stop, KSelLds<NT>& L) {
+  const double gub = okey_inv(S->gub_key);
+  SelAcc ins = sel_empty();
+  if (S->pending) insert_children<NT>(P, S, gub, ins);   // ends with a barrier
+  const int64_t nk = S->n_keys;
+  const int K = P.select_k;
+  const bool need_w = P.tol_x > 0.0;
+  // live count, GLB and widest box over the whole list
+  SelAcc a = sel_empty();
+  for (int64_t i = threadIdx.x; i < nk; i += NT) {
+    const double f = P.key_flo[i];
+    if (!(f <= gub)) continue;
+    a.cnt++;
+    if (need_w) a.wm = dmax(a.wm, P.key_wmax[i]);
+    if (f < a.best.f) a.best = Cand{f, i};
+  }
+  a = sel_block_reduce<NT>(a);
+  __shared__ int32_t go;
+  const int64_t t = S->sweeps;
+  if (threadIdx.x == 0) {
+    if (t > 0 && t - 1 < P.trace_cap) P.tr_nlive[t - 1] = a.cnt;
+    S->n_live = a.cnt;
+    S->glb = a.best.f;
+    S->wmax = a.wm;
+    int32_t stop = RUNNING;
+    if (host_stop) stop = STOP_HOST;
+    else if (a.cnt == 0) stop = STOP_EMPTY;
+    else if (gub - a.best.f <= P.tol_f && (P.tol_x <= 0.0 || a.wm < P.tol_x)) stop = STOP_CONVERGED;
+    else if (t >= P.max_sweeps) stop = STOP_SWEEPS;
+    else if (P.max_live > 0 && a.cnt > P.max_live) stop = STOP_LIVE;
+    else if ((t + 1) * K >= P.hist_cap || nk + (int64_t)K * P.nch > P.key_cap) stop = STOP_CAPACITY;
+    if (stop) S->stop = stop;
+    go = stop == RUNNING;
+    L.ncand = 0;
+  }
+  __syncthreads();
+  if (!go) return false;
+
+  // radix selection of the K-th smallest ordered key among the live boxes
+  uint64_t prefix = 0;
+  int need = K, shift = 64;
+  bool whole = a.cnt <= K;   // every live box is taken
+  if (!whole) {
+    for (shift = 56; shift >= 0; shift -= 8) {
+      for (int b = threadIdx.x; b < 256; b += NT) L.hist[b] = 0;
+      if (threadIdx.x == 0) { L.bin = 0; L.below = 0; }
+      __syncthreads();
+      const uint64_t hmask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+      for (int64_t i = threadIdx.x; i < nk; i += NT) {
+        const double f = P.key_flo[i];
+        if (!(f <= gub)) continue;
+        const uint64_t u = skey(f);
+        if ((u & hmask) == (prefix & hmask)) atomicAdd(&L.hist[(int)((u >> shift) & 255u)], 1);
+      }
+      __syncthreads();
+      if (threadIdx.x < (unsigned)kWave) {   // the bin where the count below reaches `need`
+        const int lane = threadIdx.x;
+        const int h0 = L.hist[4 * lane], h1 = L.hist[4 * lane + 1], h2 = L.hist[4 * lane + 2], h3 = L.hist[4 * lane + 3];
+        const int sum = h0 + h1 + h2 + h3;
+        int incl = sum;
+        for (int h = 1; h < kWave; h <<= 1) {
+          const int o = __shfl_up(incl, h, kWave);
+          if (lane >= h) incl += o;
+        }
+        const int excl = incl - sum;
+        if (excl < need && need <= incl) {
+          int below = excl, b = 4 * lane;
+          const int hs[4] = {h0, h1, h2, h3};
+          for (int q = 0; q < 4; ++q) {
+            if (below + hs[q] >= need) { b = 4 * lane + q; break; }
+            below += hs[q];
+          }
+          L.bin = b;
+          L.below = below;
+        }
+      }
+      __syncthreads();
+      const int b = L.bin & 255, inbin = L.hist[b];
+      prefix |= (uint64_t)b << shift;
+      need -= L.below;
+      __syncthreads();   // every thread has read the bin before the histogram is cleared
+      if (inbin == need) { whole = true; break; }
+    }
+    if (!whole) shift = 0;   // all 64 bits fixed: prefix is the K-th smallest key itself
+  }
+  // take, in list order: every live key below the bound and, when the bound is a
+  // single key value, the first `need` keys equal to it
+  const uint64_t top = shift >= 64 ? 0ull : (prefix >> shift);
+  int eqbase = 0;   // keys equal to the bound in earlier chunks (every thread keeps the same count)
+  for (int64_t c0 = 0; c0 < nk; c0 += NT) {
+    const int64_t i = c0 + threadIdx.x;
+    bool take = false, eq = false;
+    double f = 0.0;
+    if (i < nk) {
+      f = P.key_flo[i];
+      if (f <= gub) {
+        const uint64_t u = skey(f);
+        if (whole) take = shift >= 64 || (u >> shift) <= top;
+        else {
+          take = u < prefix;
+          eq = u == prefix;
+        }
+      }
+    }
+    if (!whole) {
+      int tot = 0;
+      const int rank = ksel_count_prefix<NT>(eq ? 1 : 0, L, tot);
+      if (eq && eqbase + rank < need) take = true;
+      eqbase += tot;
+    }
+    if (take) {
+      const int slot = atomicAdd(&L.ncand, 1);
+      if (slot < kMaxSelectK) {
+        L.cf[slot] = f;
+        L.ci[slot] = (int32_t)i;
+      }
+    }
+  }
+  __syncthreads();
+  ksel_finish<NT>(P, S, L, t, gub);
   return true;
 }
 
@@ -1957,6 +1993,216 @@ __global__ __launch_bounds__(NT) void k_select_k(const Params* __restrict__ PP, 
   const Params P = *PP;
   __shared__ KSelLds<NT> lds;
   select_k_body<NT>(P, S, host_stop, lds);
+}
+
+// K > 1 on long lists: the same selection in several launches, so that every
+// pass over the list runs on many workgroups (one workgroup reads a list of
+// millions of keys at a small fraction of HBM bandwidth):
+//   k_select_part    partial live count / GLB / widest side of the list
+//   k_ksel_begin     one workgroup: insert the previous records, the stop test,
+//                    the first digit (the bits every live key shares are skipped)
+//   k_ksel_hist x8   histogram of the current 8-bit digit of the keys that match
+//                    the bits fixed so far; the last workgroup to finish picks the
+//                    digit (the bin where the count below reaches the boxes still
+//                    needed) and clears the histogram for the next launch
+//   k_ksel_take      gather every live key below the bound (at most K)
+//   k_ksel_rows      one workgroup: the keys equal to the bound in list order when
+//                    the bound is one value with ties, then the ranking and rows
+// The selected set is the one the one-workgroup kernel takes.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ksel_begin(const Params* __restrict__ PP, State* __restrict__ S, int nparts) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params P = *PP;
+  const double gub = okey_inv(S->gub_key);
+  const int32_t pending = S->pending;   // read by every thread before any barrier
+  SelAcc a = sel_empty();
+  for (int k = threadIdx.x; k < nparts; k += NT) {
+    const SelAcc o{Cand{P.part_flo[k], P.part_idx[k]}, P.part_wmax[k], P.part_cnt[k]};
+    a = sel_merge(a, o);
+  }
+  a = sel_block_reduce<NT>(a);
+  if (pending) insert_children<NT>(P, S, gub, a);   // adds the inserted keys to a; ends with a barrier
+  __shared__ int32_t go;
+  const int64_t t = S->sweeps;
+  const int64_t nk = S->n_keys;
+  const int K = P.select_k;
+  if (threadIdx.x == 0) {
+    if (t > 0 && t - 1 < P.trace_cap) P.tr_nlive[t - 1] = a.cnt;
+    S->n_live = a.cnt;
+    S->glb = a.best.f;
+    S->wmax = a.wm;
+    int32_t stop = RUNNING;
+    if (a.cnt == 0) stop = STOP_EMPTY;
+    else if (gub - a.best.f <= P.tol_f && (P.tol_x <= 0.0 || a.wm < P.tol_x)) stop = STOP_CONVERGED;
+    else if (t >= P.max_sweeps) stop = STOP_SWEEPS;
+    else if (P.max_live > 0 && a.cnt > P.max_live) stop = STOP_LIVE;
+    else if ((t + 1) * K >= P.hist_cap || nk + (int64_t)K * P.nch > P.key_cap) stop = STOP_CAPACITY;
+    if (stop) S->stop = stop;
+    go = stop == RUNNING;
+    if (go) {
+      S->ks_need = K;
+      S->ks_whole = 0;
+      S->ks_done = 0;
+      if (a.cnt <= K) {   // every live box is taken
+        S->ks_done = 1;
+        S->ks_whole = 1;
+        S->ks_shift = 64;
+        S->ks_prefix = 0ull;
+      } else {
+        // every live key lies in [skey(GLB), skey(GUB)]: the bits above the first
+        // one where those two differ are the same for all of them
+        const uint64_t lo = skey(a.best.f), hi = skey(gub);
+        const int lead = lo == hi ? 64 : __clzll((long long)(lo ^ hi));
+        const int sh = lead >= 64 ? 0 : ((63 - lead) >> 3) << 3;
+        S->ks_shift = sh;
+        S->ks_prefix = sh >= 56 ? 0ull : (lo & (~0ull << (sh + 8)));
+      }
+      P.ksel->ticket = 0u;
+      P.ksel->ncand = 0u;
+    }
+  }
+  __syncthreads();
+  if (go)
+    for (int b = threadIdx.x; b < 256; b += NT) P.ksel->hist[b] = 0u;
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_ksel_hist(const Params* __restrict__ PP, State* __restrict__ S) {
+  // S->stop and S->ks_done change only between launches: the same for every workgroup
+  if (S->stop || S->ks_done) return;
+  const Params P = *PP;
+  KselBuf* B = P.ksel;
+  __shared__ uint32_t h[256];
+  __shared__ int last;
+  for (int b = threadIdx.x; b < 256; b += kSelThreads) h[b] = 0u;
+  __syncthreads();
+  const double gub = okey_inv(S->gub_key);
+  const int shift = S->ks_shift;
+  const uint64_t prefix = S->ks_prefix;
+  const uint64_t hmask = shift >= 56 ? 0ull : (~0ull << (shift + 8));
+  const int64_t nk = S->n_keys;
+  const int64_t stride = (int64_t)gridDim.x * kSelThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; i < nk; i += stride) {
+    const double f = P.key_flo[i];
+    if (!(f <= gub)) continue;
+    const uint64_t u = skey(f);
+    if ((u & hmask) == prefix) atomicAdd(&h[(int)((u >> shift) & 255u)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < 256; b += kSelThreads)
+    if (h[b]) atomicAdd(&B->hist[b], h[b]);
+  __threadfence();   // this workgroup's counts are visible before its ticket
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&B->ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last || threadIdx.x >= kWave) return;
+  __threadfence();
+  // the last workgroup: the bin where the count below reaches the boxes still needed
+  const int lane = threadIdx.x;
+  int hs[4];
+  for (int q = 0; q < 4; ++q) hs[q] = (int)__hip_atomic_load(&B->hist[4 * lane + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int need = S->ks_need;
+  const int sum = hs[0] + hs[1] + hs[2] + hs[3];
+  int incl = sum;
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int o = __shfl_up(incl, d, kWave);
+    if (lane >= d) incl += o;
+  }
+  const int excl = incl - sum;
+  if (excl < need && need <= incl) {   // one lane
+    int below = excl, b = 4 * lane;
+    for (int q = 0; q < 4; ++q) {
+      if (below + hs[q] >= need) { b = 4 * lane + q; break; }
+      below += hs[q];
+    }
+    const int inbin = hs[b - 4 * lane];
+    const int left = need - below;
+    S->ks_prefix = prefix | ((uint64_t)b << shift);
+    S->ks_need = left;
+    if (inbin == left) {           // the whole bin is taken: the bound is settled
+      S->ks_done = 1;
+      S->ks_whole = 1;
+    } else if (shift == 0) {       // one key value with more keys than needed: ties
+      S->ks_done = 1;
+      S->ks_whole = 0;
+    } else {
+      S->ks_shift = shift - 8;
+    }
+  }
+  for (int q = 0; q < 4; ++q) B->hist[4 * lane + q] = 0u;
+  if (lane == 0) B->ticket = 0u;
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_ksel_take(const Params* __restrict__ PP, State* __restrict__ S) {
+  if (S->stop) return;
+  const Params P = *PP;
+  KselBuf* B = P.ksel;
+  const double gub = okey_inv(S->gub_key);
+  const int shift = S->ks_shift;
+  const uint64_t prefix = S->ks_prefix;
+  const bool whole = S->ks_whole != 0;
+  const uint64_t top = shift >= 64 ? 0ull : (prefix >> shift);
+  const int64_t nk = S->n_keys;
+  const int64_t stride = (int64_t)gridDim.x * kSelThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; i < nk; i += stride) {
+    const double f = P.key_flo[i];
+    if (!(f <= gub)) continue;
+    const uint64_t u = skey(f);
+    const bool take = whole ? (shift >= 64 || (u >> shift) <= top) : u < prefix;
+    if (take) {
+      const uint32_t slot = atomicAdd(&B->ncand, 1u);
+      if (slot < (uint32_t)kMaxSelectK) {
+        B->cf[slot] = f;
+        B->ci[slot] = (int32_t)i;
+      }
+    }
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ksel_rows(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params P = *PP;
+  __shared__ KSelLds<NT> L;
+  const double gub = okey_inv(S->gub_key);
+  const int K = P.select_k;
+  const KselBuf* B = P.ksel;
+  if (threadIdx.x == 0) L.ncand = (int)min(B->ncand, (uint32_t)K);
+  __syncthreads();
+  const int nb = L.ncand;
+  for (int q = threadIdx.x; q < nb; q += NT) {
+    L.cf[q] = B->cf[q];
+    L.ci[q] = B->ci[q];
+  }
+  if (!S->ks_whole) {
+    // the bound is one key value: the first `need` keys equal to it, in list order
+    const uint64_t prefix = S->ks_prefix;
+    const int need = S->ks_need;
+    const int64_t nk = S->n_keys;
+    int eqbase = 0;   // keys equal to the bound in earlier chunks (every thread keeps the same count)
+    for (int64_t c0 = 0; c0 < nk && eqbase < need; c0 += NT) {
+      const int64_t i = c0 + threadIdx.x;
+      bool eq = false;
+      double f = 0.0;
+      if (i < nk) {
+        f = P.key_flo[i];
+        eq = f <= gub && skey(f) == prefix;
+      }
+      int tot = 0;
+      const int rank = ksel_count_prefix<NT>(eq ? 1 : 0, L, tot);
+      if (eq && eqbase + rank < need) {
+        const int slot = atomicAdd(&L.ncand, 1);
+        if (slot < kMaxSelectK) {
+          L.cf[slot] = f;
+          L.ci[slot] = (int32_t)i;
+        }
+      }
+      eqbase += tot;
+    }
+  }
+  __syncthreads();
+  ksel_finish<NT>(P, S, L, S->sweeps, gub);
 }
 
 // Bound the children of the selected box.
@@ -2009,6 +2255,15 @@ __device__ void bound_body(const Params& P, State* S, int cbase) {
   __shared__ double ln[kBoundWaves][kWave], lh[kBoundWaves][kWave];
   __shared__ int s_flag[kBoundWaves];
   __shared__ double s_wm[kBoundWaves];
+  // the children's midpoint bounds meet here: one GUB update per workgroup, and
+  // only when its minimum is below GUB (atomics from every child on the one
+  // address serialise in L2)
+  __shared__ unsigned long long s_ukey[kBoundWaves];
+  __shared__ int s_ucnt[kBoundWaves];
+  if (lane == 0) {
+    s_ukey[wid] = ~0ull;
+    s_ucnt[wid] = 0;
+  }
 
   // ---- pass 0 (FP32 filter, throughput mode only): a single-precision lower
   // bound over the FP32-enclosing box and the first-order test.  r32 = 2: the
@@ -2162,8 +2417,8 @@ __device__ void bound_body(const Params& P, State* S, int cbase) {
       if (lane == 0 && in) {
         if (formed) {
           if (do_ub) {
-            atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(hi_or_inf(u)));
-            atomicAdd((unsigned long long*)&S->ub_evaluated, 1ull);
+            s_ukey[wid] = okey(hi_or_inf(u));
+            s_ucnt[wid] = 1;
           }
           if (r32) {
             P.ch_flag[g] = 3;
@@ -2181,8 +2436,8 @@ __device__ void bound_body(const Params& P, State* S, int cbase) {
     if (mid_role) {
       const double u = fold_slots_hi(hacc, lane);
       if (lane == 0 && formed) {
-        atomicMin((unsigned long long*)&S->gub_key, (unsigned long long)okey(hi_or_inf(u)));
-        atomicAdd((unsigned long long*)&S->ub_evaluated, 1ull);
+        s_ukey[wid] = okey(hi_or_inf(u));
+        s_ucnt[wid] = 1;
       }
     } else if (lane == 0 && in) {
       if (formed) {
@@ -2192,6 +2447,20 @@ __device__ void bound_body(const Params& P, State* S, int cbase) {
       } else {
         P.ch_flag[g] = 0;
       }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long mn = s_ukey[0];
+    int cnt = s_ucnt[0];
+    for (int k = 1; k < kBoundWaves; ++k) {
+      mn = s_ukey[k] < mn ? s_ukey[k] : mn;
+      cnt += s_ucnt[k];
+    }
+    if (cnt > 0) {
+      if (mn < __hip_atomic_load(&S->gub_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMin((unsigned long long*)&S->gub_key, mn);
+      atomicAdd((unsigned long long*)&S->ub_evaluated, (unsigned long long)cnt);
     }
   }
 }
@@ -2322,7 +2591,10 @@ __global__ void k_interval_op(int op, int64_t cnt, const double* __restrict__ a,
     case 7: r = recip(x); break;
     case 8: r = sincos2pi(x, true, false).c; break;
     case 9: r = sincos2pi(x, false, true).s; break;
-    default: r = dabs(x); break;
+    case 10: r = dabs(x); break;
+    case 11: r = iexp(x); break;
+    case 12: r = sincos2pi(mul(x, inv_two_pi()), true, false).c; break;
+    default: r = sincos2pi(mul(x, inv_two_pi()), false, true).s; break;
   }
   if (__builtin_isnan(r.n) || __builtin_isnan(r.h)) r = entire();
   out[2 * i] = neg(r.n);
@@ -2656,6 +2928,7 @@ struct Run {
   bool pending = false;
   State hs{};
   std::chrono::steady_clock::time_point t0;
+  bool term_cache = false;   // ibb_solve's runs: keep the rows' shared terms (large n)
 };
 
 // Allocate the problem's arrays, upload it and enqueue its root box (Sec. 3.1,
@@ -2701,6 +2974,10 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   P.ch_flag = dalloc<uint8_t>(M, nrec);
   P.ch_wmax = dalloc<double>(M, nrec);
   P.sel_tab = dalloc<SelRec>(M, P.select_k);
+  P.ksel = P.select_k > 1 ? dalloc<KselBuf>(M, 1) : nullptr;
+  const bool tc = U.term_cache && P.incremental && P.select_k == 1 && P.pieces == 2 && n >= kTermCacheMinN;
+  P.tcache = tc ? dalloc<double>(M, P.hist_cap * 3 * n) : nullptr;
+  P.hist_par = tc ? dalloc<int32_t>(M, P.hist_cap) : nullptr;
   P.part_flo = dalloc<double>(M, kMaxSelBlocks);
   P.part_idx = dalloc<int64_t>(M, kMaxSelBlocks);
   P.part_wmax = dalloc<double>(M, kMaxSelBlocks);
@@ -2708,7 +2985,8 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   set_trace(P, dalloc<double>(M, 4 * P.trace_cap), P.trace_cap);
   if (!P.key_flo || !P.key_seq || !P.key_ref || !P.key_r || !P.key_wmax || !P.hist_n || !P.hist_h || !P.hist_cyc ||
       !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.sel_tab ||
-      (four && (!P.hist_cut || !P.tab || !P.tabi)) || !P.part_flo ||
+      (four && (!P.hist_cut || !P.tab || !P.tabi)) || (P.select_k > 1 && !P.ksel) ||
+      (tc && (!P.tcache || !P.hist_par)) || !P.part_flo ||
       !P.part_idx || !P.part_wmax || !P.part_cnt || !P.tr_gub || !P.tr_nsurv || !P.tr_nlive || !P.tr_sel)
     return fail(IBB_E_NOMEM, "device allocation failed");
   // root row: (-l, u)
@@ -2767,6 +3045,10 @@ ibb_status run_capacity(Run& U, int chunk) {
     take(Q.hist_mask, Q.hist_cap);
     take(Q.hist_mid, Q.hist_cap * kMaxSplit);
     if (P.pieces == 4) take(Q.hist_cut, Q.hist_cap * 3 * kMaxSplit);
+    if (P.tcache) {
+      take(Q.tcache, Q.hist_cap * 3 * n);
+      take(Q.hist_par, Q.hist_cap);
+    }
   }
   if (g_keys) {
     Q.key_cap = std::max<int64_t>(2 * P.key_cap, need_keys);
@@ -2796,7 +3078,9 @@ ibb_status run_capacity(Run& U, int chunk) {
              copy(Q.hist_h, P.hist_h, keep * n * sizeof(double)) && copy(Q.hist_cyc, P.hist_cyc, keep * sizeof(int32_t)) &&
              copy(Q.hist_mask, P.hist_mask, keep * sizeof(uint32_t)) &&
              copy(Q.hist_mid, P.hist_mid, keep * kMaxSplit * sizeof(double)) &&
-             (P.pieces != 4 || copy(Q.hist_cut, P.hist_cut, keep * 3 * kMaxSplit * sizeof(double)));
+             (P.pieces != 4 || copy(Q.hist_cut, P.hist_cut, keep * 3 * kMaxSplit * sizeof(double))) &&
+             (!P.tcache || (copy(Q.tcache, P.tcache, keep * 3 * n * sizeof(double)) &&
+                            copy(Q.hist_par, P.hist_par, keep * sizeof(int32_t))));
   }
   if (g_keys) {
     const int64_t keep = U.n_keys;
@@ -2817,6 +3101,7 @@ ibb_status run_capacity(Run& U, int chunk) {
   if (g_rows) {
     M.put(P.hist_n); M.put(P.hist_h); M.put(P.hist_cyc); M.put(P.hist_mask); M.put(P.hist_mid);
     if (P.pieces == 4) M.put(P.hist_cut);
+    if (P.tcache) { M.put(P.tcache); M.put(P.hist_par); }
   }
   if (g_keys) { M.put(P.key_flo); M.put(P.key_seq); M.put(P.key_ref); M.put(P.key_r); M.put(P.key_wmax); }
   if (g_tr) M.put(P.tr_gub);
@@ -3074,8 +3359,20 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
                               nullptr, prof ? ev[4 * s + 2] : nullptr, 0, U.dP, U.dS, rows4);
       }
       for (int s = 0; s < chunk && multi; ++s) {
-        hipExtLaunchKernelGGL(k_select_k<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
-                              prof ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP, U.dS, 0);
+        if (sb > 1) {   // a long list: the selection's passes over it on sb workgroups
+          hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream,
+                                prof ? ev[4 * s + 0] : nullptr, nullptr, 0, U.dP, U.dS);
+          hipLaunchKernelGGL(k_ksel_begin<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream, U.dP,
+                             U.dS, sb);
+          for (int q = 0; q < 8; ++q)
+            hipLaunchKernelGGL(k_ksel_hist, dim3(sb), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+          hipLaunchKernelGGL(k_ksel_take, dim3(sb), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+          hipExtLaunchKernelGGL(k_ksel_rows<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
+                                nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP, U.dS);
+        } else {
+          hipExtLaunchKernelGGL(k_select_k<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
+                                prof ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP, U.dS, 0);
+        }
         if (P.incremental)
           hipExtLaunchKernelGGL((k_ib_parents<kSweepThreads, FAM>), dim3(P.select_k), dim3(kSweepThreads), 0, M.stream,
                                 prof ? ev[4 * s + 1] : nullptr, prof ? ev[4 * s + 2] : nullptr, 0, U.dP, U.dS);
@@ -3217,6 +3514,7 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
   R->dP = U.dP;
   R->dS = U.dS;
   R->opts = U.opts;
+  U.term_cache = true;
   if ((st = run_setup(U, prob)) != IBB_OK) return bail(st);
   Params& P = R->P;
   const int n = P.n;
@@ -3409,7 +3707,7 @@ ibb_status ibb_eval_boxes(const ibb_problem* prob, int32_t precision, int64_t nb
 
 ibb_status ibb_interval_op(int32_t op, int64_t count, const double* d_a, const double* d_b, double* d_out,
                            void* hip_stream) {
-  if (op < 0 || op > 10) return fail(IBB_E_INVALID, "unknown op");
+  if (op < 0 || op > 13) return fail(IBB_E_INVALID, "unknown op");
   if (count < 0) return fail(IBB_E_INVALID, "count < 0");
   if (count == 0) return IBB_OK;
   const bool binary = op <= 3;

@@ -356,6 +356,57 @@ __device__ __forceinline__ TrigIv sincos2pi(I y, bool want_cos, bool want_sin) {
   return r;
 }
 
+// -------------------------------------------------------------------------
+// exp, and cos / sin of an argument in radians (the generic family's
+// elementary functions; Sec. 2.1 asks every operation to round outward)
+//
+// exp at a double x: x = k ln2 + r with k = rint(x log2 e); r is enclosed from
+// ln2 = LN2_HI + LN2_LO + d (LN2_HI has 42 bits, so k LN2_HI is exact for
+// |k| < 2^11; |d| < 2^-102, so |k d| < 2^-91 is covered by a margin of 2^-90);
+// e^r, |r| < 0.36, by interval Horner over the Taylor coefficients 1/j!,
+// j <= 16, each the pair of doubles around it, plus the truncation bound
+// |r|^17 e^|r| / 17! < 2^-72; then the exact scaling by 2^k.  Outside
+// [-700, 709] the bounds are e^-700 < 1e-304 and e^709 > 8.2e307.
+// cos x and sin x: cos(2 pi y), sin(2 pi y) of y = x [1 / (2 pi)], the factor
+// enclosed by the two doubles around 1 / (2 pi).
+// -------------------------------------------------------------------------
+__device__ inline I exp_point(double x) {
+  if (x == 0.0) return I{-1.0, 1.0};
+  if (x != x) return entire();
+  if (x > 709.0) return I{-8.2e307, __builtin_inf()};
+  if (x < -700.0) return I{0.0, 1e-304};
+  const double kd = __builtin_rint(x * hexd(0x3ff71547652b82feull));   // any integer near x / ln2
+  const I kI = point(kd);
+  I r = sub(point(x), mul(kI, point(hexd(0x3fe62e42fefa3800ull))));    // x - k LN2_HI
+  r = sub(r, mul(kI, point(hexd(0x3d2ef35793c76730ull))));            // - k LN2_LO
+  const double m90 = hexd(0x3a50000000000000ull);                      // 2^-90
+  r = I{r.n + m90, r.h + m90};
+  // 1/j!, j = 0 .. 16: (lower, upper)
+  const uint64_t cl[17] = {0x3ff0000000000000ull, 0x3ff0000000000000ull, 0x3fe0000000000000ull,
+                           0x3fc5555555555555ull, 0x3fa5555555555555ull, 0x3f81111111111111ull,
+                           0x3f56c16c16c16c16ull, 0x3f2a01a01a01a01aull, 0x3efa01a01a01a01aull,
+                           0x3ec71de3a556c733ull, 0x3e927e4fb7789f5cull, 0x3e5ae64567f544e3ull,
+                           0x3e21eed8eff8d897ull, 0x3de6124613a86d09ull, 0x3da93974a8c07c9dull,
+                           0x3d6ae7f3e733b81full, 0x3d2ae7f3e733b81full};
+  const uint64_t ch[17] = {0x3ff0000000000000ull, 0x3ff0000000000000ull, 0x3fe0000000000000ull,
+                           0x3fc5555555555556ull, 0x3fa5555555555556ull, 0x3f81111111111112ull,
+                           0x3f56c16c16c16c17ull, 0x3f2a01a01a01a01bull, 0x3efa01a01a01a01bull,
+                           0x3ec71de3a556c734ull, 0x3e927e4fb7789f5dull, 0x3e5ae64567f544e4ull,
+                           0x3e21eed8eff8d898ull, 0x3de6124613a86d0aull, 0x3da93974a8c07c9eull,
+                           0x3d6ae7f3e733b820ull, 0x3d2ae7f3e733b820ull};
+  I p{neg(hexd(cl[16])), hexd(ch[16])};
+  for (int j = 15; j >= 0; --j) p = add(mul(p, r), I{neg(hexd(cl[j])), hexd(ch[j])});
+  const double m72 = hexd(0x3b70000000000000ull);                      // 2^-72
+  p = I{p.n + m72, p.h + m72};
+  return scale(__builtin_ldexp(1.0, (int)kd), p);                      // exact power of two
+}
+__device__ inline I iexp(I a) {
+  if (a.n != a.n || a.h != a.h) return I{-0.0, __builtin_inf()};
+  const I l = exp_point(neg(a.n)), h = exp_point(a.h);
+  return I{dmin(l.n, 0.0), h.h};   // the lower end is never below 0
+}
+__device__ __forceinline__ I inv_two_pi() { return I{neg(hexd(0x3fc45f306dc9c882ull)), hexd(0x3fc45f306dc9c883ull)}; }
+
 // ordered 64-bit key of a double: key(x) < key(y) <=> x < y (for x, y not NaN, -0 < +0)
 __host__ __device__ __forceinline__ uint64_t okey(double x) {
   uint64_t u = __builtin_bit_cast(uint64_t, x);

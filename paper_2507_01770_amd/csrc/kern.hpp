@@ -82,6 +82,8 @@ constexpr int kTabEntry = 2 + kMaxSamples;   // F (-lo, hi), then the sample upp
 constexpr int kTabDoubles = kTabRows * 16 * kTabEntry + 2 + kMaxSamples + 1 + kMaxSplit * 4;
 constexpr int kTabInts = 4 + kTabRows * (1 + 2) + kTabRows * (1 + 3) + kTabRows * 64;
 
+struct KselBuf;
+
 struct Params {
   int32_t family, n, m, nch;              // nch = 2^m children per selected box
   double tol_f, tol_x;
@@ -137,6 +139,13 @@ struct Params {
   double* hist_cut;                       // [row][kMaxSplit][3] cut points of 4-piece rows
   double* tab;                            // the sweep's piece tables (kTabDoubles)
   int32_t* tabi;                          // their index part (kTabInts)
+  KselBuf* ksel;                          // K > 1: the selection's buffer for long lists
+  // term cache (one box per sweep, incremental bounds, large n): for every row,
+  // the terms its children share (F's enclosure and the midpoint bound of each
+  // term no split coordinate of the row touches), [row][3][n]; a selected box
+  // takes those of its parent row that its own cut leaves unchanged
+  double* tcache;                         // null: no cache
+  int32_t* hist_par;                      // [row] the row the box was cut from (-1: none)
 };
 
 struct State {
@@ -157,7 +166,26 @@ struct State {
   int32_t use32, p32_fails;
   int64_t p32_resume, fp32_pruned, fp32_sweeps;
   int32_t sel_count, pad_sel;             // K > 1: boxes selected by the last selection
+  // K > 1 on long lists, the radix selection between its launches: the bits fixed
+  // so far (ks_prefix, above bit ks_shift), how many boxes are still to be taken
+  // at the bound, whether the bound is settled (ks_done) and whether every live
+  // key up to it is taken (ks_whole; else the bound is one key value with ties)
+  uint64_t ks_prefix;
+  int32_t ks_shift, ks_need, ks_done, ks_whole;
 };
+
+// K > 1 on long lists: the current digit's histogram, the ticket that finds the
+// last workgroup of a histogram launch, and the candidates gathered below the bound
+struct KselBuf {
+  uint32_t hist[256];
+  uint32_t ticket, ncand;
+  double cf[kMaxSelectK];
+  int32_t ci[kMaxSelectK];
+};
+
+// ordered key of a lower bound for the K > 1 selection, the two zeros made one
+// (-0 + 0 is +0 when rounding up), so that equal bounds tie whatever their sign
+__device__ __forceinline__ uint64_t skey(double x) { return okey(x + 0.0); }
 
 // bisection point: 0.5 lo + 0.5 hi rounded up, kept inside [lo, hi]
 __device__ __forceinline__ double midpoint(I x) {

@@ -18,8 +18,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-SEP_COS, CHAIN, SEP_ABS_SIN2 = 1, 2, 3
-FAMILY_NAMES = {SEP_COS: "sep_cos", CHAIN: "chain", SEP_ABS_SIN2: "sep_abs_sin2"}
+SEP_COS, CHAIN, SEP_ABS_SIN2, TAPE = 1, 2, 3, 4
+FAMILY_NAMES = {SEP_COS: "sep_cos", CHAIN: "chain", SEP_ABS_SIN2: "sep_abs_sin2", TAPE: "tape"}
 
 
 @dataclass

@@ -95,7 +95,7 @@ def test_empty_inputs_are_accepted_without_device_work():
     (lambda L, k: L.ibb_eval_boxes(C.byref(k.s), 0, -1, None, None, None, None, None, None, None), "nb < 0"),
     (lambda L, k: L.ibb_eval_boxes(C.byref(k.s), 0, 4, None, None, None, None, None, None, None), "NULL"),
     (lambda L, k: L.ibb_eval_boxes(C.byref(k.s), 5, 4, None, None, None, None, None, None, None), "precision"),
-    (lambda L, k: L.ibb_interval_op(11, 4, None, None, None, None), "unknown op"),
+    (lambda L, k: L.ibb_interval_op(14, 4, None, None, None, None), "unknown op"),
     (lambda L, k: L.ibb_interval_op(0, -1, None, None, None, None), "count < 0"),
     (lambda L, k: L.ibb_interval_op(0, 4, None, None, None, None), "NULL"),
     (lambda L, k: L.ibb_point_trig(2, 4, None, None, None), "fn must be"),

@@ -63,10 +63,9 @@ def test_separable_large_n_matches_oracle(fam, n, seed, budget):
     assert r.f_lo <= 0.0 <= r.f_hi
 
 
-@pytest.mark.skip(reason="faulted the GPU once (with a per-row term cache that has since been "
-                         "taken out, cause not shown); stays off the GPU until a cause is shown on "
-                         "the CPU")
 def test_large_n_alone_batch_and_server():
+    # alone: ibb_solve with the term cache; in the batch and the server: the same
+    # iteration without it (each term evaluated from the box)
     big = [PR.chain(1100, 505, hi=2.3), PR.sep_abs_sin2(1500, 7)]
     budget = dict(max_sweeps=60)
     alone = []
@@ -95,3 +94,18 @@ def test_large_n_alone_batch_and_server():
     assert len(res) == len(tickets)
     for t, a in zip(tickets[1:], alone):
         same(a, res[t])
+
+
+def test_term_cache_at_n_10000_past_the_persistent_list_size():
+    # the non-smooth n = 10,000 workload: ibb_solve (term cache; the persistent
+    # kernel, then, once the list passes 2^18 keys, the per-sweep kernels) and
+    # the batched engine (no cache) run the same iteration bit for bit
+    p = PR.config(3)
+    budget = dict(max_sweeps=1500)
+    print("case n=10000 alone (term cache)", flush=True)
+    a = ibb.minimize(p, fetch_boxes=False, **budget)
+    print(f"largest live list {a.trace_nlive.max()}, keys inserted {a.trace_nsurv.sum()}", flush=True)
+    print("case n=10000 batch (no cache)", flush=True)
+    b = ibb.solve_batch([p], fetch_boxes=False, **budget)[0]
+    same(a, b)
+    assert a.sweeps == 1500

@@ -140,3 +140,31 @@ def test_interval_trig_contains_oracle_within_two_ulps(fn):
     dl, dh = ulps_beyond(got, ref)
     assert dl.min() >= 0 and dh.min() >= 0, report(Y[:, 0], got, ref, dl, dh)
     assert dl.max() <= 2 and dh.max() <= 2, report(Y[:, 0], got, ref, dl, dh)
+
+
+@pytest.mark.parametrize("fn", ["exp", "cos", "sin"])
+def test_exp_and_radian_trig_contain_oracle(fn):
+    # the generic family's elementary functions: the GPU enclosure holds the
+    # oracle's (same argument reduction constants, wider margins) with at most
+    # 4 (exp) or 2 (cos, sin) doubles more on each side, and the true value
+    g = np.random.default_rng(21 if fn == "exp" else 22)
+    a = np.concatenate([g.uniform(-40, 40, 1 << 15), g.uniform(-690, 700, 1 << 12),
+                        np.ldexp(g.uniform(-1, 1, 1 << 12), -g.integers(1, 60, 1 << 12)),
+                        np.array([0.0, -0.0, 0.5, -0.5, 1.0, np.log(2.0) / 2, -np.log(2.0) / 2])])
+    if fn != "exp":
+        a = a[np.abs(a) < 1e4]
+    w = np.exp(g.uniform(np.log(1e-15), np.log(0.5), a.size)) * (1 + np.abs(a))
+    w[: 1 << 12] = 0.0
+    Y = np.stack([a, a + w], axis=1)
+    print(f"case interval {fn} n={Y.shape[0]}", flush=True)
+    ref = O.iv_op(fn, Y)
+    got = gpu_op(fn, Y)
+    dl, dh = ulps_beyond(got, ref)
+    assert dl.min() >= 0 and dh.min() >= 0, ("GPU enclosure must contain the oracle's", report(Y[:, 0], got, ref, dl, dh))
+    lim = 4 if fn == "exp" else 2
+    assert dl.max() <= lim and dh.max() <= lim, report(Y[:, 0], got, ref, dl, dh)
+    mpmath.mp.prec = 200
+    f = {"exp": mpmath.exp, "cos": mpmath.cos, "sin": mpmath.sin}[fn]
+    for i in np.random.default_rng(2).choice(a.size, 300, replace=False):
+        v = f(mpmath.mpf(a[i]))
+        assert mpmath.mpf(got[i, 0]) <= v <= mpmath.mpf(got[i, 1])
