@@ -224,6 +224,24 @@ ibb_status ibb_eval_boxes(const ibb_problem* prob, int32_t precision, int64_t nb
                           const double* d_hi, double* d_F, double* d_ub_mid, uint8_t* d_mono_prune,
                           double* d_G, void* hip_stream);
 
+/* ibb_eval_boxes for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments, kernels and results, bit for bit, but the problem's coefficient
+ * records, its bounds and the kernel parameters go into one fixed device array
+ * of 16 MiB that the library holds on each GPU it runs on until the process
+ * ends.  The call makes no device allocation and frees nothing.  The inputs
+ * d_lo, d_hi and the outputs are the caller's, as for ibb_eval_boxes.
+ * Limit: the problem must fit the array (144 bytes per coordinate for the
+ * separable families with IBB_FP32_BULK, about 116,000 coordinates; 96 bytes,
+ * about 174,000, in FP64; less for the chained family); a larger one gives
+ * IBB_E_CAPACITY before any device work.  The array belongs to the current
+ * device (hipGetDevice); calls are serialised inside the library, each one
+ * rewrites the array completely and returns when its bounds are written (it
+ * synchronises hip_stream), so the array's earlier contents never matter. */
+ibb_status ibb_eval_boxes_noalloc(const ibb_problem* prob, int32_t precision, int64_t nb, const double* d_lo,
+                                  const double* d_hi, double* d_F, double* d_ub_mid, uint8_t* d_mono_prune,
+                                  double* d_G, void* hip_stream);
+
 /* Elementwise interval operations with outward rounding (Sec. 2.1, Eqs. (3)-(6)),
  * for testing the arithmetic.  d_a, d_b, d_out: device [count][2] (lo, hi).
  * op: 0 add, 1 sub, 2 mul, 3 div (= a * (1/b), Eq. (6)), 4 sqrt, 5 sqr, 6 abs,

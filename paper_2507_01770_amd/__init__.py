@@ -85,6 +85,7 @@ def lib():
     L.ibb_sweep.argtypes = [vp, i64, vp]
     L.ibb_result_free.restype = None
     L.ibb_eval_boxes.argtypes = [C.POINTER(_Problem), i32, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.ibb_eval_boxes_noalloc.argtypes = [C.POINTER(_Problem), i32, i64, vp, vp, vp, vp, vp, vp, vp]
     L.ibb_interval_op.argtypes = [i32, i64, vp, vp, vp, vp]
     L.ibb_point_trig.argtypes = [i32, i64, vp, vp, vp]
     L.ibb_interval_op32.argtypes = [i32, i64, vp, vp, vp, vp]
@@ -100,7 +101,7 @@ def lib():
     L.ibb_server_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.ibb_server_destroy.argtypes = [vp]
     for f in ["ibb_options_default", "ibb_solve", "ibb_sweep", "ibb_result_info", "ibb_result_boxes", "ibb_result_trace",
-              "ibb_eval_boxes", "ibb_interval_op", "ibb_point_trig", "ibb_interval_op32", "ibb_point_trig32",
+              "ibb_eval_boxes", "ibb_eval_boxes_noalloc", "ibb_interval_op", "ibb_point_trig", "ibb_interval_op32", "ibb_point_trig32",
               "ibb_solve_batch", "ibb_server_create",
               "ibb_server_submit", "ibb_server_poll", "ibb_server_stats", "ibb_server_destroy"]:
         getattr(L, f).restype = C.c_int
@@ -232,6 +233,12 @@ def eval_boxes(problem, lo, hi, want_grad=False, precision=FP64, stream=None):
     """Bound boxes lo, hi ([nb, n] device tensors).  Returns F [nb,2], ub [nb], mono [nb] (bool)
     and, when want_grad, G [nb, n, 2].  precision='fp32_bulk' gives the FP32 filter's F, test and G."""
     return _eval(lib().ibb_eval_boxes, problem, lo, hi, want_grad, precision, stream)
+
+
+def eval_boxes_noalloc(problem, lo, hi, want_grad=False, precision=FP64, stream=None):
+    """eval_boxes through ibb_eval_boxes_noalloc: the library allocates no device memory (its
+    problem tables go into a fixed device array); the outputs here are allocated by torch."""
+    return _eval(lib().ibb_eval_boxes_noalloc, problem, lo, hi, want_grad, precision, stream)
 
 
 def _eval(fn, problem, lo, hi, want_grad, precision, stream):

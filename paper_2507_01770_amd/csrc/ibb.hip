@@ -68,6 +68,12 @@ __global__ void k_setup_chain(int n, const double* __restrict__ coef, CoefChain*
   if (out32) out32[i] = CoefChain32{to32(point(r.al)), to32(point(r.be))};
 }
 
+// a[i] = -a[i] (exact), for the lower bounds held negated
+__global__ void k_negate(int n, double* __restrict__ a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = neg(a[i]);
+}
+
 // bound nb boxes given by their real endpoints (one wavefront per box)
 template <int FAM>
 __global__ __launch_bounds__(kWave* kBoundWaves) void k_eval_boxes(const Params* __restrict__ PP, int64_t nb,
@@ -2849,6 +2855,63 @@ void dispatch_family(int family, F&& f) {
 
 }  // namespace
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Device memory of ibb_eval_boxes_noalloc: one fixed array per GPU (each device
+// holds its own copy of a __device__ variable, for the life of the process).
+// A call carves it, 256-byte aligned, as: Params, -lower[n], upper[n], the
+// coefficients as given, the FP64 coefficient records, the FP32 ones.  Every
+// field is written by the call before its kernels read it; nothing has to start
+// at zero.  In host code `scratch` names a host-side stand-in, not device
+// memory: the address each device uses comes from hipGetSymbolAddress.
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;        // the per-device address table
+std::mutex g_scratch_call_mu;   // calls that use the array, one at a time
+void* g_scratch_addr[kScratchDevices] = {};
+
+struct ScratchLayout {
+  size_t nl, u, coef, tab, tab32, total;
+};
+
+ScratchLayout scratch_layout(const ibb_problem* p, bool want32) {
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t n = (size_t)p->n;
+  const bool chain = p->family == IBB_CHAIN;
+  ScratchLayout L{};
+  L.nl = up(sizeof(Params));
+  L.u = L.nl + up(n * sizeof(double));
+  L.coef = L.u + up(n * sizeof(double));
+  L.tab = L.coef + up((size_t)p->coef_len * sizeof(double));
+  L.tab32 = L.tab + up(n * (chain ? sizeof(CoefChain) : sizeof(CoefSep)));
+  L.total = L.tab32 + (want32 ? up(n * (chain ? sizeof(CoefChain32) : sizeof(CoefSep32))) : 0);
+  return L;
+}
+
+// the current device's address of `scratch`, looked up on the first call on
+// that device (with it current) and kept
+ibb_status scratch_for_current_device(unsigned char** out) {
+  int dev = -1;
+  const hipError_t ed = hipGetDevice(&dev);
+  if (ed != hipSuccess) return fail(IBB_E_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(ed));
+  if (dev < 0 || dev >= kScratchDevices) return fail(IBB_E_DEVICE, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(IBB_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = (unsigned char*)g_scratch_addr[dev];
+  return IBB_OK;
+}
+
+}  // namespace
+
 // result object -------------------------------------------------------------
 struct ibb_result {
   ibb_info info{};
@@ -3702,6 +3765,75 @@ ibb_status ibb_eval_boxes(const ibb_problem* prob, int32_t precision, int64_t nb
   (void)hipStreamSynchronize(M.stream);
   M.release_all();
   if (e != hipSuccess) return fail(IBB_E_DEVICE, std::string("eval launch: ") + hipGetErrorString(e));
+  return IBB_OK;
+}
+
+ibb_status ibb_eval_boxes_noalloc(const ibb_problem* prob, int32_t precision, int64_t nb, const double* d_lo,
+                                  const double* d_hi, double* d_F, double* d_ub_mid, uint8_t* d_mono_prune,
+                                  double* d_G, void* hip_stream) {
+  ibb_status st = validate(prob);
+  if (st != IBB_OK) return st;
+  if (precision != IBB_FP64 && precision != IBB_FP32_BULK) return fail(IBB_E_INVALID, "unknown precision");
+  const bool p32 = precision == IBB_FP32_BULK;
+  if (p32 && !fp32_safe(prob))
+    return fail(IBB_E_INVALID, "coefficient or domain magnitudes too large for single-precision bounds");
+  if (nb < 0) return fail(IBB_E_INVALID, "nb < 0");
+  const ScratchLayout lay = scratch_layout(prob, p32);
+  if (lay.total > kScratchBytes)
+    return fail(IBB_E_CAPACITY, "problem needs " + std::to_string(lay.total) + " bytes of the fixed device array (" +
+                                    std::to_string(kScratchBytes) + " bytes): n too large for ibb_eval_boxes_noalloc");
+  if (nb == 0) return IBB_OK;
+  if (!d_lo || !d_hi || !d_F || !d_ub_mid || !d_mono_prune) return fail(IBB_E_INVALID, "NULL device array");
+  const int64_t blocks = (nb + kBoundWaves - 1) / kBoundWaves;
+  if (blocks > 0x7fffffff) return fail(IBB_E_CAPACITY, "too many boxes");
+  std::lock_guard<std::mutex> serial(g_scratch_call_mu);   // one call at a time uses the array
+  unsigned char* base = nullptr;
+  if ((st = scratch_for_current_device(&base)) != IBB_OK) return st;
+  const hipStream_t stream = (hipStream_t)hip_stream;
+  const int n = prob->n;
+  const bool chain = prob->family == IBB_CHAIN;
+  Params P{};
+  P.family = prob->family;
+  P.n = n;
+  P.nl = (double*)(base + lay.nl);
+  P.u = (double*)(base + lay.u);
+  P.prec32 = p32 ? 1 : 0;
+  P.incremental = 0;
+  double* coef = (double*)(base + lay.coef);
+  HIPCHK(hipMemcpyAsync(base + lay.nl, prob->lower, n * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(base + lay.u, prob->upper, n * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(coef, prob->coef, prob->coef_len * sizeof(double), hipMemcpyHostToDevice, stream));
+  const int cblocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_negate, dim3(cblocks), dim3(256), 0, stream, n, (double*)(base + lay.nl));
+  if (chain) {
+    CoefChain* c = (CoefChain*)(base + lay.tab);
+    CoefChain32* c32 = p32 ? (CoefChain32*)(base + lay.tab32) : nullptr;
+    hipLaunchKernelGGL(k_setup_chain, dim3(cblocks), dim3(256), 0, stream, n, coef, c, c32);
+    P.chain = c;
+    P.chain32 = c32;
+  } else {
+    CoefSep* c = (CoefSep*)(base + lay.tab);
+    CoefSep32* c32 = p32 ? (CoefSep32*)(base + lay.tab32) : nullptr;
+    hipLaunchKernelGGL(k_setup_sep, dim3(cblocks), dim3(256), 0, stream, n, prob->family, coef, c, c32);
+    P.sep = c;
+    P.sep32 = c32;
+  }
+  Params* dP = (Params*)base;
+  HIPCHK(hipMemcpyAsync(dP, &P, sizeof(Params), hipMemcpyHostToDevice, stream));
+  dispatch_family(P.family, [&](auto fam) {
+    if (p32)
+      hipLaunchKernelGGL(k_eval_boxes32<decltype(fam)::value>, dim3((unsigned)blocks), dim3(kWave * kBoundWaves), 0,
+                         stream, dP, nb, d_lo, d_hi, d_F, d_ub_mid, d_mono_prune, d_G);
+    else
+      hipLaunchKernelGGL(k_eval_boxes<decltype(fam)::value>, dim3((unsigned)blocks), dim3(kWave * kBoundWaves), 0,
+                         stream, dP, nb, d_lo, d_hi, d_F, d_ub_mid, d_mono_prune, d_G);
+  });
+  const hipError_t e = hipGetLastError();
+  // P (host) and the caller's host arrays are read by the copies above, and the
+  // next call rewrites the array: wait for the work before returning
+  const hipError_t es = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(IBB_E_DEVICE, std::string("eval launch: ") + hipGetErrorString(e));
+  if (es != hipSuccess) return fail(IBB_E_DEVICE, std::string("eval: ") + hipGetErrorString(es));
   return IBB_OK;
 }
 

@@ -85,6 +85,7 @@ def test_empty_inputs_are_accepted_without_device_work():
     L = ibb.lib()
     k = _problem_struct()
     assert L.ibb_eval_boxes(C.byref(k.s), 0, 0, None, None, None, None, None, None, None) == 0
+    assert L.ibb_eval_boxes_noalloc(C.byref(k.s), 0, 0, None, None, None, None, None, None, None) == 0
     assert L.ibb_interval_op(0, 0, None, None, None, None) == 0
     assert L.ibb_point_trig(0, 0, None, None, None) == 0
     assert L.ibb_interval_op32(0, 0, None, None, None, None) == 0
@@ -95,6 +96,9 @@ def test_empty_inputs_are_accepted_without_device_work():
     (lambda L, k: L.ibb_eval_boxes(C.byref(k.s), 0, -1, None, None, None, None, None, None, None), "nb < 0"),
     (lambda L, k: L.ibb_eval_boxes(C.byref(k.s), 0, 4, None, None, None, None, None, None, None), "NULL"),
     (lambda L, k: L.ibb_eval_boxes(C.byref(k.s), 5, 4, None, None, None, None, None, None, None), "precision"),
+    (lambda L, k: L.ibb_eval_boxes_noalloc(C.byref(k.s), 0, -1, None, None, None, None, None, None, None), "nb < 0"),
+    (lambda L, k: L.ibb_eval_boxes_noalloc(C.byref(k.s), 0, 4, None, None, None, None, None, None, None), "NULL"),
+    (lambda L, k: L.ibb_eval_boxes_noalloc(C.byref(k.s), 5, 4, None, None, None, None, None, None, None), "precision"),
     (lambda L, k: L.ibb_interval_op(14, 4, None, None, None, None), "unknown op"),
     (lambda L, k: L.ibb_interval_op(0, -1, None, None, None, None), "count < 0"),
     (lambda L, k: L.ibb_interval_op(0, 4, None, None, None, None), "NULL"),
@@ -107,6 +111,21 @@ def test_bad_kernel_arguments_rejected_before_the_device(call, msg):
     L = ibb.lib()
     rc = call(L, _problem_struct())
     assert rc == -1 and msg in L.ibb_last_error().decode()
+
+
+@pytest.mark.parametrize("n,prec,fits", [(100_000, 1, True), (120_000, 1, False), (170_000, 0, True),
+                                         (180_000, 0, False)])
+def test_noalloc_array_limit_checked_before_the_device(n, prec, fits):
+    # the fixed device array (16 MiB) holds the problem's tables, or the call is
+    # refused with IBB_E_CAPACITY before any device work (nb = 0 returns after the check)
+    p = PR.sep_cos(n, 7)
+    k = ibb._ProblemKeep(p.family, p.coef, p.lower, p.upper, 1e-6, 0.0)
+    L = ibb.lib()
+    rc = L.ibb_eval_boxes_noalloc(C.byref(k.s), prec, 0, None, None, None, None, None, None, None)
+    if fits:
+        assert rc == 0
+    else:
+        assert rc == -4 and "fixed device array" in L.ibb_last_error().decode()
 
 
 def test_batch_and_server_take_one_box_per_sweep():
