@@ -58,7 +58,29 @@ typedef enum {
  * then folded with strides 32..1), which makes the bounds reproducible bit for
  * bit.  cos and sin are evaluated as cos(2 pi y), sin(2 pi y) of y = k (x - c)
  * (or k/2 (x - c)), so the argument reduction is exact. */
-typedef enum { IBB_SEP_COS = 1, IBB_CHAIN = 2, IBB_SEP_ABS_SIN2 = 3 } ibb_family;
+/* IBB_TAPE: a generic closed-form f given as an expression tape in coef (the
+ * benchmark functions of the paper's SI Appendix A, Eqs. S1-S21, and Appendix D,
+ * Eq. S22, are all of this form):  f = g(R_1, ..., R_K), each R_k a sum (kind 0)
+ * or a product (kind 1) over i in a range of an element program in x_i,
+ * x_{i+1} (sums only, ranges ending by n - 1), i + 1 and coefficient columns;
+ * g a scalar program of the R_k and constants.  coef (doubles):
+ *   [1, K, Q, C]                              K <= 8 reductions, 1 <= Q <= 32
+ *   per reduction: [kind, s_off, s_end, t_off, t_end, L] then L ops (1..32):
+ *       i runs from s_off + (s_end ? n : 0) to t_off + (t_end ? n : 0), exclusive
+ *   Q scalar ops, the last one's value being f
+ *   C coefficient columns of n values (coef_len must match exactly)
+ * An op is 5 doubles [code, a, b, c_lo, c_hi]; a, b index earlier ops of the
+ * same program.  Codes: 0 constant [c_lo, c_hi]; 1 x_i; 2 x_{i+1}; 3 column a
+ * at i; 4 a + b; 5 a - b; 6 a * b; 7 a / b (= a * (1/b), Eq. (6)); 8 -a; 9 a^2;
+ * 10 sqrt a; 11 exp a; 12 cos a; 13 sin a; 14 cos(2 pi a); 15 sin(2 pi a);
+ * 16 |a|; 17 reduction a (scalar program only); 18 i + 1 (element programs
+ * only; 1, 2, 3 likewise).  Every operation rounds outward (Sec. 2.1); the
+ * gradient for the first-order test (Sec. 3.1) comes from forward tangents in
+ * the element programs and adjoints of the scalar program (the order of
+ * every sum and product is fixed by the library and the same in the checks).
+ * A malformed tape is refused with IBB_E_INVALID.  The generic family is
+ * bounded in full (no incremental bounds), one box per sweep, FP64. */
+typedef enum { IBB_SEP_COS = 1, IBB_CHAIN = 2, IBB_SEP_ABS_SIN2 = 3, IBB_TAPE = 4 } ibb_family;
 
 /* IBB_FP64: every box is bounded in double precision, as in the paper's
  * experiments (Sec. 4).
@@ -80,7 +102,7 @@ typedef struct {
   int32_t family;        /* ibb_family */
   int32_t n;             /* dimension, 1 <= n <= 1<<24 (CHAIN: n >= 2) */
   const double* coef;    /* host, coef_len values, layout above */
-  int64_t coef_len;      /* 4n (SEP_COS, SEP_ABS_SIN2) or 2(n-1) (CHAIN) */
+  int64_t coef_len;      /* 4n (SEP_COS, SEP_ABS_SIN2), 2(n-1) (CHAIN), the tape's length (TAPE) */
   const double* lower;   /* host [n]: l, finite */
   const double* upper;   /* host [n]: u, finite, l_i < u_i */
   double tol_f;          /* stop once GUB - GLB (rounded up) <= tol_f; > 0 */
@@ -154,7 +176,9 @@ typedef struct {
   int32_t bound_shape;        /* shape of the bound kernel used (0..4, see ibb_options; -1: incremental) */
   int32_t pad;
   int64_t n_persistent_launches; /* with profile = 1: launches of the persistent sweep kernel (each runs a
-                                    chunk of sweeps; t_select_ms is their summed time) */
+                                    chunk of sweeps; their time is part of t_select_ms) */
+  double t_persistent_ms;        /* with profile = 1: the persistent launches' summed time */
+  int64_t n_persistent_sweeps;   /* with profile = 1: the sweeps those launches ran */
 } ibb_info;
 
 typedef struct ibb_result ibb_result;

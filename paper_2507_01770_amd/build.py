@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "ibb.hip")
-HEADERS = [os.path.join(HERE, "csrc", h) for h in ("ivl.hpp", "fam.hpp", "kern.hpp", "serve.inc")] + [
+HEADERS = [os.path.join(HERE, "csrc", h) for h in ("ivl.hpp", "fam.hpp", "kern.hpp", "tape.hpp", "serve.inc")] + [
     os.path.join(ROOT, "include", "ibb.h")]
 LIB = os.path.join(HERE, "libibb.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -19,6 +19,7 @@
 
 #include "ibb.h"
 #include "kern.hpp"
+#include "tape.hpp"
 
 using namespace ibb;
 
@@ -66,6 +67,143 @@ __global__ void k_setup_chain(int n, const double* __restrict__ coef, CoefChain*
   r.be = i < n - 1 ? coef[(n - 1) + i] : 0.0;
   out[i] = r;
   if (out32) out32[i] = CoefChain32{to32(point(r.al)), to32(point(r.be))};
+}
+
+// ---------------------------------------------------------------------------
+// The generic family (an expression tape): every child bounded in full by one
+// thread (the terms of f are not a sum of per-coordinate terms in general, so
+// there are no shared terms to reuse), the records written for the next
+// selection, GUB lowered by the smallest sample upper bound of the workgroup.
+
+// the root box (the first key) and GUB from its midpoint (no sample with the
+// diagonal samples of the paper's schedule)
+__global__ __launch_bounds__(kWave) void k_tape_root(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  const Params P = *PP;
+  if (threadIdx.x != 0) return;
+  const ChildRow X{P.hist_n, P.hist_h, P.hist_mid, P.n, P.m, 0, 0u, 0u};
+  bool mo = false;
+  const I F = tape_box<ChildRow, false>(*P.tape, P.tcols, P.n, X, P.nl, P.u, P.tws, mo, nullptr);
+  const PointRow<ChildRow> M{X, -1.0};
+  bool unused = false;
+  const double u = tape_box<PointRow<ChildRow>, false>(*P.tape, P.tcols, P.n, M, P.nl, P.u, P.tws, unused, nullptr).h;
+  double wm = 0.0;
+  for (int i = 0; i < P.n; ++i) { const I x = X.get(i); wm = dmax(wm, x.n + x.h); }
+  S->gub_key = okey(P.nsamp > 0 ? __builtin_inf() : hi_or_inf(u));
+  P.key_flo[0] = lo_or_ninf(neg(F.n));
+  P.key_seq[0] = 0;
+  P.key_ref[0] = 0;
+  P.key_r[0] = -1;
+  P.key_wmax[0] = wm;
+  P.hist_cyc[0] = 0;
+  P.hist_mask[0] = 0u;
+  S->n_keys = 1;
+  S->next_seq = 1;
+  S->sweeps = 0;
+  S->evaluated = 1;
+  S->ub_evaluated = 1;
+  S->n_live = 1;
+  S->stop = RUNNING;
+  S->pending = 0;
+  S->sel_done = 0u;
+  S->bound_done = 0u;
+}
+
+// the children of the selected box, one thread each (PIECES = 2: bisection and
+// the midpoint sample; PIECES = 4: the paper's four pieces and P.nsamp diagonal
+// samples)
+template <int PIECES>
+__global__ __launch_bounds__(256) void k_tape_children(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params& P = *PP;
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int n = P.n, m = P.m;
+  const int64_t row = S->sel_row;
+  const int cyc = S->sel_cyc;
+  const uint32_t mask = S->sel_mask;
+  const bool in = g < P.nch;
+  bool formed = in;
+  if (PIECES == 2) {
+    formed = in && ((uint32_t)g & ~mask) == 0u;
+  } else {
+    for (int j = 0; j < m; ++j)
+      if (((g >> (2 * j)) & 3) && !((mask >> j) & 1u)) formed = false;
+  }
+  double ub = __builtin_inf();
+  if (formed) {
+    using Row = typename std::conditional<PIECES == 4, ChildRow4, ChildRow>::type;
+    const Row X{P.hist_n + row * n, P.hist_h + row * n,
+                PIECES == 4 ? P.hist_cut + row * (3 * kMaxSplit) : P.hist_mid + row * kMaxSplit, n, m, cyc, mask,
+                (uint32_t)g};
+    I* ws = P.tws ? P.tws + (int64_t)g * P.tape->nprod * n : nullptr;
+    bool mo = false;
+    const I F = tape_box<Row, true>(*P.tape, P.tcols, n, X, P.nl, P.u, ws, mo, nullptr);
+    bool unused = false;
+    if (P.nsamp > 0) {
+      for (int s = 0; s < P.nsamp; ++s) {
+        const PointRow<Row> D{X, P.cs[s]};
+        ub = dmin(ub, hi_or_inf(tape_box<PointRow<Row>, false>(*P.tape, P.tcols, n, D, P.nl, P.u, ws, unused,
+                                                               nullptr).h));
+      }
+    } else {
+      const PointRow<Row> M{X, -1.0};
+      ub = hi_or_inf(tape_box<PointRow<Row>, false>(*P.tape, P.tcols, n, M, P.nl, P.u, ws, unused, nullptr).h);
+    }
+    double wm = 0.0;
+    for (int i = 0; i < n; ++i) { const I x = X.get(i); wm = dmax(wm, x.n + x.h); }
+    P.ch_flo[g] = lo_or_ninf(neg(F.n));
+    P.ch_wmax[g] = wm;
+    P.ch_flag[g] = mo ? 1 : 2;
+  } else if (in) {
+    P.ch_flag[g] = 0;
+  }
+  // the workgroup's smallest sample bound into GUB (only when it is lower)
+  __shared__ double s_u[256 / kWave];
+  __shared__ int s_n[256 / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  double um = ub;
+  int cnt = formed ? 1 : 0;
+  for (int h = 32; h >= 1; h >>= 1) {
+    um = dmin(um, __shfl_xor(um, h, kWave));
+    cnt += __shfl_xor(cnt, h, kWave);
+  }
+  if (lane == 0) { s_u[wid] = um; s_n[wid] = cnt; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mn = s_u[0];
+    int tot = s_n[0];
+    for (int k = 1; k < 256 / kWave; ++k) { mn = dmin(mn, s_u[k]); tot += s_n[k]; }
+    if (tot > 0) {
+      const unsigned long long key = okey(mn);
+      if (key < __hip_atomic_load(&S->gub_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMin((unsigned long long*)&S->gub_key, key);
+      atomicAdd((unsigned long long*)&S->ub_evaluated, (unsigned long long)tot);
+    }
+  }
+}
+
+// bound nb boxes given by their real endpoints, one thread each (ibb_eval_boxes)
+__global__ __launch_bounds__(256) void k_eval_tape(const Params* __restrict__ PP, int64_t nb,
+                                                   const double* __restrict__ lo, const double* __restrict__ hi,
+                                                   double* __restrict__ F, double* __restrict__ ub,
+                                                   uint8_t* __restrict__ mono, double* __restrict__ G, I* ws) {
+  round_up_mode();
+  const Params P = *PP;
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= nb) return;
+  const int n = P.n;
+  const PlainRow X{lo + b * n, hi + b * n};
+  bool mo = false;
+  I* w = ws ? ws + b * P.tape->nprod * n : nullptr;
+  const I f = tape_box<PlainRow, true>(*P.tape, P.tcols, n, X, P.nl, P.u, w, mo, G ? G + b * 2 * n : nullptr);
+  bool unused = false;
+  const PointRow<PlainRow> M{X, -1.0};
+  const double u = tape_box<PointRow<PlainRow>, false>(*P.tape, P.tcols, n, M, P.nl, P.u, w, unused, nullptr).h;
+  F[2 * b] = neg(f.n);
+  F[2 * b + 1] = f.h;
+  ub[b] = u;
+  mono[b] = mo ? 1 : 0;
 }
 
 // a[i] = -a[i] (exact), for the lower bounds held negated
@@ -2735,11 +2873,102 @@ struct Mem {
 
 bool finite_bounded(double v) { return std::isfinite(v) && std::fabs(v) <= 1e15; }
 
+// The tape of an IBB_TAPE problem, checked op by op (the encoding is in ibb.h);
+// cols_at receives where the coefficient columns start in coef.
+ibb_status parse_tape(const ibb_problem* p, TapeDev& T, int64_t& cols_at) {
+  const double* c = p->coef;
+  const int64_t len = p->coef_len, n = p->n;
+  auto bad = [](const std::string& why) { return fail(IBB_E_INVALID, "tape: " + why); };
+  auto as_int = [](double v, int64_t lo, int64_t hi, int64_t& out) {
+    if (!(v >= (double)lo && v <= (double)hi) || v != std::floor(v)) return false;
+    out = (int64_t)v;
+    return true;
+  };
+  if (!c || len < 4 || c[0] != 1.0) return bad("unknown format (coef[0] must be 1)");
+  int64_t K, Q, C;
+  if (!as_int(c[1], 0, kTapeMaxRed, K) || !as_int(c[2], 1, kTapeMaxOps, Q) || !as_int(c[3], 0, 64, C))
+    return bad("K, Q or C out of range");
+  T = TapeDev{};
+  T.K = (int32_t)K;
+  T.Q = (int32_t)Q;
+  T.C = (int32_t)C;
+  int64_t at = 4;
+  int nops_all = 0;
+  auto read_op = [&](int q, bool elem, int lim, TapeOp& o) -> bool {
+    int64_t code, a, b;
+    if (!as_int(c[at], 0, 18, code)) return false;
+    if (!as_int(c[at + 1], -1, kTapeMaxOps, a) || !as_int(c[at + 2], -1, kTapeMaxOps, b)) return false;
+    o.code = (int32_t)code;
+    o.a = (int32_t)a;
+    o.b = (int32_t)b;
+    o.lo = c[at + 3];
+    o.hi = c[at + 4];
+    at += 5;
+    const bool elem_only = code == 1 || code == 2 || code == 3 || code == 18;
+    if (elem_only && !elem) return false;
+    if (code == 17 && elem) return false;
+    if ((code == 3 || code == 17) && (a < 0 || a >= lim)) return false;
+    if (code >= 4 && code <= 16 && (a < 0 || a >= q)) return false;
+    if (code >= 4 && code <= 7 && (b < 0 || b >= q)) return false;
+    if (code == 0 && !(finite_bounded(o.lo) && finite_bounded(o.hi) && o.lo <= o.hi)) return false;
+    return true;
+  };
+  for (int k = 0; k < K; ++k) {
+    if (at + 6 > len) return bad("truncated");
+    int64_t kind, s_off, s_end, t_off, t_end, L;
+    if (!as_int(c[at], 0, 1, kind) || !as_int(c[at + 1], -n, n, s_off) || !as_int(c[at + 2], 0, 1, s_end) ||
+        !as_int(c[at + 3], -n, n, t_off) || !as_int(c[at + 4], 0, 1, t_end) || !as_int(c[at + 5], 1, kTapeMaxOps, L))
+      return bad("reduction header " + std::to_string(k));
+    at += 6;
+    if (at + 5 * L > len) return bad("truncated");
+    int64_t start = s_off + (s_end ? n : 0), stop = t_off + (t_end ? n : 0);
+    start = std::max<int64_t>(start, 0);
+    stop = std::min<int64_t>(stop, n);
+    stop = std::max(stop, start);
+    TapeRed& R = T.red[k];
+    R.kind = (int32_t)kind;
+    R.start = (int32_t)start;
+    R.stop = (int32_t)stop;
+    R.first = nops_all;
+    R.nops = (int32_t)L;
+    for (int q = 0; q < L; ++q) {
+      TapeOp& o = T.op[nops_all + q];
+      if (!read_op(q, true, (int)C, o)) return bad("op " + std::to_string(q) + " of reduction " + std::to_string(k));
+      if (o.code == 2 && (kind != 0 || stop > n - 1)) return bad("x_{i+1} needs a sum ending by n - 1");
+    }
+    nops_all += (int)L;
+    if (kind == 1) T.nprod++;
+  }
+  if (at + 5 * Q > len) return bad("truncated");
+  T.sc_first = nops_all;
+  for (int q = 0; q < Q; ++q)
+    if (!read_op(q, false, (int)K, T.op[nops_all + q])) return bad("scalar op " + std::to_string(q));
+  if (at + C * n != len) return bad("coef_len does not match the tape and its columns");
+  for (int64_t i = at; i < len; ++i)
+    if (!finite_bounded(c[i])) return bad("coefficient column value not finite or too large");
+  cols_at = at;
+  return IBB_OK;
+}
+
 ibb_status validate(const ibb_problem* p) {
   if (!p) return fail(IBB_E_INVALID, "problem is NULL");
-  if (p->family != IBB_SEP_COS && p->family != IBB_CHAIN && p->family != IBB_SEP_ABS_SIN2)
+  if (p->family != IBB_SEP_COS && p->family != IBB_CHAIN && p->family != IBB_SEP_ABS_SIN2 && p->family != IBB_TAPE)
     return fail(IBB_E_INVALID, "unknown family " + std::to_string(p->family));
   if (p->n < 1 || p->n > (1 << 24)) return fail(IBB_E_INVALID, "n out of range");
+  if (p->family == IBB_TAPE) {
+    if (!p->coef || !p->lower || !p->upper) return fail(IBB_E_INVALID, "NULL array");
+    TapeDev T;
+    int64_t at = 0;
+    ibb_status st = parse_tape(p, T, at);
+    if (st != IBB_OK) return st;
+    for (int i = 0; i < p->n; ++i) {
+      if (!finite_bounded(p->lower[i]) || !finite_bounded(p->upper[i])) return fail(IBB_E_INVALID, "bounds must be finite");
+      if (!(p->lower[i] < p->upper[i])) return fail(IBB_E_INVALID, "need lower < upper");
+    }
+    if (!(p->tol_f > 0.0) || !std::isfinite(p->tol_f)) return fail(IBB_E_INVALID, "tol_f must be > 0");
+    if (!(p->tol_x >= 0.0)) return fail(IBB_E_INVALID, "tol_x must be >= 0");
+    return IBB_OK;
+  }
   if (p->family == IBB_CHAIN && p->n < 2) return fail(IBB_E_INVALID, "CHAIN needs n >= 2");
   const int64_t need = p->family == IBB_CHAIN ? 2 * (int64_t)(p->n - 1) : 4 * (int64_t)p->n;
   if (p->coef_len != need) return fail(IBB_E_INVALID, "coef_len must be " + std::to_string(need));
@@ -2823,7 +3052,23 @@ ibb_status upload_problem(Mem& M, const ibb_problem* p, Params& P, bool want32 =
   P.chain32 = nullptr;
   P.prec32 = want32 ? 1 : 0;
   P.incremental = 0;
+  P.tape = nullptr;
+  P.tcols = nullptr;
+  P.tws = nullptr;
   const int blocks = (n + 255) / 256;
+  if (p->family == IBB_TAPE) {   // the tape (checked by validate) and its columns, which stay in d_coef
+    TapeDev T;
+    int64_t at = 0;
+    ibb_status st = parse_tape(p, T, at);
+    if (st != IBB_OK) return st;
+    TapeDev* dT = dalloc<TapeDev>(M, 1);
+    if (!dT) return fail(IBB_E_NOMEM, "device allocation failed");
+    HIPCHK(hipMemcpyAsync(dT, &T, sizeof(TapeDev), hipMemcpyHostToDevice, M.stream));
+    HIPCHK(hipStreamSynchronize(M.stream));   // T and nl (host) must outlive their copies
+    P.tape = dT;
+    P.tcols = d_coef + at;
+    return IBB_OK;
+  }
   if (p->family == IBB_CHAIN) {
     CoefChain* c = dalloc<CoefChain>(M, n);
     CoefChain32* c32 = want32 ? dalloc<CoefChain32>(M, n) : nullptr;
@@ -3003,7 +3248,7 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   const int n = prob->n;
   ibb_status st = upload_problem(M, prob, P, U.opts.precision == IBB_FP32_BULK && fp32_safe(prob));
   if (st != IBB_OK) return st;
-  P.incremental = U.opts.incremental ? 1 : 0;
+  P.incremental = U.opts.incremental && !P.tape ? 1 : 0;   // the generic family is bounded in full
   P.m = std::min(n, U.opts.split_dims);
   P.pieces = U.opts.pieces == 4 ? 4 : 2;
   P.nch = P.pieces == 4 ? 1 << (2 * P.m) : 1 << P.m;
@@ -3041,6 +3286,18 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   const bool tc = U.term_cache && P.incremental && P.select_k == 1 && P.pieces == 2 && n >= kTermCacheMinN;
   P.tcache = tc ? dalloc<double>(M, P.hist_cap * 3 * n) : nullptr;
   P.hist_par = tc ? dalloc<int32_t>(M, P.hist_cap) : nullptr;
+  if (P.tape) {   // right products of the product reductions: n intervals each per child record
+    TapeDev T;
+    int64_t at = 0;
+    if ((st = parse_tape(prob, T, at)) != IBB_OK) return st;
+    if (T.nprod > 0) {
+      const int64_t cnt = std::max<int64_t>(nrec, 1) * T.nprod * n;
+      if (cnt * (int64_t)sizeof(I) > ((int64_t)8 << 30))
+        return fail(IBB_E_CAPACITY, "the tape's product reductions need more than 8 GiB of workspace at this size");
+      P.tws = dalloc<I>(M, cnt);
+      if (!P.tws) return fail(IBB_E_NOMEM, "device allocation failed");
+    }
+  }
   P.part_flo = dalloc<double>(M, kMaxSelBlocks);
   P.part_idx = dalloc<int64_t>(M, kMaxSelBlocks);
   P.part_wmax = dalloc<double>(M, kMaxSelBlocks);
@@ -3063,9 +3320,12 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   st = push_params(M, P, U.dP);
   if (st != IBB_OK) return st;
   HIPCHK(hipStreamSynchronize(M.stream));   // nl must outlive its copy
-  dispatch_family(P.family, [&](auto fam) {
-    hipLaunchKernelGGL(k_root<decltype(fam)::value>, dim3(1), dim3(kWave), 0, M.stream, U.dP, U.dS);
-  });
+  if (P.tape)
+    hipLaunchKernelGGL(k_tape_root, dim3(1), dim3(kWave), 0, M.stream, U.dP, U.dS);
+  else
+    dispatch_family(P.family, [&](auto fam) {
+      hipLaunchKernelGGL(k_root<decltype(fam)::value>, dim3(1), dim3(kWave), 0, M.stream, U.dP, U.dS);
+    });
   HIPCHK(hipGetLastError());
   U.n_keys = 1;
   U.sweeps = 0;
@@ -3383,6 +3643,7 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
     // sweeps in one launch, as many as keep the list's growth within a bound
     const bool multi = P.select_k > 1;   // K boxes per sweep: a selection kernel and a bound kernel per sweep
     const bool four = P.pieces == 4;     // the paper's schedule: selection, tables, children kernels per sweep
+    const bool tape = P.tape != nullptr; // the generic family: selection and a children kernel per sweep
     const bool persist = !multi && !four && P.incremental && U.n_keys <= kPersistentMaxKeys;
     int chunk = persist ? (int)std::min<int64_t>(std::max<int64_t>(kPersistentGrowth / P.nch, 16), 256) : grow_chunk;
     if (!persist)   // the key arrays are sized for every child of the chunk surviving: keep that within 2^23 keys
@@ -3409,7 +3670,27 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
                               prof ? ev[0] : nullptr, prof ? ev[3] : nullptr, 0, U.dP, U.dS, chunk);
         return;
       }
-      for (int s = 0; s < chunk && four; ++s) {
+      for (int s = 0; s < chunk && tape; ++s) {   // the generic family: selection, then every child in full
+        if (sb > 1)
+          hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
+                                nullptr, 0, U.dP, U.dS);
+        if (four)
+          hipExtLaunchKernelGGL(k_select4<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
+                                (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
+                                U.dS, sb > 1 ? sb : 0, 0);
+        else
+          hipExtLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
+                                (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
+                                U.dS, sb > 1 ? sb : 0, 0);
+        const dim3 gch((unsigned)((P.nch + 255) / 256));
+        if (four)
+          hipExtLaunchKernelGGL(k_tape_children<4>, gch, dim3(256), 0, M.stream, prof ? ev[4 * s + 1] : nullptr,
+                                prof ? ev[4 * s + 2] : nullptr, 0, U.dP, U.dS);
+        else
+          hipExtLaunchKernelGGL(k_tape_children<2>, gch, dim3(256), 0, M.stream, prof ? ev[4 * s + 1] : nullptr,
+                                prof ? ev[4 * s + 2] : nullptr, 0, U.dP, U.dS);
+      }
+      for (int s = 0; s < chunk && four && !tape; ++s) {
         if (sb > 1)
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
                                 nullptr, 0, U.dP, U.dS);
@@ -3443,7 +3724,7 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
           launch_bound<FAM>(bound_shape, P.select_k * P.nch, M.stream, prof ? ev[4 * s + 1] : nullptr,
                             prof ? ev[4 * s + 2] : nullptr, U.dP, U.dS);
       }
-      for (int s = 0; s < chunk && !multi && !four; ++s) {
+      for (int s = 0; s < chunk && !multi && !four && !tape; ++s) {
         if (sb > 1)
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
                                 nullptr, 0, U.dP, U.dS);
@@ -3471,6 +3752,8 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
       if (hipEventElapsedTime(&ms, ev[0], ev[3]) == hipSuccess) R->info.t_select_ms += ms;
       R->info.n_select_launches += ran + (U.hs.stop ? 1 : 0);
       R->info.n_persistent_launches++;
+      R->info.t_persistent_ms += ms;
+      R->info.n_persistent_sweeps += ran + (U.hs.stop ? 1 : 0);
     } else if (prof) {
       // bound launches that did work in this chunk; the select of the stopping sweep ran too
       const int64_t ran = (U.hs.sweeps + (U.hs.pending ? 1 : 0)) - (U.sweeps + (U.pending ? 1 : 0));
@@ -3563,6 +3846,12 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
   Run U;
   U.t0 = std::chrono::steady_clock::now();
   if (opts_in) U.opts = *opts_in; else ibb_options_default(&U.opts);
+  if (prob->family == IBB_TAPE) {
+    // the generic family is bounded in full, one box per sweep, in FP64
+    if (U.opts.select_k != 1 || U.opts.precision != IBB_FP64 || U.opts.bound_shape != 0)
+      return fail(IBB_E_INVALID, "the generic family (IBB_TAPE) runs with select_k = 1, FP64 and bound_shape 0");
+    U.opts.incremental = 1;   // passes the option checks; the tape kernels bound every child in full
+  }
   if ((st = check_options(U.opts)) != IBB_OK) return st;
 
   ibb_result* R = new ibb_result();
@@ -3594,9 +3883,9 @@ static ibb_status solve_impl(const ibb_problem* prob, const ibb_options* opts_in
   const int n_tiles = (n + kWave - 1) / kWave;
   const uint64_t tune_key = ((uint64_t)P.family << 52) | ((uint64_t)std::min(P.select_k, 1 << 11) << 40) |
                             ((uint64_t)std::min(n_tiles, 1 << 20) << 8) | ((uint64_t)P.m << 1) | (uint64_t)(P.prec32 != 0);
-  if (P.incremental) bound_variant = -1;
+  if (P.incremental || P.tape) bound_variant = -1;   // the tape kernels have one shape
   else if (bound_variant < 0) bound_variant = tuned_shape(tune_key);
-  if (!P.incremental && bound_variant < 0) {
+  if (!P.incremental && !P.tape && bound_variant < 0) {
     st = autotune_bound(U, n_tiles, bound_variant);
     if (st != IBB_OK) return bail(st);
     store_tuned_shape(tune_key, bound_variant);
@@ -3737,6 +4026,7 @@ ibb_status ibb_eval_boxes(const ibb_problem* prob, int32_t precision, int64_t nb
   if (p32 && !fp32_safe(prob))
     return fail(IBB_E_INVALID, "coefficient or domain magnitudes too large for single-precision bounds");
   if (nb < 0) return fail(IBB_E_INVALID, "nb < 0");
+  if (p32 && prob->family == IBB_TAPE) return fail(IBB_E_INVALID, "the generic family (IBB_TAPE) is FP64 only");
   if (nb == 0) return IBB_OK;
   if (!d_lo || !d_hi || !d_F || !d_ub_mid || !d_mono_prune) return fail(IBB_E_INVALID, "NULL device array");
   Mem M;
@@ -3744,6 +4034,33 @@ ibb_status ibb_eval_boxes(const ibb_problem* prob, int32_t precision, int64_t nb
   Params P{};
   st = upload_problem(M, prob, P, p32);
   if (st != IBB_OK) { M.release_all(); return st; }
+  if (P.tape) {   // one thread per box; right products of the product reductions in a workspace
+    TapeDev T;
+    int64_t at = 0;
+    if ((st = parse_tape(prob, T, at)) != IBB_OK) { M.release_all(); return st; }
+    I* ws = nullptr;
+    if (T.nprod > 0) {
+      const int64_t cnt = nb * T.nprod * (int64_t)prob->n;
+      if (cnt * (int64_t)sizeof(I) > ((int64_t)8 << 30)) { M.release_all(); return fail(IBB_E_CAPACITY, "too many boxes for the workspace"); }
+      ws = dalloc<I>(M, cnt);
+      if (!ws) { M.release_all(); return fail(IBB_E_NOMEM, "device allocation failed"); }
+    }
+    Params* dP = dalloc<Params>(M, 1);
+    if (!dP) { M.release_all(); return fail(IBB_E_NOMEM, "device allocation failed"); }
+    if (hipMemcpyAsync(dP, &P, sizeof(Params), hipMemcpyHostToDevice, M.stream) != hipSuccess) {
+      M.release_all();
+      return fail(IBB_E_DEVICE, "copy failed");
+    }
+    const int64_t tb = (nb + 255) / 256;
+    if (tb > 0x7fffffff) { M.release_all(); return fail(IBB_E_CAPACITY, "too many boxes"); }
+    hipLaunchKernelGGL(k_eval_tape, dim3((unsigned)tb), dim3(256), 0, M.stream, dP, nb, d_lo, d_hi, d_F, d_ub_mid,
+                       d_mono_prune, d_G, ws);
+    const hipError_t e = hipGetLastError();
+    (void)hipStreamSynchronize(M.stream);
+    M.release_all();
+    if (e != hipSuccess) return fail(IBB_E_DEVICE, std::string("eval launch: ") + hipGetErrorString(e));
+    return IBB_OK;
+  }
   Params* dP = dalloc<Params>(M, 1);
   if (!dP) { M.release_all(); return fail(IBB_E_NOMEM, "device allocation failed"); }
   if (hipMemcpyAsync(dP, &P, sizeof(Params), hipMemcpyHostToDevice, M.stream) != hipSuccess) {
@@ -3778,6 +4095,8 @@ ibb_status ibb_eval_boxes_noalloc(const ibb_problem* prob, int32_t precision, in
   if (p32 && !fp32_safe(prob))
     return fail(IBB_E_INVALID, "coefficient or domain magnitudes too large for single-precision bounds");
   if (nb < 0) return fail(IBB_E_INVALID, "nb < 0");
+  if (prob->family == IBB_TAPE)
+    return fail(IBB_E_INVALID, "ibb_eval_boxes_noalloc takes the fixed families (the generic one needs a workspace)");
   const ScratchLayout lay = scratch_layout(prob, p32);
   if (lay.total > kScratchBytes)
     return fail(IBB_E_CAPACITY, "problem needs " + std::to_string(lay.total) + " bytes of the fixed device array (" +

@@ -84,6 +84,25 @@ constexpr int kTabInts = 4 + kTabRows * (1 + 2) + kTabRows * (1 + 3) + kTabRows 
 
 struct KselBuf;
 
+// the generic family: an expression tape (layout of the encoding in ibb.h)
+constexpr int kTapeMaxOps = 32;   // ops per program
+constexpr int kTapeMaxRed = 8;    // reductions
+struct TapeOp {
+  int32_t code, a, b, pad;
+  double lo, hi;                  // the constant [lo, hi] of code 0
+};
+struct TapeRed {
+  int32_t kind, start, stop;      // 0 sum, 1 product; i in [start, stop)
+  int32_t first, nops;            // its program: op[first .. first + nops)
+  int32_t pad;
+};
+struct TapeDev {
+  int32_t K, Q, C, sc_first;      // the scalar program: op[sc_first .. sc_first + Q)
+  int32_t nprod, pad;             // product reductions (each needs n workspace intervals per box)
+  TapeRed red[kTapeMaxRed];
+  TapeOp op[kTapeMaxOps * (kTapeMaxRed + 1)];
+};
+
 struct Params {
   int32_t family, n, m, nch;              // nch = 2^m children per selected box
   double tol_f, tol_x;
@@ -146,6 +165,10 @@ struct Params {
   // takes those of its parent row that its own cut leaves unchanged
   double* tcache;                         // null: no cache
   int32_t* hist_par;                      // [row] the row the box was cut from (-1: none)
+  // the generic family
+  const TapeDev* tape;                    // null for the fixed families
+  const double* tcols;                    // [C][n] coefficient columns
+  I* tws;                                 // [children][nprod][n] right products of the product reductions
 };
 
 struct State {

@@ -140,3 +140,27 @@ def test_batch_and_server_take_one_box_per_sweep():
     sts = (C.c_int32 * 1)()
     rc = L.ibb_solve_batch(C.byref(k.s), 1, C.byref(o), None, None, outs, sts)
     assert rc == -1 and "select_k" in L.ibb_last_error().decode()
+
+
+def test_malformed_tapes_refused_before_the_device():
+    # the generic family's tape is checked op by op before any device work
+    from paper_2507_01770_amd import tapes as TP
+    L = ibb.lib()
+    good = TP.ackley(3)
+
+    def solve(coef):
+        k = ibb._ProblemKeep(TP.TAPE, coef, good.lower, good.upper, 1e-6, 0.0)
+        o = ibb._Options()
+        L.ibb_options_default(C.byref(o))
+        h = C.c_void_p()
+        return L.ibb_solve(C.byref(k.s), C.byref(o), None, None, C.byref(h))
+
+    cases = []
+    c = good.coef.copy(); c[0] = 2.0; cases.append(c)                      # unknown format
+    c = good.coef.copy(); c[1] = 9.0; cases.append(c)                      # too many reductions
+    c = good.coef.copy(); c[4 + 6 + 5 + 1] = 5.0; cases.append(c)          # operand not an earlier op
+    c = good.coef.copy(); c[4 + 6] = 99.0; cases.append(c)                 # unknown op code
+    cases.append(good.coef[:-1].copy())                                    # length does not match
+    c = good.coef.copy(); c[4] = 1.0; c[4 + 6 + 5] = 2.0; cases.append(c)  # x_{i+1} in a product
+    for c in cases:
+        assert solve(c) == -1 and "tape" in L.ibb_last_error().decode()

@@ -87,9 +87,6 @@ def test_refused_allocation_gives_nomem_and_returns_everything(incremental):
     assert np.array_equal(again.trace_gub, ref.trace_gub)
 
 
-@pytest.mark.skip(reason="the full-bounds case faulted the GPU once in k_select_batch (memory aperture "
-                         "violation, three problems active) with its cause not shown; both cases stay off "
-                         "the GPU until a cause is shown on the CPU")
 @pytest.mark.parametrize("incremental", [False, True])
 def test_refused_allocation_in_a_batch(incremental):
     # a refusal while problems are admitted fails those problems; one while the
