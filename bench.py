@@ -18,9 +18,15 @@ Also measured in the same run (extra keys of the JSON line):
     (closed loop -> capacity mu, then Poisson arrivals at 0.8 mu), and on its
     first requests the same arrivals served one at a time by plain FP64 solves
     (full bounds, one kernel launch per step);
-  * the CPU oracle on a bounded prefix of the headline workload, on one host
-    thread and as one copy per host core.
-Rooflines use the algorithmic operation counts per child and coordinate (F, its
+  * the paper's own experiments (Sec. 4 schedule, n = 50, the benchmark functions
+    of SI Appendix A as expression tapes): time, iterations and output regions
+    per function, beside the paper's cloud-server times (other hardware);
+  * the CPU oracle bounding children of the headline workload's first sweep (its
+    per-child work), on one host thread and as one copy per host core.
+The headline kernel's roofline is against HBM: with the term cache a sweep at
+n = 10,000 mostly moves bytes (the live keys' lower bounds scanned, the selected
+row built, the parent's cached terms read and the box's written; cached_sweep_bytes).
+Other rooflines use the algorithmic operation counts per child and coordinate (F, its
 gradient and the midpoint bound; one directed endpoint operation = 1 op):
 about 175 for the separable families (five sin/cos point evaluations of about 25
 operations each and about 50 interval endpoint operations), 64 for the chained
@@ -44,6 +50,10 @@ sys.path.insert(0, ROOT)
 SEP_OPS = 175     # algorithmic operations per child and coordinate, separable families
 CHAIN_OPS = 64    # the chained family
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 64 lanes x 2 (fma) x 2.4 GHz
+# the paper's times at n = 50 on its cloud server (one GPU; Tables S2-S10 and Table 2,
+# last column), for context: other hardware, another implementation
+PAPER_CLOUD_S50 = {"ackley": 11, "belegundu": 6, "breiman": 5, "fu": 13, "griewank": 9, "levy": 15,
+                   "rastrigin": 6, "salomon": 5, "styblinski": 7, "zabinsky": 9}
 
 
 def incremental_ops_per_sweep(n: int, m: int, per_coord: int = SEP_OPS) -> float:
@@ -66,13 +76,18 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-sweeps", type=int, default=1, help="oracle prefix (sweeps) of the headline workload (0 = skip)")
+    ap.add_argument("--cpu-boxes", type=int, default=256,
+                    help="children of the headline workload bounded by the oracle for the CPU baseline (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=4096, help="requests in the serving trace (0 = skip)")
+    ap.add_argument("--serve-max-sweeps", type=int, default=8000,
+                    help="sweep budget of each serving request (requests that reach it are counted apart)")
     ap.add_argument("--serve-compare", type=int, default=96,
                     help="first requests of the trace also served one at a time by plain FP64 solves")
     ap.add_argument("--k-steps", type=int, default=3, help="solves per form of the n = 100 workload (0 = skip)")
     ap.add_argument("--workloads", type=int, default=1, help="1: also solve the n = 2 and chained n = 1000 workloads")
     ap.add_argument("--headline", type=int, default=1, help="0: skip the headline solves (profiling runs)")
+    ap.add_argument("--paper-n", type=int, default=50,
+                    help="n of the paper's benchmark-function experiments (Sec. 4 schedule; 0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM traffic counters) and exit")
     args = ap.parse_args()
@@ -191,16 +206,40 @@ def main() -> int:
                 "time_to_enclosure_ms": round(dq * 1e3, 3), "sweeps": rq.sweeps, "boxes": rq.boxes_evaluated,
                 "boxes_per_s": round(rq.boxes_evaluated / dq, 1), "enclosure": [rq.f_lo, rq.f_hi]}
 
+    # ---- the paper's own experiments (Sec. 4) with the generic family: n = 50, ten cycled
+    # coordinates cut into four pieces (4^10 subregions per iteration), ten diagonal samples,
+    # stop at width 1e-4; the paper's cloud-server times are context (other hardware)
+    paper = None
+    if args.paper_n > 0:
+        from paper_2507_01770_amd import tapes as TP
+        paper = {"n": args.paper_n, "schedule": "4 pieces x 10 cycled coordinates, 10 diagonal samples, width 1e-4"}
+        for name, make in TP.PAPER_FUNCTIONS.items():
+            if name == "rosenbrock":
+                continue
+            phase(f"paper experiment: {name} n = {args.paper_n}")
+            q = make(args.paper_n)
+            kw = dict(split_dims=10, pieces=4, diag_samples=10, tol_f=1e300, tol_x=1e-4, max_sweeps=100000,
+                      fetch_boxes=False)
+            ibb.minimize(q, **kw)
+            torch.cuda.synchronize()
+            tq = time.perf_counter()
+            rq = ibb.minimize(q, **kw)
+            torch.cuda.synchronize()
+            dq = time.perf_counter() - tq
+            paper[name] = {"seconds": round(dq, 3), "iterations": rq.sweeps, "regions": rq.n_boxes,
+                           "boxes_per_s": round(rq.boxes_evaluated / dq, 1), "enclosure": [rq.f_lo, rq.f_hi],
+                           "paper_cloud_server_s": PAPER_CLOUD_S50.get(name) if args.paper_n == 50 else None}
+
     serving = None
     if args.serve_requests > 0:
         phase("serving")
-        serving = serve_bench(args.serve_requests, args.serve_compare)
+        serving = serve_bench(args.serve_requests, args.serve_compare, args.serve_max_sweeps)
 
     # ---- the CPU oracle last, after all GPU work
     cpu = None
-    if args.cpu_sweeps > 0:
+    if args.cpu_boxes > 0:
         phase("cpu baseline (oracle)")
-        cpu = cpu_baseline(p3, args.cpu_sweeps)
+        cpu = cpu_baseline(p3, args.cpu_boxes)
 
     rs, rp, dt = (head["rs"], head["rp"], head["dt"]) if head else ([], None, 0.0)
     boxes = sum(r.boxes_evaluated for r in rs)
@@ -230,41 +269,63 @@ def main() -> int:
         "n100_forms": forms,
         "other_workloads": workloads,
         "serving": serving,
+        "paper_experiments": paper,
     }
     print(json.dumps(line), flush=True)
     return 0
 
 
+_T_START = time.perf_counter()
+
+
 def phase(name: str) -> None:
     """A progress line on stderr (the JSON result line goes to stdout)."""
-    print(f"bench: {name}", file=sys.stderr, flush=True)
+    print(f"bench: [{time.perf_counter() - _T_START:7.1f} s] {name}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(p, sweeps: int) -> dict:
-    """The oracle on the first `sweeps` sweeps of the workload (incremental child bounds):
-    one host thread, then one copy per host core at once (the oracle itself is serial;
-    the copies measure what the host's cores give together)."""
+def first_children(p, count: int, m: int = 10):
+    """The first `count` children of the workload's first sweep: the domain with its
+    first m coordinates halved (child r takes the upper half of coordinate j when bit
+    j of r is set), every endpoint a double of the domain's halving."""
+    import numpy as np
+    mid = 0.5 * p.lower + 0.5 * p.upper
+    lo = np.tile(p.lower, (count, 1))
+    hi = np.tile(p.upper, (count, 1))
+    for r in range(count):
+        for j in range(m):
+            if (r >> j) & 1:
+                lo[r, j] = mid[j]
+            else:
+                hi[r, j] = mid[j]
+    return lo, hi
+
+
+def cpu_baseline(p, boxes: int) -> dict:
+    """The oracle bounding children of the workload's first sweep (F, the first-order
+    test and the midpoint bound of each, as its solve does per child): `boxes` of them on
+    one host thread, then one copy per host core at once (the oracle itself is serial)."""
     from oracle import oracle as O
+    lo, hi = first_children(p, boxes)
     tc = time.perf_counter()
-    o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=sweeps, incremental=True)
+    O.eval_boxes(p.family, p.coef, p.lower, p.upper, lo, hi)
     t1 = time.perf_counter() - tc
-    one = o.boxes_evaluated / t1
-    phase(f"cpu baseline: one thread, {o.boxes_evaluated} boxes in {t1:.1f} s")
+    one = boxes / t1
+    phase(f"cpu baseline: one thread, {boxes} boxes in {t1:.1f} s")
     cores = min(16, len(os.sched_getaffinity(0)))
-    code = ("import sys, time; sys.path.insert(0, %r); from oracle import oracle as O; "
-            "from paper_2507_01770_amd import problems as PR; p = PR.config(3); t = time.perf_counter(); "
-            "O.solve(p.family, p.coef, p.lower, p.upper, tol_f=1e-6, max_sweeps=%d, incremental=True); "
+    code = ("import sys, time; sys.path.insert(0, %r); import bench; from oracle import oracle as O; "
+            "from paper_2507_01770_amd import problems as PR; p = PR.config(3); lo, hi = bench.first_children(p, %d); "
+            "t = time.perf_counter(); O.eval_boxes(p.family, p.coef, p.lower, p.upper, lo, hi); "
             "print('bench: cpu baseline: a copy finished in %%.1f s' %% (time.perf_counter() - t), "
-            "file=sys.stderr, flush=True)") % (ROOT, sweeps)
+            "file=sys.stderr, flush=True)") % (ROOT, boxes)
     tc = time.perf_counter()
     procs = [subprocess.Popen([sys.executable, "-c", code]) for _ in range(cores)]
     ok = all(pr.wait() == 0 for pr in procs)
     tall = time.perf_counter() - tc
     return {"value": round(one, 2), "unit": "boxes/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {o.sweeps} sweep(s) of the headline workload with incremental child bounds "
-                      f"({o.boxes_evaluated} boxes in {t1:.1f} s, one thread, rounding mode switched per endpoint "
-                      f"operation)",
-            "all_cores": {"value": round(cores * o.boxes_evaluated / tall, 2) if ok else None, "unit": "boxes/s",
+            "sample": f"{boxes} children of the headline workload's first sweep bounded by the oracle "
+                      f"(F, first-order test, midpoint bound: its per-child work), {t1:.1f} s on one thread, "
+                      f"rounding mode switched per endpoint operation",
+            "all_cores": {"value": round(cores * boxes / tall, 2) if ok else None, "unit": "boxes/s",
                           "cores": cores, "sample": f"{cores} copies of the same sample at once, {tall:.1f} s"},
             "host_cpus": os.cpu_count()}
 
@@ -305,15 +366,18 @@ def copy_probe(mib: int) -> int:
     return 0
 
 
-def serve_bench(count: int, compare: int) -> dict:
+def serve_bench(count: int, compare: int, max_sweeps: int) -> dict:
     """Serving workload: `count` requests (n log-uniform in [2, 2000], family uniform over the
-    three, seeded coefficients), each enclosed to width 1e-6.
-    1) closed loop: all requests submitted at once -> capacity mu (problems/s);
-    2) Poisson arrivals at 0.8 mu through the continuous-batching server -> problems/s, p50/p99
-       of completion - arrival (converged and budget-stopped requests counted apart);
+    three, seeded coefficients), each enclosed to width 1e-6 within `max_sweeps` sweeps.
+    1) closed loop: the first 512 requests submitted at once -> capacity mu (problems/s);
+    2) Poisson arrivals of all requests at 0.8 mu through the continuous-batching server ->
+       problems/s, p50/p99 of completion - arrival (converged and budget-stopped requests
+       counted apart);
     3) on the first `compare` requests, the same arrivals through the server and served one at
        a time, FIFO, by ibb_solve in plain FP64 (full bounds, a selection and a bound kernel
-       launch per sweep, no batching, no persistent kernel)."""
+       launch per sweep, no batching, no persistent kernel).
+    The server holds at most 96 GiB of box lists: a request whose list would grow past that
+    ends early, not converged (stop reason 8), as after its sweep budget (stop reason 2)."""
     import numpy as np
     import paper_2507_01770_amd as ibb
     from paper_2507_01770_amd import problems as PR
@@ -329,46 +393,58 @@ def serve_bench(count: int, compare: int) -> dict:
             tickets, t_arr, done = [], [], {}
             pending = []
             i = 0
+            t_note = t0
             while len(done) < len(ps):
                 now = time.perf_counter() - t0
                 while i < len(ps) and arrivals[i] <= now:
-                    t = srv.submit(ps[i])
+                    t = srv.submit(ps[i], max_sweeps=max_sweeps)
                     tickets.append(t)
                     pending.append(t)
                     t_arr.append(arrivals[i])
                     i += 1
                 still = []
                 for t in pending:
-                    r = srv.poll(t)
-                    if r is None:
-                        still.append(t)
-                    else:
-                        done[t] = (time.perf_counter() - t0, r.status)
+                    try:
+                        r = srv.poll(t)
+                        if r is None:
+                            still.append(t)
+                            continue
+                        done[t] = (time.perf_counter() - t0, r.status, r.stop_reason)
+                    except ibb.IbbError as e:   # this request only (its result could not be formed)
+                        done[t] = (time.perf_counter() - t0, -1, str(e))
                 pending = still
+                if time.perf_counter() - t_note > 20.0:
+                    t_note = time.perf_counter()
+                    phase(f"serving: {len(done)} of {len(ps)} requests done, {len(pending)} in flight")
                 time.sleep(0.0002)
             st = srv.stats()
         lat = np.array([done[t][0] - a for t, a in zip(tickets, t_arr)])
         conv = np.array([done[t][1] == ibb.OK for t in tickets])
         makespan = max(v[0] for v in done.values()) - arrivals[0]
+        st["stops"] = {"converged": int(conv.sum()),
+                       "sweep_budget": sum(v[1] == ibb.NOT_CONVERGED and v[2] == 2 for v in done.values()),
+                       "memory_budget": sum(v[1] == ibb.NOT_CONVERGED and v[2] == 8 for v in done.values()),
+                       "errors": sum(v[1] == -1 for v in done.values())}
         return lat, conv, makespan, st
 
     def pct(a, q):
         return round(float(np.percentile(a, q)) * 1e3, 2) if len(a) else None
 
-    phase(f"serving: closed loop, {len(probs)} requests")
-    lat0, conv0, span0, st0 = run_server(probs, np.zeros(len(probs)))
-    mu = len(probs) / span0
+    head = probs[:512]
+    phase(f"serving: closed loop, the first {len(head)} requests")
+    lat0, conv0, span0, st0 = run_server(head, np.zeros(len(head)))
+    mu = len(head) / span0
     lam = 0.8 * mu
     arrivals = np.cumsum(gaps) / lam
     phase(f"serving: Poisson arrivals at {lam:.1f}/s")
     lat, conv, span, st = run_server(probs, arrivals)
     out = {
         "requests": len(probs), "converged": int(conv.sum()),
-        "capacity_problems_per_s": round(mu, 2), "arrival_rate": round(lam, 2),
+        "capacity_problems_per_s": round(mu, 2), "capacity_sample_requests": len(head), "arrival_rate": round(lam, 2),
         "problems_per_s": round(len(probs) / span, 2),
         "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
         "p50_ms_converged": pct(lat[conv], 50), "p99_ms_converged": pct(lat[conv], 99),
-        "max_concurrent": st["max_active"],
+        "max_concurrent": st["max_active"], "stops": st["stops"], "max_sweeps_per_request": max_sweeps,
     }
     if compare > 0:
         ps = probs[:compare]
@@ -382,8 +458,10 @@ def serve_bench(count: int, compare: int) -> dict:
             start = max(a, free_at)
             while time.perf_counter() - t0 < start:
                 time.sleep(0.0002)
-            r = ibb.minimize(p, fetch_boxes=False, incremental=False)
+            r = ibb.minimize(p, fetch_boxes=False, incremental=False, max_sweeps=max_sweeps)
             ok1 += r.status == ibb.OK
+            if len(lat1) % 16 == 15:
+                phase(f"serving: one at a time, {len(lat1) + 1} of {compare} requests done")
             free_at = time.perf_counter() - t0
             lat1.append(free_at - a)
         lat1 = np.array(lat1)

@@ -174,7 +174,8 @@ typedef struct {
   double t_bound_ms, t_select_ms;
   int64_t n_bound_launches, n_select_launches;
   int32_t bound_shape;        /* shape of the bound kernel used (0..4, see ibb_options; -1: incremental) */
-  int32_t pad;
+  int32_t stop_reason;        /* why the run ended: 1 converged, 2 max_sweeps, 3 max_live_boxes, 5 the time
+                                 limit, 8 the server's memory budget (see ibb_server_create) */
   int64_t n_persistent_launches; /* with profile = 1: launches of the persistent sweep kernel (each runs a
                                     chunk of sweeps; their time is part of t_select_ms) */
   double t_persistent_ms;        /* with profile = 1: the persistent launches' summed time */
@@ -316,7 +317,12 @@ ibb_status ibb_solve_batch(const ibb_problem* probs, int32_t count, const ibb_op
  * not captured: the caller's threads use the device meanwhile).  Between
  * chunks it retires finished problems and admits queued ones while a slot is
  * free (at most max_slots at once) and the device memory in use plus the new
- * problem's starting footprint stays within mem_budget_bytes.  The server's
+ * problem's starting footprint stays within mem_budget_bytes.  A running problem
+ * whose box list or rows must grow past the budget, or whose growth the
+ * allocator refuses, is ended at its next sweep with IBB_NOT_CONVERGED and
+ * stop_reason 8: its enclosure and boxes are rigorous, as after any budget.  A
+ * problem whose result the server cannot form (an allocation at the end fails)
+ * gets that error as its poll status; the other problems go on.  The server's
  * device work runs on a stream of its own, ordered after the work enqueued on
  * hip_stream when the server is created; results are handed over bound to
  * hip_stream (the caller keeps it alive until the last result from this server

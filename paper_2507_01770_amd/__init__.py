@@ -58,7 +58,7 @@ class _Info(C.Structure):
                 ("seconds", C.c_double), ("status", C.c_int32), ("fp32_sweeps", C.c_int32),
                 ("ub_evaluated", C.c_int64), ("t_bound_ms", C.c_double), ("t_select_ms", C.c_double),
                 ("n_bound_launches", C.c_int64), ("n_select_launches", C.c_int64),
-                ("bound_shape", C.c_int32), ("pad", C.c_int32), ("n_persistent_launches", C.c_int64),
+                ("bound_shape", C.c_int32), ("stop_reason", C.c_int32), ("n_persistent_launches", C.c_int64),
                 ("t_persistent_ms", C.c_double), ("n_persistent_sweeps", C.c_int64)]
 
 
@@ -291,6 +291,7 @@ class Result:
     n_persistent_launches: int = 0   # launches of the persistent sweep kernel (profile=True)
     t_persistent_ms: float = 0.0     # their summed time
     n_persistent_sweeps: int = 0     # the sweeps they ran
+    stop_reason: int = 0             # 1 converged, 2 max_sweeps, 3 max_live_boxes, 5 time limit, 8 server memory
 
 
 def minimize(problem=None, *, family=None, coef=None, lower=None, upper=None, tol_f=None, tol_x=None,
@@ -343,7 +344,7 @@ def _read_result(h, n, fetch_boxes=True, max_boxes_fetched=100_000) -> Result:
                   lo, hi, flo, seq, tg[:got], tn[:got], tl[:got], tsel[:got], info.ub_evaluated,
                   info.t_bound_ms, info.t_select_ms, info.n_bound_launches, info.n_select_launches,
                   info.fp32_pruned, info.fp64_confirmed, info.fp32_sweeps, info.bound_shape,
-                  info.n_persistent_launches, info.t_persistent_ms, info.n_persistent_sweeps)
+                  info.n_persistent_launches, info.t_persistent_ms, info.n_persistent_sweeps, info.stop_reason)
 
 
 class Run:

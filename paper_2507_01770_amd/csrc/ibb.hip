@@ -662,20 +662,24 @@ __device__ __forceinline__ SelAcc scan_select_wg(const Params& P, double gub, in
   return reduce_own<NT>(P, scan_own<NT>(P, gub, nk));
 }
 
-// Large lists: every workgroup scans a stretch of the keys and writes a partial.
+// Large lists: each of `parts` workgroups scans every parts-th stretch of the keys
+// and writes partial j.
+__device__ __forceinline__ void select_part_body(const Params& P, State* S, int j, int parts) {
+  const double gub = okey_inv(S->gub_key);
+  SelAcc a = sel_empty();
+  scan_keys(P, gub, (int64_t)j * kSelThreads + threadIdx.x, S->n_keys, (int64_t)parts * kSelThreads, a);
+  a = sel_block_reduce<kSelThreads>(a);
+  if (threadIdx.x == 0) {
+    P.part_flo[j] = a.best.f;
+    P.part_idx[j] = a.best.idx;
+    P.part_wmax[j] = a.wm;
+    P.part_cnt[j] = a.cnt;
+  }
+}
 __global__ __launch_bounds__(kSelThreads) void k_select_part(const Params* __restrict__ PP, State* __restrict__ S) {
   if (S->stop) return;
   const Params P = *PP;
-  const double gub = okey_inv(S->gub_key);
-  SelAcc a = sel_empty();
-  scan_keys(P, gub, (int64_t)blockIdx.x * kSelThreads + threadIdx.x, S->n_keys, (int64_t)gridDim.x * kSelThreads, a);
-  a = sel_block_reduce<kSelThreads>(a);
-  if (threadIdx.x == 0) {
-    P.part_flo[blockIdx.x] = a.best.f;
-    P.part_idx[blockIdx.x] = a.best.idx;
-    P.part_wmax[blockIdx.x] = a.wm;
-    P.part_cnt[blockIdx.x] = a.cnt;
-  }
+  select_part_body(P, S, blockIdx.x, gridDim.x);
 }
 
 // One workgroup per sweep: insert the previous sweep's survivors, take the
@@ -3237,6 +3241,7 @@ struct Run {
   State hs{};
   std::chrono::steady_clock::time_point t0;
   bool term_cache = false;   // ibb_solve's runs: keep the rows' shared terms (large n)
+  bool mem_stop = false;     // the server ends this run at its next selection (memory budget)
 };
 
 // Allocate the problem's arrays, upload it and enqueue its root box (Sec. 3.1,
@@ -3340,17 +3345,46 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
 // they were (the run can go on with what it has, or be released).  Only when
 // every request succeeded are the contents copied, the old blocks returned, the
 // new layout taken and the parameters pushed.
-ibb_status run_capacity(Run& U, int chunk) {
-  Mem& M = U.R->mem;
-  Params& P = U.R->P;
-  const int n = P.n;
+struct GrowPlan {
+  bool rows = false, keys = false, tr = false;
+  int64_t hist_cap = 0, key_cap = 0, tr_cap = 0;
+  size_t bytes = 0;   // device memory the grown arrays take
+};
+
+GrowPlan plan_growth(const Run& U, int chunk) {
+  const Params& P = U.R->P;
+  const int64_t n = P.n;
   const int64_t K = P.select_k;
   // rows 0 .. (sweeps + 1) K are in use (the last K may belong to a pending selection)
   const int64_t need_rows = (U.sweeps + chunk + 1) * K + 1;
   const int64_t need_keys = U.n_keys + (int64_t)(chunk + 1) * K * P.nch;   // +1: children pending from the last chunk
   const int64_t need_tr = std::min<int64_t>(U.sweeps + chunk + 1, kTraceMax);
-  const bool g_rows = need_rows > P.hist_cap, g_keys = need_keys > P.key_cap, g_tr = need_tr > P.trace_cap;
+  GrowPlan g;
+  g.rows = need_rows > P.hist_cap;
+  g.keys = need_keys > P.key_cap;
+  g.tr = need_tr > P.trace_cap;
+  g.hist_cap = g.rows ? std::max<int64_t>(2 * P.hist_cap, need_rows) : P.hist_cap;
+  g.key_cap = g.keys ? std::max<int64_t>(2 * P.key_cap, need_keys) : P.key_cap;
+  g.tr_cap = g.tr ? std::min<int64_t>(std::max<int64_t>(2 * P.trace_cap, need_tr), kTraceMax) : P.trace_cap;
+  if (g.rows) {
+    int64_t per_row = 2 * n * 8 + 4 + 4 + kMaxSplit * 8;
+    if (P.pieces == 4) per_row += 3 * kMaxSplit * 8;
+    if (P.tcache) per_row += 3 * n * 8 + 4;
+    g.bytes += (size_t)(g.hist_cap * per_row);
+  }
+  if (g.keys) g.bytes += (size_t)(g.key_cap * (8 + 8 + 4 + 4 + 8));
+  if (g.tr) g.bytes += (size_t)(4 * g.tr_cap * 8);
+  return g;
+}
+
+ibb_status run_capacity(Run& U, int chunk) {
+  Mem& M = U.R->mem;
+  Params& P = U.R->P;
+  const int n = P.n;
+  const GrowPlan gp = plan_growth(U, chunk);
+  const bool g_rows = gp.rows, g_keys = gp.keys, g_tr = gp.tr;
   if (!g_rows && !g_keys && !g_tr) return IBB_OK;
+  const int64_t K = P.select_k;
   Params Q = P;   // the grown layout
   std::vector<void*> fresh;
   bool ok = true;
@@ -3361,7 +3395,7 @@ ibb_status run_capacity(Run& U, int chunk) {
     else ok = false;
   };
   if (g_rows) {
-    Q.hist_cap = std::max<int64_t>(2 * P.hist_cap, need_rows);
+    Q.hist_cap = gp.hist_cap;
     take(Q.hist_n, Q.hist_cap * n);
     take(Q.hist_h, Q.hist_cap * n);
     take(Q.hist_cyc, Q.hist_cap);
@@ -3374,7 +3408,7 @@ ibb_status run_capacity(Run& U, int chunk) {
     }
   }
   if (g_keys) {
-    Q.key_cap = std::max<int64_t>(2 * P.key_cap, need_keys);
+    Q.key_cap = gp.key_cap;
     take(Q.key_flo, Q.key_cap);
     take(Q.key_seq, Q.key_cap);
     take(Q.key_ref, Q.key_cap);
@@ -3384,7 +3418,7 @@ ibb_status run_capacity(Run& U, int chunk) {
   double* tr = nullptr;
   int64_t tr_cap = P.trace_cap;
   if (g_tr) {
-    tr_cap = std::min<int64_t>(std::max<int64_t>(2 * P.trace_cap, need_tr), kTraceMax);
+    tr_cap = gp.tr_cap;
     take(tr, 4 * tr_cap);
   }
   if (!ok) {
@@ -3430,6 +3464,17 @@ ibb_status run_capacity(Run& U, int chunk) {
   if (g_tr) M.put(P.tr_gub);
   P = Q;
   return push_params(M, P, U.dP);
+}
+
+// End the run at its next selection with no more room: that selection inserts the
+// children still pending (run_capacity left room for one sweep's children beyond
+// the last chunk) and then stops at the sweep budget, so the list it leaves
+// covers every box not yet discarded and [GLB, GUB] stays rigorous.
+ibb_status run_stop_next(Run& U) {
+  Params& P = U.R->P;
+  P.max_sweeps = std::min<int64_t>(P.max_sweeps, U.sweeps);
+  U.mem_stop = true;
+  return push_params(U.R->mem, P, U.dP);
 }
 
 // after a chunk: take the device counters, drop removed keys when they dominate
@@ -3493,6 +3538,7 @@ ibb_status run_finish(Run& U) {
   R->info.status = hs.stop == STOP_CONVERGED ? IBB_OK
                    : (hs.stop == STOP_EMPTY || hs.stop == STOP_CAPACITY || hs.stop == STOP_INTERNAL) ? IBB_E_INTERNAL
                                                                                                  : IBB_NOT_CONVERGED;
+  R->info.stop_reason = U.mem_stop && hs.stop == STOP_SWEEPS ? STOP_MEMORY : hs.stop;
   R->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - U.t0).count();
   if (hs.stop == STOP_CAPACITY) return fail(IBB_E_INTERNAL, "a sweep would pass the sized row or key capacity");
   if (hs.stop == STOP_INTERNAL) return fail(IBB_E_INTERNAL, "the selection counted live boxes but found none");

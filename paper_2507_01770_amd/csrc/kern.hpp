@@ -54,8 +54,10 @@ constexpr int64_t kPersistentGrowth = (int64_t)1 << 17;      // keys a persisten
 // STOP_CAPACITY: the next sweep would pass the row or key capacity the host sized
 // the arrays for (the host grows them before every chunk, so this only guards)
 // STOP_INTERNAL: the selection counted live keys but found none to take (a guard)
+// STOP_MEMORY: never set on the device; a run the server stopped at its memory
+// budget ends with STOP_SWEEPS and reports this code instead
 enum StopCode { RUNNING = 0, STOP_CONVERGED = 1, STOP_SWEEPS = 2, STOP_LIVE = 3, STOP_EMPTY = 4, STOP_HOST = 5,
-                STOP_CAPACITY = 6, STOP_INTERNAL = 7 };
+                STOP_CAPACITY = 6, STOP_INTERNAL = 7, STOP_MEMORY = 8 };
 
 // A bound that came out NaN says nothing about f: as a lower bound it counts as
 // -inf (the box is kept and can never be cut off), as an upper bound as +inf (it

@@ -107,6 +107,63 @@ def test_server_respects_memory_budget():
     assert st["max_active"] <= 3
 
 
+@pytest.mark.parametrize("incremental", [True, False])
+def test_long_lists_batch_and_server_equal_alone(incremental):
+    # lists past 2^18 keys are scanned on several workgroups per problem before
+    # each selection, in the batched kernels as in ibb_solve
+    ps = [PR.chain(64, 41), PR.chain(100, 42), PR.sep_cos(30, 43)]
+    kw = dict(max_sweeps=400, incremental=incremental)
+    print(f"case long lists alone incremental={incremental}", flush=True)
+    alone = [ibb.minimize(p, max_boxes_fetched=500, **kw) for p in ps]
+    assert max(int(a.trace_nlive.max()) for a in alone) > (1 << 18)
+    print("case long lists batch", flush=True)
+    for a, b in zip(alone, ibb.solve_batch(ps, max_boxes_fetched=500, **kw)):
+        same(a, b)
+    print("case long lists server", flush=True)
+    with ibb.Server(mem_budget_bytes=8 << 30, max_slots=4) as srv:
+        tickets = [srv.submit(p, **kw) for p in ps]
+        res = {}
+        t0 = time.time()
+        while len(res) < len(tickets) and time.time() - t0 < 120:
+            for t in tickets:
+                if t not in res:
+                    r = srv.poll(t, fetch_boxes=True, max_boxes_fetched=500)
+                    if r is not None:
+                        res[t] = r
+            time.sleep(0.001)
+    assert len(res) == len(tickets)
+    for t, a in zip(tickets, alone):
+        same(a, res[t])
+
+
+def test_server_ends_a_problem_at_the_memory_budget():
+    # a problem whose list would have to grow past the budget ends at its next sweep,
+    # not converged, with exactly the list, GUB and trace that ibb_solve reaches with
+    # that many sweeps as its budget; a small problem in the same server goes on
+    big, small = PR.sep_cos(100, 31), PR.sep_cos(2, 32)
+    print("case server memory stop", flush=True)
+    with ibb.Server(mem_budget_bytes=3 << 20, max_slots=4) as srv:
+        tickets = [srv.submit(big), srv.submit(small)]
+        res = {}
+        t0 = time.time()
+        while len(res) < 2 and time.time() - t0 < 120:
+            for t in tickets:
+                if t not in res:
+                    r = srv.poll(t, fetch_boxes=True, max_boxes_fetched=500)
+                    if r is not None:
+                        res[t] = r
+            time.sleep(0.001)
+    assert len(res) == 2
+    rb, rs = res[tickets[0]], res[tickets[1]]
+    assert rb.status == ibb.NOT_CONVERGED and rb.stop_reason == 8 and 0 <= rb.sweeps < 150
+    assert rb.f_lo <= 0.0 <= rb.f_hi   # the family's minimum
+    ref = ibb.minimize(big, max_sweeps=rb.sweeps, max_boxes_fetched=500)
+    assert ref.stop_reason == 2
+    same(ref, rb)
+    assert rs.status == ibb.OK and rs.stop_reason == 1
+    same(ibb.minimize(small, max_boxes_fetched=500), rs)
+
+
 def test_server_rejects_invalid():
     with ibb.Server(mem_budget_bytes=1 << 30, max_slots=2) as srv:
         p = PR.sep_cos(3, 1)
