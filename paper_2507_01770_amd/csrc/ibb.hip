@@ -10,6 +10,7 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <type_traits>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -465,8 +466,11 @@ __device__ __forceinline__ void insert_children(const Params& P, State* S, doubl
 
 // One workgroup: stop test on [GLB, GUB]; if running, remove the best key from the
 // list and build its row (child r of row ref) and the split points of that row.
+// *wb (if given) receives this thread's widest written side outside the new
+// row's window (see build_row).
 template <int NT, int PIECES = 2>
-__device__ __forceinline__ bool select_finish(const Params& P, State* S, const SelAcc& tot, double gub) {
+__device__ __forceinline__ bool select_finish(const Params& P, State* S, const SelAcc& tot, double gub,
+                                              double* wb = nullptr) {
   __shared__ int32_t go;
   if (threadIdx.x == 0) {
     const Cand b = tot.best;
@@ -502,14 +506,9 @@ __device__ __forceinline__ bool select_finish(const Params& P, State* S, const S
   const Row src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n,
                 PIECES == 4 ? P.hist_cut + (int64_t)ref * (3 * kMaxSplit) : P.hist_mid + (int64_t)ref * kMaxSplit,
                 n, P.m, pcyc, r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
-  double* dn = P.hist_n + row * n;
-  double* dh = P.hist_h + row * n;
-  for (int i = threadIdx.x; i < n; i += NT) {
-    const I x = src.get(i);
-    dn[i] = x.n;
-    dh[i] = x.h;
-  }
   const int cyc = r >= 0 ? add_mod(pcyc, P.m, n) : pcyc;   // m <= n
+  const double w = build_row<NT>(src, P.hist_n + row * n, P.hist_h + row * n, n, cyc, P.m);
+  if (wb) *wb = w;
   if (threadIdx.x < (unsigned)kWave) {
     const int j = threadIdx.x;
     bool ok = false;
@@ -688,7 +687,8 @@ __global__ __launch_bounds__(kSelThreads) void k_select_part(const Params* __res
 // the children written by k_bound and the partials visible: no device-scope
 // fences are needed.
 template <int NT, int PIECES = 2>
-__device__ __forceinline__ bool select_body(const Params& P, State* S, int nparts, int host_stop) {
+__device__ __forceinline__ bool select_body(const Params& P, State* S, int nparts, int host_stop,
+                                            double* wb = nullptr) {
   const double gub = okey_inv(S->gub_key);
   // every thread reads the pending flag before the scan's barriers: thread 0 sets
   // it again in select_finish with no barrier in between, so a later read could see
@@ -714,7 +714,7 @@ __device__ __forceinline__ bool select_body(const Params& P, State* S, int npart
     }
     return false;
   }
-  return select_finish<NT, PIECES>(P, S, a, gub);
+  return select_finish<NT, PIECES>(P, S, a, gub, wb);
 }
 
 // ---------------------------------------------------------------------------
@@ -806,8 +806,11 @@ __device__ __forceinline__ I ib_half(const double* rn, const double* rh, const d
   return b ? I{neg(md), G(rh)[i]} : I{G(rn)[i], md};
 }
 
+// wb0 >= 0: this thread's widest side outside the split window, taken when the
+// row was built (the base pass then reads the row only where it needs it);
+// negative: the base pass forms the widest side itself.
 template <int NT, int FAM>
-__device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const Sel& sel) {
+__device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const Sel& sel, double wb0 = -1.0) {
   static_assert(NT % kWave == 0, "whole wavefronts");
   __syncthreads();   // the selected row and its split points were written by other threads
   const int n = P.n, m = P.m, lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
@@ -950,8 +953,14 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
   //    With the term cache, a term that the parent row's cut left unchanged is the
   //    parent's (same intervals, same value), and every base term is kept for this
   //    row's own children.
+  const bool wknown = wb0 >= 0.0;
+  auto in_window = [&](int i) {
+    int j = i - cyc;
+    if (j < 0) j += n;
+    return j < m;
+  };
   I acc{0.0, 0.0};
-  double uacc = 0.0, wb = 0.0;
+  double uacc = 0.0, wb = wknown ? wb0 : 0.0;
   constexpr int CH = IbLds<NT>::CH;
   const int32_t par = P.tcache ? G(P.hist_par)[row] : -1;
   const int pcyc = par >= 0 ? G(P.hist_cyc)[par] : 0;
@@ -965,34 +974,57 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
   const double* ptc = par >= 0 ? P.tcache + (int64_t)par * 3 * n : nullptr;
   double* rtc = P.tcache ? P.tcache + row * 3 * n : nullptr;
   for (int c0 = 0; c0 < n; c0 += CH * NT) {
+    // Every load of the chunk is issued before any term is formed or stored: the
+    // stores into this row's cache may alias the loads as far as the compiler
+    // knows, so loads left between them would each wait for the stores before.
+    // kind: 0 split or past n, 1 width only (no base term), 2 the parent's cached
+    // term, 3 formed here
+    int kind[CH];
+    I xr[CH];
+    double pc[CH][3];
+#pragma unroll
+    for (int r = 0; r < CH; ++r) {
+      const int i = c0 + r * NT + (int)threadIdx.x;
+      int k = 0;
+      if (i < n && split_of(i) < 0) {
+        k = 1;
+        if (i < T && !(FAM == FAM_CHAIN && split_of(i + 1) >= 0))
+          k = (ptc && !cut_by_parent(i) && !(FAM == FAM_CHAIN && cut_by_parent(i + 1))) ? 2 : 3;
+      }
+      kind[r] = k;
+      if (k == 3 || (k && (!wknown || in_window(i)))) xr[r] = I{G(rn)[i], G(rh)[i]};
+      if (k == 2) {
+        pc[r][0] = G(ptc)[i];
+        pc[r][1] = G(ptc)[n + i];
+        pc[r][2] = G(ptc)[2 * n + i];
+      }
+    }
+#pragma unroll
     for (int r = 0; r < CH; ++r) {
       const int i = c0 + r * NT + (int)threadIdx.x;
       I t{0.0, 0.0};
       double u = 0.0;
-      if (i < n && split_of(i) < 0) {
-        const I x{G(rn)[i], G(rh)[i]};
-        wb = dmax(wb, x.n + x.h);
-        if (i < T && !(FAM == FAM_CHAIN && split_of(i + 1) >= 0)) {
-          if (ptc && !cut_by_parent(i) && !(FAM == FAM_CHAIN && cut_by_parent(i + 1))) {
-            t = I{G(ptc)[i], G(ptc)[n + i]};
-            u = G(ptc)[2 * n + i];
-          } else if (FAM != FAM_CHAIN) {
-            const CoefSep ci = gload(P.sep + i);
-            t = sep_term<FAM>(ci, x);
-            u = sep_point_hi<FAM>(ci, midpoint(x));
-          } else {
-            const I xn{G(rn)[i + 1], G(rh)[i + 1]};
-            I R, E;
-            const CoefChain ci = gload(P.chain + i);
-            t = chain_term(ci, x, xn, R, E);
-            u = chain_term(ci, point(midpoint(x)), point(midpoint(xn)), R, E).h;
-          }
-          if (rtc) {
-            G(rtc)[i] = t.n;
-            G(rtc)[n + i] = t.h;
-            G(rtc)[2 * n + i] = u;
-          }
+      if (kind[r] >= 1 && (!wknown || in_window(i))) wb = dmax(wb, xr[r].n + xr[r].h);
+      if (kind[r] == 2) {
+        t = I{pc[r][0], pc[r][1]};
+        u = pc[r][2];
+      } else if (kind[r] == 3) {   // a term the parent's cut changed, or no cache: formed here
+        if constexpr (FAM == FAM_CHAIN) {
+          const I xn{G(rn)[i + 1], G(rh)[i + 1]};
+          I R, E;
+          const CoefChain ci = gload(P.chain + i);
+          t = chain_term(ci, xr[r], xn, R, E);
+          u = chain_term(ci, point(midpoint(xr[r])), point(midpoint(xn)), R, E).h;
+        } else {
+          const CoefSep ci = gload(P.sep + i);
+          t = sep_term<FAM>(ci, xr[r]);
+          u = sep_point_hi<FAM>(ci, midpoint(xr[r]));
         }
+      }
+      if (kind[r] >= 2 && rtc) {
+        G(rtc)[i] = t.n;
+        G(rtc)[n + i] = t.h;
+        G(rtc)[2 * n + i] = u;
       }
       L.tfn[r * NT + threadIdx.x] = t.n;
       L.tfh[r * NT + threadIdx.x] = t.h;
@@ -1000,13 +1032,31 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
     }
     __syncthreads();
     // slot = lane: terms c0 + q*64 + lane in increasing order (rows past n hold
-    // only zeros, and a zero added to a slot sum started at +0 changes no bit)
+    // only zeros, and a zero added to a slot sum started at +0 changes no bit);
+    // V rows are read before they are added, in the same order
     const int qn = min(CH * NT / kWave, (n - c0 + kWave - 1) / kWave);
-    if (wid == 0)
-      for (int q = 0; q < qn; ++q) {
+    if (wid == 0) {
+      constexpr int V = NT >= 1024 ? 2 : 8;   // registers: 128 per lane at 1024 threads
+      int q = 0;
+      for (; q + V <= qn; q += V) {
+        double vn[V], vh[V], vu[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          vn[e] = L.tfn[(q + e) * kWave + lane];
+          vh[e] = L.tfh[(q + e) * kWave + lane];
+          vu[e] = L.tu[(q + e) * kWave + lane];
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          acc = add(acc, I{vn[e], vh[e]});
+          uacc = uacc + vu[e];
+        }
+      }
+      for (; q < qn; ++q) {
         acc = add(acc, I{L.tfn[q * kWave + lane], L.tfh[q * kWave + lane]});
         uacc = uacc + L.tu[q * kWave + lane];
       }
+    }
     __syncthreads();
   }
   if (wid == 0) {
@@ -1215,8 +1265,9 @@ __device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L
 // insert them from child records (the full-bound path): no records round-trip
 // through device memory
 template <int NT, int FAM>
-__device__ __forceinline__ void ib_children_insert(const Params& P, State* S, IbLds<NT>& L, const Sel& sel, Hot& h) {
-  ib_prepare<NT, FAM>(P, L, sel);
+__device__ __forceinline__ void ib_children_insert(const Params& P, State* S, IbLds<NT>& L, const Sel& sel, Hot& h,
+                                                   double wb0 = -1.0) {
+  ib_prepare<NT, FAM>(P, L, sel, wb0);
   int formed = 0;
   const double gub = ib_gub<NT, FAM>(P, S, L, sel.mask, h, formed);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
@@ -1370,7 +1421,7 @@ __device__ __forceinline__ void compact_in_place(const Params& P, State* S, IbLd
 // from the workgroup's own copy.  Every wavefront forms the split mask itself
 // (the same ballot over the same values), so no thread waits to read it back.
 template <int NT>
-__device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel& sel) {
+__device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel& sel, double& wb) {
   const double gub = okey_inv(h.gub_key);
   // each thread fetches the row reference of its own candidate while the
   // workgroup reduces; the winner's thread passes it on through LDS
@@ -1430,14 +1481,8 @@ __device__ __forceinline__ bool select_ib(const Params& P, State* S, Hot& h, Sel
   const int pcyc = G(P.hist_cyc)[ref];
   const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
                      n, P.m, pcyc, r >= 0 ? G(P.hist_mask)[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
-  const gptr<double> dn = G(P.hist_n + row * n);
-  const gptr<double> dh = G(P.hist_h + row * n);
-  for (int i = threadIdx.x; i < n; i += NT) {
-    const I x = src.get(i);
-    dn[i] = x.n;
-    dh[i] = x.h;
-  }
   const int cyc = r >= 0 ? add_mod(pcyc, P.m, n) : pcyc;   // m <= n
+  wb = build_row<NT>(src, P.hist_n + row * n, P.hist_h + row * n, n, cyc, P.m);
   const int lane = threadIdx.x & (kWave - 1);
   bool ok = false;
   double md = 0.0;
@@ -1487,8 +1532,9 @@ __device__ __forceinline__ void sweeps_ib(const Params& P, State* S, IbLds<NT>& 
     // dead keys dominate the list: drop them before the scan
     if (h.n_keys > 4 * (h.n_live + P.nch) && h.n_keys > 4096) compact_in_place<NT>(P, S, lds, h);
     Sel sel;
-    if (!select_ib<NT>(P, S, h, sel)) return;   // stopped (the flag is set)
-    ib_children_insert<NT, FAM>(P, S, lds, sel, h);
+    double wb;
+    if (!select_ib<NT>(P, S, h, sel, wb)) return;   // stopped (the flag is set)
+    ib_children_insert<NT, FAM>(P, S, lds, sel, h, wb);
     __syncthreads();   // keys written by other threads are read by the next selection
   }
 }
@@ -1507,10 +1553,11 @@ __global__ __launch_bounds__(NT) void k_select_ib(const Params* __restrict__ PP,
   if (S->stop) return;
   const Params P = *PP;
   __shared__ IbLds<NT> lds;
-  if (select_body<NT>(P, S, nparts, host_stop)) {
+  double wb;
+  if (select_body<NT>(P, S, nparts, host_stop, &wb)) {
     __syncthreads();   // the selection was written to the State by wavefront 0
     Hot h = hot_load(S);
-    ib_children_insert<NT, FAM>(P, S, lds, sel_load(S), h);
+    ib_children_insert<NT, FAM>(P, S, lds, sel_load(S), h, wb);
   }
 }
 
@@ -1997,11 +2044,7 @@ __device__ void ksel_finish(const Params& P, State* S, KSelLds<NT>& L, int64_t t
     const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
                        n, P.m, P.hist_cyc[ref], r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
     const int64_t row = 1 + t * K + pr;
-    for (int i = threadIdx.x; i < n; i += NT) {
-      const I x = src.get(i);
-      P.hist_n[row * n + i] = x.n;
-      P.hist_h[row * n + i] = x.h;
-    }
+    (void)build_row<NT>(src, P.hist_n + row * n, P.hist_h + row * n, n, 0, 0);
   }
   if (threadIdx.x == 0) {
     S->sel_count = nc;
@@ -3775,7 +3818,7 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
                                 nullptr, 0, U.dP, U.dS);
         if (P.incremental) {   // selection and the children's bounds in one workgroup
-          hipExtLaunchKernelGGL((k_select_ib<kSelSingleThreads, FAM>), dim3(1), dim3(kSelSingleThreads), 0, M.stream,
+          hipExtLaunchKernelGGL((k_select_ib<kSelIbThreads, FAM>), dim3(1), dim3(kSelIbThreads), 0, M.stream,
                                 (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
                                 U.dS, sb > 1 ? sb : 0, 0);
           continue;

@@ -47,6 +47,7 @@ constexpr int kMaxSplit = 16;             // M <= 16
 constexpr int kSelThreads = 256;
 constexpr int kSelSingleThreads = 1024;   // the one-workgroup selection
 constexpr int kSweepThreads = 512;        // persistent sweeps (room for 256 registers per lane)
+constexpr int kSelIbThreads = 512;        // per-sweep selection with incremental bounds (likewise)
 constexpr int kMaxSelBlocks = 1024;
 constexpr int64_t kPersistentMaxKeys = (int64_t)1 << 18;   // lists one workgroup scans about as fast as a grid
 constexpr int64_t kPersistentGrowth = (int64_t)1 << 17;      // keys a persistent launch may add (sets its sweeps)
@@ -253,6 +254,40 @@ struct ChildRow {
     return x;
   }
 };
+
+// Write row `src` (a child of a stored row) to dn/dh.  The loads of U strides are
+// issued before their stores: the stores may alias the loads as far as the
+// compiler knows, so a load after a store would wait for it.  Returns the
+// widest side (rounded up) this thread wrote among the coordinates outside the
+// window of m coordinates from wstart (those no cut of the new row touches).
+template <int NT, int U = (NT >= 1024 ? 2 : 8), class Row>
+__device__ __forceinline__ double build_row(const Row& src, double* dn, double* dh, int n, int wstart, int m) {
+  double wb = 0.0;
+  auto outside = [&](int i) {
+    int j = i - wstart;
+    if (j < 0) j += n;
+    return j >= m;
+  };
+  int i = threadIdx.x;
+  for (; i + (U - 1) * NT < n; i += U * NT) {
+    I x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = src.get(i + u * NT);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      G(dn)[i + u * NT] = x[u].n;
+      G(dh)[i + u * NT] = x[u].h;
+      if (outside(i + u * NT)) wb = dmax(wb, x[u].n + x[u].h);
+    }
+  }
+  for (; i < n; i += NT) {
+    const I x = src.get(i);
+    G(dn)[i] = x.n;
+    G(dh)[i] = x.h;
+    if (outside(i)) wb = dmax(wb, x.n + x.h);
+  }
+  return wb;
+}
 
 // child r of a stored row cut into four pieces per split coordinate: coordinate
 // (cyc + j) mod n takes piece (r >> 2j) & 3 of [lo, c_1, c_2, c_3, hi]
