@@ -96,16 +96,16 @@ def test_separable_matches_oracle(fam, n, seed, incremental):
 def test_budget_and_width_criterion(incremental):
     p = PR.sep_cos(6, 9)
     r = ibb.minimize(p, max_sweeps=4, incremental=incremental)
-    assert r.status == ibb.NOT_CONVERGED and r.sweeps == 4
+    assert r.status == ibb.NOT_CONVERGED and r.sweeps == 4 and r.stop_reason == 2
     assert r.f_lo <= 0.0 <= r.f_hi and inside_some_box(p.x_star, r.lo, r.hi)
     # a time limit stops on the host between chunks; the last children are still inserted
     r = ibb.minimize(p, time_limit_s=1e-9, incremental=incremental)
-    assert r.status == ibb.NOT_CONVERGED and r.sweeps >= 1
+    assert r.status == ibb.NOT_CONVERGED and r.sweeps >= 1 and r.stop_reason == 5
     assert r.f_lo <= 0.0 <= r.f_hi and inside_some_box(p.x_star, r.lo, r.hi)
     assert r.trace_nsurv.sum() + 1 - r.sweeps >= r.n_boxes
     p.tol_x = 1e-4
     r = ibb.minimize(p, max_sweeps=20000, incremental=incremental)
-    assert r.status == ibb.OK and np.all(r.hi - r.lo < 1e-4)
+    assert r.status == ibb.OK and np.all(r.hi - r.lo < 1e-4) and r.stop_reason == 1
 
 
 @pytest.mark.parametrize("incremental", MODES)
@@ -121,7 +121,7 @@ def test_live_box_limit_identical_to_oracle(incremental):
     o = O.solve(p.family, p.coef, p.lower, p.upper, tol_f=p.tol_f, tol_x=p.tol_x, max_sweeps=3000,
                 max_live_boxes=limit, incremental=incremental)
     assert o.status == O.ST_NOT_CONVERGED and o.sweeps == 6
-    assert r.status == ibb.NOT_CONVERGED and r.sweeps == o.sweeps
+    assert r.status == ibb.NOT_CONVERGED and r.sweeps == o.sweeps and r.stop_reason == 3
     assert np.array_equal(r.trace_nlive, o.trace_nlive) and np.array_equal(r.trace_gub, o.trace_gub)
     assert r.f_lo == o.f_lo and r.f_hi == o.f_hi
     assert np.array_equal(r.seq, o.seq) and np.array_equal(r.flo, o.flo)
