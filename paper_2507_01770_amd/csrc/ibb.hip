@@ -3727,6 +3727,19 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
   } evs;
   auto& ev = evs.v;
   int grow_chunk = 4;   // sweeps per host round trip on the per-sweep path (and under a time limit): 4, 8, ..., 256
+  // Shape of the per-sweep incremental kernel (one box per sweep, long lists):
+  // 512 or 1024 threads, i.e. 8 or 16 wavefronts and 4 or 2 base terms per thread
+  // between barriers; both give the same bits.  Tuned per (family, n, m): the
+  // first run that needs it times one chunk with each and keeps the faster.
+  const bool ib_sweep = P.incremental && P.select_k == 1 && P.pieces == 2 && P.tape == nullptr;
+  const uint64_t ib_key = (1ull << 63) | ((uint64_t)P.family << 56) | ((uint64_t)std::min(P.n, 1 << 24) << 8) |
+                          (uint64_t)P.m;
+  int ib_shape = ib_sweep ? tuned_shape(ib_key) : 0;   // 0: 512 threads, 1: 1024; -1: not known yet
+  float ib_us[2] = {-1.0f, -1.0f};
+  struct TuneEvents {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~TuneEvents() { for (auto x : e) if (x) (void)hipEventDestroy(x); }
+  } tev;
   for (;;) {
     // incremental bounds on a list one workgroup scans quickly: a whole chunk of
     // sweeps in one launch, as many as keep the list's growth within a bound
@@ -3741,6 +3754,14 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
     if ((st = run_capacity(U, chunk)) != IBB_OK) return st;
     const int sb = sel_blocks_for(U.n_keys + (int64_t)(chunk + 1) * P.nch);
     const bool prof = U.opts.profile != 0;
+    // a chunk on the per-sweep incremental path while the shape is not known times one shape
+    const bool tuning = ib_shape < 0 && !persist && !multi && !four && !tape;
+    const int ib_try = tuning ? (ib_us[0] < 0.0f ? 0 : 1) : std::max(ib_shape, 0);
+    if (tuning) {
+      for (auto& x : tev.e)
+        if (!x && hipEventCreate(&x) != hipSuccess) return fail(IBB_E_DEVICE, "hipEventCreate failed");
+      HIPCHK(hipEventRecord(tev.e[0], M.stream));
+    }
     const int nev = persist ? 4 : 4 * chunk;
     if (prof && (int)ev.size() < nev) {
       const size_t old_n = ev.size();
@@ -3818,9 +3839,14 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
                                 nullptr, 0, U.dP, U.dS);
         if (P.incremental) {   // selection and the children's bounds in one workgroup
-          hipExtLaunchKernelGGL((k_select_ib<kSelIbThreads, FAM>), dim3(1), dim3(kSelIbThreads), 0, M.stream,
-                                (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
-                                U.dS, sb > 1 ? sb : 0, 0);
+          if (ib_try == 1)
+            hipExtLaunchKernelGGL((k_select_ib<1024, FAM>), dim3(1), dim3(1024), 0, M.stream,
+                                  (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
+                                  U.dS, sb > 1 ? sb : 0, 0);
+          else
+            hipExtLaunchKernelGGL((k_select_ib<kSelIbThreads, FAM>), dim3(1), dim3(kSelIbThreads), 0, M.stream,
+                                  (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
+                                  U.dS, sb > 1 ? sb : 0, 0);
           continue;
         }
         hipExtLaunchKernelGGL(k_select<kSelSingleThreads>, dim3(1), dim3(kSelSingleThreads), 0, M.stream,
@@ -3831,9 +3857,22 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
       }
     });
     if (hipGetLastError() != hipSuccess) return (fail(IBB_E_DEVICE, "sweep launch failed"));
+    if (tuning) HIPCHK(hipEventRecord(tev.e[1], M.stream));
     if (hipMemcpyAsync(&U.hs, U.dS, sizeof(State), hipMemcpyDeviceToHost, M.stream) != hipSuccess ||
         hipStreamSynchronize(M.stream) != hipSuccess)
       return (fail(IBB_E_DEVICE, "sweep failed"));
+    if (tuning) {
+      // time per sweep of this chunk; a chunk that ran fewer than 4 sweeps is not counted
+      const int64_t ran = U.hs.sweeps - U.sweeps;
+      float ms = 0.0f;
+      if (ran >= 4 && hipEventElapsedTime(&ms, tev.e[0], tev.e[1]) == hipSuccess) {
+        ib_us[ib_try] = 1e3f * ms / (float)ran;
+        if (ib_us[0] >= 0.0f && ib_us[1] >= 0.0f) {
+          ib_shape = ib_us[1] < ib_us[0] ? 1 : 0;
+          store_tuned_shape(ib_key, ib_shape);
+        }
+      }
+    }
     if (prof && persist) {
       // one launch for the chunk: its time over the selections it made
       const int64_t ran = (U.hs.sweeps + (U.hs.pending ? 1 : 0)) - (U.sweeps + (U.pending ? 1 : 0));
