@@ -357,30 +357,32 @@ __device__ __forceinline__ SelAcc sel_block_reduce(SelAcc v) {
 
 // Insert the survivors of the previous sweep's children (lower bound <= the
 // final GUB of that sweep, first-order test passed), in child order, and fold
-// them into the running selection.  One workgroup of NT threads.
+// them into the running selection.  One workgroup of NT threads: each wavefront
+// takes a contiguous range of the records (the ranges in wavefront order keep
+// child order) and walks it in rounds of 64 consecutive records, one per lane,
+// so every load of a round is coalesced; a ballot places a round's survivors.
 template <int NT>
 __device__ __forceinline__ void insert_children(const Params& P, State* S, double gub, SelAcc& acc) {
   constexpr int NW = NT / kWave;
   __shared__ int w_ins[NW], w_form[NW], w_n32[NW];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
   // K > 1: the records of the K parents, parent-major (record p nch + c)
   const bool multi = P.select_k > 1;
   const int nrec = multi ? S->sel_count * P.nch : P.nch;
-  const int per = (nrec + NT - 1) / NT;
-  const int c0 = threadIdx.x * per, c1 = min(nrec, c0 + per);
-  int mine = 0, nformed = 0, n32 = 0;
-  for (int k = c0; k < c1; ++k) {
-    const uint8_t fl = P.ch_flag[k];
-    nformed += fl != 0;
-    n32 += fl == 3;
-    mine += (fl == 2 && !(P.ch_flo[k] > gub));
-  }
-  // prefix of the survivor counts: inclusive scan inside the wavefront, then
-  // the wavefront totals through LDS (children stay in child order)
-  int incl = mine;
-  for (int h = 1; h < kWave; h <<= 1) {
-    const int o = __shfl_up(incl, h, kWave);
-    if (lane >= h) incl += o;
+  const int per_w = (nrec + NW - 1) / NW;
+  const int r0 = min(nrec, wid * per_w), r1 = min(nrec, r0 + per_w);
+  int wsurv = 0, nformed = 0, n32 = 0;
+  for (int b = r0; b < r1; b += kWave) {
+    const int k = b + lane;
+    bool sv = false;
+    if (k < r1) {
+      const uint8_t fl = P.ch_flag[k];
+      nformed += fl != 0;
+      n32 += fl == 3;
+      sv = fl == 2 && !(P.ch_flo[k] > gub);
+    }
+    wsurv += __popcll(__ballot(sv));
   }
   for (int h = 32; h >= 1; h >>= 1) {
     nformed += __shfl_xor(nformed, h, kWave);
@@ -388,8 +390,7 @@ __device__ __forceinline__ void insert_children(const Params& P, State* S, doubl
   }
   __shared__ int w_tot[3];
   __syncthreads();   // the LDS arrays may still be read by a previous call
-  if (lane == kWave - 1) w_ins[wid] = incl;
-  if (lane == 0) { w_form[wid] = nformed; w_n32[wid] = n32; }
+  if (lane == 0) { w_ins[wid] = wsurv; w_form[wid] = nformed; w_n32[wid] = n32; }
   __syncthreads();
   if (wid == 0) {    // exclusive prefix of the wavefront totals, and the sums
     const int v = lane < NW ? w_ins[lane] : 0;
@@ -411,23 +412,31 @@ __device__ __forceinline__ void insert_children(const Params& P, State* S, doubl
   const int64_t base = S->n_keys;
   const int64_t seq0 = S->next_seq;
   const int row = S->sel_row;
-  int64_t o = base + (before + incl - mine);
+  int64_t o = base + before;   // the wavefront's next key
   SelAcc a = sel_empty();
-  for (int k = c0; k < c1; ++k) {
-    const double f = P.ch_flo[k];
-    if (P.ch_flag[k] == 2 && !(f > gub)) {
-      const int64_t sq = seq0 + (o - base);
-      P.key_flo[o] = f;
-      P.key_seq[o] = sq;
-      P.key_ref[o] = multi ? P.sel_tab[k >> P.m].row : row;
-      P.key_r[o] = multi ? (k & (P.nch - 1)) : k;
-      P.key_wmax[o] = P.ch_wmax[k];
-      a.cnt++;
-      a.wm = dmax(a.wm, P.ch_wmax[k]);
-      const Cand cd{f, o};
-      if (better(cd, a.best)) a.best = cd;
-      ++o;
+  for (int b = r0; b < r1; b += kWave) {
+    const int k = b + lane;
+    double f = 0.0;
+    bool sv = false;
+    if (k < r1) {
+      f = P.ch_flo[k];
+      sv = P.ch_flag[k] == 2 && !(f > gub);
     }
+    const unsigned long long bal = __ballot(sv);
+    if (sv) {
+      const int64_t ok = o + __popcll(bal & below);
+      P.key_flo[ok] = f;
+      P.key_seq[ok] = seq0 + (ok - base);
+      P.key_ref[ok] = multi ? P.sel_tab[k >> P.m].row : row;
+      P.key_r[ok] = multi ? (k & (P.nch - 1)) : k;
+      const double w = P.ch_wmax[k];
+      P.key_wmax[ok] = w;
+      a.cnt++;
+      a.wm = dmax(a.wm, w);
+      const Cand cd{f, ok};
+      if (better(cd, a.best)) a.best = cd;
+    }
+    o += __popcll(bal);
   }
   a = sel_block_reduce<NT>(a);
   acc = sel_merge(acc, a);
