@@ -110,11 +110,52 @@ __global__ __launch_bounds__(kWave) void k_tape_root(const Params* __restrict__ 
   S->bound_done = 0u;
 }
 
-// the children of the selected box, one thread each (PIECES = 2: bisection and
-// the midpoint sample; PIECES = 4: the paper's four pieces and P.nsamp diagonal
-// samples)
+// F, the first-order test and the record of every child of the selected box,
+// one thread each (PIECES = 2: bisection; PIECES = 4: the paper's four pieces);
+// the children's sample bounds are k_tape_samples' (the midpoint, or P.nsamp
+// diagonal points)
 template <int PIECES>
 __global__ __launch_bounds__(256) void k_tape_children(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params& P = *PP;
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int n = P.n, m = P.m;
+  const int64_t row = S->sel_row;
+  const int cyc = S->sel_cyc;
+  const uint32_t mask = S->sel_mask;
+  const bool in = g < P.nch;
+  bool formed = in;
+  if (PIECES == 2) {
+    formed = in && ((uint32_t)g & ~mask) == 0u;
+  } else {
+    for (int j = 0; j < m; ++j)
+      if (((g >> (2 * j)) & 3) && !((mask >> j) & 1u)) formed = false;
+  }
+  if (formed) {
+    using Row = typename std::conditional<PIECES == 4, ChildRow4, ChildRow>::type;
+    const Row X{P.hist_n + row * n, P.hist_h + row * n,
+                PIECES == 4 ? P.hist_cut + row * (3 * kMaxSplit) : P.hist_mid + row * kMaxSplit, n, m, cyc, mask,
+                (uint32_t)g};
+    I* ws = P.tws ? P.tws + (int64_t)g * P.tape->nprod * n : nullptr;
+    bool mo = false;
+    const I F = tape_box<Row, true>(*P.tape, P.tcols, n, X, P.nl, P.u, ws, mo, nullptr);
+    double wm = 0.0;
+    for (int i = 0; i < n; ++i) { const I x = X.get(i); wm = dmax(wm, x.n + x.h); }
+    P.ch_flo[g] = lo_or_ninf(neg(F.n));
+    P.ch_wmax[g] = wm;
+    P.ch_flag[g] = mo ? 1 : 2;
+  } else if (in) {
+    P.ch_flag[g] = 0;
+  }
+}
+
+// The sample upper bounds of the same children (their diagonal points, or the
+// midpoint), one thread per child, and the workgroup's smallest into GUB.  A
+// kernel of its own: point values need no tangents or adjoints, so it holds
+// about half the registers of the pass above and runs twice the wavefronts.
+template <int PIECES>
+__global__ __launch_bounds__(256) void k_tape_samples(const Params* __restrict__ PP, State* __restrict__ S) {
   round_up_mode();
   if (S->stop) return;
   const Params& P = *PP;
@@ -137,27 +178,17 @@ __global__ __launch_bounds__(256) void k_tape_children(const Params* __restrict_
     const Row X{P.hist_n + row * n, P.hist_h + row * n,
                 PIECES == 4 ? P.hist_cut + row * (3 * kMaxSplit) : P.hist_mid + row * kMaxSplit, n, m, cyc, mask,
                 (uint32_t)g};
-    I* ws = P.tws ? P.tws + (int64_t)g * P.tape->nprod * n : nullptr;
-    bool mo = false;
-    const I F = tape_box<Row, true>(*P.tape, P.tcols, n, X, P.nl, P.u, ws, mo, nullptr);
     bool unused = false;
     if (P.nsamp > 0) {
       for (int s = 0; s < P.nsamp; ++s) {
         const PointRow<Row> D{X, P.cs[s]};
-        ub = dmin(ub, hi_or_inf(tape_box<PointRow<Row>, false>(*P.tape, P.tcols, n, D, P.nl, P.u, ws, unused,
+        ub = dmin(ub, hi_or_inf(tape_box<PointRow<Row>, false>(*P.tape, P.tcols, n, D, P.nl, P.u, nullptr, unused,
                                                                nullptr).h));
       }
     } else {
       const PointRow<Row> M{X, -1.0};
-      ub = hi_or_inf(tape_box<PointRow<Row>, false>(*P.tape, P.tcols, n, M, P.nl, P.u, ws, unused, nullptr).h);
+      ub = hi_or_inf(tape_box<PointRow<Row>, false>(*P.tape, P.tcols, n, M, P.nl, P.u, nullptr, unused, nullptr).h);
     }
-    double wm = 0.0;
-    for (int i = 0; i < n; ++i) { const I x = X.get(i); wm = dmax(wm, x.n + x.h); }
-    P.ch_flo[g] = lo_or_ninf(neg(F.n));
-    P.ch_wmax[g] = wm;
-    P.ch_flag[g] = mo ? 1 : 2;
-  } else if (in) {
-    P.ch_flag[g] = 0;
   }
   // the workgroup's smallest sample bound into GUB (only when it is lower)
   __shared__ double s_u[256 / kWave];
@@ -3802,12 +3833,17 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
                                 (prof && sb == 1) ? ev[4 * s + 0] : nullptr, prof ? ev[4 * s + 3] : nullptr, 0, U.dP,
                                 U.dS, sb > 1 ? sb : 0, 0);
         const dim3 gch((unsigned)((P.nch + 255) / 256));
-        if (four)
+        if (four) {
           hipExtLaunchKernelGGL(k_tape_children<4>, gch, dim3(256), 0, M.stream, prof ? ev[4 * s + 1] : nullptr,
+                                nullptr, 0, U.dP, U.dS);
+          hipExtLaunchKernelGGL(k_tape_samples<4>, gch, dim3(256), 0, M.stream, nullptr,
                                 prof ? ev[4 * s + 2] : nullptr, 0, U.dP, U.dS);
-        else
+        } else {
           hipExtLaunchKernelGGL(k_tape_children<2>, gch, dim3(256), 0, M.stream, prof ? ev[4 * s + 1] : nullptr,
+                                nullptr, 0, U.dP, U.dS);
+          hipExtLaunchKernelGGL(k_tape_samples<2>, gch, dim3(256), 0, M.stream, nullptr,
                                 prof ? ev[4 * s + 2] : nullptr, 0, U.dP, U.dS);
+        }
       }
       for (int s = 0; s < chunk && four && !tape; ++s) {
         if (sb > 1)
