@@ -139,7 +139,11 @@ __global__ __launch_bounds__(256) void k_tape_children(const Params* __restrict_
                 (uint32_t)g};
     I* ws = P.tws ? P.tws + (int64_t)g * P.tape->nprod * n : nullptr;
     bool mo = false;
-    const I F = tape_box<Row, true>(*P.tape, P.tcols, n, X, P.nl, P.u, ws, mo, nullptr);
+    // GUB at this sweep's selection, never below the sweep's final GUB: a child
+    // whose lower bound exceeds it is not inserted, so its first-order test is
+    // not needed (its record still counts as formed)
+    const double gub0 = S->gub_start;
+    const I F = tape_box<Row, true>(*P.tape, P.tcols, n, X, P.nl, P.u, ws, mo, nullptr, gub0);
     double wm = 0.0;
     for (int i = 0; i < n; ++i) { const I x = X.get(i); wm = dmax(wm, x.n + x.h); }
     P.ch_flo[g] = lo_or_ninf(neg(F.n));
@@ -154,6 +158,9 @@ __global__ __launch_bounds__(256) void k_tape_children(const Params* __restrict_
 // midpoint), one thread per child, and the workgroup's smallest into GUB.  A
 // kernel of its own: point values need no tangents or adjoints, so it holds
 // about half the registers of the pass above and runs twice the wavefronts.
+// A child whose lower bound (written by the pass above) exceeds GUB is skipped:
+// every sample bound of a point of its box is at least that lower bound, so it
+// could not lower GUB.
 template <int PIECES>
 __global__ __launch_bounds__(256) void k_tape_samples(const Params* __restrict__ PP, State* __restrict__ S) {
   round_up_mode();
@@ -173,6 +180,9 @@ __global__ __launch_bounds__(256) void k_tape_samples(const Params* __restrict__
       if (((g >> (2 * j)) & 3) && !((mask >> j) & 1u)) formed = false;
   }
   double ub = __builtin_inf();
+  // GUB at this sweep's selection (not the running one, which other workgroups
+  // lower meanwhile: the count of bounds evaluated stays the same on every run)
+  if (formed && P.ch_flo[g] > S->gub_start) formed = false;   // counted as not evaluated
   if (formed) {
     using Row = typename std::conditional<PIECES == 4, ChildRow4, ChildRow>::type;
     const Row X{P.hist_n + row * n, P.hist_h + row * n,

@@ -176,9 +176,11 @@ struct PointRow {
 // F over the box X; with TEST also the first-order test (Sec. 3.1) against the
 // domain [nl, u], and with G != nullptr the gradient ([n][2] real endpoints).
 // ws: n intervals per product reduction for this thread (the right products).
+// cut: with no gradient asked for, a box whose lower bound exceeds it skips the
+// test (mono stays false): the caller discards such a box anyway.
 template <class ROW, bool TEST>
 __device__ I tape_box(const TapeDev& T, const double* cols, int n, const ROW& X, const double* nl, const double* u,
-                      I* ws, bool& mono, double* G) {
+                      I* ws, bool& mono, double* G, double cut = __builtin_inf()) {
   I V[kTapeMaxOps], D0[kTapeMaxOps], D1[kTapeMaxOps];
   uint8_t fl[kTapeMaxOps];
   I red[kTapeMaxRed];
@@ -203,6 +205,7 @@ __device__ I tape_box(const TapeDev& T, const double* cols, int n, const ROW& X,
   const I F = SV[T.Q - 1];
   mono = false;
   if (!TEST && !G) return F;
+  if (!G && lo_or_ninf(neg(F.n)) > cut) return F;
   // adjoints of the scalar program, in reverse op order
   I A[kTapeMaxOps], AR[kTapeMaxRed];
   bool hA[kTapeMaxOps], hR[kTapeMaxRed];
