@@ -514,6 +514,137 @@ __device__ __forceinline__ void insert_children(const Params& P, State* S, doubl
   __syncthreads();
 }
 
+// The same insertion on many workgroups, for the 4^m records of the paper's
+// schedule (one box per sweep, FP64): workgroup b takes the contiguous records
+// [b R, (b + 1) R) and, as insert_children does within its workgroup, each
+// wavefront a contiguous part of those, walked 64 consecutive records at a time.
+// k_ins_count counts each workgroup's survivors; k_ins_scatter places them after
+// those of the workgroups before it (so keys stay in child order) and its last
+// workgroup (a ticket counter) updates the counters, so that the selection's scan
+// that follows finds the new keys with everything else and inserts nothing
+// itself.  Both do nothing unless children are pending.
+__device__ __forceinline__ void ins_range(int nrec, int& r0, int& r1) {
+  const int per_b = (nrec + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int b0 = min(nrec, (int)blockIdx.x * per_b), b1 = min(nrec, b0 + per_b);
+  constexpr int NW = kSelThreads / kWave;
+  const int wid = threadIdx.x >> 6;
+  const int per_w = (b1 - b0 + NW - 1) / NW;
+  r0 = min(b1, b0 + wid * per_w);
+  r1 = min(b1, r0 + per_w);
+}
+__global__ __launch_bounds__(kSelThreads) void k_ins_count(const Params* __restrict__ PP, State* __restrict__ S) {
+  if (S->stop || !S->pending) return;
+  const Params P = *PP;
+  const double gub = okey_inv(S->gub_key);
+  int r0, r1;
+  ins_range(P.nch, r0, r1);
+  const int lane = threadIdx.x & (kWave - 1);
+  int surv = 0, formed = 0;
+  for (int b = r0; b < r1; b += kWave) {
+    const int k = b + lane;
+    bool sv = false;
+    if (k < r1) {
+      const uint8_t fl = P.ch_flag[k];
+      formed += fl != 0;
+      sv = fl == 2 && !(P.ch_flo[k] > gub);
+    }
+    surv += __popcll(__ballot(sv));
+  }
+  for (int h = 32; h >= 1; h >>= 1) formed += __shfl_xor(formed, h, kWave);
+  __shared__ int s_s[kSelThreads / kWave], s_f[kSelThreads / kWave];
+  if (lane == 0) { s_s[threadIdx.x >> 6] = surv; s_f[threadIdx.x >> 6] = formed; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ts = 0, tf = 0;
+    for (int w = 0; w < kSelThreads / kWave; ++w) { ts += s_s[w]; tf += s_f[w]; }
+    P.ins_cnt[blockIdx.x] = ts;
+    P.ins_cnt[kMaxSelBlocks + blockIdx.x] = tf;
+  }
+}
+__global__ __launch_bounds__(kSelThreads) void k_ins_scatter(const Params* __restrict__ PP, State* __restrict__ S) {
+  if (S->stop || !S->pending) return;
+  const Params P = *PP;
+  const double gub = okey_inv(S->gub_key);
+  const int64_t base = S->n_keys, seq0 = S->next_seq;   // read before this workgroup's ticket
+  const int row = S->sel_row;
+  constexpr int NW = kSelThreads / kWave;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  // survivors of the workgroups before this one, and of this one's wavefronts before this one
+  __shared__ int s_before, s_w[NW];
+  if (wid == 0) {
+    int x = 0;
+    for (int q = lane; q < (int)blockIdx.x; q += kWave) x += P.ins_cnt[q];
+    for (int h = 32; h >= 1; h >>= 1) x += __shfl_xor(x, h, kWave);
+    if (lane == 0) s_before = x;
+  }
+  int r0, r1;
+  ins_range(P.nch, r0, r1);
+  int wsurv = 0;
+  for (int b = r0; b < r1; b += kWave) {
+    const int k = b + lane;
+    const bool sv = k < r1 && P.ch_flag[k] == 2 && !(P.ch_flo[k] > gub);
+    wsurv += __popcll(__ballot(sv));
+  }
+  if (lane == 0) s_w[wid] = wsurv;
+  __syncthreads();
+  int64_t o = base + s_before;
+  for (int w = 0; w < wid; ++w) o += s_w[w];
+  for (int b = r0; b < r1; b += kWave) {
+    const int k = b + lane;
+    double f = 0.0;
+    bool sv = false;
+    if (k < r1) {
+      f = P.ch_flo[k];
+      sv = P.ch_flag[k] == 2 && !(f > gub);
+    }
+    const unsigned long long bal = __ballot(sv);
+    if (sv) {
+      const int64_t ok = o + __popcll(bal & below);
+      P.key_flo[ok] = f;
+      P.key_seq[ok] = seq0 + (ok - base);
+      P.key_ref[ok] = row;
+      P.key_r[ok] = k;
+      P.key_wmax[ok] = P.ch_wmax[k];
+    }
+    o += __popcll(bal);
+  }
+  // the last workgroup to finish updates the counters (the keys are visible to
+  // the next kernel in any case; the fence orders this workgroup's reads of the
+  // counters before its ticket)
+  __threadfence();
+  __syncthreads();
+  __shared__ uint32_t s_last;
+  if (threadIdx.x == 0) s_last = atomicAdd(&S->ins_ticket, 1u) == gridDim.x - 1 ? 1u : 0u;
+  __syncthreads();
+  if (!s_last) return;
+  if (wid == 0) {
+    int ts = 0, tf = 0;
+    for (int q = lane; q < (int)gridDim.x; q += kWave) {
+      ts += P.ins_cnt[q];
+      tf += P.ins_cnt[kMaxSelBlocks + q];
+    }
+    for (int h = 32; h >= 1; h >>= 1) {
+      ts += __shfl_xor(ts, h, kWave);
+      tf += __shfl_xor(tf, h, kWave);
+    }
+    if (lane == 0) {
+      const int64_t t = S->sweeps;
+      if (t < P.trace_cap) {
+        P.tr_gub[t] = gub;
+        P.tr_nsurv[t] = ts;
+        P.tr_sel[t] = S->sel_seq;
+      }
+      S->n_keys = base + ts;
+      S->next_seq = seq0 + ts;
+      S->evaluated += tf;
+      S->sweeps = t + 1;
+      S->pending = 0;
+      S->ins_ticket = 0u;
+    }
+  }
+}
+
 // One workgroup: stop test on [GLB, GUB]; if running, remove the best key from the
 // list and build its row (child r of row ref) and the split points of that row.
 // *wb (if given) receives this thread's widest written side outside the new
@@ -3376,6 +3507,7 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   P.hist_cut = four ? dalloc<double>(M, P.hist_cap * 3 * kMaxSplit) : nullptr;
   P.tab = four ? dalloc<double>(M, kTabDoubles) : nullptr;
   P.tabi = four ? dalloc<int32_t>(M, kTabInts) : nullptr;
+  P.ins_cnt = four ? dalloc<int32_t>(M, 2 * kMaxSelBlocks) : nullptr;
   P.ch_flo = dalloc<double>(M, nrec);
   P.ch_flag = dalloc<uint8_t>(M, nrec);
   P.ch_wmax = dalloc<double>(M, nrec);
@@ -3403,7 +3535,7 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   set_trace(P, dalloc<double>(M, 4 * P.trace_cap), P.trace_cap);
   if (!P.key_flo || !P.key_seq || !P.key_ref || !P.key_r || !P.key_wmax || !P.hist_n || !P.hist_h || !P.hist_cyc ||
       !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.sel_tab ||
-      (four && (!P.hist_cut || !P.tab || !P.tabi)) || (P.select_k > 1 && !P.ksel) ||
+      (four && (!P.hist_cut || !P.tab || !P.tabi || !P.ins_cnt)) || (P.select_k > 1 && !P.ksel) ||
       (tc && (!P.tcache || !P.hist_par)) || !P.part_flo ||
       !P.part_idx || !P.part_wmax || !P.part_cnt || !P.tr_gub || !P.tr_nsurv || !P.tr_nlive || !P.tr_sel)
     return fail(IBB_E_NOMEM, "device allocation failed");
@@ -3803,6 +3935,11 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
     if (U.opts.time_limit_s > 0.0) chunk = std::min(chunk, grow_chunk);   // the limit is checked between launches
     if ((st = run_capacity(U, chunk)) != IBB_OK) return st;
     const int sb = sel_blocks_for(U.n_keys + (int64_t)(chunk + 1) * P.nch);
+    // the paper's schedule with many records per sweep: their insertion on many
+    // workgroups (about 1024 records each) before the selection, not in it
+    const int ins_blocks = four && !multi && !P.prec32 && P.nch >= (1 << 16)
+                               ? (int)std::min<int64_t>(kMaxSelBlocks, ((int64_t)P.nch + 1023) / 1024)
+                               : 0;
     const bool prof = U.opts.profile != 0;
     // a chunk on the per-sweep incremental path while the shape is not known times one shape
     const bool tuning = ib_shape < 0 && !persist && !multi && !four && !tape;
@@ -3831,6 +3968,10 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
         return;
       }
       for (int s = 0; s < chunk && tape; ++s) {   // the generic family: selection, then every child in full
+        if (ins_blocks > 0) {
+          hipLaunchKernelGGL(k_ins_count, dim3(ins_blocks), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+          hipLaunchKernelGGL(k_ins_scatter, dim3(ins_blocks), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+        }
         if (sb > 1)
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
                                 nullptr, 0, U.dP, U.dS);
@@ -3856,6 +3997,10 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
         }
       }
       for (int s = 0; s < chunk && four && !tape; ++s) {
+        if (ins_blocks > 0) {
+          hipLaunchKernelGGL(k_ins_count, dim3(ins_blocks), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+          hipLaunchKernelGGL(k_ins_scatter, dim3(ins_blocks), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+        }
         if (sb > 1)
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
                                 nullptr, 0, U.dP, U.dS);

@@ -162,6 +162,8 @@ struct Params {
   double* tab;                            // the sweep's piece tables (kTabDoubles)
   int32_t* tabi;                          // their index part (kTabInts)
   KselBuf* ksel;                          // K > 1: the selection's buffer for long lists
+  int32_t* ins_cnt;                       // four pieces: survivors and formed records per insertion
+                                          // workgroup ([2][kMaxSelBlocks])
   // term cache (one box per sweep, incremental bounds, large n): for every row,
   // the terms its children share (F's enclosure and the midpoint bound of each
   // term no split coordinate of the row touches), [row][3][n]; a selected box
@@ -191,7 +193,8 @@ struct State {
   double gub_start;
   int32_t use32, p32_fails;
   int64_t p32_resume, fp32_pruned, fp32_sweeps;
-  int32_t sel_count, pad_sel;             // K > 1: boxes selected by the last selection
+  int32_t sel_count;                      // K > 1: boxes selected by the last selection
+  uint32_t ins_ticket;                    // workgroups of k_ins_scatter done in this sweep
   // K > 1 on long lists, the radix selection between its launches: the bits fixed
   // so far (ks_prefix, above bit ks_shift), how many boxes are still to be taken
   // at the bound, whether the bound is settled (ks_done) and whether every live
