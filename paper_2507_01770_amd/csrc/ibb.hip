@@ -519,10 +519,10 @@ __device__ __forceinline__ void insert_children(const Params& P, State* S, doubl
 // [b R, (b + 1) R) and, as insert_children does within its workgroup, each
 // wavefront a contiguous part of those, walked 64 consecutive records at a time.
 // k_ins_count counts each workgroup's survivors; k_ins_scatter places them after
-// those of the workgroups before it (so keys stay in child order) and its last
-// workgroup (a ticket counter) updates the counters, so that the selection's scan
-// that follows finds the new keys with everything else and inserts nothing
-// itself.  Both do nothing unless children are pending.
+// those of the workgroups before it (so keys stay in child order); k_ins_finish
+// (one workgroup) updates the counters, so that the selection's scan that
+// follows finds the new keys with everything else and inserts nothing itself.
+// All three do nothing unless children are pending.
 __device__ __forceinline__ void ins_range(int nrec, int& r0, int& r1) {
   const int per_b = (nrec + (int)gridDim.x - 1) / (int)gridDim.x;
   const int b0 = min(nrec, (int)blockIdx.x * per_b), b1 = min(nrec, b0 + per_b);
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(kSelThreads) void k_ins_scatter(const Params* __res
   if (S->stop || !S->pending) return;
   const Params P = *PP;
   const double gub = okey_inv(S->gub_key);
-  const int64_t base = S->n_keys, seq0 = S->next_seq;   // read before this workgroup's ticket
+  const int64_t base = S->n_keys, seq0 = S->next_seq;   // k_ins_finish changes them afterwards
   const int row = S->sel_row;
   constexpr int NW = kSelThreads / kWave;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
@@ -609,39 +609,33 @@ __global__ __launch_bounds__(kSelThreads) void k_ins_scatter(const Params* __res
     }
     o += __popcll(bal);
   }
-  // the last workgroup to finish updates the counters (the keys are visible to
-  // the next kernel in any case; the fence orders this workgroup's reads of the
-  // counters before its ticket)
-  __threadfence();
-  __syncthreads();
-  __shared__ uint32_t s_last;
-  if (threadIdx.x == 0) s_last = atomicAdd(&S->ins_ticket, 1u) == gridDim.x - 1 ? 1u : 0u;
-  __syncthreads();
-  if (!s_last) return;
-  if (wid == 0) {
-    int ts = 0, tf = 0;
-    for (int q = lane; q < (int)gridDim.x; q += kWave) {
-      ts += P.ins_cnt[q];
-      tf += P.ins_cnt[kMaxSelBlocks + q];
+}
+// the counters after the insertion (nb: the workgroups of the two kernels above)
+__global__ __launch_bounds__(kWave) void k_ins_finish(const Params* __restrict__ PP, State* __restrict__ S, int nb) {
+  if (S->stop || !S->pending) return;
+  const Params P = *PP;
+  const int lane = threadIdx.x;
+  int ts = 0, tf = 0;
+  for (int q = lane; q < nb; q += kWave) {
+    ts += P.ins_cnt[q];
+    tf += P.ins_cnt[kMaxSelBlocks + q];
+  }
+  for (int h = 32; h >= 1; h >>= 1) {
+    ts += __shfl_xor(ts, h, kWave);
+    tf += __shfl_xor(tf, h, kWave);
+  }
+  if (lane == 0) {
+    const int64_t t = S->sweeps;
+    if (t < P.trace_cap) {
+      P.tr_gub[t] = okey_inv(S->gub_key);
+      P.tr_nsurv[t] = ts;
+      P.tr_sel[t] = S->sel_seq;
     }
-    for (int h = 32; h >= 1; h >>= 1) {
-      ts += __shfl_xor(ts, h, kWave);
-      tf += __shfl_xor(tf, h, kWave);
-    }
-    if (lane == 0) {
-      const int64_t t = S->sweeps;
-      if (t < P.trace_cap) {
-        P.tr_gub[t] = gub;
-        P.tr_nsurv[t] = ts;
-        P.tr_sel[t] = S->sel_seq;
-      }
-      S->n_keys = base + ts;
-      S->next_seq = seq0 + ts;
-      S->evaluated += tf;
-      S->sweeps = t + 1;
-      S->pending = 0;
-      S->ins_ticket = 0u;
-    }
+    S->n_keys += ts;
+    S->next_seq += ts;
+    S->evaluated += tf;
+    S->sweeps = t + 1;
+    S->pending = 0;
   }
 }
 
@@ -3971,6 +3965,7 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
         if (ins_blocks > 0) {
           hipLaunchKernelGGL(k_ins_count, dim3(ins_blocks), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
           hipLaunchKernelGGL(k_ins_scatter, dim3(ins_blocks), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+          hipLaunchKernelGGL(k_ins_finish, dim3(1), dim3(kWave), 0, M.stream, U.dP, U.dS, ins_blocks);
         }
         if (sb > 1)
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
@@ -4000,6 +3995,7 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
         if (ins_blocks > 0) {
           hipLaunchKernelGGL(k_ins_count, dim3(ins_blocks), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
           hipLaunchKernelGGL(k_ins_scatter, dim3(ins_blocks), dim3(kSelThreads), 0, M.stream, U.dP, U.dS);
+          hipLaunchKernelGGL(k_ins_finish, dim3(1), dim3(kWave), 0, M.stream, U.dP, U.dS, ins_blocks);
         }
         if (sb > 1)
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,

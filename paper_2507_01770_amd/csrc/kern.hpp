@@ -193,8 +193,7 @@ struct State {
   double gub_start;
   int32_t use32, p32_fails;
   int64_t p32_resume, fp32_pruned, fp32_sweeps;
-  int32_t sel_count;                      // K > 1: boxes selected by the last selection
-  uint32_t ins_ticket;                    // workgroups of k_ins_scatter done in this sweep
+  int32_t sel_count, pad_sel;             // K > 1: boxes selected by the last selection
   // K > 1 on long lists, the radix selection between its launches: the bits fixed
   // so far (ks_prefix, above bit ks_shift), how many boxes are still to be taken
   // at the bound, whether the bound is settled (ks_done) and whether every live
