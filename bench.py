@@ -2,9 +2,10 @@
 
 Headline (the largest single-GPU workload): the non-smooth separable family
 f = sum s_i |x_i - c_i| + b_i sin^2(pi k_i (x_i - c_i)), n = 10,000, domain
-[-10, 10]^10000, seeded coefficients, enclosure width 1e-6, solved by the
-persistent sweep kernel (incremental child bounds, one box per sweep as in the
-paper).  One step = one whole solve, so ms_per_step is the time to enclosure
+[-10, 10]^10000, seeded coefficients, enclosure width 1e-6, one box per sweep as
+in the paper with incremental child bounds and the term cache, each sweep on
+several workgroups (selection, row and base terms over coordinate blocks, slot
+sums, children).  One step = one whole solve, so ms_per_step is the time to enclosure
 and value is boxes bounded per second.
 
 Also measured in the same run (extra keys of the JSON line):
@@ -23,7 +24,7 @@ Also measured in the same run (extra keys of the JSON line):
     per function, beside the paper's cloud-server times (other hardware);
   * the CPU oracle bounding children of the headline workload's first sweep (its
     per-child work), on one host thread and as one copy per host core.
-The headline kernel's roofline is against HBM: with the term cache a sweep at
+The headline's roofline is per sweep and against HBM: with the term cache a sweep at
 n = 10,000 mostly moves bytes (the live keys' lower bounds scanned, the selected
 row built, the parent's cached terms read and the box's written; cached_sweep_bytes).
 Other rooflines use the algorithmic operation counts per child and coordinate (F, its
@@ -118,34 +119,33 @@ def main() -> int:
             assert r.sweeps == rp.sweeps and r.boxes_evaluated == rp.boxes_evaluated
         return rs, rp, dt
 
-    # ---- headline: workload 3 (n = 10,000), one box per sweep, persistent kernel
+    # ---- headline: workload 3 (n = 10,000), one box per sweep, each on several workgroups
     p3 = PR.config(3)
     head = roofline = None
     if args.headline:
         phase("headline: non-smooth separable n = 10000")
         rs, rp, dt = timed(p3, args.steps, args.warmup)
         m = min(p3.n, 10)
-        # the persistent kernel's launches (lists up to 2^18 keys): with the term cache a
-        # sweep moves bytes rather than evaluating terms, so it is priced against HBM; the
-        # keys scanned per sweep are the live counts of the sweeps those launches ran
-        launches = max(1, rp.n_persistent_launches)
-        t_launch = rp.t_persistent_ms * 1e-3 / launches
-        sweeps_launch = rp.n_persistent_sweeps / launches
-        k_sweeps = max(1, rp.n_persistent_sweeps)
-        live = rp.trace_nlive[rp.trace_nlive <= (1 << 18)]
-        keys = float(np.mean(live)) if live.size else 0.0
+        # one sweep is five launches on the library's stream (k_select_part on long
+        # lists, k_ib_pick, k_ib_rowterms, k_ib_slots, k_ib_finish), timed together by
+        # its HIP events around them; with the term cache a sweep moves bytes rather
+        # than evaluating terms, so it is priced against HBM, the keys scanned per
+        # sweep being the sweeps' live counts
+        sweeps = max(1, rp.n_select_launches)
+        t_sweep = rp.t_select_ms * 1e-3 / sweeps
+        keys = float(np.mean(rp.trace_nlive)) if rp.trace_nlive.size else 0.0
         bytes_sweep = cached_sweep_bytes(p3.n, keys)
-        ach = bytes_sweep * sweeps_launch / t_launch / 1e9 if t_launch > 0 else 0.0
+        ach = bytes_sweep / t_sweep / 1e9 if t_sweep > 0 else 0.0
         ops_sweep = 3 * m * SEP_OPS + 3 * p3.n + (1 << m) * m * 3   # fresh terms, the base sum, the children
         roofline = {
-            "bound": "hbm", "kernel": "k_sweeps_ib<512, SEP_ABS_SIN2> (persistent, one workgroup per problem)",
+            "bound": "hbm",
+            "kernel": "one sweep: k_select_part, k_ib_pick<512>, k_ib_rowterms<SEP_ABS_SIN2>, k_ib_slots, "
+                      "k_ib_finish<512, SEP_ABS_SIN2> (per sweep; achieved and traffic per sweep)",
             "achieved": round(ach, 3), "peak": 8000.0, "unit": "GB/s", "frac": round(ach / 8000.0, 6),
-            "traffic": measured_traffic(), "avg_launch_us": round(t_launch * 1e6, 2),
-            "sweeps_per_launch": round(sweeps_launch, 2), "bytes_per_sweep": round(bytes_sweep),
-            "avg_sweep_us": round(rp.t_persistent_ms * 1e3 / k_sweeps, 3), "launches_per_solve": launches,
-            "alu_tflops": round(ops_sweep * sweeps_launch / t_launch / 1e12, 6) if t_launch > 0 else 0.0,
+            "traffic": measured_traffic(), "avg_sweep_us": round(t_sweep * 1e6, 3), "sweeps_timed": sweeps,
+            "bytes_per_sweep": round(bytes_sweep), "mean_live_keys": round(keys),
+            "alu_tflops": round(ops_sweep / t_sweep / 1e12, 6) if t_sweep > 0 else 0.0,
             "ops_per_sweep": ops_sweep,
-            "all_sweeps_avg_us": round(rp.t_select_ms * 1e3 / max(1, rp.n_select_launches), 3),
         }
         head = {"rs": rs, "rp": rp, "dt": dt}
 
@@ -331,7 +331,7 @@ def cpu_baseline(p, boxes: int) -> dict:
 
 
 def measured_traffic():
-    """HBM bytes per launch of the headline's persistent sweep kernel, from the committed
+    """HBM bytes per sweep of the headline (its five launches), from the committed
     rocprofv3 FETCH_SIZE and WRITE_SIZE counts (scaled by a plain copy's), when the kernel
     sources are the ones measured; else None."""
     import glob
@@ -344,7 +344,7 @@ def measured_traffic():
     if not m:
         return None
     rec = json.loads(m.group(1))
-    return rec["bytes_per_launch"] if rec.get("source_hash") == kernel_source_hash() else None
+    return rec["bytes_per_sweep"] if rec.get("source_hash") == kernel_source_hash() else None
 
 
 def kernel_source_hash() -> str:

@@ -645,7 +645,7 @@ __global__ __launch_bounds__(kWave) void k_ins_finish(const Params* __restrict__
 // row's window (see build_row).
 template <int NT, int PIECES = 2>
 __device__ __forceinline__ bool select_finish(const Params& P, State* S, const SelAcc& tot, double gub,
-                                              double* wb = nullptr) {
+                                              double* wb = nullptr, bool build = true) {
   __shared__ int32_t go;
   if (threadIdx.x == 0) {
     const Cand b = tot.best;
@@ -682,8 +682,10 @@ __device__ __forceinline__ bool select_finish(const Params& P, State* S, const S
                 PIECES == 4 ? P.hist_cut + (int64_t)ref * (3 * kMaxSplit) : P.hist_mid + (int64_t)ref * kMaxSplit,
                 n, P.m, pcyc, r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
   const int cyc = r >= 0 ? add_mod(pcyc, P.m, n) : pcyc;   // m <= n
-  const double w = build_row<NT>(src, P.hist_n + row * n, P.hist_h + row * n, n, cyc, P.m);
-  if (wb) *wb = w;
+  if (build) {   // else k_ib_rowterms builds the row on several workgroups
+    const double w = build_row<NT>(src, P.hist_n + row * n, P.hist_h + row * n, n, cyc, P.m);
+    if (wb) *wb = w;
+  }
   if (threadIdx.x < (unsigned)kWave) {
     const int j = threadIdx.x;
     bool ok = false;
@@ -707,6 +709,8 @@ __device__ __forceinline__ bool select_finish(const Params& P, State* S, const S
       P.hist_mask[row] = mask;
       P.hist_cyc[row] = cyc;
       if (P.hist_par) P.hist_par[row] = r >= 0 ? ref : -1;
+      S->sel_ref = ref;
+      S->sel_r = r;
       S->sel_mask = mask;
       S->sel_cyc = cyc;
       S->sel_row = (int32_t)row;
@@ -863,7 +867,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_part(const Params* __res
 // fences are needed.
 template <int NT, int PIECES = 2>
 __device__ __forceinline__ bool select_body(const Params& P, State* S, int nparts, int host_stop,
-                                            double* wb = nullptr) {
+                                            double* wb = nullptr, bool build = true) {
   const double gub = okey_inv(S->gub_key);
   // every thread reads the pending flag before the scan's barriers: thread 0 sets
   // it again in select_finish with no barrier in between, so a later read could see
@@ -889,7 +893,7 @@ __device__ __forceinline__ bool select_body(const Params& P, State* S, int npart
     }
     return false;
   }
-  return select_finish<NT, PIECES>(P, S, a, gub, wb);
+  return select_finish<NT, PIECES>(P, S, a, gub, wb, build);
 }
 
 // ---------------------------------------------------------------------------
@@ -983,9 +987,13 @@ __device__ __forceinline__ I ib_half(const double* rn, const double* rh, const d
 
 // wb0 >= 0: this thread's widest side outside the split window, taken when the
 // row was built (the base pass then reads the row only where it needs it);
-// negative: the base pass forms the widest side itself.
+// negative: the base pass forms the widest side itself.  presum: the base pass
+// was done on several workgroups (k_ib_rowterms, k_ib_slots), which left the 64
+// slot sums of F's endpoints and of the midpoint bound and the widest unsplit
+// side of each of nblk coordinate blocks there.
 template <int NT, int FAM>
-__device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const Sel& sel, double wb0 = -1.0) {
+__device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const Sel& sel, double wb0 = -1.0,
+                                           const double* presum = nullptr, int nblk = 0) {
   static_assert(NT % kWave == 0, "whole wavefronts");
   __syncthreads();   // the selected row and its split points were written by other threads
   const int n = P.n, m = P.m, lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
@@ -1148,7 +1156,17 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
   };
   const double* ptc = par >= 0 ? P.tcache + (int64_t)par * 3 * n : nullptr;
   double* rtc = P.tcache ? P.tcache + row * 3 * n : nullptr;
-  for (int c0 = 0; c0 < n; c0 += CH * NT) {
+  if (presum) {
+    for (int k = (int)threadIdx.x; k < nblk; k += NT) wb = dmax(wb, G(presum)[3 * kWave + k]);
+    if (wid == 0) {
+      acc = I{G(presum)[lane], G(presum)[kWave + lane]};
+      uacc = G(presum)[2 * kWave + lane];
+    }
+    // the chunk loop's barriers are skipped: this one orders the tables and
+    // widths of step 2 (other wavefronts) before the prefix step reads them
+    __syncthreads();
+  }
+  for (int c0 = 0; c0 < n && !presum; c0 += CH * NT) {
     // Every load of the chunk is issued before any term is formed or stored: the
     // stores into this row's cache may alias the loads as far as the compiler
     // knows, so loads left between them would each wait for the stores before.
@@ -1441,8 +1459,9 @@ __device__ __forceinline__ double ib_gub(const Params& P, State* S, IbLds<NT>& L
 // through device memory
 template <int NT, int FAM>
 __device__ __forceinline__ void ib_children_insert(const Params& P, State* S, IbLds<NT>& L, const Sel& sel, Hot& h,
-                                                   double wb0 = -1.0) {
-  ib_prepare<NT, FAM>(P, L, sel, wb0);
+                                                   double wb0 = -1.0, const double* presum = nullptr,
+                                                   int nblk = 0) {
+  ib_prepare<NT, FAM>(P, L, sel, wb0, presum, nblk);
   int formed = 0;
   const double gub = ib_gub<NT, FAM>(P, S, L, sel.mask, h, formed);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
@@ -1734,6 +1753,169 @@ __global__ __launch_bounds__(NT) void k_select_ib(const Params* __restrict__ PP,
     Hot h = hot_load(S);
     ib_children_insert<NT, FAM>(P, S, lds, sel_load(S), h, wb);
   }
+}
+
+// The same sweep with the term cache on several workgroups (one box per sweep,
+// n >= kIbPipeMinN): the O(n) work of one box (its row, its base terms) is what
+// one workgroup is bound by there, and it splits without changing any sum:
+//   k_ib_pick      the selection (select_body; on a long list after the
+//                  partials of k_select_part) without the row;
+//   k_ib_rowterms  one coordinate per thread: the row, each base term from the
+//                  parent's cache or formed (ib_prepare's rules), into this
+//                  row's cache, and each block's widest unsplit side;
+//   k_ib_slots     the 64 slot sums of F's two endpoints and of the midpoint
+//                  bound, one workgroup per sum: each slot adds its terms in
+//                  increasing index, as the one-workgroup base pass does (the
+//                  slots are independent chains);
+//   k_ib_finish    ib_children_insert from those sums (folds, tables, children,
+//                  GUB, insertion).
+// The results are those of the one-workgroup sweep bit for bit.
+constexpr int kIbRowBlock = 256;   // coordinates per k_ib_rowterms workgroup, one per thread
+constexpr int kIbPipeMinN = 8192;  // below this n the extra launches cost more than spreading the O(n) pass saves
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ib_pick(const Params* __restrict__ PP, State* __restrict__ S, int nparts,
+                                                int host_stop) {
+  round_up_mode();
+  if (S->stop) return;
+  const Params P = *PP;
+  (void)select_body<NT>(P, S, nparts, host_stop, nullptr, false);
+}
+
+// a base term of the selected row (the one-workgroup pass's kind 2 or 3): i is
+// not cut in the row, has a term, and (chained family) its neighbour is not cut
+struct IbRowView {
+  int n, m, cyc, T;
+  uint32_t mask;
+  bool chain;
+  __device__ __forceinline__ bool split(int i) const {
+    if (i < 0 || i >= n) return false;
+    int j = i - cyc;
+    if (j < 0) j += n;
+    return j < m && ((mask >> j) & 1u);
+  }
+  __device__ __forceinline__ bool base_term(int i) const {
+    return i < n && !split(i) && i < T && !(chain && split(i + 1));
+  }
+};
+
+template <int FAM>
+__global__ __launch_bounds__(kIbRowBlock) void k_ib_rowterms(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  if (S->stop || !S->pending) return;
+  const Params P = *PP;
+  const int n = P.n, m = P.m;
+  const int64_t row = S->sel_row;
+  const int32_t ref = S->sel_ref, r = S->sel_r;
+  const IbRowView V{n, m, S->sel_cyc, FAM == FAM_CHAIN ? n - 1 : n, S->sel_mask, FAM == FAM_CHAIN};
+  const ChildRow src{P.hist_n + (int64_t)ref * n, P.hist_h + (int64_t)ref * n, P.hist_mid + (int64_t)ref * kMaxSplit,
+                     n, m, P.hist_cyc[ref], r >= 0 ? P.hist_mask[ref] : 0u, r >= 0 ? (uint32_t)r : 0u};
+  const int32_t par = G(P.hist_par)[row];
+  const int pcyc = par >= 0 ? G(P.hist_cyc)[par] : 0;
+  const uint32_t pmask = par >= 0 ? G(P.hist_mask)[par] : 0u;
+  auto cut_by_parent = [&](int i) -> bool {
+    if (i >= n) return false;
+    int j = i - pcyc;
+    if (j < 0) j += n;
+    return j < m && ((pmask >> j) & 1u);
+  };
+  const double* ptc = par >= 0 ? P.tcache + (int64_t)par * 3 * n : nullptr;
+  double* rtc = P.tcache + row * 3 * n;
+  double* rn = P.hist_n + row * n;
+  double* rh = P.hist_h + row * n;
+  // one coordinate per thread, every load issued before the stores (which the
+  // compiler must assume may alias them)
+  const int i = (int)blockIdx.x * kIbRowBlock + (int)threadIdx.x;
+  double wb = 0.0;
+  if (i < n) {
+    const I x = src.get(i);
+    const bool sp = V.split(i), bt = V.base_term(i);
+    const bool reuse = bt && ptc && !cut_by_parent(i) && !(FAM == FAM_CHAIN && cut_by_parent(i + 1));
+    I t{0.0, 0.0};
+    double u = 0.0;
+    if (reuse) {
+      t = I{G(ptc)[i], G(ptc)[n + i]};
+      u = G(ptc)[2 * n + i];
+    } else if (bt) {
+      if constexpr (FAM != FAM_CHAIN) {
+        const CoefSep ci = gload(P.sep + i);
+        t = sep_term<FAM>(ci, x);
+        u = sep_point_hi<FAM>(ci, midpoint(x));
+      } else {
+        const I xn = src.get(i + 1);   // the next coordinate of this row
+        I R, E;
+        const CoefChain ci = gload(P.chain + i);
+        t = chain_term(ci, x, xn, R, E);
+        u = chain_term(ci, point(midpoint(x)), point(midpoint(xn)), R, E).h;
+      }
+    }
+    G(rn)[i] = x.n;
+    G(rh)[i] = x.h;
+    if (!sp) wb = x.n + x.h;
+    if (bt) {
+      G(rtc)[i] = t.n;
+      G(rtc)[n + i] = t.h;
+      G(rtc)[2 * n + i] = u;
+    }
+  }
+  wb = wave_max(wb);
+  __shared__ double s_w[kIbRowBlock / kWave];
+  if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x >> 6] = wb;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double w = s_w[0];
+    for (int k = 1; k < kIbRowBlock / kWave; ++k) w = dmax(w, s_w[k]);
+    G(P.ibsum)[3 * kWave + blockIdx.x] = w;
+  }
+}
+
+// Workgroup w forms sum w (0: F's negated lower endpoint, 1: its upper
+// endpoint, 2: the midpoint bound).  The column is staged in LDS a chunk at a
+// time, every load of a chunk in flight together; then lane s of the first
+// wavefront adds the terms s, s + 64, ... of the chunk in increasing index.
+constexpr int kIbSlotsThreads = 1024;
+constexpr int kIbSlotsChunk = 16384;   // 128 KB of LDS (gfx950 has 160 KB per CU)
+
+__global__ __launch_bounds__(kIbSlotsThreads) void k_ib_slots(const Params* __restrict__ PP, State* __restrict__ S) {
+  round_up_mode();
+  if (S->stop || !S->pending) return;
+  const Params P = *PP;
+  const int n = P.n;
+  const bool chain = P.family == FAM_CHAIN;
+  const IbRowView V{n, P.m, S->sel_cyc, chain ? n - 1 : n, S->sel_mask, chain};
+  const int which = blockIdx.x, lane = threadIdx.x & (kWave - 1);
+  const double* col = P.tcache + (int64_t)S->sel_row * 3 * n + (int64_t)which * n;
+  __shared__ double buf[kIbSlotsChunk];
+  constexpr int R = kIbSlotsChunk / kIbSlotsThreads;
+  double acc = 0.0;
+  for (int c0 = 0; c0 < n; c0 += kIbSlotsChunk) {
+    double v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = c0 + r * kIbSlotsThreads + (int)threadIdx.x;
+      v[r] = V.base_term(i) ? G(col)[i] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[r * kIbSlotsThreads + threadIdx.x] = v[r];
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+      const int rows = (min(kIbSlotsChunk, n - c0) + kWave - 1) / kWave;   // rows past n hold zeros
+      for (int q = 0; q < rows; ++q) acc = acc + buf[q * kWave + lane];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kWave) G(P.ibsum)[which * kWave + lane] = acc;
+}
+
+// nblk: the workgroups of k_ib_rowterms (each left its widest unsplit side)
+template <int NT, int FAM>
+__global__ __launch_bounds__(NT) void k_ib_finish(const Params* __restrict__ PP, State* __restrict__ S, int nblk) {
+  round_up_mode();
+  if (S->stop || !S->pending) return;
+  const Params P = *PP;
+  __shared__ IbLds<NT> lds;
+  Hot h = hot_load(S);
+  ib_children_insert<NT, FAM>(P, S, lds, sel_load(S), h, -1.0, P.ibsum, nblk);
 }
 
 // K > 1 with incremental bounds: workgroup p bounds the children of the box of
@@ -3510,6 +3692,7 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   const bool tc = U.term_cache && P.incremental && P.select_k == 1 && P.pieces == 2 && n >= kTermCacheMinN;
   P.tcache = tc ? dalloc<double>(M, P.hist_cap * 3 * n) : nullptr;
   P.hist_par = tc ? dalloc<int32_t>(M, P.hist_cap) : nullptr;
+  P.ibsum = tc ? dalloc<double>(M, 3 * kWave + (n + kIbRowBlock - 1) / kIbRowBlock) : nullptr;
   if (P.tape) {   // right products of the product reductions: n intervals each per child record
     TapeDev T;
     int64_t at = 0;
@@ -3530,7 +3713,7 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   if (!P.key_flo || !P.key_seq || !P.key_ref || !P.key_r || !P.key_wmax || !P.hist_n || !P.hist_h || !P.hist_cyc ||
       !P.hist_mask || !P.hist_mid || !P.ch_flo || !P.ch_flag || !P.ch_wmax || !P.sel_tab ||
       (four && (!P.hist_cut || !P.tab || !P.tabi || !P.ins_cnt)) || (P.select_k > 1 && !P.ksel) ||
-      (tc && (!P.tcache || !P.hist_par)) || !P.part_flo ||
+      (tc && (!P.tcache || !P.hist_par || !P.ibsum)) || !P.part_flo ||
       !P.part_idx || !P.part_wmax || !P.part_cnt || !P.tr_gub || !P.tr_nsurv || !P.tr_nlive || !P.tr_sel)
     return fail(IBB_E_NOMEM, "device allocation failed");
   // root row: (-l, u)
@@ -3907,7 +4090,10 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
   // 512 or 1024 threads, i.e. 8 or 16 wavefronts and 4 or 2 base terms per thread
   // between barriers; both give the same bits.  Tuned per (family, n, m): the
   // first run that needs it times one chunk with each and keeps the faster.
-  const bool ib_sweep = P.incremental && P.select_k == 1 && P.pieces == 2 && P.tape == nullptr;
+  const bool ib_sweep = P.incremental && P.select_k == 1 && P.pieces == 2 && P.tape == nullptr && !P.tcache;
+  // one box per sweep at large n: every sweep on several workgroups (k_ib_pick ... k_ib_finish)
+  const bool ib_pipe = P.incremental && P.select_k == 1 && P.pieces == 2 && P.tape == nullptr && P.tcache &&
+                       P.n >= kIbPipeMinN;
   const uint64_t ib_key = (1ull << 63) | ((uint64_t)P.family << 56) | ((uint64_t)std::min(P.n, 1 << 24) << 8) |
                           (uint64_t)P.m;
   int ib_shape = ib_sweep ? tuned_shape(ib_key) : 0;   // 0: 512 threads, 1: 1024; -1: not known yet
@@ -3922,7 +4108,7 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
     const bool multi = P.select_k > 1;   // K boxes per sweep: a selection kernel and a bound kernel per sweep
     const bool four = P.pieces == 4;     // the paper's schedule: selection, tables, children kernels per sweep
     const bool tape = P.tape != nullptr; // the generic family: selection and a children kernel per sweep
-    const bool persist = !multi && !four && P.incremental && U.n_keys <= kPersistentMaxKeys;
+    const bool persist = !multi && !four && !ib_pipe && P.incremental && U.n_keys <= kPersistentMaxKeys;
     int chunk = persist ? (int)std::min<int64_t>(std::max<int64_t>(kPersistentGrowth / P.nch, 16), 256) : grow_chunk;
     if (!persist)   // the key arrays are sized for every child of the chunk surviving: keep that within 2^23 keys
       chunk = (int)std::max<int64_t>(1, std::min<int64_t>(chunk, ((int64_t)1 << 23) / ((int64_t)P.select_k * P.nch)));
@@ -4034,6 +4220,17 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
         if (sb > 1)
           hipExtLaunchKernelGGL(k_select_part, dim3(sb), dim3(kSelThreads), 0, M.stream, prof ? ev[4 * s + 0] : nullptr,
                                 nullptr, 0, U.dP, U.dS);
+        if (ib_pipe) {   // the sweep on several workgroups
+          const int nblk = (P.n + kIbRowBlock - 1) / kIbRowBlock;
+          hipExtLaunchKernelGGL(k_ib_pick<kSelIbThreads>, dim3(1), dim3(kSelIbThreads), 0, M.stream,
+                                (prof && sb == 1) ? ev[4 * s + 0] : nullptr, nullptr, 0, U.dP, U.dS, sb > 1 ? sb : 0,
+                                0);
+          hipLaunchKernelGGL(k_ib_rowterms<FAM>, dim3(nblk), dim3(kIbRowBlock), 0, M.stream, U.dP, U.dS);
+          hipLaunchKernelGGL(k_ib_slots, dim3(3), dim3(kIbSlotsThreads), 0, M.stream, U.dP, U.dS);
+          hipExtLaunchKernelGGL((k_ib_finish<kSelIbThreads, FAM>), dim3(1), dim3(kSelIbThreads), 0, M.stream, nullptr,
+                                prof ? ev[4 * s + 3] : nullptr, 0, U.dP, U.dS, nblk);
+          continue;
+        }
         if (P.incremental) {   // selection and the children's bounds in one workgroup
           if (ib_try == 1)
             hipExtLaunchKernelGGL((k_select_ib<1024, FAM>), dim3(1), dim3(1024), 0, M.stream,

@@ -169,6 +169,9 @@ struct Params {
   // term no split coordinate of the row touches), [row][3][n]; a selected box
   // takes those of its parent row that its own cut leaves unchanged
   double* tcache;                         // null: no cache
+  double* ibsum;                          // with the cache, the sweep on several workgroups: the 64
+                                          // slot sums of F's endpoints and of the midpoint bound
+                                          // [3][64], then the widest unsplit side per row block
   int32_t* hist_par;                      // [row] the row the box was cut from (-1: none)
   // the generic family
   const TapeDev* tape;                    // null for the fixed families
@@ -194,6 +197,7 @@ struct State {
   int32_t use32, p32_fails;
   int64_t p32_resume, fp32_pruned, fp32_sweeps;
   int32_t sel_count, pad_sel;             // K > 1: boxes selected by the last selection
+  int32_t sel_ref, sel_r;                 // K = 1: the selected key's parent row and child index
   // K > 1 on long lists, the radix selection between its launches: the bits fixed
   // so far (ks_prefix, above bit ks_shift), how many boxes are still to be taken
   // at the bound, whether the bound is settled (ks_done) and whether every live

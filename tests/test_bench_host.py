@@ -28,7 +28,7 @@ def _fake_tree(tmp_path, sources, recorded_hash):
         (csrc / name).write_bytes(text)
     prof = tmp_path / "profiles"
     prof.mkdir()
-    rec = {"bytes_per_launch": 12345, "source_hash": recorded_hash}
+    rec = {"bytes_per_sweep": 12345, "source_hash": recorded_hash}
     (prof / "hbm_bytes_sep_abs_sin2_n10000.md").write_text("# HBM bytes\n\n```json\n" + json.dumps(rec) + "\n```\n")
 
 

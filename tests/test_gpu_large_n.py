@@ -96,16 +96,31 @@ def test_large_n_alone_batch_and_server():
         same(a, res[t])
 
 
-def test_term_cache_at_n_10000_past_the_persistent_list_size():
-    # the non-smooth n = 10,000 workload: ibb_solve (term cache; the persistent
-    # kernel, then, once the list passes 2^18 keys, the per-sweep kernels) and
-    # the batched engine (no cache) run the same iteration bit for bit
+def test_term_cache_at_n_10000_whole_solve():
+    # the non-smooth n = 10,000 workload to its enclosure: ibb_solve (term cache;
+    # from n = 8192 on each sweep runs on several workgroups: the selection, the
+    # row and base terms over blocks of coordinates, the slot sums, then the
+    # children in one workgroup) and the batched engine (no cache, one workgroup
+    # per sweep) run the same iteration bit for bit
     p = PR.config(3)
-    budget = dict(max_sweeps=1500)
+    budget = dict(max_sweeps=40000)
     print("case n=10000 alone (term cache)", flush=True)
     a = ibb.minimize(p, fetch_boxes=False, **budget)
-    print(f"largest live list {a.trace_nlive.max()}, keys inserted {a.trace_nsurv.sum()}", flush=True)
+    print(f"{a.sweeps} sweeps, largest live list {a.trace_nlive.max()}", flush=True)
     print("case n=10000 batch (no cache)", flush=True)
     b = ibb.solve_batch([p], fetch_boxes=False, **budget)[0]
     same(a, b)
-    assert a.sweeps == 1500
+    assert a.status == ibb.OK and a.f_lo <= 0.0 <= a.f_hi and a.f_hi - a.f_lo <= 1e-6
+
+
+@pytest.mark.parametrize("make,sweeps", [(lambda: PR.chain(8300, 505, hi=2.3), 2000),
+                                         (lambda: PR.sep_cos(9000, 9), 3000)],
+                         ids=["chain_n8300", "sep_cos_n9000"])
+def test_several_workgroup_sweeps_equal_the_batched_engine(make, sweeps):
+    # n past 8192 and ragged against the coordinate blocks (256) and the slots
+    # (64): the other two families through the several-workgroup sweep
+    p = make()
+    print(f"case {p.name} alone and batch, {sweeps} sweeps", flush=True)
+    a = ibb.minimize(p, fetch_boxes=False, max_sweeps=sweeps)
+    b = ibb.solve_batch([p], fetch_boxes=False, max_sweeps=sweeps)[0]
+    same(a, b)
