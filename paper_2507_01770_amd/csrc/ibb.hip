@@ -942,6 +942,13 @@ struct Sel {
 };
 
 constexpr int kIbChunkTerms = 2048;  // base terms evaluated by the workgroup between two barriers
+// The sweep on several workgroups leaves in Params::ibsum: the 64 slot sums of F's
+// two endpoints and of the midpoint bound [3][64]; for the separable families the
+// table entries of each split index j and half b [kMaxSplit][2][4] (F's enclosure
+// of the term, its midpoint bound, the first-order test as 0 or 1); the widest
+// unsplit side of each block of coordinates.
+constexpr int kIbTabOff = 3 * kWave;
+constexpr int kIbWOff = kIbTabOff + kMaxSplit * 2 * 4;
 constexpr int kTermCacheMinN = 1024;  // the term cache pays for its 24 n bytes per row from this n on
 constexpr int kIbMaxTerms = kMaxSplit + 1;
 constexpr int kIbCacheChildren = 1024;   // children whose bounds are kept in LDS between the two passes
@@ -1078,7 +1085,18 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
     const int na = L.naff, ng = L.ngc;
     if (FAM != FAM_CHAIN) {                     // separable: F, midpoint bound, first-order test of each half
       const int part = q >> 6, r = q & (kWave - 1);
-      if (part < 3 && r < 2 * na) {
+      if (part < 3 && r < 2 * na && presum) {   // formed by k_ib_rowterms (the same functions of the same halves)
+        const int k = r >> 1, b = r & 1;
+        const double* e = presum + kIbTabOff + (L.aj[k][0] * 2 + b) * 4;
+        if (part == 0) {
+          L.t_n[k][b] = G(e)[0];
+          L.t_h[k][b] = G(e)[1];
+        } else if (part == 1) {
+          L.t_u[k][b] = G(e)[2];
+        } else {
+          L.gmono[k][b] = G(e)[3] != 0.0 ? 1 : 0;
+        }
+      } else if (part < 3 && r < 2 * na) {
         const int k = r >> 1, b = r & 1;
         const int a = L.aff[k];
         const I x = ib_half(rn, rh, mid, a, L.aj[k][0], b);
@@ -1157,7 +1175,7 @@ __device__ __forceinline__ void ib_prepare(const Params& P, IbLds<NT>& L, const 
   const double* ptc = par >= 0 ? P.tcache + (int64_t)par * 3 * n : nullptr;
   double* rtc = P.tcache ? P.tcache + row * 3 * n : nullptr;
   if (presum) {
-    for (int k = (int)threadIdx.x; k < nblk; k += NT) wb = dmax(wb, G(presum)[3 * kWave + k]);
+    for (int k = (int)threadIdx.x; k < nblk; k += NT) wb = dmax(wb, G(presum)[kIbWOff + k]);
     if (wid == 0) {
       acc = I{G(presum)[lane], G(presum)[kWave + lane]};
       uacc = G(presum)[2 * kWave + lane];
@@ -1762,15 +1780,18 @@ __global__ __launch_bounds__(NT) void k_select_ib(const Params* __restrict__ PP,
 //                  partials of k_select_part) without the row;
 //   k_ib_rowterms  one coordinate per thread: the row, each base term from the
 //                  parent's cache or formed (ib_prepare's rules), into this
-//                  row's cache, and each block's widest unsplit side;
+//                  row's cache, and each block's widest unsplit side; for the
+//                  separable families one more workgroup forms the table
+//                  entries of the split coordinates' halves;
 //   k_ib_slots     the 64 slot sums of F's two endpoints and of the midpoint
 //                  bound, one workgroup per sum: each slot adds its terms in
 //                  increasing index, as the one-workgroup base pass does (the
 //                  slots are independent chains);
-//   k_ib_finish    ib_children_insert from those sums (folds, tables, children,
-//                  GUB, insertion).
+//   k_ib_finish    ib_children_insert from those sums and tables (folds,
+//                  prefix table, children, GUB, insertion).
 // The results are those of the one-workgroup sweep bit for bit.
 constexpr int kIbRowBlock = 256;   // coordinates per k_ib_rowterms workgroup, one per thread
+static_assert(3 * 2 * kMaxSplit <= kIbRowBlock, "one thread per table entry of the split halves");
 constexpr int kIbPipeMinN = 8192;  // below this n the extra launches cost more than spreading the O(n) pass saves
 
 template <int NT>
@@ -1823,6 +1844,33 @@ __global__ __launch_bounds__(kIbRowBlock) void k_ib_rowterms(const Params* __res
   double* rtc = P.tcache + row * 3 * n;
   double* rn = P.hist_n + row * n;
   double* rh = P.hist_h + row * n;
+  if (FAM != FAM_CHAIN && (int)blockIdx.x * kIbRowBlock >= n) {
+    // the separable families' last workgroup: the table entries of the split
+    // coordinates' halves, which the finishing workgroup would otherwise form
+    // (ib_prepare's step 2) while the rest of it waits
+    const int part = (int)threadIdx.x / (2 * kMaxSplit), q = (int)threadIdx.x % (2 * kMaxSplit);
+    const int j = q >> 1, b = q & 1;
+    if (part < 3 && j < m && ((S->sel_mask >> j) & 1u)) {
+      const int a = add_mod(S->sel_cyc, j, n);
+      const I xa = src.get(a);
+      const double md = G(P.hist_mid)[row * kMaxSplit + j];
+      const I x = b ? I{neg(md), xa.h} : I{xa.n, md};
+      const CoefSep ci = gload(P.sep + a);
+      double* e = P.ibsum + kIbTabOff + (j * 2 + b) * 4;
+      if (part == 0) {
+        const I t = sep_term<FAM>(ci, x);
+        G(e)[0] = t.n;
+        G(e)[1] = t.h;
+      } else if (part == 1) {
+        G(e)[2] = sep_point_hi<FAM>(ci, midpoint(x));
+      } else {
+        I t, Gr;
+        sep_box<FAM>(ci, x, t, Gr);
+        G(e)[3] = ((Gr.n < 0.0 && x.n != G(P.nl)[a]) || (Gr.h < 0.0 && x.h != G(P.u)[a])) ? 1.0 : 0.0;
+      }
+    }
+    return;
+  }
   // one coordinate per thread, every load issued before the stores (which the
   // compiler must assume may alias them)
   const int i = (int)blockIdx.x * kIbRowBlock + (int)threadIdx.x;
@@ -1865,7 +1913,7 @@ __global__ __launch_bounds__(kIbRowBlock) void k_ib_rowterms(const Params* __res
   if (threadIdx.x == 0) {
     double w = s_w[0];
     for (int k = 1; k < kIbRowBlock / kWave; ++k) w = dmax(w, s_w[k]);
-    G(P.ibsum)[3 * kWave + blockIdx.x] = w;
+    G(P.ibsum)[kIbWOff + blockIdx.x] = w;
   }
 }
 
@@ -3692,7 +3740,7 @@ ibb_status run_setup(Run& U, const ibb_problem* prob) {
   const bool tc = U.term_cache && P.incremental && P.select_k == 1 && P.pieces == 2 && n >= kTermCacheMinN;
   P.tcache = tc ? dalloc<double>(M, P.hist_cap * 3 * n) : nullptr;
   P.hist_par = tc ? dalloc<int32_t>(M, P.hist_cap) : nullptr;
-  P.ibsum = tc ? dalloc<double>(M, 3 * kWave + (n + kIbRowBlock - 1) / kIbRowBlock) : nullptr;
+  P.ibsum = tc ? dalloc<double>(M, kIbWOff + (n + kIbRowBlock - 1) / kIbRowBlock) : nullptr;
   if (P.tape) {   // right products of the product reductions: n intervals each per child record
     TapeDev T;
     int64_t at = 0;
@@ -4225,7 +4273,9 @@ ibb_status run_sweeps(Run& U, int bound_shape) {
           hipExtLaunchKernelGGL(k_ib_pick<kSelIbThreads>, dim3(1), dim3(kSelIbThreads), 0, M.stream,
                                 (prof && sb == 1) ? ev[4 * s + 0] : nullptr, nullptr, 0, U.dP, U.dS, sb > 1 ? sb : 0,
                                 0);
-          hipLaunchKernelGGL(k_ib_rowterms<FAM>, dim3(nblk), dim3(kIbRowBlock), 0, M.stream, U.dP, U.dS);
+          // the separable families: one more workgroup for the tables of the split halves
+          hipLaunchKernelGGL(k_ib_rowterms<FAM>, dim3(nblk + (FAM != FAM_CHAIN ? 1 : 0)), dim3(kIbRowBlock), 0,
+                             M.stream, U.dP, U.dS);
           hipLaunchKernelGGL(k_ib_slots, dim3(3), dim3(kIbSlotsThreads), 0, M.stream, U.dP, U.dS);
           hipExtLaunchKernelGGL((k_ib_finish<kSelIbThreads, FAM>), dim3(1), dim3(kSelIbThreads), 0, M.stream, nullptr,
                                 prof ? ev[4 * s + 3] : nullptr, 0, U.dP, U.dS, nblk);

@@ -171,7 +171,8 @@ struct Params {
   double* tcache;                         // null: no cache
   double* ibsum;                          // with the cache, the sweep on several workgroups: the 64
                                           // slot sums of F's endpoints and of the midpoint bound
-                                          // [3][64], then the widest unsplit side per row block
+                                          // [3][64], the separable families' tables of the split
+                                          // halves, the widest unsplit side per block of coordinates
   int32_t* hist_par;                      // [row] the row the box was cut from (-1: none)
   // the generic family
   const TapeDev* tape;                    // null for the fixed families
