@@ -1792,7 +1792,10 @@ __global__ __launch_bounds__(NT) void k_select_ib(const Params* __restrict__ PP,
 // The results are those of the one-workgroup sweep bit for bit.
 constexpr int kIbRowBlock = 256;   // coordinates per k_ib_rowterms workgroup, one per thread
 static_assert(3 * 2 * kMaxSplit <= kIbRowBlock, "one thread per table entry of the split halves");
-constexpr int kIbPipeMinN = 8192;  // below this n the extra launches cost more than spreading the O(n) pass saves
+// below this n the extra launches cost more than spreading the O(n) pass saves
+// (per sweep, one workgroup against several: n = 2048 28 against 30 us, 4096 36
+// against 36, 6144 39 against 35)
+constexpr int kIbPipeMinN = 5120;
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_ib_pick(const Params* __restrict__ PP, State* __restrict__ S, int nparts,

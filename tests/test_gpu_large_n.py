@@ -98,7 +98,7 @@ def test_large_n_alone_batch_and_server():
 
 def test_term_cache_at_n_10000_whole_solve():
     # the non-smooth n = 10,000 workload to its enclosure: ibb_solve (term cache;
-    # from n = 8192 on each sweep runs on several workgroups: the selection, the
+    # from n = 5120 on each sweep runs on several workgroups: the selection, the
     # row and base terms over blocks of coordinates, the slot sums, then the
     # children in one workgroup) and the batched engine (no cache, one workgroup
     # per sweep) run the same iteration bit for bit
@@ -114,10 +114,10 @@ def test_term_cache_at_n_10000_whole_solve():
 
 
 @pytest.mark.parametrize("make,sweeps", [(lambda: PR.chain(8300, 505, hi=2.3), 2000),
-                                         (lambda: PR.sep_cos(9000, 9), 3000)],
-                         ids=["chain_n8300", "sep_cos_n9000"])
+                                         (lambda: PR.sep_cos(5200, 9), 3000)],
+                         ids=["chain_n8300", "sep_cos_n5200"])
 def test_several_workgroup_sweeps_equal_the_batched_engine(make, sweeps):
-    # n past 8192 and ragged against the coordinate blocks (256) and the slots
+    # n past 5120 and ragged against the coordinate blocks (256) and the slots
     # (64): the other two families through the several-workgroup sweep
     p = make()
     print(f"case {p.name} alone and batch, {sweeps} sweeps", flush=True)
